@@ -1,0 +1,303 @@
+"""CPU oracle for the superstep engine -- test infrastructure only.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The device library
+(``paper_2203_13005_amd``) never imports it and shares no code with it; the
+two meet only in the seeded inputs from ``gen``.
+
+The arithmetic lives in ``oracle.c`` (plain C, single threaded, PageRank in
+float64).  The functions here drive it superstep by superstep and hold the
+independent pins that check it: a dense linear solve for the PageRank fixed
+point and a hop-bounded Bellman-Ford written as whole-array relaxation.
+Each function names the passage of the paper it follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "_oracle.so")
+_lib = None
+
+INF = 0xFFFFFFFF
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c into _oracle.so with gcc (no device code involved)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        P, I64, I32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        sig = {
+            "or_out_degree": (None, [I64, I64, P, P]),
+            "or_pr_superstep": (None, [I64, I64, P, P, P, D, P, P]),
+            "or_ppr_superstep": (None, [I64, I64, P, P, P, D, I32, P, P]),
+            "or_min_superstep": (I64, [I64, I64, P, P, P, ctypes.c_int, P, P, P, P, P]),
+            "or_sssp": (I64, [I64, I64, P, P, P, I32, I64, P, P, P, P]),
+            "or_cc": (I64, [I64, I64, P, P, P, I64, P, P, P, P]),
+            "or_delta": (I64, [I64, P, P, P, P, P, P]),
+            "or_dijkstra": (ctypes.c_int, [I64, I64, P, P, P, I32, P, P]),
+            "or_cc_hops": (I64, [I64, I64, P, P, P]),
+            "or_union_find_min": (ctypes.c_int, [I64, I64, P, P, P, P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _edges(g):
+    src = np.ascontiguousarray(np.repeat(np.arange(g.V, dtype=np.int32), np.diff(g.row_ptr)))
+    dst = np.ascontiguousarray(g.col, dtype=np.int32)
+    w = np.ascontiguousarray(g.w, dtype=np.uint32)
+    return src, dst, w
+
+
+def out_degree(g) -> np.ndarray:
+    src, _, _ = _edges(g)
+    deg = np.empty(max(g.V, 1), np.int32)
+    _load().or_out_degree(g.V, g.E, _p(src), _p(deg))
+    return deg[: g.V]
+
+
+# --------------------------------------------------------------------------
+# PageRank / personalised PageRank (algorithms named in Section "Setup"; the
+# iteration follows the template of Section "Algorithm Template").
+# --------------------------------------------------------------------------
+
+def pagerank(g, T: int, d: float = 0.85, x0: np.ndarray | None = None,
+             history: bool = False):
+    """x after T supersteps from x0 (default 1/V), float64.  With history=True
+    also returns the list of states x_0 .. x_T."""
+    lib = _load()
+    src, dst, _ = _edges(g)
+    deg = out_degree(g)
+    x = np.full(g.V, 1.0 / g.V) if x0 is None else np.array(x0, np.float64)
+    hist = [x.copy()] if history else None
+    nxt = np.empty_like(x)
+    for _ in range(T):
+        lib.or_pr_superstep(g.V, g.E, _p(src), _p(dst), _p(deg), d, _p(x), _p(nxt))
+        x, nxt = nxt, x
+        if history:
+            hist.append(x.copy())
+    return (x, hist) if history else x
+
+
+def ppr(g, seed: int, T: int, d: float = 0.85, history: bool = False):
+    """Personalised PageRank from seed after T supersteps, x0 = e_seed."""
+    lib = _load()
+    src, dst, _ = _edges(g)
+    deg = out_degree(g)
+    x = np.zeros(g.V)
+    x[seed] = 1.0
+    hist = [x.copy()] if history else None
+    nxt = np.empty_like(x)
+    for _ in range(T):
+        lib.or_ppr_superstep(g.V, g.E, _p(src), _p(dst), _p(deg), d, int(seed), _p(x), _p(nxt))
+        x, nxt = nxt, x
+        if history:
+            hist.append(x.copy())
+    return (x, hist) if history else x
+
+
+# --------------------------------------------------------------------------
+# Min-combine algorithms (Bellman-Ford SSSP and label propagation, Section
+# "Setup"), run to convergence under the iteration control of Section
+# "Iteration Control".
+# --------------------------------------------------------------------------
+
+@dataclass
+class MinRun:
+    state: np.ndarray          # uint32 [V]
+    K: int                     # supersteps including the last one with no change (-1: cap hit)
+    front: np.ndarray          # |F_k| per superstep
+    msgs: np.ndarray           # messages generated per superstep
+    changed: np.ndarray        # |F_{k+1}| per superstep
+
+
+def sssp(g, source: int, max_steps: int = 1 << 30) -> MinRun:
+    lib = _load()
+    src, dst, w = _edges(g)
+    cap = min(max_steps, g.V + 2)
+    dist = np.empty(max(g.V, 1), np.uint32)
+    fs, ef, ch = (np.zeros(cap, np.int64) for _ in range(3))
+    K = lib.or_sssp(g.V, g.E, _p(src), _p(dst), _p(w), int(source), cap, _p(dist), _p(fs), _p(ef), _p(ch))
+    if K == -2:
+        raise MemoryError("oracle sssp")
+    n = K if K > 0 else cap
+    return MinRun(dist[: g.V], int(K), fs[:n], ef[:n], ch[:n])
+
+
+def cc(g, max_steps: int = 1 << 30) -> MinRun:
+    lib = _load()
+    src, dst, _ = _edges(g)
+    l2g = None if g.l2g is None else np.ascontiguousarray(g.l2g, np.int32)
+    cap = min(max_steps, g.V + 2)
+    lab = np.empty(max(g.V, 1), np.uint32)
+    fs, ef, ch = (np.zeros(cap, np.int64) for _ in range(3))
+    K = lib.or_cc(g.V, g.E, _p(src), _p(dst), _p(l2g), cap, _p(lab), _p(fs), _p(ef), _p(ch))
+    if K == -2:
+        raise MemoryError("oracle cc")
+    n = K if K > 0 else cap
+    return MinRun(lab[: g.V], int(K), fs[:n], ef[:n], ch[:n])
+
+
+def min_superstep(g, state: np.ndarray, front: np.ndarray, weighted: bool, both_dirs: bool):
+    """One Jacobi min superstep; returns (state', front')."""
+    lib = _load()
+    src, dst, w = _edges(g)
+    st = np.ascontiguousarray(state, np.uint32)
+    fr = np.ascontiguousarray(front, np.uint8)
+    nst = np.empty(max(g.V, 1), np.uint32)
+    nfr = np.empty(max(g.V, 1), np.uint8)
+    lib.or_min_superstep(g.V, g.E, _p(src), _p(dst), _p(w) if weighted else None, int(both_dirs),
+                         _p(st), _p(fr), _p(nst), _p(nfr), None)
+    return nst[: g.V], nfr[: g.V].astype(bool)
+
+
+def sssp_frontiers(g, source: int, max_steps: int = 1 << 30):
+    """States and frontiers of every superstep: lists dist_k, F_k (k = 0..K)."""
+    dist = np.full(g.V, INF, np.uint32)
+    front = np.zeros(g.V, bool)
+    dist[source] = 0
+    front[source] = True
+    dists, fronts = [dist.copy()], [front.copy()]
+    for _ in range(max_steps):
+        dist, front = min_superstep(g, dist, front, True, False)
+        dists.append(dist.copy())
+        fronts.append(front.copy())
+        if not front.any():
+            break
+    return dists, fronts
+
+
+# --------------------------------------------------------------------------
+# Sync set (Sections "Synchronization Caching" and "Synchronization
+# Skipping").
+# --------------------------------------------------------------------------
+
+REMOTE_OUT = 2
+REMOTE_ANY = 4
+
+
+def remote_mask(g, algo: str, mode: str = "remote") -> np.ndarray:
+    """Which vertices another node needs: out-edges elsewhere for PageRank and
+    SSSP (their values flow along out-edges), any edge elsewhere for CC."""
+    if mode == "all" or g.flags is None:
+        return np.ones(g.V, np.uint8) if (mode == "all") else np.zeros(g.V, np.uint8)
+    bit = REMOTE_ANY if algo == "cc" else REMOTE_OUT
+    return ((g.flags & bit) != 0).astype(np.uint8)
+
+
+def delta(g, remote: np.ndarray, now: np.ndarray, synced: np.ndarray):
+    """Lazy upload: (gid, value bits) of remote vertices whose value differs
+    from the last uploaded copy, ascending gid.  `synced` is updated in place.
+    Returns (gids, vals, skippable)."""
+    lib = _load()
+    now_b = np.ascontiguousarray(now).view(np.uint32)
+    assert synced.dtype == np.uint32 and synced.flags.c_contiguous
+    rem = np.ascontiguousarray(remote, np.uint8)
+    l2g = None if g.l2g is None else np.ascontiguousarray(g.l2g, np.int32)
+    gid = np.empty(max(g.V, 1), np.int32)
+    val = np.empty(max(g.V, 1), np.uint32)
+    n = lib.or_delta(g.V, _p(rem), _p(l2g), _p(now_b), _p(synced), _p(gid), _p(val))
+    return gid[:n].copy(), val[:n].copy(), n == 0
+
+
+# --------------------------------------------------------------------------
+# Independent pins.
+# --------------------------------------------------------------------------
+
+def dijkstra(g, source: int, with_hops: bool = False):
+    lib = _load()
+    src, dst, w = _edges(g)
+    dist = np.empty(max(g.V, 1), np.uint32)
+    hops = np.empty(max(g.V, 1), np.int32) if with_hops else None
+    rc = lib.or_dijkstra(g.V, g.E, _p(src), _p(dst), _p(w), int(source), _p(dist), _p(hops))
+    if rc != 0:
+        raise RuntimeError("or_dijkstra rc=%d" % rc)
+    return (dist[: g.V], hops[: g.V]) if with_hops else dist[: g.V]
+
+
+def union_find_labels(g) -> np.ndarray:
+    lib = _load()
+    src, dst, _ = _edges(g)
+    l2g = None if g.l2g is None else np.ascontiguousarray(g.l2g, np.int32)
+    lab = np.empty(max(g.V, 1), np.uint32)
+    if lib.or_union_find_min(g.V, g.E, _p(src), _p(dst), _p(l2g), _p(lab)) != 0:
+        raise MemoryError("union find")
+    return lab[: g.V]
+
+
+def cc_max_hops(g) -> int:
+    lib = _load()
+    src, dst, _ = _edges(g)
+    hop = np.empty(max(g.V, 1), np.int32)
+    return int(lib.or_cc_hops(g.V, g.E, _p(src), _p(dst), _p(hop)))
+
+
+def pagerank_fixed_point_dense(g, d: float = 0.85) -> np.ndarray:
+    """Solves (I - d M) x = (1-d)/V * 1 with a dense LU (numpy), where
+    M[v, u] = 1/outdeg(u) for an edge u->v and 1/V for every v when u has no
+    out-edge.  Only for small V."""
+    V = g.V
+    deg = np.diff(g.row_ptr).astype(np.float64)
+    M = np.zeros((V, V))
+    src = np.repeat(np.arange(V), np.diff(g.row_ptr))
+    M[g.col, src] += 1.0 / deg[src]
+    M[:, deg == 0] = 1.0 / V
+    return np.linalg.solve(np.eye(V) - d * M, np.full(V, (1.0 - d) / V))
+
+
+def ppr_fixed_point_dense(g, seed: int, d: float = 0.85) -> np.ndarray:
+    """Solves (I - d M_s) x = (1-d) e_s, with dangling columns sending their
+    mass to the seed."""
+    V = g.V
+    deg = np.diff(g.row_ptr).astype(np.float64)
+    M = np.zeros((V, V))
+    src = np.repeat(np.arange(V), np.diff(g.row_ptr))
+    M[g.col, src] += 1.0 / deg[src]
+    M[seed, deg == 0] = 1.0
+    b = np.zeros(V)
+    b[seed] = 1.0 - d
+    return np.linalg.solve(np.eye(V) - d * M, b)
+
+
+def hop_bounded_distances(g, source: int, k: int) -> np.ndarray:
+    """Brute force: the shortest distance over paths of at most k edges, by k
+    rounds of relaxing EVERY edge from the previous round's values (no
+    frontier)."""
+    src = np.repeat(np.arange(g.V), np.diff(g.row_ptr))
+    d = np.full(g.V, np.iinfo(np.int64).max // 4, np.int64)
+    d[source] = 0
+    for _ in range(k):
+        cand = d[src] + g.w.astype(np.int64)
+        nd = d.copy()
+        np.minimum.at(nd, g.col, cand)
+        d = nd
+    out = np.where(d >= np.iinfo(np.int64).max // 4, INF, d)
+    return np.minimum(out, INF).astype(np.uint32)

@@ -1,0 +1,397 @@
+/*
+ * CPU oracle for the superstep engine -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load this file's library.  The device library never links, calls or
+ * includes it, and this file includes nothing from the device library.
+ *
+ * What it computes is one superstep of the paper's vertex-program template
+ * (Section "Algorithm Template": MSGGen produces a message per edge from the
+ * source vertex, MSGMerge combines the messages bound for one destination,
+ * MSGApply folds the combined message into the vertex state), executed in the
+ * BSP order Gen -> Merge -> Apply (Section "PowerGraph", which contrasts it
+ * with GAS order).  Messages of one iteration have no data dependencies on
+ * each other (Section "Pipeline Shuffling", Pipeline Parallelism paragraph),
+ * so every message of superstep k is generated from the state as it stood at
+ * the start of superstep k (Jacobi semantics).
+ *
+ * The three algorithms are the ones the evaluation runs (Section "Setup"):
+ * PageRank, Bellman-Ford SSSP and label propagation (read as min-label
+ * connected components).  The paper gives no formulas for them; the readings
+ * used are:
+ *   PageRank  x0 = 1/V; D = sum of x over vertices with out-degree 0;
+ *             x'[v] = (1-d)/V + d * (sum_{u->v} x[u]/outdeg(u) + D/V).
+ *   PPR       as PageRank with the teleport term and the dangling mass D sent
+ *             to the seed s only; x0 = e_s.
+ *   SSSP      dist[s] = 0, others INF = 0xFFFFFFFF; F1 = {s}; a vertex in
+ *             F_k sends sat_add(dist[u], w) along each out-edge; the merge is
+ *             min; F_{k+1} = vertices whose distance strictly decreased.
+ *   CC        label[v] = global id of v; F1 = vertices with an edge; labels
+ *             travel along both directions of every edge; merge is min.
+ * Everything runs in plain loops over the edge list, single threaded, with
+ * PageRank in double precision.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_INF 0xFFFFFFFFu
+
+static inline uint32_t sat_add_u32(uint32_t a, uint32_t b)
+{
+    uint64_t s = (uint64_t)a + (uint64_t)b;
+    return s > OR_INF ? OR_INF : (uint32_t)s;
+}
+
+/* Out-degree of every vertex from the edge list. */
+void or_out_degree(int64_t V, int64_t E, const int32_t *src, int32_t *deg)
+{
+    memset(deg, 0, (size_t)V * sizeof(int32_t));
+    for (int64_t e = 0; e < E; e++) deg[src[e]]++;
+}
+
+/*
+ * One PageRank superstep (template order Gen -> Merge -> Apply).
+ *   Gen:   each edge u->v carries x[u] / outdeg(u).
+ *   Merge: acc[v] = sum of the messages bound for v (edge-list order).
+ *   Apply: x'[v] = (1-d)/V + d * (acc[v] + D/V), D = dangling mass.
+ * x_next must not alias x.
+ */
+void or_pr_superstep(int64_t V, int64_t E, const int32_t *src, const int32_t *dst,
+                     const int32_t *deg, double d, const double *x, double *x_next)
+{
+    double D = 0.0;
+    for (int64_t u = 0; u < V; u++)
+        if (deg[u] == 0) D += x[u];
+    for (int64_t v = 0; v < V; v++) x_next[v] = 0.0;
+    for (int64_t e = 0; e < E; e++) {
+        int32_t u = src[e];
+        x_next[dst[e]] += x[u] / (double)deg[u];
+    }
+    double base = (1.0 - d) / (double)V;
+    for (int64_t v = 0; v < V; v++) x_next[v] = base + d * (x_next[v] + D / (double)V);
+}
+
+/*
+ * One personalised-PageRank superstep for seed s: the same Gen and Merge;
+ * Apply sends the teleport (1-d) and the dangling mass D to the seed only:
+ *   x'[v] = (1-d)*[v==s] + d * (acc[v] + D*[v==s]).
+ */
+void or_ppr_superstep(int64_t V, int64_t E, const int32_t *src, const int32_t *dst,
+                      const int32_t *deg, double d, int32_t s, const double *x, double *x_next)
+{
+    double D = 0.0;
+    for (int64_t u = 0; u < V; u++)
+        if (deg[u] == 0) D += x[u];
+    for (int64_t v = 0; v < V; v++) x_next[v] = 0.0;
+    for (int64_t e = 0; e < E; e++) {
+        int32_t u = src[e];
+        x_next[dst[e]] += x[u] / (double)deg[u];
+    }
+    for (int64_t v = 0; v < V; v++) x_next[v] = d * x_next[v];
+    x_next[s] += (1.0 - d) + d * D;
+}
+
+/*
+ * One min-combine superstep shared by SSSP and CC (Jacobi):
+ *   Gen:   every edge (u, v) with u in the frontier carries
+ *          sat_add(state[u], w) (SSSP) or state[u] (CC, w == NULL).
+ *          With `both_dirs` the edge also carries state[v] to u
+ *          (CC treats edges as undirected).
+ *   Merge: min over the messages bound for a vertex.
+ *   Apply: state'[v] = min(state[v], merged); v joins the next frontier
+ *          iff state'[v] < state[v].
+ * Messages read `state` (start of superstep) and are folded into
+ * `state_next`, so no message sees a value produced in the same superstep.
+ * Returns |F_{k+1}|; *edges_out receives the number of messages generated.
+ */
+int64_t or_min_superstep(int64_t V, int64_t E, const int32_t *src, const int32_t *dst,
+                         const uint32_t *w, int both_dirs, const uint32_t *state,
+                         const uint8_t *front, uint32_t *state_next, uint8_t *front_next,
+                         int64_t *edges_out)
+{
+    int64_t msgs = 0;
+    memcpy(state_next, state, (size_t)V * sizeof(uint32_t));
+    for (int64_t e = 0; e < E; e++) {
+        int32_t u = src[e], v = dst[e];
+        if (front[u]) {
+            uint32_t m = w ? sat_add_u32(state[u], w[e]) : state[u];
+            if (m < state_next[v]) state_next[v] = m;
+            msgs++;
+        }
+        if (both_dirs && front[v]) {
+            uint32_t m = state[v];
+            if (m < state_next[u]) state_next[u] = m;
+            msgs++;
+        }
+    }
+    int64_t changed = 0;
+    for (int64_t v = 0; v < V; v++) {
+        front_next[v] = state_next[v] < state[v];
+        changed += front_next[v];
+    }
+    if (edges_out) *edges_out = msgs;
+    return changed;
+}
+
+/*
+ * SSSP to convergence by repeated supersteps (Section "Iteration Control":
+ * iterate until no vertex changes).  dist: V outputs.  Per superstep k
+ * (0-based) the optional arrays receive |F_k|, the messages generated and
+ * |F_{k+1}|.  Returns the number of supersteps K including the last one that
+ * changed nothing, or -1 if max_steps was reached first (dist then holds the
+ * state after max_steps supersteps), or -2 on allocation failure.
+ */
+int64_t or_sssp(int64_t V, int64_t E, const int32_t *src, const int32_t *dst, const uint32_t *w,
+                int32_t s, int64_t max_steps, uint32_t *dist,
+                int64_t *front_size, int64_t *edges, int64_t *changed)
+{
+    uint32_t *nd = (uint32_t *)malloc((size_t)(V > 0 ? V : 1) * sizeof(uint32_t));
+    uint8_t *f = (uint8_t *)calloc((size_t)(V > 0 ? V : 1), 1);
+    uint8_t *nf = (uint8_t *)calloc((size_t)(V > 0 ? V : 1), 1);
+    if (!nd || !f || !nf) { free(nd); free(f); free(nf); return -2; }
+    for (int64_t v = 0; v < V; v++) dist[v] = OR_INF;
+    int64_t fs = 0;
+    if (s >= 0 && s < V) { dist[s] = 0; f[s] = 1; fs = 1; }
+    int64_t k = 0, K = -1;
+    while (k < max_steps) {
+        int64_t ef = 0;
+        int64_t c = or_min_superstep(V, E, src, dst, w, 0, dist, f, nd, nf, &ef);
+        if (front_size) front_size[k] = fs;
+        if (edges) edges[k] = ef;
+        if (changed) changed[k] = c;
+        memcpy(dist, nd, (size_t)V * sizeof(uint32_t));
+        uint8_t *t = f; f = nf; nf = t;
+        fs = c;
+        k++;
+        if (c == 0) { K = k; break; }
+    }
+    free(nd); free(f); free(nf);
+    return K;
+}
+
+/*
+ * Min-label connected components to convergence.  label[v] starts at the
+ * global id (l2g[v], or v when l2g is NULL); F1 = vertices with at least one
+ * edge.  Same return convention as or_sssp.
+ */
+int64_t or_cc(int64_t V, int64_t E, const int32_t *src, const int32_t *dst, const int32_t *l2g,
+              int64_t max_steps, uint32_t *label,
+              int64_t *front_size, int64_t *edges, int64_t *changed)
+{
+    uint32_t *nl = (uint32_t *)malloc((size_t)(V > 0 ? V : 1) * sizeof(uint32_t));
+    uint8_t *f = (uint8_t *)calloc((size_t)(V > 0 ? V : 1), 1);
+    uint8_t *nf = (uint8_t *)calloc((size_t)(V > 0 ? V : 1), 1);
+    if (!nl || !f || !nf) { free(nl); free(f); free(nf); return -2; }
+    for (int64_t v = 0; v < V; v++) label[v] = l2g ? (uint32_t)l2g[v] : (uint32_t)v;
+    for (int64_t e = 0; e < E; e++) { f[src[e]] = 1; f[dst[e]] = 1; }
+    int64_t fs = 0;
+    for (int64_t v = 0; v < V; v++) fs += f[v];
+    int64_t k = 0, K = -1;
+    while (k < max_steps) {
+        int64_t ef = 0;
+        int64_t c = or_min_superstep(V, E, src, dst, NULL, 1, label, f, nl, nf, &ef);
+        if (front_size) front_size[k] = fs;
+        if (edges) edges[k] = ef;
+        if (changed) changed[k] = c;
+        memcpy(label, nl, (size_t)V * sizeof(uint32_t));
+        uint8_t *t = f; f = nf; nf = t;
+        fs = c;
+        k++;
+        if (c == 0) { K = k; break; }
+    }
+    free(nl); free(f); free(nf);
+    return K;
+}
+
+/*
+ * Sync set (Section "Synchronization Caching", lazy uploading; Section
+ * "Synchronization Skipping"): a vertex is uploaded only when another node
+ * needs it (remote[v] != 0) and its value differs from the copy last
+ * uploaded (bitwise); only its final value is sent.  Emits (gid, value) in
+ * ascending local id order, which is ascending gid because local ids follow
+ * global order.  Returns the count; an empty set means the synchronisation
+ * of this iteration can be skipped.  `synced` is updated to the uploaded
+ * values.
+ */
+int64_t or_delta(int64_t V, const uint8_t *remote, const int32_t *l2g, const uint32_t *now,
+                 uint32_t *synced, int32_t *gid_out, uint32_t *val_out)
+{
+    int64_t n = 0;
+    for (int64_t v = 0; v < V; v++) {
+        if (!remote[v] || now[v] == synced[v]) continue;
+        gid_out[n] = l2g ? l2g[v] : (int32_t)v;
+        val_out[n] = now[v];
+        synced[v] = now[v];
+        n++;
+    }
+    return n;
+}
+
+/* ------------------------------------------------------------------------
+ * Independent pins.  These reach the same answers by different algorithms
+ * and are used only to check the functions above.
+ * ------------------------------------------------------------------------ */
+
+/*
+ * Binary-heap Dijkstra.  With hops == NULL it returns exact shortest
+ * distances (unreachable -> INF).  With hops != NULL it orders paths
+ * lexicographically by (distance, number of edges), by running on the
+ * composite weight w * 2^26 + 1, and also returns for every vertex the
+ * fewest edges among its shortest paths (-1 when unreachable).  Requires
+ * V < 2^26 in that mode.
+ */
+int or_dijkstra(int64_t V, int64_t E, const int32_t *src, const int32_t *dst, const uint32_t *w,
+                int32_t s, uint32_t *dist, int32_t *hops)
+{
+    const int HB = 26;
+    int64_t *rp = (int64_t *)calloc((size_t)V + 1, sizeof(int64_t));
+    int32_t *adj = (int32_t *)malloc((size_t)(E > 0 ? E : 1) * sizeof(int32_t));
+    uint64_t *aw = (uint64_t *)malloc((size_t)(E > 0 ? E : 1) * sizeof(uint64_t));
+    uint64_t *d = (uint64_t *)malloc((size_t)(V > 0 ? V : 1) * sizeof(uint64_t));
+    uint8_t *done = (uint8_t *)calloc((size_t)(V > 0 ? V : 1), 1);
+    int64_t *pos = (int64_t *)malloc((size_t)(V > 0 ? V : 1) * sizeof(int64_t));
+    int64_t hcap = E + 1;
+    uint64_t *hk = (uint64_t *)malloc((size_t)hcap * sizeof(uint64_t));
+    int32_t *hv = (int32_t *)malloc((size_t)hcap * sizeof(int32_t));
+    int rc = 0;
+    if (!rp || !adj || !aw || !d || !done || !pos || !hk || !hv) { rc = -2; goto out; }
+    if (hops && V >= ((int64_t)1 << HB)) { rc = -1; goto out; }
+    for (int64_t e = 0; e < E; e++) rp[src[e] + 1]++;
+    for (int64_t v = 0; v < V; v++) rp[v + 1] += rp[v];
+    for (int64_t v = 0; v < V; v++) pos[v] = rp[v];
+    for (int64_t e = 0; e < E; e++) {
+        int64_t p = pos[src[e]]++;
+        adj[p] = dst[e];
+        aw[p] = hops ? (((uint64_t)w[e] << HB) + 1) : (uint64_t)w[e];
+    }
+    for (int64_t v = 0; v < V; v++) d[v] = UINT64_MAX;
+    int64_t hn = 0;
+    if (s >= 0 && s < V) { d[s] = 0; hk[0] = 0; hv[0] = s; hn = 1; }
+    while (hn > 0) {
+        uint64_t key = hk[0];
+        int32_t u = hv[0];
+        hn--;
+        if (hn > 0) {  /* move the last element to the root and sift it down */
+            uint64_t lk = hk[hn];
+            int32_t lv = hv[hn];
+            int64_t i = 0;
+            for (;;) {
+                int64_t c = 2 * i + 1;
+                if (c >= hn) break;
+                if (c + 1 < hn && hk[c + 1] < hk[c]) c++;
+                if (hk[c] >= lk) break;
+                hk[i] = hk[c]; hv[i] = hv[c]; i = c;
+            }
+            hk[i] = lk; hv[i] = lv;
+        }
+        if (done[u] || key != d[u]) continue;
+        done[u] = 1;
+        for (int64_t p = rp[u]; p < rp[u + 1]; p++) {
+            int32_t v = adj[p];
+            uint64_t nd = key + aw[p];
+            if (nd >= d[v]) continue;
+            d[v] = nd;
+            if (hn == hcap) {
+                int64_t nc = hcap * 2;
+                uint64_t *k2 = (uint64_t *)realloc(hk, (size_t)nc * sizeof(uint64_t));
+                if (!k2) { rc = -2; goto out; }
+                hk = k2;
+                int32_t *v2 = (int32_t *)realloc(hv, (size_t)nc * sizeof(int32_t));
+                if (!v2) { rc = -2; goto out; }
+                hv = v2;
+                hcap = nc;
+            }
+            int64_t i = hn++;  /* sift up */
+            while (i > 0) {
+                int64_t p2 = (i - 1) / 2;
+                if (hk[p2] <= nd) break;
+                hk[i] = hk[p2]; hv[i] = hv[p2]; i = p2;
+            }
+            hk[i] = nd; hv[i] = v;
+        }
+    }
+    for (int64_t v = 0; v < V; v++) {
+        uint64_t x = d[v];
+        if (x == UINT64_MAX) {
+            dist[v] = OR_INF;
+            if (hops) hops[v] = -1;
+            continue;
+        }
+        uint64_t dv = hops ? (x >> HB) : x;
+        dist[v] = dv > (uint64_t)OR_INF ? OR_INF : (uint32_t)dv;
+        if (hops) hops[v] = (int32_t)(x & (((uint64_t)1 << HB) - 1));
+    }
+out:
+    free(rp); free(adj); free(aw); free(d); free(done); free(pos); free(hk); free(hv);
+    return rc;
+}
+
+/*
+ * Undirected BFS from the smallest vertex of every component (vertices are
+ * scanned in increasing id; an unvisited vertex is the smallest of its
+ * component).  hop[v] = edges from v to that smallest vertex.  Returns the
+ * maximum hop over all vertices, or -2 on allocation failure.
+ */
+int64_t or_cc_hops(int64_t V, int64_t E, const int32_t *src, const int32_t *dst, int32_t *hop)
+{
+    int64_t *rp = (int64_t *)calloc((size_t)V + 1, sizeof(int64_t));
+    int32_t *adj = (int32_t *)malloc((size_t)(2 * E > 0 ? 2 * E : 1) * sizeof(int32_t));
+    int64_t *pos = (int64_t *)malloc((size_t)(V > 0 ? V : 1) * sizeof(int64_t));
+    int32_t *q = (int32_t *)malloc((size_t)(V > 0 ? V : 1) * sizeof(int32_t));
+    if (!rp || !adj || !pos || !q) { free(rp); free(adj); free(pos); free(q); return -2; }
+    for (int64_t e = 0; e < E; e++) { rp[src[e] + 1]++; rp[dst[e] + 1]++; }
+    for (int64_t v = 0; v < V; v++) rp[v + 1] += rp[v];
+    for (int64_t v = 0; v < V; v++) pos[v] = rp[v];
+    for (int64_t e = 0; e < E; e++) { adj[pos[src[e]]++] = dst[e]; adj[pos[dst[e]]++] = src[e]; }
+    for (int64_t v = 0; v < V; v++) hop[v] = -1;
+    int64_t maxh = 0;
+    for (int64_t r = 0; r < V; r++) {
+        if (hop[r] >= 0) continue;
+        int64_t qh = 0, qt = 0;
+        hop[r] = 0;
+        q[qt++] = (int32_t)r;
+        while (qh < qt) {
+            int32_t u = q[qh++];
+            for (int64_t p = rp[u]; p < rp[u + 1]; p++) {
+                int32_t v = adj[p];
+                if (hop[v] >= 0) continue;
+                hop[v] = hop[u] + 1;
+                if (hop[v] > maxh) maxh = hop[v];
+                q[qt++] = v;
+            }
+        }
+    }
+    free(rp); free(adj); free(pos); free(q);
+    return maxh;
+}
+
+/* Union-find (path halving, union by smaller root id): min id per component
+ * over undirected edges; label[v] = min over the component of gid. */
+int or_union_find_min(int64_t V, int64_t E, const int32_t *src, const int32_t *dst,
+                      const int32_t *l2g, uint32_t *label)
+{
+    int64_t *par = (int64_t *)malloc((size_t)(V > 0 ? V : 1) * sizeof(int64_t));
+    if (!par) return -2;
+    for (int64_t v = 0; v < V; v++) par[v] = v;
+    for (int64_t e = 0; e < E; e++) {
+        int64_t a = src[e], b = dst[e];
+        while (par[a] != a) { par[a] = par[par[a]]; a = par[a]; }
+        while (par[b] != b) { par[b] = par[par[b]]; b = par[b]; }
+        if (a == b) continue;
+        if (a < b) par[b] = a; else par[a] = b;
+    }
+    uint32_t *best = (uint32_t *)malloc((size_t)(V > 0 ? V : 1) * sizeof(uint32_t));
+    if (!best) { free(par); return -2; }
+    for (int64_t v = 0; v < V; v++) best[v] = OR_INF;
+    for (int64_t v = 0; v < V; v++) {
+        int64_t r = v;
+        while (par[r] != r) r = par[r];
+        par[v] = r;
+        uint32_t g = l2g ? (uint32_t)l2g[v] : (uint32_t)v;
+        if (g < best[r]) best[r] = g;
+    }
+    for (int64_t v = 0; v < V; v++) label[v] = best[par[v]];
+    free(par); free(best);
+    return 0;
+}

@@ -1,0 +1,262 @@
+"""Pins of the CPU oracle against results fixed independently of it.
+
+Each check reaches the expected value by a different route than the oracle
+(Dijkstra, union-find, BFS, dense LU, closed forms, a hand-worked example,
+whole-array relaxation), so a dropped term, a wrong sign, index or operand
+order in the oracle fails at least one of them.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+INF = oracle.INF
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def random_graph(V, E, seed, wmax=255):
+    rng = np.random.default_rng(seed)
+    src = rng.integers(0, V, E)
+    dst = rng.integers(0, V, E)
+    w = rng.integers(1, wmax + 1, E)
+    return gen.from_edges(V, src, dst, w)
+
+
+def load_hand():
+    with open(os.path.join(GOLDEN, "hand_sssp_cc_7v.json")) as f:
+        h = json.load(f)
+    e = np.array(h["edges"])
+    g = gen.from_edges(h["V"], e[:, 0], e[:, 1], e[:, 2])
+    return h, g
+
+
+# ---------------------------------------------------------------- hand example
+
+def test_hand_example_sssp():
+    h, g = load_hand()
+    run = oracle.sssp(g, h["sssp_source"])
+    assert run.K == h["sssp_K"]
+    assert run.state.tolist() == h["sssp_dist"]
+    assert run.msgs.tolist() == h["sssp_messages"]
+    dists, fronts = oracle.sssp_frontiers(g, h["sssp_source"])
+    assert [np.nonzero(f)[0].tolist() for f in fronts] == h["sssp_frontiers"]
+    assert [d.tolist() for d in dists[1:]] == h["sssp_dist_after_step"]
+
+
+def test_hand_example_cc():
+    h, g = load_hand()
+    run = oracle.cc(g)
+    assert run.state.tolist() == h["cc_labels"]
+    assert run.K == h["cc_K"]
+    assert run.changed.tolist() == h["cc_changed"]
+
+
+# ---------------------------------------------------------------- SSSP
+
+SSSP_CASES = [("rand", 40, 120, s) for s in range(6)] + [("rand", 64, 64, 7), ("rand", 50, 400, 8)]
+
+
+@pytest.mark.parametrize("kind,V,E,seed", SSSP_CASES)
+def test_sssp_equals_dijkstra_and_hop_bound(kind, V, E, seed):
+    g = random_graph(V, E, seed)
+    for s in (0, V // 3):
+        run = oracle.sssp(g, s)
+        dj, hops = oracle.dijkstra(g, s, with_hops=True)
+        assert np.array_equal(run.state, dj)
+        reach = hops >= 0
+        assert run.K == 1 + int(hops[reach].max())
+        # every intermediate state equals the best path of <= k edges
+        dists, _ = oracle.sssp_frontiers(g, s)
+        for k, dk in enumerate(dists):
+            assert np.array_equal(dk, oracle.hop_bounded_distances(g, s, k)), k
+
+
+@pytest.mark.parametrize("scale,seed", [(10, 1), (12, 2), (14, 5)])
+def test_sssp_rmat_dijkstra_and_certificate(scale, seed):
+    g = gen.rmat(scale, seed=seed)
+    run = oracle.sssp(g, 0)
+    dj, hops = oracle.dijkstra(g, 0, with_hops=True)
+    assert np.array_equal(run.state, dj)
+    assert run.K == 1 + int(hops[hops >= 0].max())
+    d = run.state.astype(np.int64)
+    src = g.src
+    fin = d[src] < INF
+    # triangle inequality on every edge out of a reached vertex
+    assert np.all(d[g.col[fin]] <= d[src[fin]] + g.w[fin])
+    # every reached non-source vertex has a tight in-edge
+    tight = np.zeros(g.V, bool)
+    t = fin & (d[g.col] == d[src] + g.w)
+    tight[g.col[t]] = True
+    reached = d < INF
+    reached[0] = False
+    assert np.all(tight[reached])
+    # frontier bookkeeping: |F_{k+1}| of step k is |F| of step k+1
+    assert np.array_equal(run.changed[:-1], run.front[1:])
+    assert run.changed[-1] == 0
+    deg = np.diff(g.row_ptr)
+    assert run.msgs[0] == deg[0]
+
+
+def test_sssp_special_cases():
+    # single vertex, no edges
+    g = gen.from_edges(1, [], [])
+    r = oracle.sssp(g, 0)
+    assert r.K == 1 and r.state.tolist() == [0]
+    # chain of V vertices: K = V
+    V = 9
+    g = gen.from_edges(V, np.arange(V - 1), np.arange(1, V), np.arange(1, V))
+    r = oracle.sssp(g, 0)
+    assert r.K == V
+    assert r.state.tolist() == np.cumsum(np.r_[0, np.arange(1, V)]).tolist()
+    # saturation: a path whose length exceeds 2^32-1 stays at INF
+    g = gen.from_edges(3, [0, 1], [1, 2], [0xFFFFFFF0, 0xFFFFFFF0])
+    r = oracle.sssp(g, 0)
+    assert r.state.tolist() == [0, 0xFFFFFFF0, INF]
+    # unreachable vertices stay INF; the source with no out-edge needs 1 step
+    g = gen.from_edges(4, [1, 2], [2, 3], [5, 5])
+    r = oracle.sssp(g, 0)
+    assert r.K == 1 and r.state.tolist() == [0, INF, INF, INF]
+
+
+# ---------------------------------------------------------------- CC
+
+@pytest.mark.parametrize("V,E,seed", [(50, 40, 1), (60, 90, 2), (64, 30, 3), (200, 150, 4)])
+def test_cc_equals_union_find(V, E, seed):
+    g = random_graph(V, E, seed)
+    r = oracle.cc(g)
+    assert np.array_equal(r.state, oracle.union_find_labels(g))
+    assert r.K == 1 + oracle.cc_max_hops(g)
+
+
+@pytest.mark.parametrize("scale,seed", [(11, 1), (13, 6)])
+def test_cc_rmat(scale, seed):
+    g = gen.rmat(scale, seed=seed)
+    r = oracle.cc(g)
+    assert np.array_equal(r.state, oracle.union_find_labels(g))
+    assert r.K == 1 + oracle.cc_max_hops(g)
+
+
+def test_cc_partition_uses_global_ids():
+    p = gen.rmat_part(12, seed=3, part=0)
+    r = oracle.cc(p)
+    uf = oracle.union_find_labels(p)
+    assert np.array_equal(r.state, uf)
+    # labels are global ids of the component's smallest member
+    assert set(np.unique(r.state)).issubset(set(p.l2g.tolist()))
+    assert r.K == 1 + oracle.cc_max_hops(p)
+
+
+# ---------------------------------------------------------------- PageRank
+
+def test_pagerank_mass_and_floor():
+    g = gen.rmat(10, seed=3)
+    d = 0.85
+    _, hist = oracle.pagerank(g, 20, d, history=True)
+    for x in hist:
+        assert abs(x.sum() - 1.0) < 1e-12
+    for x in hist[1:]:
+        assert x.min() >= (1 - d) / g.V - 1e-18
+
+
+def test_pagerank_closed_forms():
+    d = 0.85
+    # directed cycle: uniform at every step
+    V = 7
+    g = gen.from_edges(V, np.arange(V), (np.arange(V) + 1) % V)
+    x, hist = oracle.pagerank(g, 10, d, history=True)
+    for xt in hist:
+        assert np.allclose(xt, 1.0 / V, atol=1e-15, rtol=0)
+    # no edges: every vertex dangling, uniform at every step
+    g = gen.from_edges(5, [], [])
+    assert np.allclose(oracle.pagerank(g, 3, d), 0.2, atol=1e-15, rtol=0)
+    # two vertices 0 -> 1 (1 dangling): x0_t = x* + (1/2 - x*) (-d/2)^t,
+    # x* = 1/(2+d) (solved by hand from the fixed point)
+    g = gen.from_edges(2, [0], [1])
+    _, hist = oracle.pagerank(g, 12, d, history=True)
+    xs = 1.0 / (2.0 + d)
+    for t, xt in enumerate(hist):
+        x0 = xs + (0.5 - xs) * (-d / 2) ** t
+        assert abs(xt[0] - x0) < 1e-14 and abs(xt[1] - (1 - x0)) < 1e-14
+
+
+@pytest.mark.parametrize("V,E,seed", [(30, 60, 1), (80, 150, 2), (200, 900, 3), (300, 250, 4)])
+def test_pagerank_fixed_point_dense_lu(V, E, seed):
+    g = random_graph(V, E, seed)
+    x = oracle.pagerank(g, 300, 0.85)
+    ref = oracle.pagerank_fixed_point_dense(g, 0.85)
+    assert np.max(np.abs(x - ref)) < 1e-12
+
+
+def test_pagerank_fixed_point_rmat():
+    g = gen.rmat(9, seed=11)
+    x = oracle.pagerank(g, 300, 0.85)
+    ref = oracle.pagerank_fixed_point_dense(g, 0.85)
+    assert np.max(np.abs(x - ref)) < 1e-12
+
+
+@pytest.mark.parametrize("V,E,seed", [(40, 80, 5), (120, 200, 6)])
+def test_ppr_fixed_point_dense_lu(V, E, seed):
+    g = random_graph(V, E, seed)
+    s = 3
+    x, hist = oracle.ppr(g, s, 400, 0.85, history=True)
+    for xt in hist:
+        assert abs(xt.sum() - 1.0) < 1e-12
+    ref = oracle.ppr_fixed_point_dense(g, s, 0.85)
+    assert np.max(np.abs(x - ref)) < 1e-12
+
+
+def test_ppr_star_closed_form():
+    # star 0 -> 1..n, leaves dangling; seed 0.  Fixed point by hand:
+    # x0 = (1-d) + d * L, each leaf = d * x0 / n, L = n * leaf = d x0
+    # => x0 = (1-d) / (1 - d^2) = 1/(1+d), leaf = d / (n (1+d)).
+    n, d = 6, 0.85
+    g = gen.from_edges(n + 1, np.zeros(n, int), np.arange(1, n + 1))
+    x = oracle.ppr(g, 0, 400, d)
+    assert abs(x[0] - 1 / (1 + d)) < 1e-13
+    assert np.allclose(x[1:], d / (n * (1 + d)), atol=1e-13, rtol=0)
+
+
+# ---------------------------------------------------------------- sync set
+
+def test_delta_sets_follow_state_changes():
+    p = gen.rmat_part(12, seed=3, part=0)
+    rem = oracle.remote_mask(p, "cc")
+    assert rem.sum() > 0
+    # CC superstep by superstep; delta of each step = changed & remote
+    lab = p.l2g.astype(np.uint32).copy()
+    synced = lab.copy()
+    front = np.zeros(p.V, bool)
+    front[np.unique(np.r_[p.src, p.col])] = True
+    skipped = 0
+    for _ in range(100):
+        new, nf = oracle.min_superstep(p, lab, front, weighted=False, both_dirs=True)
+        gids, vals, skip = oracle.delta(p, rem, new, synced)
+        want = np.nonzero(nf & (rem != 0))[0]
+        assert gids.tolist() == p.l2g[want].tolist()
+        assert vals.tolist() == new[want].tolist()
+        assert np.all(np.diff(gids) > 0)
+        skipped += skip
+        lab, front = new, nf
+        if not nf.any():
+            break
+    # after the last upload the remote copies equal the final state
+    assert np.array_equal(synced[rem != 0], lab[rem != 0])
+    # a pass with no change has an empty set (skippable)
+    gids, _, skip = oracle.delta(p, rem, lab, synced)
+    assert skip and len(gids) == 0
+
+
+def test_delta_lazy_keeps_only_final_value():
+    p = gen.rmat_part(11, seed=3, part=0)
+    rem = oracle.remote_mask(p, "pr")
+    x0 = np.full(p.V, 1.0 / p.V, np.float32)
+    synced = x0.view(np.uint32).copy()
+    x5 = oracle.pagerank(p, 5).astype(np.float32)
+    gids, vals, _ = oracle.delta(p, rem, x5, synced)
+    changed = (x5.view(np.uint32) != x0.view(np.uint32)) & (rem != 0)
+    assert gids.tolist() == p.l2g[changed].tolist()
+    assert vals.tolist() == x5.view(np.uint32)[changed].tolist()
