@@ -1,0 +1,299 @@
+/*
+ * gx.h -- C ABI of the MI355X (gfx950) superstep engine.
+ *
+ * The engine runs the per-iteration compute of an accelerator daemon in the
+ * sense of GX-Plug (arXiv 2203.13005): one superstep of the algorithm
+ * template MSGGen -> MSGMerge -> MSGApply (Section "Algorithm Template")
+ * over one worker's edge partition, for PageRank, Bellman-Ford SSSP and
+ * label propagation read as min-label connected components (the algorithms
+ * of Section "Setup"), in BSP order (Section "PowerGraph" contrasts it with
+ * GAS order).  Calls map onto the paper's operation interfaces (Section
+ * "Operation Interfaces"):
+ *
+ *   connect() + transfer()          -> gx_graph_load
+ *   requestGen/Merge/Apply()         -> gx_superstep
+ *   iteration control                -> gx_run_until_converged
+ *     (Section "Iteration Control")
+ *   update(): lazy upload + skip     -> gx_sync_delta
+ *     (Sections "Synchronization Caching", "Synchronization Skipping")
+ *   disconnect()                     -> gx_graph_free / gx_state_free
+ *
+ * Conventions shared by every call:
+ *  - Every call returns a gx_status; nothing is thrown across the ABI.
+ *    gx_last_error() returns a message for the last failing call on the
+ *    calling thread (valid until the next gx_* call on that thread).
+ *  - Host arrays passed in are read during the call and stay owned by the
+ *    caller.
+ *  - Device memory is owned by the caller: graphs and states live in
+ *    caller-provided device buffers ("arenas") whose sizes the *_bytes calls
+ *    report.  The library sub-allocates inside them; on the superstep path it
+ *    never allocates device memory.  Arenas must be 256-byte aligned.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Calls
+ *    are asynchronous on it unless stated otherwise.
+ *  - Arguments are validated on the host before any device work, so
+ *    GX_EINVAL / GX_ENOMEM are reported without touching the GPU.
+ *  - A device error is sticky: the handle answers GX_EDEVICE from then on.
+ *  - Handles are not thread safe; distinct handles may be used concurrently
+ *    on distinct streams.
+ */
+#ifndef GX_H
+#define GX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gx_status;
+#define GX_OK            0
+#define GX_EINVAL        1  /* malformed argument or graph */
+#define GX_ENOMEM        2  /* arena / capacity too small, or host allocation failed */
+#define GX_EDEVICE       3  /* HIP runtime error (sticky per handle) */
+#define GX_ENOTCONVERGED 4  /* superstep cap reached; the state is valid */
+#define GX_EBUSY         5  /* serving: no room for the request right now */
+#define GX_ENOTFOUND     6  /* serving: unknown graph or request id */
+
+typedef enum {
+    GX_PAGERANK = 0,  /* float32 ranks; fixed number of supersteps */
+    GX_SSSP     = 1,  /* uint32 distances, INF = 0xFFFFFFFF; to convergence */
+    GX_CC       = 2,  /* uint32 labels (global ids); to convergence */
+    GX_PPR      = 3   /* float32 personalised PageRank (batched / serving only) */
+} gx_algo;
+
+/* Which device images gx_graph_load builds (bitmask). */
+#define GX_NEED_OUT 1u  /* out-CSR (dst, weight) + in-CSR (src, weight): SSSP push and pull */
+#define GX_NEED_IN  2u  /* in-CSR (sources ascending) + out-degree: PageRank, PPR */
+#define GX_NEED_SYM 4u  /* symmetric deduplicated adjacency: CC */
+
+/* Per-vertex flags of a partition (one part of a vertex-cut). */
+#define GX_FLAG_MASTER     1u  /* this part holds the master copy */
+#define GX_FLAG_REMOTE_OUT 2u  /* the vertex has an out-edge in another part */
+#define GX_FLAG_REMOTE_ANY 4u  /* the vertex has any edge in another part */
+
+/*
+ * Host description of one worker's graph: out-CSR with rows sorted by
+ * destination.  row_ptr[V+1] (int32, row_ptr[0] = 0, non-decreasing,
+ * row_ptr[V] = E), col[E] (int32 in [0, V)), w[E] (uint32, required when
+ * GX_NEED_OUT is asked; may be NULL otherwise).  l2g[V] maps local to global
+ * ids (ascending; NULL = identity) and flags[V] holds GX_FLAG_* bits (NULL =
+ * unpartitioned: no vertex is remote).  Self-loops are allowed in the input
+ * and ignored by CC; duplicates are allowed.  E < 2^31, V < 2^31.
+ */
+typedef struct gx_graph_desc {
+    int64_t V, E;
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const uint32_t *w;
+    const int32_t *l2g;
+    const uint8_t *flags;
+    uint32_t needs;
+} gx_graph_desc;
+
+/* Sync-set selection (gx_params.delta_mode). */
+#define GX_DELTA_REMOTE 0u  /* only vertices another part needs (lazy uploading) */
+#define GX_DELTA_ALL    1u  /* every changed vertex */
+
+typedef struct gx_params {
+    int32_t  algo;            /* gx_algo: GX_PAGERANK, GX_SSSP or GX_CC */
+    float    damping;         /* PageRank damping d, in [0, 1) */
+    int32_t  source;          /* SSSP source (local id) */
+    uint32_t max_supersteps;  /* cap used by gx_run_until_converged (PageRank: exactly this many) */
+    uint32_t delta_mode;      /* GX_DELTA_REMOTE or GX_DELTA_ALL */
+    uint32_t timing;          /* nonzero: time the edge kernels of every superstep with HIP events */
+    float    pull_fraction;   /* SSSP/CC: a superstep whose active out-edges exceed this fraction of
+                                 all edges pulls over in-edge tiles instead of pushing; 0 = default
+                                 (0.15), >= 1 = always push */
+} gx_params;
+
+/* Statistics of one superstep (counts are exact). */
+typedef struct gx_step_stats {
+    int64_t frontier;      /* |F_k|: active vertices (PageRank: V) */
+    int64_t edges;         /* messages generated: out-edges of F_k (PageRank: E) */
+    int64_t changed;       /* vertices whose value changed (|F_{k+1}| for SSSP/CC) */
+    int64_t pulled;        /* 1 if the superstep ran as a pull over in-edge tiles */
+    double  kernel_ms;     /* with gx_params.timing: HIP-event time of its edge kernels, else 0 */
+} gx_step_stats;
+
+typedef struct gx_run_stats {
+    int64_t supersteps;    /* supersteps executed by this call */
+    int64_t edges;         /* sum of gx_step_stats.edges over them */
+    int64_t converged;     /* 1 if the last superstep changed nothing (SSSP/CC) */
+    double  edge_kernel_ms;   /* with timing: summed HIP-event time of the edge kernel */
+    int64_t edge_kernel_launches;
+    double  wall_ms;       /* host wall time of the call */
+} gx_run_stats;
+
+typedef struct gx_graph gx_graph;
+typedef struct gx_state gx_state;
+
+const char *gx_last_error(void);
+const char *gx_version(void);
+
+/* Device arena bytes gx_graph_load needs for this description. */
+gx_status gx_graph_bytes(const gx_graph_desc *desc, size_t *arena_bytes);
+
+/*
+ * connect() + transfer() (Section "Operation Interfaces"): validates the
+ * host CSR, builds the requested device images inside `dev_arena` and
+ * streams them host-to-device in fixed-size blocks through three rotating
+ * pinned staging buffers on a copy stream (the n/c/u block rotation of
+ * Section "Pipeline Shuffling").  Host packaging of block i+1 overlaps the
+ * copy of block i.  `stream` waits for the copies, so work enqueued on it
+ * afterwards sees the graph.  Synchronous with respect to the host arrays.
+ * Errors: GX_EINVAL (bad CSR, ids out of range), GX_ENOMEM (arena too
+ * small), GX_EDEVICE.
+ */
+gx_status gx_graph_load(const gx_graph_desc *desc, void *dev_arena, size_t arena_bytes,
+                        void *stream, gx_graph **out);
+gx_status gx_graph_free(gx_graph *g);
+gx_status gx_graph_info(const gx_graph *g, int64_t *V, int64_t *E, uint32_t *needs);
+
+/* Device bytes the state of `params` needs on `g`. */
+gx_status gx_state_bytes(const gx_graph *g, const gx_params *params, size_t *bytes);
+
+/*
+ * Initialises a state inside `dev_state`: PageRank x0 = 1/V; SSSP dist =
+ * INF, dist[source] = 0, F1 = {source}; CC label = global id, F1 = vertices
+ * with an edge.  The initial values count as already synchronised.
+ */
+gx_status gx_state_init(gx_graph *g, const gx_params *params, void *dev_state, size_t bytes,
+                        void *stream, gx_state **out);
+gx_status gx_state_free(gx_state *s);
+
+/* Device pointer to the current vertex values (float32 or uint32, V entries). */
+gx_status gx_state_values(gx_state *s, void **dev_values);
+/* Device pointer to the current frontier bitmap (uint32 words, bit v%32 of
+ * word v/32 = vertex v active in the next superstep); SSSP/CC only. */
+gx_status gx_state_frontier(gx_state *s, void **dev_bitmap);
+/* Supersteps executed since init. */
+gx_status gx_state_superstep(gx_state *s, int64_t *k);
+
+/*
+ * requestGen() -> requestMerge() -> requestApply() in BSP order: one
+ * superstep.  SSSP/CC: compact the frontier into an active list with
+ * start-of-superstep snapshots, split the active out-edges into equal
+ * tiles, relax by integer min, set next-frontier and dirty bits.  PageRank:
+ * pull over the in-CSR in equal edge tiles with a fixed summation order.
+ * With stats == NULL the call is asynchronous; otherwise it synchronises
+ * `stream` and fills *stats.
+ */
+gx_status gx_superstep(gx_state *s, void *stream, gx_step_stats *stats);
+
+/*
+ * Iteration control: SSSP/CC run supersteps until one changes nothing or
+ * max_supersteps have run (GX_ENOTCONVERGED, state valid); PageRank runs
+ * exactly max_supersteps.  Synchronises `stream`.  per_step (optional, room
+ * for max_supersteps entries) receives every superstep's statistics.
+ */
+gx_status gx_run_until_converged(gx_state *s, uint32_t max_supersteps, void *stream,
+                                 gx_run_stats *out, gx_step_stats *per_step);
+
+/*
+ * update() with lazy uploading and synchronisation skipping: emits the
+ * (global id, value bits) pairs of vertices that (GX_DELTA_REMOTE) another
+ * part needs -- remote_out for PageRank/SSSP, remote_any for CC -- and whose
+ * value differs from the last emitted one, in ascending global id; only
+ * the final value is sent.  dev_gid/dev_val are device buffers of `cap`
+ * entries.  *count receives the number of pairs, *skippable = (count == 0).
+ * GX_ENOMEM if count > cap (nothing beyond cap is written; the sync
+ * record is left unchanged).  Synchronises `stream`.
+ */
+gx_status gx_sync_delta(gx_state *s, int32_t *dev_gid, uint32_t *dev_val, uint32_t cap,
+                        uint32_t *count, int32_t *skippable, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Batched lanes: B independent single-source SSSP (or personalised
+ * PageRank) solves over one resident graph, run as one persistent kernel
+ * over a [V x B] state tile (B contiguous per vertex).  Generalises the
+ * evaluation's several SSSP sources computed simultaneously (Section
+ * "Setup", first footnote).
+ * --------------------------------------------------------------------- */
+
+typedef struct gx_tune {
+    uint32_t block;   /* threads per workgroup (64..1024, multiple of 64); 0 = default */
+    uint32_t tile;    /* edges per work tile; 0 = default */
+    uint32_t width;   /* lanes per pass (32, 64, 128 or 256, <= B); 0 = default */
+    uint32_t grid;    /* workgroups of the persistent grid; 0 = occupancy bound */
+} gx_tune;
+
+/* Device workspace bytes gx_batch_run needs (excluding the output tile). */
+gx_status gx_batch_bytes(const gx_graph *g, int32_t algo, uint32_t B, size_t *bytes);
+
+/*
+ * Runs B lanes to completion: SSSP lanes until no lane changes (each lane
+ * equals the plain solve from its source), PPR lanes for `iters`
+ * supersteps with seed sources[b].  dev_out: [V x B] uint32 (SSSP) or
+ * float32 (PPR), row-major (lane b of vertex v at v*B + b).  sources: B host
+ * ids.  B: 1..1024 (SSSP: multiple of 32).  tune may be NULL.  Synchronises
+ * `stream`.
+ */
+gx_status gx_batch_run(gx_graph *g, int32_t algo, const int32_t *sources, uint32_t B,
+                       float damping, uint32_t iters, void *dev_work, size_t work_bytes,
+                       void *dev_out, const gx_tune *tune, void *stream, gx_run_stats *out);
+
+/*
+ * Times the candidate launch shapes of gx_batch_run on this graph (each
+ * candidate runs once on `sources`) and writes the fastest to *best.
+ * Every candidate must produce the same result; the call fails with
+ * GX_EDEVICE if one does not.
+ */
+gx_status gx_batch_autotune(gx_graph *g, int32_t algo, const int32_t *sources, uint32_t B,
+                            float damping, uint32_t iters, void *dev_work, size_t work_bytes,
+                            void *dev_out, void *stream, gx_tune *best, double *best_ms);
+
+/* ---------------------------------------------------------------------
+ * Serving: continuous batching of SSSP / PPR queries over resident graphs.
+ * A scheduler thread keeps per-graph lane pools; queries that arrive while
+ * others run are admitted into free lanes at superstep boundaries when the
+ * HBM budget allows, advance together with the running ones, and retire
+ * when converged (SSSP) or after their iterations (PPR).
+ * --------------------------------------------------------------------- */
+
+typedef struct gx_server gx_server;
+
+typedef struct gx_server_config {
+    void    *dev_arena;       /* device memory for lane pools */
+    size_t   arena_bytes;     /* budget: lane pools are admitted only while they fit */
+    uint32_t lanes_per_pool;  /* lanes per pool (multiple of 32, <= 256); 0 = 64 */
+    uint32_t max_pools;       /* concurrently running pools (one stream each); 0 = 4 */
+    uint32_t epoch_supersteps;/* supersteps per pool launch before admitting/retiring; 0 = 4 */
+    float    damping;         /* PPR damping; 0 = 0.85 */
+    uint32_t ppr_iters;       /* PPR supersteps per query; 0 = 50 */
+} gx_server_config;
+
+typedef struct gx_query_result {
+    int64_t  id;
+    int32_t  graph;
+    int32_t  algo;
+    int32_t  source;
+    int32_t  status;          /* GX_OK or an error */
+    double   submit_s, start_s, done_s;  /* host monotonic clock, seconds */
+    int64_t  supersteps;
+} gx_query_result;
+
+gx_status gx_server_bytes_per_lane(const gx_graph *g, int32_t algo, size_t *bytes);
+gx_status gx_server_create(const gx_server_config *cfg, gx_server **out);
+/* Registers a loaded graph (needs GX_NEED_OUT | GX_NEED_IN); returns its id. */
+gx_status gx_server_add_graph(gx_server *s, gx_graph *g, int32_t *graph_id);
+/*
+ * Queues a query.  `result` is a host buffer of V uint32 (SSSP) or float32
+ * (PPR) that receives the answer when the query completes; it must stay
+ * valid until gx_server_poll reports the query.  *id receives the query id.
+ */
+gx_status gx_server_submit(gx_server *s, int32_t graph_id, int32_t algo, int32_t source,
+                           void *result, int64_t *id);
+/* Moves up to `cap` completed queries into `out`; *n receives the count.
+ * With wait_ms > 0 blocks until at least one completes or the time passes. */
+gx_status gx_server_poll(gx_server *s, gx_query_result *out, uint32_t cap, uint32_t *n,
+                         int32_t wait_ms);
+/* Queries queued or running. */
+gx_status gx_server_pending(gx_server *s, int64_t *n);
+gx_status gx_server_destroy(gx_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GX_H */

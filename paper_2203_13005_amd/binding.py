@@ -1,0 +1,428 @@
+"""ctypes marshalling for libgx.so (see include/gx.h for the contract)."""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_PKG, "libgx.so")
+
+GX_OK, GX_EINVAL, GX_ENOMEM, GX_EDEVICE, GX_ENOTCONVERGED, GX_EBUSY, GX_ENOTFOUND = range(7)
+GX_PAGERANK, GX_SSSP, GX_CC, GX_PPR = 0, 1, 2, 3
+GX_NEED_OUT, GX_NEED_IN, GX_NEED_SYM = 1, 2, 4
+GX_DELTA_REMOTE, GX_DELTA_ALL = 0, 1
+INF = 0xFFFFFFFF
+
+_STATUS = {0: "GX_OK", 1: "GX_EINVAL", 2: "GX_ENOMEM", 3: "GX_EDEVICE", 4: "GX_ENOTCONVERGED",
+           5: "GX_EBUSY", 6: "GX_ENOTFOUND"}
+
+
+class GxError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _GraphDesc(ctypes.Structure):
+    _fields_ = [("V", ctypes.c_int64), ("E", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("w", ctypes.c_void_p), ("l2g", ctypes.c_void_p),
+                ("flags", ctypes.c_void_p), ("needs", ctypes.c_uint32)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_int32), ("damping", ctypes.c_float), ("source", ctypes.c_int32),
+                ("max_supersteps", ctypes.c_uint32), ("delta_mode", ctypes.c_uint32),
+                ("timing", ctypes.c_uint32), ("pull_fraction", ctypes.c_float)]
+
+
+class StepStats(ctypes.Structure):
+    _fields_ = [("frontier", ctypes.c_int64), ("edges", ctypes.c_int64), ("changed", ctypes.c_int64),
+                ("pulled", ctypes.c_int64), ("kernel_ms", ctypes.c_double)]
+
+    def as_tuple(self):
+        return (self.frontier, self.edges, self.changed)
+
+    def as_dict(self):
+        return dict(frontier=self.frontier, edges=self.edges, changed=self.changed, pulled=self.pulled,
+                    kernel_ms=self.kernel_ms)
+
+
+class RunStats(ctypes.Structure):
+    _fields_ = [("supersteps", ctypes.c_int64), ("edges", ctypes.c_int64), ("converged", ctypes.c_int64),
+                ("edge_kernel_ms", ctypes.c_double), ("edge_kernel_launches", ctypes.c_int64),
+                ("wall_ms", ctypes.c_double)]
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_uint32), ("tile", ctypes.c_uint32), ("width", ctypes.c_uint32),
+                ("grid", ctypes.c_uint32)]
+
+    def __repr__(self):
+        return f"Tune(block={self.block}, tile={self.tile}, width={self.width}, grid={self.grid})"
+
+
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("dev_arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t),
+                ("lanes_per_pool", ctypes.c_uint32), ("max_pools", ctypes.c_uint32),
+                ("epoch_supersteps", ctypes.c_uint32), ("damping", ctypes.c_float),
+                ("ppr_iters", ctypes.c_uint32)]
+
+
+class QueryResult(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("graph", ctypes.c_int32), ("algo", ctypes.c_int32),
+                ("source", ctypes.c_int32), ("status", ctypes.c_int32), ("submit_s", ctypes.c_double),
+                ("start_s", ctypes.c_double), ("done_s", ctypes.c_double), ("supersteps", ctypes.c_int64)]
+
+
+_P = ctypes.c_void_p
+_SIGS = {
+    "gx_last_error": (ctypes.c_char_p, []),
+    "gx_version": (ctypes.c_char_p, []),
+    "gx_graph_bytes": (ctypes.c_int32, [ctypes.POINTER(_GraphDesc), ctypes.POINTER(ctypes.c_size_t)]),
+    "gx_graph_load": (ctypes.c_int32, [ctypes.POINTER(_GraphDesc), _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
+    "gx_graph_free": (ctypes.c_int32, [_P]),
+    "gx_graph_info": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_uint32)]),
+    "gx_state_bytes": (ctypes.c_int32, [_P, ctypes.POINTER(_Params), ctypes.POINTER(ctypes.c_size_t)]),
+    "gx_state_init": (ctypes.c_int32, [_P, ctypes.POINTER(_Params), _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
+    "gx_state_free": (ctypes.c_int32, [_P]),
+    "gx_state_values": (ctypes.c_int32, [_P, ctypes.POINTER(_P)]),
+    "gx_state_frontier": (ctypes.c_int32, [_P, ctypes.POINTER(_P)]),
+    "gx_state_superstep": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "gx_superstep": (ctypes.c_int32, [_P, _P, ctypes.POINTER(StepStats)]),
+    "gx_run_until_converged": (ctypes.c_int32, [_P, ctypes.c_uint32, _P, ctypes.POINTER(RunStats),
+                                                ctypes.POINTER(StepStats)]),
+    "gx_sync_delta": (ctypes.c_int32, [_P, _P, _P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
+                                       ctypes.POINTER(ctypes.c_int32), _P]),
+    "gx_batch_bytes": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_size_t)]),
+    "gx_batch_run": (ctypes.c_int32, [_P, ctypes.c_int32, _P, ctypes.c_uint32, ctypes.c_float, ctypes.c_uint32,
+                                      _P, ctypes.c_size_t, _P, ctypes.POINTER(Tune), _P,
+                                      ctypes.POINTER(RunStats)]),
+    "gx_batch_autotune": (ctypes.c_int32, [_P, ctypes.c_int32, _P, ctypes.c_uint32, ctypes.c_float,
+                                           ctypes.c_uint32, _P, ctypes.c_size_t, _P, _P, ctypes.POINTER(Tune),
+                                           ctypes.POINTER(ctypes.c_double)]),
+    "gx_server_bytes_per_lane": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "gx_server_create": (ctypes.c_int32, [ctypes.POINTER(_ServerConfig), ctypes.POINTER(_P)]),
+    "gx_server_add_graph": (ctypes.c_int32, [_P, _P, ctypes.POINTER(ctypes.c_int32)]),
+    "gx_server_submit": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
+                                          ctypes.POINTER(ctypes.c_int64)]),
+    "gx_server_poll": (ctypes.c_int32, [_P, ctypes.POINTER(QueryResult), ctypes.c_uint32,
+                                        ctypes.POINTER(ctypes.c_uint32), ctypes.c_int32]),
+    "gx_server_pending": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "gx_server_destroy": (ctypes.c_int32, [_P]),
+}
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950).  There is no CPU fallback.")
+    L = ctypes.CDLL(_LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(L, name, None)
+        if f is None:
+            continue
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+lib = _load()
+
+
+def exported_symbols() -> list[str]:
+    return [n for n in _SIGS if getattr(lib, n, None) is not None]
+
+
+def _check(st: int):
+    if st != GX_OK:
+        raise GxError(st, lib.gx_last_error().decode(errors="replace"))
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _arena(nbytes: int, device):
+    import torch
+    t = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+    if t.data_ptr() % 256:
+        raise GxError(GX_EINVAL, "torch returned a device buffer that is not 256-byte aligned")
+    return t
+
+
+class DeviceGraph:
+    """A worker's graph resident in HBM.  ``host`` is any object with V, E,
+    row_ptr, col, w and optional l2g / flags numpy arrays (out-CSR)."""
+
+    def __init__(self, host, needs: int, device="cuda:0", stream=None):
+        import torch
+        self.device = torch.device(device)
+        self._keep = [np.ascontiguousarray(host.row_ptr, np.int32), np.ascontiguousarray(host.col, np.int32),
+                      None if host.w is None else np.ascontiguousarray(host.w, np.uint32),
+                      None if getattr(host, "l2g", None) is None else np.ascontiguousarray(host.l2g, np.int32),
+                      None if getattr(host, "flags", None) is None else np.ascontiguousarray(host.flags, np.uint8)]
+        rp, col, w, l2g, flags = self._keep
+        self.desc = _GraphDesc(int(host.V), int(host.E), _np_ptr(rp), _np_ptr(col), _np_ptr(w), _np_ptr(l2g),
+                               _np_ptr(flags), int(needs))
+        nbytes = ctypes.c_size_t(0)
+        _check(lib.gx_graph_bytes(ctypes.byref(self.desc), ctypes.byref(nbytes)))
+        self.arena_bytes = nbytes.value
+        with torch.cuda.device(self.device):
+            self.arena = _arena(nbytes.value, self.device)
+            h = ctypes.c_void_p()
+            _check(lib.gx_graph_load(ctypes.byref(self.desc), ctypes.c_void_p(self.arena.data_ptr()), nbytes.value,
+                                     _stream_handle(stream), ctypes.byref(h)))
+        self.handle = h
+        self.V, self.E, self.needs = int(host.V), int(host.E), int(needs)
+        self._keep = None
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.gx_graph_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class State:
+    """Vertex state of one algorithm on a DeviceGraph (caller-owned memory)."""
+
+    def __init__(self, graph: DeviceGraph, algo: int, source: int = 0, damping: float = 0.85,
+                 max_supersteps: int = 1 << 20, delta_mode: int = GX_DELTA_REMOTE, timing: bool = False,
+                 pull_fraction: float = 0.0, stream=None):
+        import torch
+        self.graph = graph
+        self.algo = algo
+        self.params = _Params(int(algo), float(damping), int(source), int(max_supersteps), int(delta_mode),
+                              int(bool(timing)), float(pull_fraction))
+        nbytes = ctypes.c_size_t(0)
+        _check(lib.gx_state_bytes(graph.handle, ctypes.byref(self.params), ctypes.byref(nbytes)))
+        with torch.cuda.device(graph.device):
+            self.mem = _arena(nbytes.value, graph.device)
+            h = ctypes.c_void_p()
+            _check(lib.gx_state_init(graph.handle, ctypes.byref(self.params), ctypes.c_void_p(self.mem.data_ptr()),
+                                     nbytes.value, _stream_handle(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def reset(self, stream=None):
+        """Re-initialises the state in the same device memory (no allocation)."""
+        self.close()
+        h = ctypes.c_void_p()
+        _check(lib.gx_state_init(self.graph.handle, ctypes.byref(self.params), ctypes.c_void_p(self.mem.data_ptr()),
+                                 self.mem.numel(), _stream_handle(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def _view(self, ptr: int, nbytes: int):
+        off = ptr - self.mem.data_ptr()
+        assert 0 <= off and off + nbytes <= self.mem.numel()
+        return self.mem[off: off + nbytes]
+
+    def values(self):
+        """Device view of the current values (float32 for PageRank, int32
+        bit pattern of uint32 otherwise)."""
+        import torch
+        p = ctypes.c_void_p()
+        _check(lib.gx_state_values(self.handle, ctypes.byref(p)))
+        v = self._view(p.value, 4 * self.graph.V)
+        return v.view(torch.float32) if self.algo == GX_PAGERANK else v.view(torch.int32)
+
+    def values_numpy(self) -> np.ndarray:
+        import torch
+        torch.cuda.synchronize(self.graph.device)
+        a = self.values().cpu().numpy()
+        return a if self.algo == GX_PAGERANK else a.view(np.uint32)
+
+    def frontier_numpy(self) -> np.ndarray:
+        """Boolean frontier (vertices active in the next superstep)."""
+        import torch
+        p = ctypes.c_void_p()
+        _check(lib.gx_state_frontier(self.handle, ctypes.byref(p)))
+        W = (self.graph.V + 31) // 32
+        torch.cuda.synchronize(self.graph.device)
+        words = self._view(p.value, 4 * W).view(torch.int32).cpu().numpy().view(np.uint32)
+        bits = np.unpackbits(words.view(np.uint8), bitorder="little")
+        return bits[: self.graph.V].astype(bool)
+
+    @property
+    def superstep_index(self) -> int:
+        k = ctypes.c_int64()
+        _check(lib.gx_state_superstep(self.handle, ctypes.byref(k)))
+        return k.value
+
+    def superstep(self, stats: bool = True, stream=None):
+        st = StepStats()
+        _check(lib.gx_superstep(self.handle, _stream_handle(stream), ctypes.byref(st) if stats else None))
+        return st.as_tuple() if stats else None
+
+    def run(self, max_supersteps: int, stream=None, per_step: bool = False, allow_cap: bool = False,
+            detail: bool = False):
+        rs = RunStats()
+        ps = (StepStats * max(1, max_supersteps))() if per_step else None
+        st = lib.gx_run_until_converged(self.handle, int(max_supersteps), _stream_handle(stream), ctypes.byref(rs),
+                                        ps)
+        if not (st == GX_ENOTCONVERGED and allow_cap):
+            _check(st)
+        steps = None
+        if per_step:
+            steps = [(ps[i].as_dict() if detail else ps[i].as_tuple()) for i in range(rs.supersteps)]
+        return rs, steps
+
+    def sync_delta(self, cap: int | None = None, stream=None):
+        """Returns (gids int32, value bits uint32, skippable) as numpy arrays."""
+        import torch
+        cap = self.graph.V if cap is None else int(cap)
+        gid = torch.empty(max(cap, 1), dtype=torch.int32, device=self.graph.device)
+        val = torch.empty(max(cap, 1), dtype=torch.int32, device=self.graph.device)
+        n = ctypes.c_uint32()
+        sk = ctypes.c_int32()
+        _check(lib.gx_sync_delta(self.handle, ctypes.c_void_p(gid.data_ptr()), ctypes.c_void_p(val.data_ptr()),
+                                 cap, ctypes.byref(n), ctypes.byref(sk), _stream_handle(stream)))
+        c = n.value
+        return gid[:c].cpu().numpy(), val[:c].cpu().numpy().view(np.uint32), bool(sk.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.gx_state_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_run(graph: DeviceGraph, algo: int, sources, damping: float = 0.85, iters: int = 50,
+              tune: Tune | None = None, out=None, stream=None):
+    """B lanes in one persistent launch; returns ([V, B] tensor, RunStats)."""
+    import torch
+    src = np.ascontiguousarray(sources, np.int32)
+    B = len(src)
+    nbytes = ctypes.c_size_t(0)
+    _check(lib.gx_batch_bytes(graph.handle, int(algo), B, ctypes.byref(nbytes)))
+    with torch.cuda.device(graph.device):
+        work = _arena(nbytes.value, graph.device)
+        if out is None:
+            out = torch.empty((graph.V, B), dtype=torch.float32 if algo == GX_PPR else torch.int32,
+                              device=graph.device)
+        rs = RunStats()
+        _check(lib.gx_batch_run(graph.handle, int(algo), _np_ptr(src), B, float(damping), int(iters),
+                                ctypes.c_void_p(work.data_ptr()), nbytes.value, ctypes.c_void_p(out.data_ptr()),
+                                ctypes.byref(tune) if tune is not None else None, _stream_handle(stream),
+                                ctypes.byref(rs)))
+    return out, rs
+
+
+def batch_autotune(graph: DeviceGraph, algo: int, sources, damping: float = 0.85, iters: int = 50, stream=None):
+    import torch
+    src = np.ascontiguousarray(sources, np.int32)
+    B = len(src)
+    nbytes = ctypes.c_size_t(0)
+    _check(lib.gx_batch_bytes(graph.handle, int(algo), B, ctypes.byref(nbytes)))
+    with torch.cuda.device(graph.device):
+        work = _arena(nbytes.value, graph.device)
+        out = torch.empty((graph.V, B), dtype=torch.float32 if algo == GX_PPR else torch.int32, device=graph.device)
+        best = Tune()
+        ms = ctypes.c_double()
+        _check(lib.gx_batch_autotune(graph.handle, int(algo), _np_ptr(src), B, float(damping), int(iters),
+                                     ctypes.c_void_p(work.data_ptr()), nbytes.value,
+                                     ctypes.c_void_p(out.data_ptr()), _stream_handle(stream), ctypes.byref(best),
+                                     ctypes.byref(ms)))
+    return best, ms.value
+
+
+@dataclass
+class Completed:
+    id: int
+    graph: int
+    algo: int
+    source: int
+    status: int
+    submit_s: float
+    start_s: float
+    done_s: float
+    supersteps: int
+    result: np.ndarray
+
+    @property
+    def latency_s(self) -> float:
+        return self.done_s - self.submit_s
+
+
+class Server:
+    """Continuous-batching query server over resident graphs."""
+
+    def __init__(self, arena_bytes: int, lanes_per_pool: int = 64, max_pools: int = 4, epoch_supersteps: int = 4,
+                 damping: float = 0.85, ppr_iters: int = 50, device="cuda:0"):
+        import torch
+        self.device = torch.device(device)
+        with torch.cuda.device(self.device):
+            self.arena = _arena(arena_bytes, self.device)
+        cfg = _ServerConfig(ctypes.c_void_p(self.arena.data_ptr()), int(arena_bytes), int(lanes_per_pool),
+                            int(max_pools), int(epoch_supersteps), float(damping), int(ppr_iters))
+        h = ctypes.c_void_p()
+        _check(lib.gx_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+        self.graphs: list[DeviceGraph] = []
+        self._buffers: dict[int, np.ndarray] = {}
+
+    def add_graph(self, g: DeviceGraph) -> int:
+        gid = ctypes.c_int32()
+        _check(lib.gx_server_add_graph(self.handle, g.handle, ctypes.byref(gid)))
+        self.graphs.append(g)
+        return gid.value
+
+    def submit(self, graph_id: int, algo: int, source: int) -> int:
+        V = self.graphs[graph_id].V
+        buf = np.empty(V, np.float32 if algo == GX_PPR else np.uint32)
+        qid = ctypes.c_int64()
+        _check(lib.gx_server_submit(self.handle, int(graph_id), int(algo), int(source), _np_ptr(buf),
+                                    ctypes.byref(qid)))
+        self._buffers[qid.value] = buf
+        return qid.value
+
+    def poll(self, cap: int = 256, wait_ms: int = 0) -> list[Completed]:
+        arr = (QueryResult * cap)()
+        n = ctypes.c_uint32()
+        _check(lib.gx_server_poll(self.handle, arr, cap, ctypes.byref(n), int(wait_ms)))
+        out = []
+        for i in range(n.value):
+            r = arr[i]
+            out.append(Completed(r.id, r.graph, r.algo, r.source, r.status, r.submit_s, r.start_s, r.done_s,
+                                 r.supersteps, self._buffers.pop(r.id)))
+        return out
+
+    def pending(self) -> int:
+        n = ctypes.c_int64()
+        _check(lib.gx_server_pending(self.handle, ctypes.byref(n)))
+        return n.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.gx_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,388 @@
+// Graph ingestion: host validation, host packaging of the device images, and
+// block-streamed host-to-device transfer through three rotating pinned
+// buffers (the n/c/u block rotation of Section "Pipeline Shuffling": while
+// block i is in flight on the copy stream, block i+1 is packaged into the
+// next buffer; pointers rotate instead of data being copied between stages).
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <functional>
+#include <thread>
+
+#include "gx_internal.h"
+
+namespace gx {
+
+static thread_local std::string g_err;
+
+void set_error(const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+void clear_error() { g_err.clear(); }
+
+int device_cus(int device) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n <= 0) n = 256;
+    return n;
+}
+
+template <class F>
+static void parallel_for(int64_t n, F f) {
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (n < 65536 || nt == 1) {
+        f(0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; t++) {
+        int64_t lo = n * t / nt, hi = n * (t + 1) / nt;
+        th.emplace_back([=] { f(lo, hi); });
+    }
+    for (auto &x : th) x.join();
+}
+
+// Host images built from the description before upload.
+struct HostImages {
+    std::vector<int32_t> in_rp, in_col, outdeg, tile_row;
+    std::vector<uint32_t> in_w;
+    std::vector<int32_t> sym_rp, sym_col, sym_tile_row;
+    std::vector<uint32_t> rem_out, rem_any;
+};
+
+static gx_status validate(const gx_graph_desc *d) {
+    GX_REQUIRE(d, GX_EINVAL, "desc is NULL");
+    GX_REQUIRE(d->V >= 0 && d->V < (int64_t(1) << 31) - 64, GX_EINVAL, "V=%lld out of range", (long long)d->V);
+    GX_REQUIRE(d->E >= 0 && d->E < (int64_t(1) << 31) - PR_TILE, GX_EINVAL, "E=%lld out of range", (long long)d->E);
+    GX_REQUIRE(d->needs != 0 && (d->needs & ~7u) == 0, GX_EINVAL, "needs=%u invalid", d->needs);
+    GX_REQUIRE(d->row_ptr || d->V == 0, GX_EINVAL, "row_ptr is NULL");
+    GX_REQUIRE(d->col || d->E == 0, GX_EINVAL, "col is NULL");
+    GX_REQUIRE(!(d->needs & GX_NEED_OUT) || d->w || d->E == 0, GX_EINVAL, "weights required for GX_NEED_OUT");
+    if (d->V == 0) {
+        GX_REQUIRE(d->E == 0, GX_EINVAL, "E > 0 with V == 0");
+        return GX_OK;
+    }
+    GX_REQUIRE(d->row_ptr[0] == 0, GX_EINVAL, "row_ptr[0] != 0");
+    GX_REQUIRE(d->row_ptr[d->V] == d->E, GX_EINVAL, "row_ptr[V]=%d != E=%lld", d->row_ptr[d->V], (long long)d->E);
+    for (int64_t v = 0; v < d->V; v++)
+        GX_REQUIRE(d->row_ptr[v + 1] >= d->row_ptr[v], GX_EINVAL, "row_ptr decreases at %lld", (long long)v);
+    bool bad = false;
+    int64_t badpos = -1;
+    for (int64_t e = 0; e < d->E; e++)
+        if ((uint32_t)d->col[e] >= (uint32_t)d->V) {
+            bad = true;
+            badpos = e;
+            break;
+        }
+    GX_REQUIRE(!bad, GX_EINVAL, "col[%lld]=%d out of [0,V)", (long long)badpos, bad ? d->col[badpos] : 0);
+    if (d->l2g) {
+        GX_REQUIRE(d->l2g[0] >= 0, GX_EINVAL, "l2g[0] negative");
+        for (int64_t v = 1; v < d->V; v++)
+            GX_REQUIRE(d->l2g[v] > d->l2g[v - 1], GX_EINVAL, "l2g not strictly ascending at %lld", (long long)v);
+    }
+    return GX_OK;
+}
+
+// Stable counting sort of the edges by destination: in-rows list their
+// sources in ascending order.
+static void build_in_csr(const gx_graph_desc *d, HostImages &h) {
+    int64_t V = d->V, E = d->E;
+    h.in_rp.assign(V + 1, 0);
+    h.in_col.resize(E);
+    for (int64_t e = 0; e < E; e++) h.in_rp[d->col[e] + 1]++;
+    for (int64_t v = 0; v < V; v++) h.in_rp[v + 1] += h.in_rp[v];
+    std::vector<int32_t> pos(h.in_rp.begin(), h.in_rp.end() - 1);
+    bool wts = d->w && (d->needs & GX_NEED_OUT);
+    if (wts) h.in_w.resize(E);
+    for (int64_t u = 0; u < V; u++)
+        for (int32_t e = d->row_ptr[u]; e < d->row_ptr[u + 1]; e++) {
+            int32_t p = pos[d->col[e]]++;
+            h.in_col[p] = (int32_t)u;
+            if (wts) h.in_w[p] = d->w[e];
+        }
+}
+
+// Pull tiles: tile t covers edges [t*T, (t+1)*T) of a CSR and owns the rows
+// whose first edge position falls in that range (the last tile also owns the
+// rows starting at E).
+static int64_t ntiles_for(int64_t E) { return std::max<int64_t>(1, (E + PR_TILE - 1) / PR_TILE); }
+
+static void build_tiles(const std::vector<int32_t> &rp, std::vector<int32_t> &tile_row) {
+    int64_t V = (int64_t)rp.size() - 1, E = rp.back();
+    int64_t nt = ntiles_for(E);
+    tile_row.resize(nt + 1);
+    for (int64_t t = 0; t < nt; t++)
+        tile_row[t] = (int32_t)(std::lower_bound(rp.begin(), rp.end() - 1, (int32_t)(t * PR_TILE)) - rp.begin());
+    tile_row[0] = 0;
+    tile_row[nt] = (int32_t)V;
+}
+
+// Symmetric adjacency: sorted union of out- and in-neighbours, self
+// excluded, duplicates removed (needs the in-CSR).
+static void build_sym(const gx_graph_desc *d, HostImages &h) {
+    int64_t V = d->V;
+    const int32_t *orp = d->row_ptr, *oc = d->col;
+    const int32_t *irp = h.in_rp.data(), *ic = h.in_col.data();
+    auto merge_row = [&](int64_t u, int32_t *out) -> int32_t {
+        int32_t a = orp[u], ae = orp[u + 1], b = irp[u], be = irp[u + 1], n = 0, last = -1;
+        while (a < ae || b < be) {
+            int32_t x;
+            if (b >= be || (a < ae && oc[a] <= ic[b])) x = oc[a++];
+            else x = ic[b++];
+            if (x == (int32_t)u || x == last) continue;
+            if (out) out[n] = x;
+            n++;
+            last = x;
+        }
+        return n;
+    };
+    h.sym_rp.assign(V + 1, 0);
+    parallel_for(V, [&](int64_t lo, int64_t hi) {
+        for (int64_t u = lo; u < hi; u++) h.sym_rp[u + 1] = merge_row(u, nullptr);
+    });
+    for (int64_t v = 0; v < V; v++) h.sym_rp[v + 1] += h.sym_rp[v];
+    h.sym_col.resize(h.sym_rp[V]);
+    parallel_for(V, [&](int64_t lo, int64_t hi) {
+        for (int64_t u = lo; u < hi; u++) merge_row(u, h.sym_col.data() + h.sym_rp[u]);
+    });
+}
+
+static void build_flags(const gx_graph_desc *d, int32_t W, HostImages &h) {
+    h.rem_out.assign(W, 0);
+    h.rem_any.assign(W, 0);
+    if (!d->flags) return;
+    for (int64_t v = 0; v < d->V; v++) {
+        uint32_t bit = 1u << (v & 31);
+        if (d->flags[v] & GX_FLAG_REMOTE_OUT) h.rem_out[v >> 5] |= bit;
+        if (d->flags[v] & GX_FLAG_REMOTE_ANY) h.rem_any[v >> 5] |= bit;
+    }
+}
+
+// Device layout; with a measuring Carver it only sizes the arena.  E_sym
+// must be known for the symmetric image (computed by the caller).
+static void layout(const gx_graph_desc *desc, int64_t E_sym, Carver &c, DevGraph *d) {
+    int64_t V = desc->V, E = desc->E;
+    d->V = V;
+    d->E = E;
+    d->E_sym = E_sym;
+    d->W = (int32_t)((V + 31) / 32);
+    if (desc->needs & GX_NEED_OUT) {
+        d->out_rp = c.take<int32_t>(V + 1);
+        d->out_adj = c.take<uint2>(E);
+    }
+    if (desc->needs & (GX_NEED_IN | GX_NEED_OUT)) {
+        d->in_rp = c.take<int32_t>(V + 1);
+        d->pr_ntiles = (int32_t)ntiles_for(E);
+        d->pr_tile_row = c.take<int32_t>(d->pr_ntiles + 1);
+    }
+    if (desc->needs & GX_NEED_IN) {
+        d->in_col = c.take<int32_t>(E);
+        d->outdeg = c.take<int32_t>(V);
+    }
+    if (desc->needs & GX_NEED_OUT) d->in_adj = c.take<uint2>(E);
+    if (desc->needs & GX_NEED_SYM) {
+        d->sym_rp = c.take<int32_t>(V + 1);
+        d->sym_col = c.take<int32_t>(E_sym);
+        d->sym_ntiles = (int32_t)ntiles_for(E_sym);
+        d->sym_tile_row = c.take<int32_t>(d->sym_ntiles + 1);
+    }
+    if (desc->l2g) d->l2g = c.take<int32_t>(V);
+    if (desc->flags) {
+        d->remote_out = c.take<uint32_t>(d->W);
+        d->remote_any = c.take<uint32_t>(d->W);
+    }
+}
+
+// Upper bound of the symmetric image without building it: every directed
+// edge contributes at most two neighbour entries.
+static int64_t sym_bound(const gx_graph_desc *d) { return 2 * d->E; }
+
+// Streams byte ranges produced by `fill` to device memory in fixed blocks
+// through three rotating pinned buffers on a dedicated copy stream.
+struct Uploader {
+    static constexpr size_t BLOCK = size_t(16) << 20;
+    hipStream_t copy = nullptr;
+    void *buf[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    uint64_t idx = 0;
+    hipError_t err = hipSuccess;
+
+    hipError_t open() {
+        if ((err = hipStreamCreateWithFlags(&copy, hipStreamNonBlocking)) != hipSuccess) return err;
+        for (int i = 0; i < 3; i++) {
+            if ((err = hipHostMalloc(&buf[i], BLOCK, hipHostMallocDefault)) != hipSuccess) return err;
+            if ((err = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming)) != hipSuccess) return err;
+        }
+        return hipSuccess;
+    }
+    hipError_t put(void *dev, size_t bytes, const std::function<void(char *, size_t, size_t)> &fill) {
+        for (size_t off = 0; off < bytes && err == hipSuccess; off += BLOCK) {
+            size_t n = std::min(BLOCK, bytes - off);
+            int b = (int)(idx++ % 3);
+            if ((err = hipEventSynchronize(ev[b])) != hipSuccess) break;  // buffer b free again
+            fill(static_cast<char *>(buf[b]), off, n);                     // package block (host)
+            if ((err = hipMemcpyAsync(static_cast<char *>(dev) + off, buf[b], n, hipMemcpyHostToDevice, copy)) !=
+                hipSuccess)
+                break;
+            err = hipEventRecord(ev[b], copy);
+        }
+        return err;
+    }
+    hipError_t put_array(void *dev, const void *host, size_t bytes) {
+        return put(dev, bytes, [host](char *dst, size_t off, size_t n) {
+            std::memcpy(dst, static_cast<const char *>(host) + off, n);
+        });
+    }
+    hipError_t finish(hipStream_t user) {
+        hipEvent_t done = nullptr;
+        if (err == hipSuccess) err = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+        if (err == hipSuccess) err = hipEventRecord(done, copy);
+        if (err == hipSuccess) err = hipStreamWaitEvent(user, done, 0);
+        if (err == hipSuccess) err = hipStreamSynchronize(copy);
+        if (done) (void)hipEventDestroy(done);
+        return err;
+    }
+    ~Uploader() {
+        if (copy) (void)hipStreamSynchronize(copy);
+        for (int i = 0; i < 3; i++) {
+            if (ev[i]) (void)hipEventDestroy(ev[i]);
+            if (buf[i]) (void)hipHostFree(buf[i]);
+        }
+        if (copy) (void)hipStreamDestroy(copy);
+    }
+};
+
+}  // namespace gx
+
+using namespace gx;
+
+extern "C" const char *gx_last_error(void) { return g_err.c_str(); }
+extern "C" const char *gx_version(void) { return "gx 0.1 (gfx950)"; }
+
+extern "C" gx_status gx_graph_bytes(const gx_graph_desc *desc, size_t *arena_bytes) {
+    clear_error();
+    GX_REQUIRE(arena_bytes, GX_EINVAL, "arena_bytes is NULL");
+    gx_status st = validate(desc);
+    if (st != GX_OK) return st;
+    Carver c(nullptr, 0);
+    DevGraph d;
+    layout(desc, sym_bound(desc), c, &d);
+    *arena_bytes = c.used;
+    return GX_OK;
+}
+
+extern "C" gx_status gx_graph_load(const gx_graph_desc *desc, void *dev_arena, size_t arena_bytes, void *stream,
+                                   gx_graph **out) {
+    clear_error();
+    GX_REQUIRE(out, GX_EINVAL, "out is NULL");
+    *out = nullptr;
+    gx_status st = validate(desc);
+    if (st != GX_OK) return st;
+    GX_REQUIRE(dev_arena || arena_bytes == 0, GX_EINVAL, "dev_arena is NULL");
+    GX_REQUIRE(reinterpret_cast<uintptr_t>(dev_arena) % ALIGN == 0, GX_EINVAL, "dev_arena not 256-byte aligned");
+    {
+        Carver m(nullptr, 0);
+        DevGraph tmp;
+        layout(desc, sym_bound(desc), m, &tmp);
+        GX_REQUIRE(m.used <= arena_bytes, GX_ENOMEM, "arena too small: need %zu bytes, have %zu", m.used, arena_bytes);
+    }
+
+    HostImages h;
+    int32_t W = (int32_t)((desc->V + 31) / 32);
+    try {
+        build_in_csr(desc, h);
+        build_tiles(h.in_rp, h.tile_row);
+        if (desc->needs & GX_NEED_SYM) {
+            build_sym(desc, h);
+            build_tiles(h.sym_rp, h.sym_tile_row);
+        }
+        build_flags(desc, W, h);
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed while packaging the graph");
+        return GX_ENOMEM;
+    }
+
+    gx_graph *g = new (std::nothrow) gx_graph();
+    GX_REQUIRE(g, GX_ENOMEM, "host allocation failed");
+    Carver c(dev_arena, arena_bytes);
+    layout(desc, (int64_t)h.sym_col.size(), c, &g->d);
+    g->needs = desc->needs;
+    g->arena = dev_arena;
+    g->arena_bytes = arena_bytes;
+    if (hipGetDevice(&g->device) != hipSuccess) g->device = 0;
+    g->num_cus = device_cus(g->device);
+    g->host_outdeg.resize(desc->V);
+    for (int64_t v = 0; v < desc->V; v++) g->host_outdeg[v] = desc->row_ptr[v + 1] - desc->row_ptr[v];
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Uploader up;
+    hipError_t e = up.open();
+    const DevGraph &d = g->d;
+    int64_t V = desc->V, E = desc->E;
+    if (e == hipSuccess && d.out_rp) e = up.put_array((void *)d.out_rp, desc->row_ptr, (V + 1) * 4);
+    if (e == hipSuccess && d.out_adj) {
+        const int32_t *col = desc->col;
+        const uint32_t *w = desc->w;
+        // Package (destination, weight) pairs block by block.
+        e = up.put((void *)d.out_adj, E * sizeof(uint2), [col, w](char *dst, size_t off, size_t n) {
+            uint2 *o = reinterpret_cast<uint2 *>(dst);
+            size_t e0 = off / sizeof(uint2), cnt = n / sizeof(uint2);
+            for (size_t i = 0; i < cnt; i++) o[i] = make_uint2((uint32_t)col[e0 + i], w[e0 + i]);
+        });
+    }
+    if (e == hipSuccess && d.in_rp) {
+        e = up.put_array((void *)d.in_rp, h.in_rp.data(), (V + 1) * 4);
+        if (e == hipSuccess) e = up.put_array((void *)d.pr_tile_row, h.tile_row.data(), h.tile_row.size() * 4);
+    }
+    if (e == hipSuccess && d.in_col) {
+        e = up.put_array((void *)d.in_col, h.in_col.data(), E * 4);
+        if (e == hipSuccess) e = up.put_array((void *)d.outdeg, g->host_outdeg.data(), V * 4);
+    }
+    if (e == hipSuccess && d.in_adj) {
+        const int32_t *ic = h.in_col.data();
+        const uint32_t *iw = h.in_w.data();
+        e = up.put((void *)d.in_adj, E * sizeof(uint2), [ic, iw](char *dst, size_t off, size_t n) {
+            uint2 *o = reinterpret_cast<uint2 *>(dst);
+            size_t e0 = off / sizeof(uint2), cnt = n / sizeof(uint2);
+            for (size_t i = 0; i < cnt; i++) o[i] = make_uint2((uint32_t)ic[e0 + i], iw[e0 + i]);
+        });
+    }
+    if (e == hipSuccess && d.sym_rp) {
+        e = up.put_array((void *)d.sym_rp, h.sym_rp.data(), (V + 1) * 4);
+        if (e == hipSuccess) e = up.put_array((void *)d.sym_col, h.sym_col.data(), h.sym_col.size() * 4);
+        if (e == hipSuccess)
+            e = up.put_array((void *)d.sym_tile_row, h.sym_tile_row.data(), h.sym_tile_row.size() * 4);
+    }
+    if (e == hipSuccess && d.l2g) e = up.put_array((void *)d.l2g, desc->l2g, V * 4);
+    if (e == hipSuccess && d.remote_out) {
+        e = up.put_array((void *)d.remote_out, h.rem_out.data(), (size_t)W * 4);
+        if (e == hipSuccess) e = up.put_array((void *)d.remote_any, h.rem_any.data(), (size_t)W * 4);
+    }
+    if (e == hipSuccess) e = up.finish(s);
+    if (e != hipSuccess) {
+        set_error("graph upload failed: %s", hipGetErrorString(e));
+        delete g;
+        return GX_EDEVICE;
+    }
+    *out = g;
+    return GX_OK;
+}
+
+extern "C" gx_status gx_graph_free(gx_graph *g) {
+    clear_error();
+    delete g;
+    return GX_OK;
+}
+
+extern "C" gx_status gx_graph_info(const gx_graph *g, int64_t *V, int64_t *E, uint32_t *needs) {
+    clear_error();
+    GX_REQUIRE(g, GX_EINVAL, "graph is NULL");
+    if (V) *V = g->d.V;
+    if (E) *E = g->d.E;
+    if (needs) *needs = g->needs;
+    return GX_OK;
+}

@@ -1,0 +1,123 @@
+// Internal declarations of the gx engine (host + device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gx.h"
+
+namespace gx {
+
+constexpr uint32_t INF = 0xFFFFFFFFu;
+constexpr size_t ALIGN = 256;
+
+// ---------------------------------------------------------------- errors
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define GX_CHECK_HIP(expr, handle)                                                       \
+    do {                                                                                 \
+        hipError_t _e = (expr);                                                          \
+        if (_e != hipSuccess) {                                                          \
+            ::gx::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e),        \
+                            __FILE__, __LINE__);                                         \
+            if (handle) (handle)->dev_error = true;                                      \
+            return GX_EDEVICE;                                                           \
+        }                                                                                \
+    } while (0)
+
+#define GX_REQUIRE(cond, code, ...)        \
+    do {                                   \
+        if (!(cond)) {                     \
+            ::gx::set_error(__VA_ARGS__);  \
+            return (code);                 \
+        }                                  \
+    } while (0)
+
+inline size_t align_up(size_t x, size_t a = ALIGN) { return (x + a - 1) / a * a; }
+
+// Bump allocator over a caller-owned device arena.
+struct Carver {
+    char *base;
+    size_t cap, used = 0;
+    bool measure_only;
+    Carver(void *b, size_t c) : base(static_cast<char *>(b)), cap(c), measure_only(b == nullptr) {}
+    template <class T>
+    T *take(size_t count) {
+        size_t off = used;
+        used = align_up(used + count * sizeof(T) + (count == 0 ? 1 : 0));
+        return measure_only ? nullptr : reinterpret_cast<T *>(base + off);
+    }
+    bool fits() const { return used <= cap; }
+};
+
+// ---------------------------------------------------------------- graph
+// Edge tile of the PageRank pull (in-edges per workgroup tile).
+constexpr int PR_BLOCK = 256;
+constexpr int PR_VT = 8;
+constexpr int PR_TILE = PR_BLOCK * PR_VT;
+
+struct DevGraph {
+    int64_t V = 0, E = 0, E_sym = 0;
+    int32_t W = 0;                 // bitmap words: ceil(V / 32)
+    // out-CSR (SSSP push): row_ptr + interleaved (dst, weight)
+    const int32_t *out_rp = nullptr;
+    const uint2 *out_adj = nullptr;
+    // in-CSR: sources only (PageRank pull) and interleaved (source, weight)
+    // (SSSP pull); out-degree; equal in-edge tiles shared by both pulls
+    const int32_t *in_rp = nullptr;
+    const int32_t *in_col = nullptr;
+    const uint2 *in_adj = nullptr;
+    const int32_t *outdeg = nullptr;
+    int32_t pr_ntiles = 0;
+    const int32_t *pr_tile_row = nullptr;  // [pr_ntiles + 1]
+    // symmetric adjacency (CC push and pull) and its equal edge tiles
+    const int32_t *sym_rp = nullptr;
+    const int32_t *sym_col = nullptr;
+    int32_t sym_ntiles = 0;
+    const int32_t *sym_tile_row = nullptr;
+    // partition metadata
+    const int32_t *l2g = nullptr;          // nullptr = identity
+    const uint32_t *remote_out = nullptr;  // bitmaps of W words (nullptr = none remote)
+    const uint32_t *remote_any = nullptr;
+};
+
+}  // namespace gx
+
+struct gx_graph {
+    gx::DevGraph d;
+    uint32_t needs = 0;
+    void *arena = nullptr;
+    size_t arena_bytes = 0;
+    int device = 0;
+    int num_cus = 0;
+    bool dev_error = false;
+    std::vector<int32_t> host_outdeg;  // out-degree (host copy, for sources and stats)
+};
+
+namespace gx {
+
+// Host-side build + upload of the device images (gx_graph.hip).
+gx_status graph_layout(const gx_graph_desc *desc, Carver &c, DevGraph *d);
+
+// Per-superstep statistics slot kept in device memory.
+struct DevStep {
+    unsigned long long list;      // (entries << 32) | edges, via one 64-bit add per workgroup
+    unsigned long long frontier;  // |F_k|
+    unsigned long long changed;   // |F_{k+1}| (or PageRank changed values)
+    unsigned long long pad;
+};
+constexpr int STEP_RING = 4096;
+
+// Tiles of the push relaxation (active out-edges per workgroup tile).
+constexpr int PUSH_BLOCK = 256;
+constexpr int PUSH_VT = 8;
+constexpr int PUSH_TILE = PUSH_BLOCK * PUSH_VT;
+
+int device_cus(int device);
+
+}  // namespace gx

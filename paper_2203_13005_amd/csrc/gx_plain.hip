@@ -1,0 +1,1039 @@
+// One worker's superstep engine: PageRank (pull), Bellman-Ford SSSP and
+// min-label CC (frontier push), the lazy-upload sync set, and iteration
+// control.
+//
+// A superstep is the algorithm template MSGGen -> MSGMerge -> MSGApply of
+// Section "Algorithm Template", in BSP order.  Messages of one superstep
+// are generated from the state at its start (no dependency between the
+// edge triplets of one iteration, Section "Pipeline Shuffling"), so the
+// frontier compaction stores a snapshot of every active vertex's value.
+//
+// SSSP / CC superstep k:
+//   k_compact : frontier bitmap F_k -> active list of (edge offset, CSR base,
+//               snapshot) for active vertices with out-edges; one 64-bit
+//               atomic per workgroup reserves list slots and edge offsets;
+//               every PUSH_TILE-edge tile records the entry where it starts.
+//               This replaces the paper's synchronisation skipping by a
+//               frontier (Section "Synchronization Skipping") and its
+//               fixed-size edge blocks (Section "Data Flows & Management")
+//               by equal edge tiles over the active out-edges (the balanced
+//               objective of Section "Workload Balancing").
+//   k_push    : every workgroup tile relaxes exactly PUSH_TILE active
+//               out-edges: Gen = snapshot (+ weight), Merge + Apply =
+//               integer atomicMin on the destination; an improvement sets
+//               the next-frontier bit and the dirty bit.
+// PageRank superstep:
+//   k_pr_pull : equal in-edge tiles; contributions are gathered into LDS and
+//               summed per destination row in a fixed order; rows that
+//               cross a tile boundary leave fixed partials.
+//   k_pr_fix  : one workgroup completes the crossing rows in tile order and
+//               reduces the dangling mass for the next superstep in a fixed
+//               order.  No floating-point atomics: results are bitwise
+//               reproducible.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "gx_device.h"
+#include "gx_internal.h"
+
+using namespace gx;
+
+struct gx_state {
+    gx_graph *g = nullptr;
+    gx_params p{};
+    int64_t k = 0;
+    bool dev_error = false;
+    int push_grid = 0;
+    // SSSP / CC
+    uint32_t *val = nullptr;
+    uint32_t *front[2] = {nullptr, nullptr};
+    uint32_t *dirty = nullptr;
+    uint4 *list = nullptr;
+    uint32_t *tile_start = nullptr;
+    uint32_t *snap = nullptr;      // start-of-superstep values of active vertices (pull)
+    uint32_t pull_edges = 0xFFFFFFFFu;
+    int pull_grid = 0;
+    // PageRank
+    float *x[2] = {nullptr, nullptr};
+    float *contrib[2] = {nullptr, nullptr};
+    uint32_t *synced = nullptr;
+    double *head = nullptr, *tailp = nullptr;
+    int32_t *spill_row = nullptr;
+    double *dpart = nullptr;
+    double *Dval = nullptr;
+    // shared
+    DevStep *steps = nullptr;
+    uint32_t *blk_cnt = nullptr;
+    uint32_t *delta_total = nullptr;
+    int delta_blocks = 0;
+    // edge-kernel timing
+    std::vector<hipEvent_t> ev_pool;
+    struct Pending {
+        int64_t k;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> ev_pending;
+    double kernel_ms = 0;
+    int64_t kernel_launches = 0;
+    ~gx_state() {
+        for (auto e : ev_pool) (void)hipEventDestroy(e);
+        for (auto &pr : ev_pending) {
+            (void)hipEventDestroy(pr.a);
+            (void)hipEventDestroy(pr.b);
+        }
+    }
+};
+
+namespace {
+
+// ------------------------------------------------------------ SSSP / CC
+
+__global__ __launch_bounds__(256) void k_min_init(uint32_t *val, uint32_t *f0, uint32_t *f1, uint32_t *dirty,
+                                                  const int32_t *l2g, const int32_t *rp, int64_t V, int32_t W,
+                                                  int32_t algo, int32_t source, DevStep *step0) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *step0 = DevStep{0, 0, 0, 0};
+    if (i < W) {
+        uint32_t word = 0;
+        if (algo == GX_CC) {
+            for (int b = 0; b < 32; b++) {
+                int64_t v = i * 32 + b;
+                if (v < V && rp[v + 1] > rp[v]) word |= 1u << b;
+            }
+        } else if (source >= 0 && (source >> 5) == i) {
+            word = 1u << (source & 31);
+        }
+        f0[i] = word;
+        f1[i] = 0;
+        dirty[i] = 0;
+    }
+    if (i < V) {
+        uint32_t x;
+        if (algo == GX_CC) x = l2g ? (uint32_t)l2g[i] : (uint32_t)i;
+        else x = (i == source) ? 0u : INF;
+        val[i] = x;
+    }
+}
+
+// Frontier bitmap -> active list, one thread per vertex (256 vertices = 8
+// bitmap words per workgroup; a workgroup whose words are all zero leaves at
+// once).  Active vertices with out-edges get a list entry (edge offset, CSR
+// base, snapshot) in one 64-bit atomic per workgroup; the tiles that start
+// inside an entry's edges record it.  The workgroup also clears its words of
+// the bitmap this superstep's relaxation fills (it held F_{k-1}) and stores
+// the snapshot of its active vertices for the pull.
+__global__ __launch_bounds__(256) void k_compact(const uint32_t *__restrict__ front, uint32_t *__restrict__ front_clear,
+                                                 const int32_t *__restrict__ rp, const uint32_t *__restrict__ val,
+                                                 uint32_t *__restrict__ snap, int64_t V, int32_t W,
+                                                 uint4 *__restrict__ list, uint32_t *__restrict__ tile_start,
+                                                 DevStep *__restrict__ step, DevStep *__restrict__ next_step) {
+    __shared__ unsigned long long s_scan[4];
+    __shared__ unsigned long long s_base;
+    __shared__ uint32_t s_words[8];
+    __shared__ int s_nf[4];
+    const int tid = threadIdx.x;
+    const int32_t w0 = blockIdx.x * 8;
+    if (blockIdx.x == 0 && tid == 0) *next_step = DevStep{0, 0, 0, 0};
+    if (tid < 8) {
+        const int32_t wi = w0 + tid;
+        uint32_t word = 0u;
+        if (wi < W) {
+            word = front[wi];
+            front_clear[wi] = 0u;
+        }
+        s_words[tid] = word;
+    }
+    __syncthreads();
+    const uint32_t any = s_words[0] | s_words[1] | s_words[2] | s_words[3] | s_words[4] | s_words[5] | s_words[6] |
+                         s_words[7];
+    if (!any) return;  // uniform: every thread read the same words
+    const int64_t u = (int64_t)w0 * 32 + tid;
+    const bool act = u < V && ((s_words[tid >> 5] >> (tid & 31)) & 1u);
+    int32_t r0 = 0, d = 0;
+    if (act) {
+        r0 = rp[u];
+        d = rp[u + 1] - r0;
+    }
+    const bool has = act && d > 0;
+    unsigned long long mine = has ? ((1ull << 32) | (uint32_t)d) : 0ull, total;
+    unsigned long long pre = block_excl_scan_u64(mine, &total, s_scan);
+    int nf = act ? 1 : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) nf += __shfl_down(nf, o, 64);
+    if ((tid & 63) == 0) s_nf[tid >> 6] = nf;
+    if (tid == 0) s_base = total ? atomicAdd(&step->list, total) : 0ull;
+    __syncthreads();
+    if (tid == 0) {
+        const int t = s_nf[0] + s_nf[1] + s_nf[2] + s_nf[3];
+        if (t) atomicAdd(&step->frontier, (unsigned long long)t);
+    }
+    if (!has) return;
+    const unsigned long long pos = s_base + pre;
+    const uint32_t idx = (uint32_t)(pos >> 32), off = (uint32_t)pos;
+    const uint32_t x = val[u];
+    snap[u] = x;
+    list[idx] = make_uint4(off, (uint32_t)(r0 - (int32_t)off), x, (uint32_t)u);
+    const uint32_t t0 = (off + PUSH_TILE - 1) / PUSH_TILE, t1 = (off + (uint32_t)d - 1) / PUSH_TILE;
+    for (uint32_t t = t0; t <= t1; t++) tile_start[t] = idx;
+}
+
+// Relaxes the active out-edges, PUSH_TILE per workgroup tile (persistent
+// grid; the tile count comes from the compaction's counter).
+template <bool WEIGHTED>
+__global__ __launch_bounds__(PUSH_BLOCK) void k_push(const uint4 *__restrict__ list,
+                                                     const uint32_t *__restrict__ tile_start,
+                                                     const void *__restrict__ adj, uint32_t *__restrict__ val,
+                                                     uint32_t *__restrict__ front_next, uint32_t *__restrict__ dirty,
+                                                     DevStep *__restrict__ step, uint32_t pull_edges) {
+    __shared__ uint32_t s_base[PUSH_TILE + 1];
+    __shared__ uint32_t s_snap[PUSH_TILE + 1];
+    __shared__ int32_t s_own[PUSH_TILE];
+    __shared__ int32_t s_red[4];
+    __shared__ unsigned long long s_cnt[4];
+    const int tid = threadIdx.x;
+    const unsigned long long le = step->list;
+    const uint32_t L = (uint32_t)(le >> 32), EF = (uint32_t)le;
+    if (EF >= pull_edges) return;  // this superstep pulls
+    const uint32_t ntiles = (EF + PUSH_TILE - 1) / PUSH_TILE;
+    unsigned long long changed = 0;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint32_t e0 = t * PUSH_TILE;
+        const int n = (int)min((uint32_t)PUSH_TILE, EF - e0);
+        const uint32_t s0 = tile_start[t];
+        const uint32_t s1 = (t + 1 < ntiles) ? tile_start[t + 1] : L - 1;
+        const int m = (int)(s1 - s0) + 1;
+        for (int p = tid; p < n; p += PUSH_BLOCK) s_own[p] = 0;
+        __syncthreads();
+        for (int i = tid; i < m; i += PUSH_BLOCK) {
+            uint4 en = list[s0 + i];
+            s_base[i] = en.y + e0;  // CSR index of the tile's edge p is s_base[j] + p
+            s_snap[i] = en.z;
+            uint32_t rel = en.x - e0;
+            if (i > 0 && rel < (uint32_t)n) s_own[rel] = i;
+        }
+        __syncthreads();
+        block_max_scan<PUSH_VT>(s_own, n, s_red);
+        for (int p = tid; p < n; p += PUSH_BLOCK) {
+            const int j = s_own[p];
+            const uint32_t idx = s_base[j] + (uint32_t)p;
+            uint32_t dst, cand;
+            if (WEIGHTED) {
+                uint2 a = static_cast<const uint2 *>(adj)[idx];
+                dst = a.x;
+                cand = sat_add(s_snap[j], a.y);
+            } else {
+                dst = (uint32_t) static_cast<const int32_t *>(adj)[idx];
+                cand = s_snap[j];
+            }
+            if (cand < val[dst]) {
+                uint32_t old = atomicMin(&val[dst], cand);
+                if (cand < old) {
+                    const uint32_t bit = 1u << (dst & 31);
+                    uint32_t prev = atomicOr(&front_next[dst >> 5], bit);
+                    if (!(prev & bit)) {
+                        changed++;
+                        atomicOr(&dirty[dst >> 5], bit);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    unsigned long long tot = block_sum<unsigned long long>(changed, s_cnt);
+    if (tid == 0 && tot) atomicAdd(&step->changed, tot);
+}
+
+// Marks v as changed in this superstep: next-frontier bit and dirty bit;
+// counts it once.
+__device__ __forceinline__ void mark_changed(uint32_t v, uint32_t *front_next, uint32_t *dirty,
+                                             unsigned long long &changed) {
+    const uint32_t bit = 1u << (v & 31);
+    uint32_t prev = atomicOr(&front_next[v >> 5], bit);
+    if (!(prev & bit)) {
+        changed++;
+        atomicOr(&dirty[v >> 5], bit);
+    }
+}
+
+// Pull form of the same superstep, for large frontiers: equal tiles over the
+// in-edges (static, built at load).  Every in-edge whose source is active
+// carries the source's snapshot (+ weight); the merge is a min per
+// destination row computed in LDS (each thread sums a contiguous chunk, rows
+// spanning threads are combined by walking back over the threads' trailing
+// pieces).  A row inside one tile is written by one thread with a plain
+// store; only rows that cross a tile boundary (the high-degree tail) use
+// atomicMin.  Runs only when the frontier's out-edges reach pull_edges.
+template <bool WEIGHTED>
+__global__ __launch_bounds__(PR_BLOCK) void k_pull(const int32_t *__restrict__ rp, const void *__restrict__ adj,
+                                                   const int32_t *__restrict__ tile_row, int32_t ntiles, int64_t E,
+                                                   const uint32_t *__restrict__ front_cur,
+                                                   const uint32_t *__restrict__ snap, uint32_t *__restrict__ val,
+                                                   uint32_t *__restrict__ front_next, uint32_t *__restrict__ dirty,
+                                                   DevStep *__restrict__ step, uint32_t pull_edges) {
+    __shared__ uint32_t s_val[PR_TILE];
+    __shared__ int32_t s_own[PR_TILE];
+    __shared__ uint32_t s_last[PR_BLOCK];
+    __shared__ int32_t s_last_start[PR_BLOCK];
+    __shared__ int32_t s_red[4];
+    __shared__ unsigned long long s_c[4];
+    const uint32_t EF = (uint32_t)step->list;
+    if (EF < pull_edges) return;
+    const int tid = threadIdx.x;
+    if (blockIdx.x == 0 && tid == 0) step->pad = 1;
+    unsigned long long changed = 0;
+    for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t e0 = (int64_t)t * PR_TILE;
+        const int n = (int)max((int64_t)0, min((int64_t)PR_TILE, E - e0));
+        const int32_t r_lo = tile_row[t], r_hi = tile_row[t + 1];
+        for (int p = tid; p < n; p += PR_BLOCK) {
+            uint32_t u, w = 0, m = INF;
+            if (WEIGHTED) {
+                uint2 a = static_cast<const uint2 *>(adj)[e0 + p];
+                u = a.x;
+                w = a.y;
+            } else {
+                u = (uint32_t) static_cast<const int32_t *>(adj)[e0 + p];
+            }
+            if ((front_cur[u >> 5] >> (u & 31)) & 1u) m = WEIGHTED ? sat_add(snap[u], w) : snap[u];
+            s_val[p] = m;
+            s_own[p] = 0;
+        }
+        __syncthreads();
+        for (int32_t r = r_lo + tid; r < r_hi; r += PR_BLOCK) {
+            int32_t a = rp[r], b = rp[r + 1];
+            if (b > a) s_own[a - e0] = r - r_lo + 1;
+        }
+        __syncthreads();
+        block_max_scan<PR_VT>(s_own, n, s_red);
+
+        auto finish = [&](int o, uint32_t m, bool ends_tile) {
+            if (m == INF) return;
+            const int32_t r = o == 0 ? r_lo - 1 : r_lo + o - 1;  // owner 0: row begun in an earlier tile
+            const bool crossing = (o == 0) || (ends_tile && rp[r + 1] > e0 + n);
+            uint32_t old;
+            if (crossing) {
+                old = atomicMin(&val[r], m);
+            } else {
+                old = val[r];
+                if (m < old) val[r] = m;
+            }
+            if (m < old) mark_changed((uint32_t)r, front_next, dirty, changed);
+        };
+        const int c0 = tid * PR_VT, c1 = min(c0 + PR_VT, n);
+        int own = -1, first_own = -1;
+        bool started = false, first = true, defer = false, defer_end = false;
+        uint32_t mn = INF, first_mn = INF;
+        for (int p = c0; p < c1; p++) {
+            int o = s_own[p];
+            if (o != own) {
+                if (own >= 0) {
+                    if (first && !started) {
+                        defer = true;
+                        first_mn = mn;
+                        first_own = own;
+                    } else {
+                        finish(own, mn, false);
+                    }
+                    first = false;
+                }
+                own = o;
+                mn = INF;
+                started = (p == 0) ? (o != 0) : (p > c0 || s_own[p - 1] != o);
+            }
+            mn = min(mn, s_val[p]);
+        }
+        bool last_ends_here = false;
+        if (own >= 0) {
+            last_ends_here = (c1 == n) || (s_own[c1] != own);
+            if (last_ends_here) {
+                if (first && !started) {
+                    defer = true;
+                    defer_end = (c1 == n);
+                    first_mn = mn;
+                    first_own = own;
+                } else {
+                    finish(own, mn, c1 == n);
+                }
+            }
+        }
+        s_last[tid] = (own >= 0 && !last_ends_here) ? mn : INF;
+        s_last_start[tid] = started ? 1 : 0;
+        __syncthreads();
+        if (defer) {
+            uint32_t tot = first_mn;
+            for (int j = tid - 1; j >= 0; j--) {
+                tot = min(tot, s_last[j]);
+                if (s_last_start[j]) break;
+            }
+            finish(first_own, tot, defer_end);
+        }
+        __syncthreads();
+    }
+    unsigned long long tot = block_sum<unsigned long long>(changed, s_c);
+    if (tid == 0 && tot) atomicAdd(&step->changed, tot);
+}
+
+// ------------------------------------------------------------ PageRank
+
+__global__ __launch_bounds__(256) void k_pr_init(float *x, float *contrib, uint32_t *synced,
+                                                 const int32_t *__restrict__ outdeg, int64_t V, float x0,
+                                                 double *dpart, DevStep *step0) {
+    __shared__ double s_d[4];
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v == 0) *step0 = DevStep{0, 0, 0, 0};
+    double dl = 0.0;
+    if (v < V) {
+        int od = outdeg[v];
+        x[v] = x0;
+        synced[v] = __float_as_uint(x0);
+        contrib[v] = od > 0 ? x0 / (float)od : 0.0f;
+        if (od == 0) dl = (double)x0;
+    }
+    double t = block_sum<double>(dl, s_d);
+    if (threadIdx.x == 0) dpart[blockIdx.x] = t;
+}
+
+// Single workgroup: D = sum of n partials in a fixed order.
+__global__ __launch_bounds__(1024) void k_reduce_D(const double *__restrict__ part, int n, double *D) {
+    __shared__ double s_d[16];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) a += part[i];
+    double t = block_sum<double>(a, s_d);
+    if (threadIdx.x == 0) *D = t;
+}
+
+struct PrApply {
+    double base, d, dD;  // x' = base + d * acc + dD, with dD = d * D / V
+    const int32_t *outdeg;
+    const float *x_in;
+    float *x_out, *c_out;
+    __device__ __forceinline__ void operator()(int32_t r, double acc, double &dsum, int &chg) const {
+        float xn = (float)(base + d * acc + dD);
+        x_out[r] = xn;
+        int od = outdeg[r];
+        c_out[r] = od > 0 ? xn / (float)od : 0.0f;
+        if (od == 0) dsum += (double)xn;
+        chg += __float_as_uint(xn) != __float_as_uint(x_in[r]);
+    }
+};
+
+__global__ __launch_bounds__(PR_BLOCK) void k_pr_pull(const int32_t *__restrict__ in_rp,
+                                                      const int32_t *__restrict__ in_col,
+                                                      const int32_t *__restrict__ tile_row, int64_t E,
+                                                      const float *__restrict__ c_in, PrApply ap,
+                                                      const double *__restrict__ Dp, double inv_V,
+                                                      double *__restrict__ head, double *__restrict__ tailp,
+                                                      int32_t *__restrict__ spill_row, double *__restrict__ dpart,
+                                                      DevStep *__restrict__ step) {
+    __shared__ float s_val[PR_TILE];
+    __shared__ int32_t s_own[PR_TILE];
+    __shared__ double s_last[PR_BLOCK];
+    __shared__ int32_t s_last_start[PR_BLOCK];
+    __shared__ int32_t s_red[4];
+    __shared__ double s_d[4];
+    __shared__ unsigned long long s_c[4];
+    const int tid = threadIdx.x;
+    const int32_t t = blockIdx.x;
+    const int64_t e0 = (int64_t)t * PR_TILE;
+    const int n = (int)max((int64_t)0, min((int64_t)PR_TILE, E - e0));
+    const int32_t r_lo = tile_row[t], r_hi = tile_row[t + 1];
+    ap.dD = ap.d * (*Dp) * inv_V;
+    if (tid == 0) spill_row[t] = -1;
+    for (int p = tid; p < n; p += PR_BLOCK) {
+        s_val[p] = c_in[in_col[e0 + p]];
+        s_own[p] = 0;
+    }
+    __syncthreads();
+    for (int32_t r = r_lo + tid; r < r_hi; r += PR_BLOCK) {
+        int32_t a = in_rp[r], b = in_rp[r + 1];
+        if (b > a) s_own[a - e0] = r - r_lo + 1;
+    }
+    __syncthreads();
+    block_max_scan<PR_VT>(s_own, n, s_red);
+
+    // Per-thread contiguous chunk: sequential sums per destination row.
+    double dsum = 0.0;
+    int chg = 0;
+    const int c0 = tid * PR_VT, c1 = min(c0 + PR_VT, n);
+    int own = -1;
+    bool started = false, first = true;
+    double sum = 0.0, first_sum = 0.0;
+    int first_own = -1;
+    bool defer_first = false, defer_ends_tile = false;
+    auto finish = [&](int o, double total, bool ends_tile) {
+        if (o == 0) {
+            head[t] = total;  // row continued from an earlier tile
+            return;
+        }
+        int32_t r = r_lo + o - 1;
+        if (ends_tile && in_rp[r + 1] > e0 + n) {
+            tailp[t] = total;  // row continues into later tiles
+            spill_row[t] = r;
+            return;
+        }
+        ap(r, total, dsum, chg);
+    };
+    for (int p = c0; p < c1; p++) {
+        int o = s_own[p];
+        if (o != own) {
+            if (own >= 0) {  // run `own` ended at p-1 inside this chunk
+                if (first && !started) {
+                    defer_first = true;
+                    first_sum = sum;
+                    first_own = own;
+                } else {
+                    finish(own, sum, false);
+                }
+                first = false;
+            }
+            own = o;
+            sum = 0.0;
+            started = (p == 0) ? (o != 0) : (p > c0 || s_own[p - 1] != o);
+        }
+        sum += (double)s_val[p];
+    }
+    bool last_ends_here = false;
+    if (own >= 0) {
+        last_ends_here = (c1 == n) || (s_own[c1] != own);
+        if (last_ends_here) {
+            if (first && !started) {
+                defer_first = true;
+                defer_ends_tile = (c1 == n);
+                first_sum = sum;
+                first_own = own;
+            } else {
+                finish(own, sum, c1 == n);
+            }
+        }
+    }
+    s_last[tid] = (own >= 0 && !last_ends_here) ? sum : 0.0;
+    s_last_start[tid] = started ? 1 : 0;
+    __syncthreads();
+    if (defer_first) {  // walk back over the threads holding earlier pieces of this row
+        double total = first_sum;
+        for (int j = tid - 1; j >= 0; j--) {
+            total += s_last[j];
+            if (s_last_start[j]) break;
+        }
+        finish(first_own, total, defer_ends_tile);
+    }
+    // Rows of this tile without in-edges.
+    for (int32_t r = r_lo + tid; r < r_hi; r += PR_BLOCK)
+        if (in_rp[r + 1] == in_rp[r]) ap(r, 0.0, dsum, chg);
+    double td = block_sum<double>(dsum, s_d);
+    unsigned long long tc = block_sum<unsigned long long>((unsigned long long)chg, s_c);
+    if (tid == 0) {
+        dpart[t] = td;
+        if (tc) atomicAdd(&step->changed, tc);
+    }
+}
+
+// Completes the rows that cross tile boundaries (in tile order) and reduces
+// the dangling mass of the new ranks for the next superstep.  One block.
+__global__ __launch_bounds__(1024) void k_pr_fix(const int32_t *__restrict__ in_rp, int32_t ntiles,
+                                                 const double *__restrict__ head, const double *__restrict__ tailp,
+                                                 const int32_t *__restrict__ spill_row,
+                                                 const double *__restrict__ dpart, PrApply ap, double *Dp,
+                                                 double inv_V, DevStep *__restrict__ step,
+                                                 DevStep *__restrict__ next_step) {
+    __shared__ double s_d[16];
+    __shared__ unsigned long long s_c[16];
+    ap.dD = ap.d * (*Dp) * inv_V;
+    double dsum = 0.0;
+    int chg = 0;
+    for (int32_t t = threadIdx.x; t < ntiles; t += blockDim.x) {
+        int32_t r = spill_row[t];
+        if (r >= 0) {
+            double total = tailp[t];
+            int32_t t_end = (in_rp[r + 1] - 1) / PR_TILE;
+            for (int32_t t2 = t + 1; t2 <= t_end; t2++) total += head[t2];
+            ap(r, total, dsum, chg);
+        }
+        dsum += dpart[t];
+    }
+    __syncthreads();
+    double td = block_sum<double>(dsum, s_d);
+    unsigned long long tc = block_sum<unsigned long long>((unsigned long long)chg, s_c);
+    if (threadIdx.x == 0) {
+        *Dp = td;  // dangling mass of x_{t+1}
+        if (tc) atomicAdd(&step->changed, tc);
+        step->frontier = 0;
+        *next_step = DevStep{0, 0, 0, 0};
+    }
+}
+
+// ------------------------------------------------------------ sync set
+
+__device__ __forceinline__ uint32_t delta_word(int32_t w, int64_t V, const uint32_t *remote, bool all,
+                                               const uint32_t *dirty, const uint32_t *vals,
+                                               const uint32_t *synced) {
+    uint32_t valid = (int64_t)(w + 1) * 32 <= V ? 0xFFFFFFFFu : ((1u << (V - (int64_t)w * 32)) - 1u);
+    uint32_t mask = (all ? 0xFFFFFFFFu : (remote ? remote[w] : 0u)) & valid;
+    if (!mask) return 0;
+    if (dirty) return dirty[w] & mask;
+    uint32_t out = 0;
+    for (uint32_t m = mask; m; m &= m - 1) {
+        int b = __ffs(m) - 1;
+        int64_t v = (int64_t)w * 32 + b;
+        if (vals[v] != synced[v]) out |= 1u << b;
+    }
+    return out;
+}
+
+__global__ __launch_bounds__(256) void k_delta_count(int32_t W, int64_t V, const uint32_t *remote, int all,
+                                                     const uint32_t *dirty, const uint32_t *vals,
+                                                     const uint32_t *synced, uint32_t *blk_cnt) {
+    __shared__ unsigned long long s[4];
+    int32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t c = w < W ? __popc(delta_word(w, V, remote, all, dirty, vals, synced)) : 0u;
+    unsigned long long t = block_sum<unsigned long long>(c, s);
+    if (threadIdx.x == 0) blk_cnt[blockIdx.x] = (uint32_t)t;
+}
+
+__global__ __launch_bounds__(256) void k_delta_emit(int32_t W, int64_t V, const uint32_t *remote, int all,
+                                                    uint32_t *dirty, const uint32_t *vals, uint32_t *synced,
+                                                    const int32_t *l2g, const uint32_t *__restrict__ blk_cnt,
+                                                    int nblk, uint32_t cap, int32_t *gid_out, uint32_t *val_out,
+                                                    uint32_t *total_out) {
+    __shared__ unsigned long long s_scan[4];
+    __shared__ unsigned long long s_pre[4], s_all[4];
+    const int tid = threadIdx.x;
+    unsigned long long pre = 0, all_ = 0;
+    for (int b = tid; b < nblk; b += blockDim.x) {
+        unsigned long long c = blk_cnt[b];
+        all_ += c;
+        if (b < (int)blockIdx.x) pre += c;
+    }
+    // block sums of pre / all (same tree for every block: identical totals)
+    {
+        const int lane = tid & 63, wid = tid >> 6;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            pre += __shfl_down(pre, o, 64);
+            all_ += __shfl_down(all_, o, 64);
+        }
+        if (lane == 0) {
+            s_pre[wid] = pre;
+            s_all[wid] = all_;
+        }
+        __syncthreads();
+        pre = s_pre[0] + s_pre[1] + s_pre[2] + s_pre[3];
+        all_ = s_all[0] + s_all[1] + s_all[2] + s_all[3];
+        __syncthreads();
+    }
+    if (blockIdx.x == 0 && tid == 0) *total_out = (uint32_t)all_;
+    const bool commit = all_ <= cap;
+    int32_t w = blockIdx.x * blockDim.x + tid;
+    uint32_t bits = w < W ? delta_word(w, V, remote, all, dirty, vals, synced) : 0u;
+    unsigned long long tot;
+    unsigned long long pos = pre + block_excl_scan_u64(__popc(bits), &tot, s_scan);
+    for (uint32_t m = bits; m; m &= m - 1) {
+        int64_t v = (int64_t)w * 32 + __ffs(m) - 1;
+        if (pos < cap) {
+            gid_out[pos] = l2g ? l2g[v] : (int32_t)v;
+            val_out[pos] = vals[v];
+        }
+        pos++;
+        if (commit && synced) synced[v] = vals[v];
+    }
+    if (commit && dirty && w < W) dirty[w] = 0u;
+}
+
+template <class T>
+inline unsigned grid_for(T n, unsigned block) {
+    return (unsigned)std::max<T>(1, (n + block - 1) / block);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host
+
+template <class K>
+static int persistent_grid(gx_graph *g, K kernel, int block) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu <= 0)
+        per_cu = 2;
+    return g->num_cus * per_cu;
+}
+
+static size_t state_layout(gx_graph *g, const gx_params *p, Carver &c, gx_state *s) {
+    const DevGraph &d = g->d;
+    int64_t V = d.V;
+    int32_t W = d.W;
+    if (p->algo == GX_PAGERANK) {
+        int32_t nt = d.pr_ntiles;
+        s->x[0] = c.take<float>(V);
+        s->x[1] = c.take<float>(V);
+        s->contrib[0] = c.take<float>(V);
+        s->contrib[1] = c.take<float>(V);
+        s->synced = c.take<uint32_t>(V);
+        s->head = c.take<double>(nt);
+        s->tailp = c.take<double>(nt);
+        s->spill_row = c.take<int32_t>(nt);
+        s->dpart = c.take<double>(std::max<int64_t>(nt, grid_for<int64_t>(V, 256)));
+        s->Dval = c.take<double>(1);
+    } else {
+        int64_t Eimg = p->algo == GX_SSSP ? d.E : d.E_sym;
+        s->val = c.take<uint32_t>(V);
+        s->front[0] = c.take<uint32_t>(W);
+        s->front[1] = c.take<uint32_t>(W);
+        s->dirty = c.take<uint32_t>(W);
+        s->list = c.take<uint4>(V);
+        s->tile_start = c.take<uint32_t>(Eimg / PUSH_TILE + 2);
+        s->snap = c.take<uint32_t>(V);
+    }
+    s->steps = c.take<DevStep>(STEP_RING);
+    s->delta_blocks = (int)grid_for<int64_t>(W, 256);
+    s->blk_cnt = c.take<uint32_t>(s->delta_blocks);
+    s->delta_total = c.take<uint32_t>(1);
+    return c.used;
+}
+
+static gx_status check_params(const gx_graph *g, const gx_params *p) {
+    GX_REQUIRE(g, GX_EINVAL, "graph is NULL");
+    GX_REQUIRE(p, GX_EINVAL, "params is NULL");
+    GX_REQUIRE(!g->dev_error, GX_EDEVICE, "graph handle has a sticky device error");
+    GX_REQUIRE(p->algo == GX_PAGERANK || p->algo == GX_SSSP || p->algo == GX_CC, GX_EINVAL,
+               "algo %d not supported by the plain engine", p->algo);
+    GX_REQUIRE(p->delta_mode <= GX_DELTA_ALL, GX_EINVAL, "delta_mode %u invalid", p->delta_mode);
+    if (p->algo == GX_PAGERANK) {
+        GX_REQUIRE(g->needs & GX_NEED_IN, GX_EINVAL, "PageRank needs GX_NEED_IN");
+        GX_REQUIRE(p->damping >= 0.f && p->damping < 1.f, GX_EINVAL, "damping %f out of [0,1)", p->damping);
+    }
+    if (p->algo == GX_SSSP) {
+        GX_REQUIRE(g->needs & GX_NEED_OUT, GX_EINVAL, "SSSP needs GX_NEED_OUT");
+        GX_REQUIRE(p->source >= 0 && p->source < g->d.V, GX_EINVAL, "source %d out of [0,V)", p->source);
+    }
+    if (p->algo == GX_CC) GX_REQUIRE(g->needs & GX_NEED_SYM, GX_EINVAL, "CC needs GX_NEED_SYM");
+    return GX_OK;
+}
+
+extern "C" gx_status gx_state_bytes(const gx_graph *g, const gx_params *p, size_t *bytes) {
+    clear_error();
+    GX_REQUIRE(bytes, GX_EINVAL, "bytes is NULL");
+    gx_status st = check_params(g, p);
+    if (st != GX_OK) return st;
+    Carver c(nullptr, 0);
+    gx_state tmp;
+    *bytes = state_layout(const_cast<gx_graph *>(g), p, c, &tmp);
+    return GX_OK;
+}
+
+extern "C" gx_status gx_state_init(gx_graph *g, const gx_params *p, void *dev_state, size_t bytes, void *stream,
+                                   gx_state **out) {
+    clear_error();
+    GX_REQUIRE(out, GX_EINVAL, "out is NULL");
+    *out = nullptr;
+    gx_status st = check_params(g, p);
+    if (st != GX_OK) return st;
+    GX_REQUIRE(dev_state, GX_EINVAL, "dev_state is NULL");
+    GX_REQUIRE(reinterpret_cast<uintptr_t>(dev_state) % ALIGN == 0, GX_EINVAL, "dev_state not 256-byte aligned");
+    {
+        Carver m(nullptr, 0);
+        gx_state tmp;
+        size_t need = state_layout(g, p, m, &tmp);
+        GX_REQUIRE(need <= bytes, GX_ENOMEM, "state buffer too small: need %zu bytes, have %zu", need, bytes);
+    }
+    gx_state *s = new (std::nothrow) gx_state();
+    GX_REQUIRE(s, GX_ENOMEM, "host allocation failed");
+    s->g = g;
+    s->p = *p;
+    Carver c(dev_state, bytes);
+    state_layout(g, p, c, s);
+    s->push_grid = persistent_grid(g, k_push<true>, PUSH_BLOCK);
+    s->pull_grid = persistent_grid(g, k_pull<true>, PR_BLOCK);
+    if (p->algo != GX_PAGERANK) {
+        const DevGraph &dg = g->d;
+        bool can_pull = p->algo == GX_SSSP ? (dg.in_adj != nullptr) : (dg.sym_tile_row != nullptr);
+        double frac = p->pull_fraction > 0.f ? (double)p->pull_fraction : 0.15;
+        double Eimg = (double)(p->algo == GX_SSSP ? dg.E : dg.E_sym);
+        s->pull_edges = (!can_pull || frac >= 1.0) ? 0xFFFFFFFFu : (uint32_t)std::max(1.0, std::ceil(frac * Eimg));
+    }
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const DevGraph &d = g->d;
+    int64_t V = d.V;
+    if (p->algo == GX_PAGERANK) {
+        float x0 = V > 0 ? (float)(1.0 / (double)V) : 0.f;
+        unsigned nb = grid_for<int64_t>(V, 256);
+        hipLaunchKernelGGL(k_pr_init, dim3(nb), dim3(256), 0, hs, s->x[0], s->contrib[0], s->synced, d.outdeg, V, x0,
+                           s->dpart, s->steps);
+        hipLaunchKernelGGL(k_reduce_D, dim3(1), dim3(1024), 0, hs, s->dpart, (int)nb, s->Dval);
+    } else {
+        int64_t n = std::max<int64_t>(V, d.W);
+        const int32_t *rp = p->algo == GX_CC ? d.sym_rp : d.out_rp;
+        hipLaunchKernelGGL(k_min_init, dim3(grid_for<int64_t>(n, 256)), dim3(256), 0, hs, s->val, s->front[0],
+                           s->front[1], s->dirty, d.l2g, rp, V, d.W, p->algo, p->source, s->steps);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error("state init launch failed: %s", hipGetErrorString(e));
+        delete s;
+        return GX_EDEVICE;
+    }
+    *out = s;
+    return GX_OK;
+}
+
+extern "C" gx_status gx_state_free(gx_state *s) {
+    clear_error();
+    delete s;
+    return GX_OK;
+}
+
+extern "C" gx_status gx_state_values(gx_state *s, void **dev_values) {
+    clear_error();
+    GX_REQUIRE(s && dev_values, GX_EINVAL, "NULL argument");
+    *dev_values = s->p.algo == GX_PAGERANK ? (void *)s->x[s->k & 1] : (void *)s->val;
+    return GX_OK;
+}
+
+extern "C" gx_status gx_state_frontier(gx_state *s, void **dev_bitmap) {
+    clear_error();
+    GX_REQUIRE(s && dev_bitmap, GX_EINVAL, "NULL argument");
+    GX_REQUIRE(s->p.algo != GX_PAGERANK, GX_EINVAL, "PageRank has no frontier");
+    *dev_bitmap = s->front[s->k & 1];
+    return GX_OK;
+}
+
+extern "C" gx_status gx_state_superstep(gx_state *s, int64_t *k) {
+    clear_error();
+    GX_REQUIRE(s && k, GX_EINVAL, "NULL argument");
+    *k = s->k;
+    return GX_OK;
+}
+
+static hipEvent_t pool_event(gx_state *s) {
+    if (!s->ev_pool.empty()) {
+        hipEvent_t e = s->ev_pool.back();
+        s->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Enqueues superstep s->k on `hs` and advances s->k.
+static gx_status enqueue_superstep(gx_state *s, hipStream_t hs) {
+    const DevGraph &d = s->g->d;
+    const gx_params &p = s->p;
+    DevStep *step = s->steps + (s->k % STEP_RING);
+    DevStep *next = s->steps + ((s->k + 1) % STEP_RING);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (p.timing) {
+        e0 = pool_event(s);
+        e1 = pool_event(s);
+    }
+    if (p.algo == GX_PAGERANK) {
+        int cur = (int)(s->k & 1);
+        double dd = p.damping;
+        PrApply ap{(1.0 - dd) / (double)d.V, dd, 0.0, d.outdeg, s->x[cur], s->x[cur ^ 1], s->contrib[cur ^ 1]};
+        double inv_V = d.V > 0 ? 1.0 / (double)d.V : 0.0;
+        if (d.V > 0) {
+            if (e0) (void)hipEventRecord(e0, hs);
+            hipLaunchKernelGGL(k_pr_pull, dim3(d.pr_ntiles), dim3(PR_BLOCK), 0, hs, d.in_rp, d.in_col, d.pr_tile_row,
+                               d.E, s->contrib[cur], ap, s->Dval, inv_V, s->head, s->tailp, s->spill_row, s->dpart,
+                               step);
+            if (e1) (void)hipEventRecord(e1, hs);
+            hipLaunchKernelGGL(k_pr_fix, dim3(1), dim3(1024), 0, hs, d.in_rp, d.pr_ntiles, s->head, s->tailp,
+                               s->spill_row, s->dpart, ap, s->Dval, inv_V, step, next);
+        }
+    } else {
+        int cur = (int)(s->k & 1);
+        const bool cc = p.algo == GX_CC;
+        const int32_t *rp = cc ? d.sym_rp : d.out_rp;
+        if (d.W > 0) {
+            hipLaunchKernelGGL(k_compact, dim3(grid_for<int32_t>(d.W, 8)), dim3(256), 0, hs, s->front[cur],
+                               s->front[cur ^ 1], rp, s->val, s->snap, d.V, d.W, s->list, s->tile_start, step, next);
+            if (e0) (void)hipEventRecord(e0, hs);
+            if (!cc) {
+                hipLaunchKernelGGL(k_push<true>, dim3(s->push_grid), dim3(PUSH_BLOCK), 0, hs, s->list, s->tile_start,
+                                   (const void *)d.out_adj, s->val, s->front[cur ^ 1], s->dirty, step, s->pull_edges);
+                if (s->pull_edges != 0xFFFFFFFFu)
+                    hipLaunchKernelGGL(k_pull<true>, dim3(s->pull_grid), dim3(PR_BLOCK), 0, hs, d.in_rp,
+                                       (const void *)d.in_adj, d.pr_tile_row, d.pr_ntiles, d.E, s->front[cur],
+                                       s->snap, s->val, s->front[cur ^ 1], s->dirty, step, s->pull_edges);
+            } else {
+                hipLaunchKernelGGL(k_push<false>, dim3(s->push_grid), dim3(PUSH_BLOCK), 0, hs, s->list,
+                                   s->tile_start, (const void *)d.sym_col, s->val, s->front[cur ^ 1], s->dirty, step,
+                                   s->pull_edges);
+                if (s->pull_edges != 0xFFFFFFFFu)
+                    hipLaunchKernelGGL(k_pull<false>, dim3(s->pull_grid), dim3(PR_BLOCK), 0, hs, d.sym_rp,
+                                       (const void *)d.sym_col, d.sym_tile_row, d.sym_ntiles, d.E_sym, s->front[cur],
+                                       s->snap, s->val, s->front[cur ^ 1], s->dirty, step, s->pull_edges);
+            }
+            if (e1) (void)hipEventRecord(e1, hs);
+        }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error("superstep launch failed: %s", hipGetErrorString(e));
+        s->dev_error = true;
+        return GX_EDEVICE;
+    }
+    if (e0 && e1) s->ev_pending.push_back({s->k, e0, e1});
+    s->k++;
+    return GX_OK;
+}
+
+// After a stream synchronisation: fold the pending kernel timings; with
+// `per_step`, superstep k's time goes to per_step[k - k0] when in range.
+static void collect_timings(gx_state *s, gx_step_stats *per_step = nullptr, int64_t k0 = 0, int64_t n = 0) {
+    for (auto &pr : s->ev_pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, pr.a, pr.b) == hipSuccess) {
+            s->kernel_ms += ms;
+            s->kernel_launches++;
+            if (per_step && pr.k >= k0 && pr.k < k0 + n) per_step[pr.k - k0].kernel_ms = ms;
+        }
+        s->ev_pool.push_back(pr.a);
+        s->ev_pool.push_back(pr.b);
+    }
+    s->ev_pending.clear();
+}
+
+static void to_stats(const gx_state *s, const DevStep &ds, gx_step_stats *o) {
+    if (s->p.algo == GX_PAGERANK) {
+        o->frontier = s->g->d.V;
+        o->edges = s->g->d.E;
+        o->pulled = 1;
+    } else {
+        o->frontier = (int64_t)ds.frontier;
+        o->edges = (int64_t)(uint32_t)ds.list;
+        o->pulled = ds.pad ? 1 : 0;
+    }
+    o->changed = (int64_t)ds.changed;
+    o->kernel_ms = 0.0;
+}
+
+extern "C" gx_status gx_superstep(gx_state *s, void *stream, gx_step_stats *stats) {
+    clear_error();
+    GX_REQUIRE(s, GX_EINVAL, "state is NULL");
+    GX_REQUIRE(!s->dev_error && !s->g->dev_error, GX_EDEVICE, "sticky device error");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    int64_t k = s->k;
+    gx_status st = enqueue_superstep(s, hs);
+    if (st != GX_OK) return st;
+    if (stats) {
+        DevStep ds;
+        GX_CHECK_HIP(hipMemcpyAsync(&ds, s->steps + (k % STEP_RING), sizeof ds, hipMemcpyDeviceToHost, hs), s);
+        GX_CHECK_HIP(hipStreamSynchronize(hs), s);
+        to_stats(s, ds, stats);
+        collect_timings(s, stats, k, 1);
+    }
+    return GX_OK;
+}
+
+extern "C" gx_status gx_run_until_converged(gx_state *s, uint32_t max_supersteps, void *stream, gx_run_stats *out,
+                                            gx_step_stats *per_step) {
+    clear_error();
+    GX_REQUIRE(s, GX_EINVAL, "state is NULL");
+    GX_REQUIRE(!s->dev_error && !s->g->dev_error, GX_EDEVICE, "sticky device error");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    auto t0 = std::chrono::steady_clock::now();
+    double ms0 = s->kernel_ms;
+    int64_t l0 = s->kernel_launches;
+    gx_run_stats rs{};
+    std::vector<DevStep> host(64);
+    gx_status result = GX_OK;
+    const int64_t k_begin = s->k;
+    if (s->p.algo == GX_PAGERANK) {
+        int64_t kfirst = s->k;
+        for (uint32_t i = 0; i < max_supersteps; i++) {
+            gx_status st = enqueue_superstep(s, hs);
+            if (st != GX_OK) return st;
+        }
+        host.resize(std::max<size_t>(host.size(), max_supersteps));
+        for (uint32_t i = 0; i < max_supersteps; i++)
+            GX_CHECK_HIP(hipMemcpyAsync(&host[i], s->steps + ((kfirst + i) % STEP_RING), sizeof(DevStep),
+                                        hipMemcpyDeviceToHost, hs),
+                         s);
+        GX_CHECK_HIP(hipStreamSynchronize(hs), s);
+        for (uint32_t i = 0; i < max_supersteps; i++) {
+            gx_step_stats o;
+            to_stats(s, host[i], &o);
+            if (per_step) per_step[i] = o;
+            rs.edges += o.edges;
+        }
+        rs.supersteps = max_supersteps;
+        rs.converged = 0;
+    } else {
+        uint32_t done = 0, spec = 2;
+        bool conv = false;
+        while (done < max_supersteps && !conv) {
+            uint32_t g = std::min(spec, max_supersteps - done);
+            int64_t kfirst = s->k;
+            for (uint32_t i = 0; i < g; i++) {
+                gx_status st = enqueue_superstep(s, hs);
+                if (st != GX_OK) return st;
+            }
+            if (host.size() < g) host.resize(g);
+            for (uint32_t i = 0; i < g; i++)
+                GX_CHECK_HIP(hipMemcpyAsync(&host[i], s->steps + ((kfirst + i) % STEP_RING), sizeof(DevStep),
+                                            hipMemcpyDeviceToHost, hs),
+                             s);
+            GX_CHECK_HIP(hipStreamSynchronize(hs), s);
+            for (uint32_t i = 0; i < g; i++) {
+                gx_step_stats o;
+                to_stats(s, host[i], &o);
+                if (per_step) per_step[done] = o;
+                rs.edges += o.edges;
+                done++;
+                if (o.changed == 0) {
+                    conv = true;
+                    // supersteps enqueued after this one found an empty frontier and changed nothing
+                    s->k = kfirst + i + 1;
+                    break;
+                }
+            }
+            spec = std::min<uint32_t>(spec * 2, 8);
+        }
+        rs.supersteps = done;
+        rs.converged = conv ? 1 : 0;
+        if (!conv) {
+            set_error("not converged after %u supersteps", max_supersteps);
+            result = GX_ENOTCONVERGED;
+        }
+    }
+    collect_timings(s, per_step, k_begin, rs.supersteps);
+    rs.edge_kernel_ms = s->kernel_ms - ms0;
+    rs.edge_kernel_launches = s->kernel_launches - l0;
+    rs.wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (out) *out = rs;
+    return result;
+}
+
+extern "C" gx_status gx_sync_delta(gx_state *s, int32_t *dev_gid, uint32_t *dev_val, uint32_t cap, uint32_t *count,
+                                   int32_t *skippable, void *stream) {
+    clear_error();
+    GX_REQUIRE(s && count, GX_EINVAL, "NULL argument");
+    GX_REQUIRE(cap == 0 || (dev_gid && dev_val), GX_EINVAL, "output buffers are NULL");
+    GX_REQUIRE(!s->dev_error && !s->g->dev_error, GX_EDEVICE, "sticky device error");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const DevGraph &d = s->g->d;
+    *count = 0;
+    if (skippable) *skippable = 1;
+    if (d.W == 0) return GX_OK;
+    bool all = s->p.delta_mode == GX_DELTA_ALL;
+    const uint32_t *remote = s->p.algo == GX_CC ? d.remote_any : d.remote_out;
+    bool pr = s->p.algo == GX_PAGERANK;
+    const uint32_t *vals = pr ? reinterpret_cast<const uint32_t *>(s->x[s->k & 1]) : s->val;
+    uint32_t *dirty = pr ? nullptr : s->dirty;
+    uint32_t *synced = pr ? s->synced : nullptr;
+    hipLaunchKernelGGL(k_delta_count, dim3(s->delta_blocks), dim3(256), 0, hs, d.W, d.V, remote, (int)all, dirty,
+                       vals, synced, s->blk_cnt);
+    hipLaunchKernelGGL(k_delta_emit, dim3(s->delta_blocks), dim3(256), 0, hs, d.W, d.V, remote, (int)all, dirty,
+                       vals, synced, d.l2g, s->blk_cnt, s->delta_blocks, cap, dev_gid, dev_val, s->delta_total);
+    GX_CHECK_HIP(hipGetLastError(), s);
+    uint32_t total = 0;
+    GX_CHECK_HIP(hipMemcpyAsync(&total, s->delta_total, 4, hipMemcpyDeviceToHost, hs), s);
+    GX_CHECK_HIP(hipStreamSynchronize(hs), s);
+    *count = total;
+    if (skippable) *skippable = total == 0;
+    if (total > cap) {
+        set_error("sync set has %u entries, capacity %u", total, cap);
+        return GX_ENOMEM;
+    }
+    return GX_OK;
+}

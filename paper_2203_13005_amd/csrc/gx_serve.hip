@@ -1,0 +1,567 @@
+// Serving: continuous batching of SSSP and personalised-PageRank queries over
+// graphs kept resident in HBM.
+//
+// A scheduler thread owns per-(graph, algorithm) lane pools.  Each pool is a
+// [V x B] batched state (the lanes of the batched engine) with its own
+// stream.  A pool advances in epochs of a few supersteps; between epochs
+// (superstep boundaries) the scheduler retires lanes whose query is done --
+// SSSP when the lane activated nothing in a superstep, PPR after its
+// iterations -- copies their column to the caller's buffer, and admits
+// queued queries into free lanes.  New pools are created only while the
+// device budget allows (first-fit inside the caller's arena); idle empty
+// pools are evicted to make room.  Pools on different streams overlap on the
+// GPU, so pool epochs use ordinary launches (no grid-wide co-residency is
+// assumed).  Every lane's arithmetic is independent of the other lanes, so a
+// query's answer is the same alone and in the mix.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+
+#include "gx_batch.h"
+#include "gx_device.h"
+#include "gx_internal.h"
+
+using namespace gx;
+
+namespace {
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct SQuery {
+    int64_t id;
+    int32_t graph, algo, source;
+    void *result;
+    double t_submit = 0, t_start = 0, t_done = 0;
+    int64_t steps = 0;
+    int32_t status = GX_OK;
+};
+
+// First-fit allocator over the server arena (256-byte granules).
+struct ArenaAlloc {
+    char *base = nullptr;
+    size_t cap = 0;
+    std::map<size_t, size_t> free_;  // offset -> size
+    void init(void *b, size_t c) {
+        base = static_cast<char *>(b);
+        size_t off = (ALIGN - reinterpret_cast<uintptr_t>(b) % ALIGN) % ALIGN;
+        cap = c > off ? c - off : 0;
+        base += off;
+        free_.clear();
+        if (cap) free_[0] = cap;
+    }
+    void *alloc(size_t n) {
+        n = align_up(n);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n) continue;
+            size_t off = it->first, sz = it->second;
+            free_.erase(it);
+            if (sz > n) free_[off + n] = sz - n;
+            return base + off;
+        }
+        return nullptr;
+    }
+    void release(void *p, size_t n) {
+        n = align_up(n);
+        size_t off = static_cast<char *>(p) - base;
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+struct Pool {
+    int32_t graph = -1, algo = -1;
+    gx_graph *g = nullptr;
+    uint32_t B = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    void *mem = nullptr;
+    size_t bytes = 0;
+    // SSSP
+    uint32_t *D = nullptr;
+    BsWork bw{};
+    uint32_t *lane_cnt = nullptr;
+    // PPR
+    BpWork pw{};
+    // result staging
+    uint32_t *stage = nullptr;
+    uint32_t *host_stage = nullptr;  // pinned, V words
+    uint32_t *host_cnt = nullptr;    // pinned, epoch x B activation counts
+    std::vector<int64_t> lane_q;     // query id per lane, -1 = free
+    std::vector<int64_t> lane_age;   // supersteps since the lane joined
+    std::vector<int32_t> seeds;      // PPR seed per lane (-1 = free)
+    uint32_t k = 0;                  // supersteps run (buffer parity)
+    bool in_flight = false;
+    uint32_t epoch_len = 0;
+    int occupied() const {
+        int n = 0;
+        for (auto q : lane_q) n += q >= 0;
+        return n;
+    }
+};
+
+size_t pool_bytes(const gx_graph *g, int32_t algo, uint32_t B, uint32_t epoch_max) {
+    Carver c(nullptr, 0);
+    const DevGraph &d = g->d;
+    if (algo == GX_SSSP) {
+        c.take<uint32_t>((size_t)d.V * B);
+        BsWork w;
+        bs_layout(d, B, c, &w);
+        c.take<uint32_t>((size_t)epoch_max * B);
+    } else {
+        BpWork w;
+        bp_layout(d, B, c, &w);
+    }
+    c.take<uint32_t>(d.V);
+    return c.used;
+}
+
+}  // namespace
+
+struct gx_server {
+    gx_server_config cfg{};
+    ArenaAlloc arena;
+    std::vector<gx_graph *> graphs;
+    std::vector<std::unique_ptr<Pool>> pools;
+    std::deque<SQuery> queue;
+    std::map<int64_t, SQuery> running;
+    std::vector<gx_query_result> completed;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::thread worker;
+    bool stop = false;
+    int64_t next_id = 1;
+    std::string fatal;
+    int grid = 0;
+
+    ~gx_server() {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            stop = true;
+        }
+        cv_work.notify_all();
+        if (worker.joinable()) worker.join();
+        for (auto &p : pools) destroy_pool(*p, false);
+    }
+
+    void destroy_pool(Pool &p, bool give_back) {
+        if (p.stream) (void)hipStreamSynchronize(p.stream);
+        if (p.done) (void)hipEventDestroy(p.done);
+        if (p.stream) (void)hipStreamDestroy(p.stream);
+        if (p.host_stage) (void)hipHostFree(p.host_stage);
+        if (p.host_cnt) (void)hipHostFree(p.host_cnt);
+        if (give_back && p.mem) arena.release(p.mem, p.bytes);
+        p.stream = nullptr;
+        p.done = nullptr;
+        p.host_stage = p.host_cnt = nullptr;
+        p.mem = nullptr;
+    }
+
+    uint32_t epoch_max() const { return cfg.epoch_supersteps; }
+
+    // Creates a pool for (graph, algo) inside the budget; nullptr if it does not fit.
+    Pool *create_pool(int32_t graph, int32_t algo) {
+        gx_graph *g = graphs[graph];
+        const uint32_t B = cfg.lanes_per_pool;
+        size_t bytes = pool_bytes(g, algo, B, epoch_max());
+        void *mem = arena.alloc(bytes);
+        if (!mem) {  // evict idle empty pools, then retry
+            for (size_t i = 0; i < pools.size();) {
+                Pool &p = *pools[i];
+                if (!p.in_flight && p.occupied() == 0) {
+                    destroy_pool(p, true);
+                    pools.erase(pools.begin() + i);
+                } else {
+                    i++;
+                }
+            }
+            mem = arena.alloc(bytes);
+            if (!mem) return nullptr;
+        }
+        auto p = std::make_unique<Pool>();
+        p->graph = graph;
+        p->algo = algo;
+        p->g = g;
+        p->B = B;
+        p->mem = mem;
+        p->bytes = bytes;
+        p->lane_q.assign(B, -1);
+        p->lane_age.assign(B, 0);
+        p->seeds.assign(B, -1);
+        const DevGraph &d = g->d;
+        Carver c(mem, bytes);
+        bool ok = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) == hipSuccess &&
+                  hipEventCreateWithFlags(&p->done, hipEventDisableTiming) == hipSuccess &&
+                  hipHostMalloc((void **)&p->host_stage, std::max<size_t>(4, d.V * 4), hipHostMallocDefault) ==
+                      hipSuccess &&
+                  hipHostMalloc((void **)&p->host_cnt, std::max<size_t>(4, (size_t)epoch_max() * B * 4),
+                                hipHostMallocDefault) == hipSuccess;
+        if (algo == GX_SSSP) {
+            p->D = c.take<uint32_t>((size_t)d.V * B);
+            bs_layout(d, B, c, &p->bw);
+            p->lane_cnt = c.take<uint32_t>((size_t)epoch_max() * B);
+        } else {
+            bp_layout(d, B, c, &p->pw);
+        }
+        p->stage = c.take<uint32_t>(d.V);
+        if (ok) {
+            hipStream_t s = p->stream;
+            if (algo == GX_SSSP) {
+                const size_t VG = (size_t)d.V * (B / 32);
+                ok = hipMemsetAsync(p->D, 0xFF, (size_t)d.V * B * 4, s) == hipSuccess &&
+                     hipMemsetAsync(p->bw.M[0], 0, VG * 4, s) == hipSuccess &&
+                     hipMemsetAsync(p->bw.M[1], 0, VG * 4, s) == hipSuccess &&
+                     hipMemsetAsync(p->bw.ctl, 0, sizeof(BsCtl), s) == hipSuccess;
+            } else {
+                const size_t n = (size_t)d.V * B * 4;
+                ok = hipMemsetAsync(p->pw.x[0], 0, n, s) == hipSuccess &&
+                     hipMemsetAsync(p->pw.x[1], 0, n, s) == hipSuccess &&
+                     hipMemsetAsync(p->pw.c[0], 0, n, s) == hipSuccess &&
+                     hipMemsetAsync(p->pw.c[1], 0, n, s) == hipSuccess &&
+                     hipMemsetAsync(p->pw.D[0], 0, B * 8, s) == hipSuccess &&
+                     hipMemsetAsync(p->pw.D[1], 0, B * 8, s) == hipSuccess &&
+                     bp_make_tiles(d.in_rp, d.V, p->pw.ntiles, p->pw.trow, s) == hipSuccess &&
+                     hipMemcpyAsync(p->pw.seed, p->seeds.data(), B * 4, hipMemcpyHostToDevice, s) == hipSuccess;
+            }
+            ok = ok && hipStreamSynchronize(s) == hipSuccess;
+        }
+        if (!ok) {
+            destroy_pool(*p, true);
+            fatal = "pool creation failed (HIP error)";
+            return nullptr;
+        }
+        pools.push_back(std::move(p));
+        return pools.back().get();
+    }
+
+    BsArgs bs_args(Pool &p) {
+        const DevGraph &d = p.g->d;
+        BsArgs a{};
+        a.rp = d.out_rp;
+        a.adj = d.out_adj;
+        a.V = d.V;
+        a.B = p.B;
+        a.l0 = 0;
+        a.G = p.B / 32;
+        a.D = p.D;
+        a.M[0] = p.bw.M[0];
+        a.M[1] = p.bw.M[1];
+        a.list = p.bw.list;
+        a.S = p.bw.S;
+        a.tile_start = p.bw.tile_start;
+        a.ctl = p.bw.ctl;
+        a.max_steps = 1;
+        a.lane_cnt = p.lane_cnt;
+        a.stop_when_idle = 0;
+        return a;
+    }
+
+    BpArgs bp_args(Pool &p) {
+        const DevGraph &d = p.g->d;
+        BpArgs a{};
+        a.in_rp = d.in_rp;
+        a.in_col = d.in_col;
+        a.outdeg = d.outdeg;
+        a.trow = p.pw.trow;
+        a.ntiles = p.pw.ntiles;
+        a.V = d.V;
+        a.E = d.E;
+        a.B = p.B;
+        a.d = cfg.damping;
+        a.seed = p.pw.seed;
+        a.x[0] = p.pw.x[0];
+        a.x[1] = p.pw.x[1];
+        a.c[0] = p.pw.c[0];
+        a.c[1] = p.pw.c[1];
+        a.head = p.pw.head;
+        a.tailp = p.pw.tailp;
+        a.dsum = p.pw.dsum;
+        a.dpart = p.pw.dpart;
+        a.D[0] = p.pw.D[0];
+        a.D[1] = p.pw.D[1];
+        a.spill = p.pw.spill;
+        a.bar = nullptr;
+        return a;
+    }
+
+    bool admit(Pool &p, SQuery &q, uint32_t lane) {
+        const DevGraph &d = p.g->d;
+        hipError_t e;
+        if (p.algo == GX_SSSP) {
+            e = bs_lane_reset(p.D, p.bw.M[p.k & 1], p.bw.M[(p.k + 1) & 1], d.V, p.B, p.B / 32, lane, q.source,
+                              p.stream);
+        } else {
+            p.seeds[lane] = q.source;
+            e = bp_lane_reset(p.pw.x[p.k & 1], p.pw.c[p.k & 1], p.pw.D[p.k & 1], d.outdeg, d.V, p.B, lane, q.source,
+                              p.stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(p.pw.seed + lane, &p.seeds[lane], 4, hipMemcpyHostToDevice, p.stream);
+        }
+        if (e != hipSuccess) return false;
+        p.lane_q[lane] = q.id;
+        p.lane_age[lane] = 0;
+        q.t_start = now_s();
+        running[q.id] = q;
+        return true;
+    }
+
+    void retire(Pool &p, uint32_t lane, int64_t steps) {
+        const DevGraph &d = p.g->d;
+        auto it = running.find(p.lane_q[lane]);
+        if (it == running.end()) return;
+        SQuery &q = it->second;
+        const uint32_t *tile = p.algo == GX_SSSP ? p.D : reinterpret_cast<const uint32_t *>(p.pw.x[p.k & 1]);
+        hipError_t e = lane_extract(tile, d.V, p.B, lane, p.stage, p.stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(p.host_stage, p.stage, d.V * 4, hipMemcpyDeviceToHost, p.stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
+        if (e == hipSuccess) std::memcpy(q.result, p.host_stage, d.V * 4);
+        q.status = e == hipSuccess ? GX_OK : GX_EDEVICE;
+        q.steps = steps;
+        q.t_done = now_s();
+        gx_query_result r{q.id, q.graph, q.algo, q.source, q.status, q.t_submit, q.t_start, q.t_done, q.steps};
+        completed.push_back(r);
+        running.erase(it);
+        p.lane_q[lane] = -1;
+        p.seeds[lane] = -1;
+        cv_done.notify_all();
+    }
+
+    void finish_epoch(Pool &p) {
+        p.in_flight = false;
+        const uint32_t B = p.B;
+        if (p.algo == GX_SSSP) {
+            for (uint32_t b = 0; b < B; b++) {
+                if (p.lane_q[b] < 0) continue;
+                int64_t conv = -1;
+                for (uint32_t it = 0; it < p.epoch_len; it++)
+                    if (p.host_cnt[(size_t)it * B + b] == 0) {
+                        conv = it;
+                        break;
+                    }
+                if (conv >= 0) {
+                    retire(p, b, p.lane_age[b] + conv + 1);
+                } else {
+                    p.lane_age[b] += p.epoch_len;
+                }
+            }
+        } else {
+            for (uint32_t b = 0; b < B; b++) {
+                if (p.lane_q[b] < 0) continue;
+                p.lane_age[b] += p.epoch_len;
+                if (p.lane_age[b] >= (int64_t)cfg.ppr_iters) retire(p, b, p.lane_age[b]);
+            }
+        }
+    }
+
+    bool launch_epoch(Pool &p) {
+        if (p.algo == GX_SSSP) {
+            p.epoch_len = epoch_max();
+            if (hipMemsetAsync(p.lane_cnt, 0, (size_t)p.epoch_len * p.B * 4, p.stream) != hipSuccess) return false;
+            BsArgs a = bs_args(p);
+            for (uint32_t it = 0; it < p.epoch_len; it++)
+                if (bs_launch_superstep(a, p.k + it, it, grid, p.stream) != hipSuccess) return false;
+            if (hipMemcpyAsync(p.host_cnt, p.lane_cnt, (size_t)p.epoch_len * p.B * 4, hipMemcpyDeviceToHost,
+                               p.stream) != hipSuccess)
+                return false;
+        } else {
+            int64_t left = cfg.ppr_iters;
+            for (uint32_t b = 0; b < p.B; b++)
+                if (p.lane_q[b] >= 0) left = std::min<int64_t>(left, (int64_t)cfg.ppr_iters - p.lane_age[b]);
+            p.epoch_len = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(left, epoch_max()));
+            BpArgs a = bp_args(p);
+            for (uint32_t it = 0; it < p.epoch_len; it++)
+                if (bp_launch_superstep(a, p.k + it, grid, p.stream) != hipSuccess) return false;
+        }
+        p.k += p.epoch_len;
+        if (hipEventRecord(p.done, p.stream) != hipSuccess) return false;
+        p.in_flight = true;
+        return true;
+    }
+
+    // Admission in arrival order: a query takes a free lane of an idle pool of
+    // its (graph, algorithm); it waits while such a pool is mid-epoch and has
+    // a free lane (lanes join at superstep boundaries); otherwise a new pool
+    // is created if the budget allows, else it waits.
+    void admit_queued() {
+        for (size_t i = 0; i < queue.size();) {
+            SQuery &q = queue[i];
+            Pool *target = nullptr;
+            uint32_t lane = 0;
+            bool wait_boundary = false;
+            for (auto &pp : pools) {
+                Pool &p = *pp;
+                if (p.graph != q.graph || p.algo != q.algo) continue;
+                int free_lane = -1;
+                for (uint32_t b = 0; b < p.B; b++)
+                    if (p.lane_q[b] < 0) {
+                        free_lane = (int)b;
+                        break;
+                    }
+                if (free_lane < 0) continue;
+                if (p.in_flight) {
+                    wait_boundary = true;
+                    continue;
+                }
+                target = &p;
+                lane = (uint32_t)free_lane;
+                break;
+            }
+            if (!target && !wait_boundary) target = create_pool(q.graph, q.algo);
+            if (target && admit(*target, q, lane)) {
+                queue.erase(queue.begin() + i);
+                continue;
+            }
+            i++;
+        }
+    }
+
+    int device = 0;
+
+    void run() {
+        (void)hipSetDevice(device);
+        std::unique_lock<std::mutex> lk(mu);
+        while (true) {
+            bool any_flight = false;
+            for (auto &pp : pools) {
+                Pool &p = *pp;
+                if (p.in_flight && hipEventQuery(p.done) == hipSuccess) finish_epoch(p);
+            }
+            admit_queued();
+            int flying = 0;
+            for (auto &pp : pools) flying += pp->in_flight;
+            for (auto &pp : pools) {
+                Pool &p = *pp;
+                if (!p.in_flight && p.occupied() > 0 && flying < (int)cfg.max_pools) {
+                    if (launch_epoch(p)) flying++;
+                    else fatal = "epoch launch failed";
+                }
+            }
+            for (auto &pp : pools) any_flight |= pp->in_flight;
+            if (stop && !any_flight) break;
+            if (!any_flight && queue.empty()) {
+                cv_work.wait_for(lk, std::chrono::milliseconds(5));
+            } else {
+                lk.unlock();
+                std::this_thread::sleep_for(std::chrono::microseconds(20));
+                lk.lock();
+            }
+        }
+    }
+};
+
+extern "C" gx_status gx_server_bytes_per_lane(const gx_graph *g, int32_t algo, size_t *bytes) {
+    clear_error();
+    GX_REQUIRE(g && bytes, GX_EINVAL, "NULL argument");
+    GX_REQUIRE(algo == GX_SSSP || algo == GX_PPR, GX_EINVAL, "algo must be GX_SSSP or GX_PPR");
+    *bytes = (pool_bytes(g, algo, 64, 8) + 63) / 64;
+    return GX_OK;
+}
+
+extern "C" gx_status gx_server_create(const gx_server_config *cfg, gx_server **out) {
+    clear_error();
+    GX_REQUIRE(cfg && out, GX_EINVAL, "NULL argument");
+    GX_REQUIRE(cfg->dev_arena && cfg->arena_bytes > 0, GX_EINVAL, "server needs a device arena");
+    gx_server_config c = *cfg;
+    if (c.lanes_per_pool == 0) c.lanes_per_pool = 64;
+    if (c.max_pools == 0) c.max_pools = 4;
+    if (c.epoch_supersteps == 0) c.epoch_supersteps = 4;
+    if (c.damping == 0.f) c.damping = 0.85f;
+    if (c.ppr_iters == 0) c.ppr_iters = 50;
+    GX_REQUIRE(c.lanes_per_pool % 32 == 0 && c.lanes_per_pool <= 256, GX_EINVAL,
+               "lanes_per_pool must be a multiple of 32 up to 256");
+    GX_REQUIRE(c.epoch_supersteps <= 64, GX_EINVAL, "epoch_supersteps must be <= 64");
+    GX_REQUIRE(c.damping > 0.f && c.damping < 1.f, GX_EINVAL, "damping out of (0,1)");
+    gx_server *s = new (std::nothrow) gx_server();
+    GX_REQUIRE(s, GX_ENOMEM, "host allocation failed");
+    s->cfg = c;
+    s->arena.init(c.dev_arena, c.arena_bytes);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    s->device = dev;
+    s->grid = device_cus(dev) * 2;
+    s->worker = std::thread([s] { s->run(); });
+    *out = s;
+    return GX_OK;
+}
+
+extern "C" gx_status gx_server_add_graph(gx_server *s, gx_graph *g, int32_t *graph_id) {
+    clear_error();
+    GX_REQUIRE(s && g && graph_id, GX_EINVAL, "NULL argument");
+    GX_REQUIRE((g->needs & (GX_NEED_OUT | GX_NEED_IN)) == (GX_NEED_OUT | GX_NEED_IN), GX_EINVAL,
+               "serving needs graphs loaded with GX_NEED_OUT | GX_NEED_IN");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->graphs.push_back(g);
+    *graph_id = (int32_t)s->graphs.size() - 1;
+    return GX_OK;
+}
+
+extern "C" gx_status gx_server_submit(gx_server *s, int32_t graph_id, int32_t algo, int32_t source, void *result,
+                                      int64_t *id) {
+    clear_error();
+    GX_REQUIRE(s && result && id, GX_EINVAL, "NULL argument");
+    GX_REQUIRE(algo == GX_SSSP || algo == GX_PPR, GX_EINVAL, "algo must be GX_SSSP or GX_PPR");
+    std::lock_guard<std::mutex> lk(s->mu);
+    GX_REQUIRE(graph_id >= 0 && graph_id < (int32_t)s->graphs.size(), GX_ENOTFOUND, "unknown graph %d", graph_id);
+    gx_graph *g = s->graphs[graph_id];
+    GX_REQUIRE(source >= 0 && source < g->d.V, GX_EINVAL, "source %d out of [0,V)", source);
+    const size_t need = pool_bytes(g, algo, s->cfg.lanes_per_pool, s->cfg.epoch_supersteps);
+    GX_REQUIRE(need <= s->arena.cap, GX_ENOMEM, "one lane pool needs %zu bytes, the budget is %zu", need,
+               s->arena.cap);
+    GX_REQUIRE(s->fatal.empty(), GX_EDEVICE, "server failed: %s", s->fatal.c_str());
+    SQuery q;
+    q.id = s->next_id++;
+    q.graph = graph_id;
+    q.algo = algo;
+    q.source = source;
+    q.result = result;
+    q.t_submit = now_s();
+    s->queue.push_back(q);
+    *id = q.id;
+    s->cv_work.notify_all();
+    return GX_OK;
+}
+
+extern "C" gx_status gx_server_poll(gx_server *s, gx_query_result *out, uint32_t cap, uint32_t *n, int32_t wait_ms) {
+    clear_error();
+    GX_REQUIRE(s && n && (out || cap == 0), GX_EINVAL, "NULL argument");
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->completed.empty() && wait_ms > 0)
+        s->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms), [s] { return !s->completed.empty(); });
+    uint32_t m = (uint32_t)std::min<size_t>(cap, s->completed.size());
+    for (uint32_t i = 0; i < m; i++) out[i] = s->completed[i];
+    s->completed.erase(s->completed.begin(), s->completed.begin() + m);
+    *n = m;
+    GX_REQUIRE(s->fatal.empty(), GX_EDEVICE, "server failed: %s", s->fatal.c_str());
+    return GX_OK;
+}
+
+extern "C" gx_status gx_server_pending(gx_server *s, int64_t *n) {
+    clear_error();
+    GX_REQUIRE(s && n, GX_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    *n = (int64_t)(s->queue.size() + s->running.size());
+    return GX_OK;
+}
+
+extern "C" gx_status gx_server_destroy(gx_server *s) {
+    clear_error();
+    delete s;
+    return GX_OK;
+}

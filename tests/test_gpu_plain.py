@@ -1,0 +1,340 @@
+"""Parity of the HIP superstep engine with the CPU oracle (runs on MI355X).
+
+SSSP distances, CC labels, frontiers, superstep counts and sync sets must
+match the oracle bit for bit; PageRank must stay within max-abs 1e-6 of the
+float64 oracle (float32 on the device).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+PR_TOL = 1e-6
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def gx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2203_13005_amd as m
+    return m
+
+
+def load(gx, g, needs=None):
+    if needs is None:
+        needs = gx.GX_NEED_OUT | gx.GX_NEED_IN | gx.GX_NEED_SYM
+    return gx.DeviceGraph(g, needs)
+
+
+def random_graph(V, E, seed):
+    rng = np.random.default_rng(seed)
+    return gen.from_edges(V, rng.integers(0, V, E), rng.integers(0, V, E), rng.integers(1, 256, E))
+
+
+def star_into(V, hub=0):
+    src = np.arange(V)
+    src = src[src != hub]
+    return gen.from_edges(V, src, np.full(len(src), hub), (src % 255) + 1)
+
+
+# ------------------------------------------------------------------ SSSP
+
+# pull_fraction: 1.0 = always push, 1e-9 = pull whenever a message exists,
+# 0 = the default switch point
+MODES = [1.0, 1e-9, 0.0]
+
+
+def check_sssp_stepwise(gx, g, s, pull_fraction=0.0):
+    dg = load(gx, g, gx.GX_NEED_OUT)
+    st = gx.State(dg, gx.GX_SSSP, source=s, pull_fraction=pull_fraction)
+    dists, fronts = oracle.sssp_frontiers(g, s)
+    deg = np.diff(g.row_ptr)
+    for k in range(1, len(dists)):
+        f_prev = fronts[k - 1]
+        fr, edges, changed = st.superstep(stats=True)
+        assert fr == f_prev.sum(), k
+        assert edges == deg[f_prev].sum(), k
+        assert changed == fronts[k].sum(), k
+        assert np.array_equal(st.values_numpy(), dists[k]), k
+        assert np.array_equal(st.frontier_numpy(), fronts[k]), k
+    return st
+
+
+def test_sssp_hand_example(gx):
+    h = json.load(open(os.path.join(GOLDEN, "hand_sssp_cc_7v.json")))
+    e = np.array(h["edges"])
+    g = gen.from_edges(h["V"], e[:, 0], e[:, 1], e[:, 2])
+    st = check_sssp_stepwise(gx, g, 0)
+    assert st.values_numpy().tolist() == h["sssp_dist"]
+    st2 = gx.State(load(gx, g, gx.GX_NEED_OUT), gx.GX_SSSP, source=0)
+    rs, steps = st2.run(100, per_step=True)
+    assert rs.supersteps == h["sssp_K"] and rs.converged == 1
+    assert [s[1] for s in steps] == h["sssp_messages"]
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("V,E,seed", [(64, 200, 1), (300, 3000, 2), (1000, 500, 3), (5000, 40000, 4)])
+def test_sssp_random_stepwise(gx, V, E, seed, mode):
+    g = random_graph(V, E, seed)
+    check_sssp_stepwise(gx, g, 0, mode)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("scale,seed", [(12, 1), (16, 2), (18, 3)])
+def test_sssp_rmat_against_oracle(gx, scale, seed, mode):
+    g = gen.rmat(scale, seed=seed)
+    ref = oracle.sssp(g, 0)
+    st = gx.State(load(gx, g, gx.GX_NEED_OUT), gx.GX_SSSP, source=0, pull_fraction=mode)
+    rs, steps = st.run(10_000, per_step=True)
+    assert rs.supersteps == ref.K
+    assert np.array_equal(st.values_numpy(), ref.state)
+    steps = np.array(steps)
+    assert np.array_equal(steps[:, 0], ref.front)
+    assert np.array_equal(steps[:, 1], ref.msgs)
+    assert np.array_equal(steps[:, 2], ref.changed)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_sssp_hub_spanning_many_tiles(gx, mode):
+    # vertex 0 has 20000 out-edges (10 push tiles); a chain hangs off it
+    V = 20001
+    src = np.r_[np.zeros(V - 1, int), np.arange(1, 200)]
+    dst = np.r_[np.arange(1, V), np.arange(2, 201)]
+    w = np.r_[np.full(V - 1, 255), np.ones(199, int)]
+    g = gen.from_edges(V, src, dst, w)
+    check_sssp_stepwise(gx, g, 0, mode)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_sssp_in_hub_spanning_many_pull_tiles(gx, mode):
+    # vertex 5 has in-degree 9000 (crosses five 2048-edge pull tiles) and the
+    # sources reach it at different supersteps
+    V = 9002
+    src = np.r_[np.arange(6, V), np.zeros(V - 6, int), [0, 1, 2, 3], [1, 2, 3, 4]]
+    dst = np.r_[np.full(V - 6, 5), np.arange(6, V), [1, 2, 3, 4], [5, 5, 5, 5]]
+    w = np.r_[np.full(V - 6, 7), (np.arange(V - 6) % 255) + 1, [1, 1, 1, 1], [200, 100, 50, 1]]
+    g = gen.from_edges(V, src, dst, w)
+    check_sssp_stepwise(gx, g, 0, mode)
+
+
+def test_sssp_edge_cases(gx):
+    g = gen.from_edges(1, [], [])
+    st = gx.State(load(gx, g, gx.GX_NEED_OUT), gx.GX_SSSP, source=0)
+    rs, _ = st.run(10)
+    assert rs.supersteps == 1 and st.values_numpy().tolist() == [0]
+    # source without out-edges; others unreachable
+    g = gen.from_edges(40, [1, 2], [2, 3], [5, 5])
+    st = gx.State(load(gx, g, gx.GX_NEED_OUT), gx.GX_SSSP, source=0)
+    rs, _ = st.run(10)
+    assert rs.supersteps == 1
+    assert st.values_numpy().tolist() == [0] + [gx.INF] * 39
+    # superstep cap: a chain needs V supersteps
+    V = 50
+    g = gen.from_edges(V, np.arange(V - 1), np.arange(1, V), np.ones(V - 1, int))
+    st = gx.State(load(gx, g, gx.GX_NEED_OUT), gx.GX_SSSP, source=0)
+    with pytest.raises(gx.GxError) as ei:
+        st.run(10)
+    assert ei.value.status == 4  # GX_ENOTCONVERGED, state valid
+    d = st.values_numpy()
+    assert d[:11].tolist() == list(range(11)) and np.all(d[11:] == gx.INF)
+    rs, _ = st.run(100)  # resume to convergence
+    assert st.values_numpy().tolist() == list(range(V))
+
+
+def test_sssp_deterministic_rerun(gx):
+    g = gen.rmat(16, seed=9)
+    dg = load(gx, g, gx.GX_NEED_OUT)
+    outs = []
+    for _ in range(2):
+        st = gx.State(dg, gx.GX_SSSP, source=0)
+        st.run(10_000)
+        outs.append(st.values_numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+# ------------------------------------------------------------------ CC
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("V,E,seed", [(64, 50, 1), (500, 400, 2), (3000, 2500, 3), (20000, 60000, 4)])
+def test_cc_random(gx, V, E, seed, mode):
+    g = random_graph(V, E, seed)
+    ref = oracle.cc(g)
+    st = gx.State(load(gx, g, gx.GX_NEED_SYM), gx.GX_CC, pull_fraction=mode)
+    rs, steps = st.run(10_000, per_step=True)
+    assert np.array_equal(st.values_numpy(), ref.state)
+    assert rs.supersteps == ref.K
+    steps = np.array(steps)
+    assert np.array_equal(steps[:, 0], ref.front)
+    assert np.array_equal(steps[:, 2], ref.changed)
+
+
+def test_cc_hand_example(gx):
+    h = json.load(open(os.path.join(GOLDEN, "hand_sssp_cc_7v.json")))
+    e = np.array(h["edges"])
+    g = gen.from_edges(h["V"], e[:, 0], e[:, 1], e[:, 2])
+    st = gx.State(load(gx, g, gx.GX_NEED_SYM), gx.GX_CC)
+    rs, steps = st.run(100, per_step=True)
+    assert st.values_numpy().tolist() == h["cc_labels"]
+    assert rs.supersteps == h["cc_K"]
+    assert [s[2] for s in steps] == h["cc_changed"]
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("scale,seed", [(14, 3), (17, 5)])
+def test_cc_rmat_partition(gx, scale, seed, mode):
+    p = gen.rmat_part(scale, seed=seed, part=0)
+    ref = oracle.cc(p)
+    st = gx.State(load(gx, p, gx.GX_NEED_SYM), gx.GX_CC, pull_fraction=mode)
+    rs, steps = st.run(10_000, per_step=True)
+    assert np.array_equal(st.values_numpy(), ref.state)
+    assert rs.supersteps == ref.K
+    assert np.array_equal(np.array(steps)[:, 2], ref.changed)
+
+
+# ------------------------------------------------------------------ PageRank
+
+def check_pr(gx, g, T, d=0.85, tol=PR_TOL):
+    ref = oracle.pagerank(g, T, d)
+    st = gx.State(load(gx, g, gx.GX_NEED_IN), gx.GX_PAGERANK, damping=d)
+    rs, steps = st.run(T, per_step=True)
+    x = st.values_numpy().astype(np.float64)
+    err = np.max(np.abs(x - ref)) if g.V else 0.0
+    assert err <= tol, err
+    assert rs.supersteps == T and all(s[0] == g.V and s[1] == g.E for s in steps)
+    return st, x, ref
+
+
+def test_pagerank_rmat_scale14_20_steps(gx):
+    g = gen.rmat(14, seed=1)
+    st, x, ref = check_pr(gx, g, 20)
+    rel = np.max(np.abs(x - ref) / ref)
+    assert rel < 1e-4
+
+
+@pytest.mark.parametrize("V,E,seed", [(50, 100, 1), (3000, 9000, 2), (10000, 300, 3)])
+def test_pagerank_random(gx, V, E, seed):
+    check_pr(gx, random_graph(V, E, seed), 15)
+
+
+def test_pagerank_hub_rows_span_tiles(gx):
+    # in-degree 9000 at vertex 0 and 3000 at vertex 1: rows cross several
+    # 2048-edge tiles; plus rows ending exactly on a tile boundary
+    V = 9001
+    src = np.r_[np.arange(1, V), np.arange(2, 3002)]
+    dst = np.r_[np.zeros(V - 1, int), np.ones(3000, int)]
+    g = gen.from_edges(V, src, dst)
+    check_pr(gx, g, 10)
+    g = star_into(2049)  # E = 2048: exactly one full tile
+    check_pr(gx, g, 10)
+    g = star_into(4097, hub=4096)  # E = 4096, the hub is the last row
+    check_pr(gx, g, 10)
+
+
+def test_pagerank_edge_cases(gx):
+    check_pr(gx, gen.from_edges(1, [], []), 5)
+    check_pr(gx, gen.from_edges(7, [], []), 5)
+    g = gen.from_edges(2, [0], [1])
+    check_pr(gx, g, 12)
+
+
+def test_pagerank_deterministic_and_checkpoint(gx):
+    g = gen.rmat(15, seed=4)
+    dg = load(gx, g, gx.GX_NEED_IN)
+    a = gx.State(dg, gx.GX_PAGERANK)
+    a.run(20)
+    b = gx.State(dg, gx.GX_PAGERANK)
+    b.run(20)
+    assert np.array_equal(a.values_numpy().view(np.uint32), b.values_numpy().view(np.uint32))
+    c = gx.State(dg, gx.GX_PAGERANK)
+    c.run(7)
+    c.run(13)
+    assert np.array_equal(a.values_numpy().view(np.uint32), c.values_numpy().view(np.uint32))
+
+
+# ------------------------------------------------------------------ sync set
+
+@pytest.mark.parametrize("mode", [1.0, 1e-9])
+def test_sync_delta_cc_partition(gx, mode):
+    p = gen.rmat_part(14, seed=3, part=0)
+    rem = oracle.remote_mask(p, "cc")
+    st = gx.State(load(gx, p, gx.GX_NEED_SYM), gx.GX_CC, pull_fraction=mode)
+    lab = p.l2g.astype(np.uint32).copy()
+    synced = lab.copy()
+    front = np.zeros(p.V, bool)
+    front[np.unique(np.r_[p.src, p.col])] = True
+    skips = 0
+    for k in range(200):
+        lab, front = oracle.min_superstep(p, lab, front, weighted=False, both_dirs=True)
+        st.superstep()
+        gids, vals, skip = st.sync_delta()
+        rg, rv, rskip = oracle.delta(p, rem, lab, synced)
+        assert np.array_equal(gids, rg) and np.array_equal(vals, rv) and skip == rskip, k
+        skips += skip
+        if not front.any():
+            break
+    assert np.array_equal(st.values_numpy(), lab)
+
+
+@pytest.mark.parametrize("mode", [1.0, 1e-9])
+def test_sync_delta_sssp_lazy_and_capacity(gx, mode):
+    p = gen.rmat_part(14, seed=3, part=0)
+    rem = oracle.remote_mask(p, "sssp")
+    src = int(np.argmax(np.diff(p.row_ptr)))
+    st = gx.State(load(gx, p, gx.GX_NEED_OUT), gx.GX_SSSP, source=src, pull_fraction=mode)
+    dists, _ = oracle.sssp_frontiers(p, src)
+    synced = dists[0].copy()
+    # lazy: sync only every 3rd superstep; only final values are sent
+    for k in range(1, len(dists)):
+        st.superstep()
+        if k % 3 == 0 or k == len(dists) - 1:
+            rg, rv, rskip = oracle.delta(p, rem, dists[k], synced)
+            if len(rg) > 1:
+                with pytest.raises(gx.GxError):
+                    st.sync_delta(cap=len(rg) - 1)  # too small: nothing committed
+            gids, vals, skip = st.sync_delta()
+            assert np.array_equal(gids, rg) and np.array_equal(vals, rv) and skip == rskip, k
+
+
+def test_sync_delta_pagerank_all_mode(gx):
+    g = gen.rmat(12, seed=8)
+    st = gx.State(load(gx, g, gx.GX_NEED_IN), gx.GX_PAGERANK, delta_mode=gx.GX_DELTA_ALL)
+    prev = st.values_numpy().copy()
+    for _ in range(3):
+        st.superstep()
+        cur = st.values_numpy().copy()
+        gids, vals, skip = st.sync_delta()
+        want = np.nonzero(cur.view(np.uint32) != prev.view(np.uint32))[0]
+        assert np.array_equal(gids, want)
+        assert np.array_equal(vals, cur.view(np.uint32)[want])
+        prev = cur
+    # unpartitioned graph in REMOTE mode: nothing is remote, every sync skippable
+    st2 = gx.State(load(gx, g, gx.GX_NEED_IN), gx.GX_PAGERANK)
+    st2.superstep()
+    gids, _, skip = st2.sync_delta()
+    assert skip and len(gids) == 0
+
+
+# ------------------------------------------------------------------ full size
+
+@pytest.mark.slow
+@pytest.mark.parametrize("mode", [0.0, 1.0])
+def test_sssp_full_scale22_source0(gx, mode):
+    """The benchmarked workload: R-MAT scale 22, source 0, to convergence
+    (default switch point = the benchmarked launch configuration)."""
+    g = gen.rmat(22, seed=2)
+    ref = oracle.sssp(g, 0)
+    st = gx.State(load(gx, g, gx.GX_NEED_OUT), gx.GX_SSSP, source=0, pull_fraction=mode)
+    rs, steps = st.run(10_000, per_step=True)
+    assert rs.supersteps == ref.K
+    assert np.array_equal(st.values_numpy(), ref.state)
+    steps = np.array(steps)
+    assert np.array_equal(steps[:, 1], ref.msgs)
+    assert np.array_equal(steps[:, 2], ref.changed)
