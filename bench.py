@@ -73,6 +73,179 @@ def cpu_baseline(g, edges_per_solve, budget_s=20.0):
             "host_cpu": platform.processor() or platform.machine(), "host_nproc": os.cpu_count()}
 
 
+def bench_batched(gx, torch, np, gen, steps=3):
+    """256 seeded sources on R-MAT scale 20 (seed 4): one persistent batched
+    launch (autotuned) against 256 sequential plain solves on the same GPU."""
+    import paper_2203_13005_amd as m
+    g = gen.rmat(20, seed=4)
+    src = gen.pick_sources(g, 256, seed=40)
+    dg = gx.DeviceGraph(g, gx.GX_NEED_OUT | gx.GX_NEED_IN)
+    log(f"batched: V={g.V} E={g.E}, autotuning over block/tile/width")
+    best, best_ms = gx.batch_autotune(dg, gx.GX_SSSP, src)
+    log(f"batched: best {best} at {best_ms:.2f} ms")
+    out = torch.empty((g.V, 256), dtype=torch.int32, device="cuda:0")
+    gx.batch_run(dg, gx.GX_SSSP, src, tune=best, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, rs = gx.batch_run(dg, gx.GX_SSSP, src, tune=best, out=out)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / steps
+    D = out.cpu().numpy().view(np.uint32)
+    # plain: 256 sequential solves, one state re-initialised per source
+    st = m.State(dg, gx.GX_SSSP, source=int(src[0]))
+    st.run(100_000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain_edges = 0
+    for b, s_ in enumerate(src):
+        st.params.source = int(s_)
+        st.reset()
+        rsp, _ = st.run(100_000)
+        plain_edges += rsp.edges
+        if b in (0, 17, 255):
+            torch.cuda.synchronize()
+            assert np.array_equal(st.values_numpy(), D[:, b]), f"lane {b} differs from its plain solve"
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    log(f"batched: {t_batch * 1e3:.2f} ms for 256 lanes ({rs.supersteps} supersteps); "
+        f"256 plain solves {t_plain * 1e3:.1f} ms")
+    return {"workload": "256 seeded sources (seed 40, out-degree > 0), Bellman-Ford SSSP, R-MAT scale 20 "
+                        f"({g.V} vertices, {g.E} edges after dedup, seed 4), uint32 weights in [1,255]",
+            "queries_per_s": 256 / t_batch, "ms_per_batch": t_batch * 1e3, "supersteps": int(rs.supersteps),
+            "plain_queries_per_s": 256 / t_plain, "plain_ms_total": t_plain * 1e3,
+            "speedup_vs_plain": t_plain / t_batch, "lane_messages_per_batch": int(plain_edges),
+            "lane_gteps": plain_edges / t_batch / 1e9,
+            "tune": {"block": best.block, "tile": best.tile, "width": best.width}}
+
+
+def bench_serving(gx, torch, np, gen, n_queries=2000, qps_frac=0.7, budget_gib=24.0, lanes=64):
+    """16 resident R-MAT graphs (scales 16..22, seeds 100..115), 50% SSSP /
+    50% PPR (50 iterations), Poisson arrivals (seed 5) at a fixed rate of
+    qps_frac x the measured closed-loop capacity."""
+    graphs, dgs = [], []
+    t0 = time.perf_counter()
+    for i in range(16):
+        sc = 16 + (7 * i) // 16
+        g = gen.rmat(sc, seed=100 + i)
+        graphs.append(g)
+        dgs.append(gx.DeviceGraph(g, gx.GX_NEED_OUT | gx.GX_NEED_IN))
+    log(f"serving: 16 graphs ({sum(g.E for g in graphs)} edges) generated and loaded in "
+        f"{time.perf_counter() - t0:.1f}s")
+    rng = np.random.default_rng(5)
+    cands = [np.nonzero(np.diff(g.row_ptr) > 0)[0] for g in graphs]
+
+    def make(n):
+        qs = []
+        for i in range(n):
+            gi = int(rng.integers(0, 16))
+            qs.append((gi, gx.GX_SSSP if rng.random() < 0.5 else gx.GX_PPR, int(rng.choice(cands[gi]))))
+        return qs
+
+    budget = int(budget_gib * (1 << 30))
+
+    def run(qs, arrivals):
+        srv = gx.Server(budget, lanes_per_pool=lanes, max_pools=8, epoch_supersteps=4, ppr_iters=50)
+        ids = [srv.add_graph(d) for d in dgs]
+        done = []
+        t_start = time.perf_counter()
+        i = 0
+        while len(done) < len(qs):
+            now = time.perf_counter() - t_start
+            while i < len(qs) and arrivals[i] <= now:
+                gi, algo, s_ = qs[i]
+                srv.submit(ids[gi], algo, s_)
+                i += 1
+            for c in srv.poll(wait_ms=0 if i < len(qs) else 20):
+                assert c.status == 0
+                done.append(c)
+            if i < len(qs):
+                time.sleep(max(0.0, min(0.002, arrivals[i] - (time.perf_counter() - t_start))))
+        wall = time.perf_counter() - t_start
+        srv.close()
+        return done, wall
+
+    cap_q = make(512)
+    done, wall = run(cap_q, np.zeros(len(cap_q)))
+    capacity = len(cap_q) / wall
+    log(f"serving: closed-loop capacity {capacity:.1f} queries/s")
+    qps = qps_frac * capacity
+    qs = make(n_queries)
+    arrivals = np.cumsum(np.random.default_rng(5).exponential(1.0 / qps, n_queries))
+    done, wall = run(qs, arrivals)
+    lat = np.array([c.done_s - c.submit_s for c in done])
+    log(f"serving: {len(done)} queries at {qps:.1f} q/s offered -> {len(done) / wall:.1f} q/s, "
+        f"p50 {np.percentile(lat, 50) * 1e3:.1f} ms p99 {np.percentile(lat, 99) * 1e3:.1f} ms")
+    return {"workload": "16 resident R-MAT graphs, scales 16..22 (scale 16 + floor(7i/16), seeds 100..115, "
+                        "edge factor 16), queries 50% SSSP / 50% personalised PageRank (50 iterations), "
+                        "Poisson arrivals (seed 5)",
+            "queries": len(done), "offered_qps": qps, "closed_loop_capacity_qps": capacity,
+            "queries_per_s": len(done) / wall, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "hbm_budget_gib": budget_gib,
+            "lanes_per_pool": lanes}
+
+
+def bench_pagerank_small(gx, torch, np, gen, reps=20):
+    """PageRank, 20 supersteps, d = 0.85, R-MAT scale 14 (seed 1)."""
+    g = gen.rmat(14, seed=1)
+    dg = gx.DeviceGraph(g, gx.GX_NEED_IN)
+    st = gx.State(dg, gx.GX_PAGERANK, damping=0.85, timing=True)
+    st.run(20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kern = 0.0
+    for _ in range(reps):
+        st.reset()
+        rs, _ = st.run(20)
+        kern += rs.edge_kernel_ms
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    return {"workload": f"PageRank 20 supersteps, d=0.85, R-MAT scale 14 ({g.V} vertices, {g.E} edges, seed 1)",
+            "ms_per_run": dt * 1e3, "us_per_superstep": dt * 1e6 / 20, "gteps": 20 * g.E / dt / 1e9,
+            "pull_kernel_us_per_superstep": kern * 1e3 / reps / 20}
+
+
+def bench_partition(gx, torch, np, gen, reps=3):
+    """One part (1 of 8) of a hash vertex-cut of R-MAT scale 25 (seed 3):
+    30 PageRank supersteps and min-label CC to convergence."""
+    t0 = time.perf_counter()
+    p = gen.rmat_part(25, seed=3, part=0)
+    log(f"partition: V_p={p.V} E_p={p.E} generated in {time.perf_counter() - t0:.1f}s")
+    dg = gx.DeviceGraph(p, gx.GX_NEED_IN | gx.GX_NEED_SYM)
+    st = gx.State(dg, gx.GX_PAGERANK, damping=0.85, timing=True)
+    st.run(30)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kern = 0.0
+    for _ in range(reps):
+        st.reset()
+        rs, _ = st.run(30)
+        kern += rs.edge_kernel_ms
+    torch.cuda.synchronize()
+    t_pr = (time.perf_counter() - t0) / reps
+    pr_bytes = 30 * (4 * p.E + 20 * p.V)
+    cc = gx.State(dg, gx.GX_CC, timing=True)
+    cc.run(100_000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cc_edges = 0
+    for _ in range(reps):
+        cc.reset()
+        rs_cc, steps = cc.run(100_000, per_step=True, detail=True)
+        cc_edges += rs_cc.edges
+        gids, vals, skip = cc.sync_delta()
+    torch.cuda.synchronize()
+    t_cc = (time.perf_counter() - t0) / reps
+    return {"workload": f"part 0 of an 8-way hash vertex-cut of R-MAT scale 25 (seed 3): V_p={p.V}, E_p={p.E}; "
+                        "PageRank 30 supersteps + min-label CC to convergence + final sync set",
+            "pagerank_ms": t_pr * 1e3, "pagerank_gteps": 30 * p.E / t_pr / 1e9,
+            "pagerank_pull_roofline_frac": pr_bytes / (kern / reps / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "cc_ms": t_cc * 1e3, "cc_supersteps": int(rs_cc.supersteps), "cc_gteps": cc_edges / reps / t_cc / 1e9,
+            "sync_set_final": int(len(gids)),
+            "cc_per_superstep": [dict(edges=d["edges"], pulled=d["pulled"], us=round(d["kernel_ms"] * 1e3, 1))
+                                 for d in steps]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +255,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pull-fraction", type=float, default=0.0,
                     help="SSSP switch point to the pull form (0 = library default, >= 1 = push only)")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--partition", action="store_true", help="also run the scale-25 partition (PR 30 + CC)")
+    ap.add_argument("--no-pagerank", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-queries", type=int, default=2000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -204,6 +382,14 @@ def main():
                                    us=round(d["kernel_ms"] * 1e3, 1)) for p, d in zip(per_step, detail)],
         },
     }
+    if not args.no_pagerank:
+        out["pagerank_scale14"] = bench_pagerank_small(gx, torch, np, gen)
+    if args.partition:
+        out["partition_scale25"] = bench_partition(gx, torch, np, gen)
+    if not args.no_batched:
+        out["batched"] = bench_batched(gx, torch, np, gen)
+    if not args.no_serving:
+        out["serving"] = bench_serving(gx, torch, np, gen, n_queries=args.serving_queries)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(g, edges_per_solve)

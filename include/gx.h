@@ -164,18 +164,20 @@ gx_status gx_state_free(gx_state *s);
 
 /* Device pointer to the current vertex values (float32 or uint32, V entries). */
 gx_status gx_state_values(gx_state *s, void **dev_values);
-/* Device pointer to the current frontier bitmap (uint32 words, bit v%32 of
- * word v/32 = vertex v active in the next superstep); SSSP/CC only. */
+/* Device pointer to the current frontier as a byte map (uint8 per vertex,
+ * nonzero = vertex v is active in the next superstep); SSSP/CC only. */
 gx_status gx_state_frontier(gx_state *s, void **dev_bitmap);
 /* Supersteps executed since init. */
 gx_status gx_state_superstep(gx_state *s, int64_t *k);
 
 /*
  * requestGen() -> requestMerge() -> requestApply() in BSP order: one
- * superstep.  SSSP/CC: compact the frontier into an active list with
- * start-of-superstep snapshots, split the active out-edges into equal
- * tiles, relax by integer min, set next-frontier and dirty bits.  PageRank:
- * pull over the in-CSR in equal edge tiles with a fixed summation order.
+ * superstep.  SSSP/CC: relax the active list (built with start-of-superstep
+ * snapshots by the previous call or by gx_state_init) over equal tiles of
+ * active out-edges (push) or of all in-edges (pull, for large frontiers),
+ * merge by integer min, mark changed vertices in the next frontier and the
+ * dirty map, then compact the next frontier.  PageRank: pull over the
+ * in-CSR in equal edge tiles with a fixed summation order.
  * With stats == NULL the call is asynchronous; otherwise it synchronises
  * `stream` and fills *stats.
  */

@@ -256,11 +256,8 @@ class State:
         import torch
         p = ctypes.c_void_p()
         _check(lib.gx_state_frontier(self.handle, ctypes.byref(p)))
-        W = (self.graph.V + 31) // 32
         torch.cuda.synchronize(self.graph.device)
-        words = self._view(p.value, 4 * W).view(torch.int32).cpu().numpy().view(np.uint32)
-        bits = np.unpackbits(words.view(np.uint8), bitorder="little")
-        return bits[: self.graph.V].astype(bool)
+        return self._view(p.value, self.graph.V).cpu().numpy() != 0
 
     @property
     def superstep_index(self) -> int:

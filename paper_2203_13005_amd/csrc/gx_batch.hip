@@ -136,38 +136,72 @@ __device__ __forceinline__ void bs_relax(const BsArgs &a, uint32_t k, uint32_t i
         }
         __syncthreads();
         block_max_scan<VT>(sh.own, n, sh.red);
-        for (int p = tid >> 3; p < n; p += UNITS) {
-            const int j = sh.own[p];
-            const uint2 ed = a.adj[sh.base[j] + (uint32_t)p];
-            const uint32_t v = ed.x, w = ed.y, g = sh.g[j];
-            const uint32_t my4 = (sh.mask[j] >> (sub * 4)) & 15u;
-            uint32_t imp = 0;
-            if (my4) {
-                const uint4 sn = a.S[(size_t)(s0 + j) * 8 + sub];
-                uint32_t *dp = a.D + (size_t)v * a.B + a.l0 + g * 32 + sub * 4;
-                const uint4 cur = *reinterpret_cast<const uint4 *>(dp);
-                const uint32_t snv[4] = {sn.x, sn.y, sn.z, sn.w};
-                const uint32_t cv[4] = {cur.x, cur.y, cur.z, cur.w};
+        // UB work units per 8-thread group at a time: their edge loads, then
+        // their snapshot and destination loads, then the relaxations.
+        constexpr int UB = 4;
+        for (int p0 = tid >> 3; p0 < n; p0 += UNITS * UB) {
+            uint2 ed[UB];
+            uint32_t my4[UB], gq[UB], jq[UB];
 #pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    if (!((my4 >> q) & 1u)) continue;
-                    const uint32_t cand = sat_add(snv[q], w);
-                    if (cand < cv[q]) {
-                        uint32_t old = atomicMin(dp + q, cand);
-                        if (cand < old) imp |= 1u << q;
-                    }
+            for (int q = 0; q < UB; q++) {
+                const int p = p0 + q * UNITS;
+                ed[q] = make_uint2(0u, 0u);
+                my4[q] = 0u;
+                gq[q] = 0u;
+                jq[q] = 0u;
+                if (p < n) {
+                    const int j = sh.own[p];
+                    jq[q] = (uint32_t)j;
+                    gq[q] = sh.g[j];
+                    my4[q] = (sh.mask[j] >> (sub * 4)) & 15u;
+                    ed[q] = a.adj[sh.base[j] + (uint32_t)p];
                 }
             }
-            uint32_t word = imp << (sub * 4);
-            word |= __shfl_xor(word, 1, 8);
-            word |= __shfl_xor(word, 2, 8);
-            word |= __shfl_xor(word, 4, 8);
-            if (sub == 0 && word) {
-                uint32_t prev = atomicOr(&Mn[(size_t)v * a.G + g], word);
-                uint32_t nb = word & ~prev;
-                changed += __popc(nb);
-                if (a.lane_cnt)
-                    for (uint32_t mm = nb; mm; mm &= mm - 1) atomicAdd(&sh.lane[g * 32 + __ffs(mm) - 1], 1u);
+            uint4 sn[UB], cur[UB];
+#pragma unroll
+            for (int q = 0; q < UB; q++) {
+                if (my4[q]) {
+                    sn[q] = a.S[(size_t)(s0 + jq[q]) * 8 + sub];
+                    cur[q] = *reinterpret_cast<const uint4 *>(a.D + (size_t)ed[q].x * a.B + a.l0 + gq[q] * 32 +
+                                                              sub * 4);
+                } else {
+                    sn[q] = make_uint4(INF, INF, INF, INF);
+                    cur[q] = make_uint4(0u, 0u, 0u, 0u);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < UB; q++) {
+                const int p = p0 + q * UNITS;
+                uint32_t imp = 0;
+                if (my4[q]) {
+                    uint32_t *dp = a.D + (size_t)ed[q].x * a.B + a.l0 + gq[q] * 32 + sub * 4;
+                    const uint32_t snv[4] = {sn[q].x, sn[q].y, sn[q].z, sn[q].w};
+                    const uint32_t cv[4] = {cur[q].x, cur[q].y, cur[q].z, cur[q].w};
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        if (!((my4[q] >> r) & 1u)) continue;
+                        const uint32_t cand = sat_add(snv[r], ed[q].y);
+                        if (cand < cv[r]) {
+                            uint32_t old = atomicMin(dp + r, cand);
+                            if (cand < old) imp |= 1u << r;
+                        }
+                    }
+                }
+                if (p < n) {  // uniform within the 8-thread group
+                    uint32_t word = imp << (sub * 4);
+                    word |= __shfl_xor(word, 1, 8);
+                    word |= __shfl_xor(word, 2, 8);
+                    word |= __shfl_xor(word, 4, 8);
+                    if (sub == 0 && word) {
+                        const uint32_t v = ed[q].x, g = gq[q];
+                        uint32_t prev = atomicOr(&Mn[(size_t)v * a.G + g], word);
+                        uint32_t nb = word & ~prev;
+                        changed += __popc(nb);
+                        if (a.lane_cnt)
+                            for (uint32_t mm = nb; mm; mm &= mm - 1)
+                                atomicAdd(&sh.lane[g * 32 + __ffs(mm) - 1], 1u);
+                    }
+                }
             }
         }
         __syncthreads();
@@ -489,10 +523,14 @@ const void *bp_kernel(uint32_t B) {
     }
 }
 
+// Workgroups of a cooperative (grid-barrier) launch.  The occupancy query's
+// bound is not trusted to the last workgroup: at most 2 per CU and at most
+// half of the reported bound, so every workgroup is resident at once.
 int coop_grid(const void *kernel, int block, int num_cus, int want) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu <= 0)
         per_cu = 1;
+    per_cu = std::max(1, std::min(2, per_cu / 2));
     int cap = per_cu * num_cus;
     if (want > 0) return std::min(want, cap);
     return cap;

@@ -115,7 +115,7 @@ __device__ __forceinline__ bool grid_sync(GridBar *b, unsigned int nblocks, unsi
             unsigned long long polls = 0;
             while (__hip_atomic_load(&b->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
                 __builtin_amdgcn_s_sleep(2);
-                if (++polls > (1ull << 27)) {  // several seconds: give up, report, let every block leave
+                if (++polls > (1ull << 22)) {  // seconds: give up, report, let every block leave
                     atomicOr(&b->error, 1u);
                     break;
                 }

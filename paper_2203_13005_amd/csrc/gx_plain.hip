@@ -8,20 +8,26 @@
 // edge triplets of one iteration, Section "Pipeline Shuffling"), so the
 // frontier compaction stores a snapshot of every active vertex's value.
 //
-// SSSP / CC superstep k:
-//   k_compact : frontier bitmap F_k -> active list of (edge offset, CSR base,
-//               snapshot) for active vertices with out-edges; one 64-bit
-//               atomic per workgroup reserves list slots and edge offsets;
-//               every PUSH_TILE-edge tile records the entry where it starts.
-//               This replaces the paper's synchronisation skipping by a
-//               frontier (Section "Synchronization Skipping") and its
-//               fixed-size edge blocks (Section "Data Flows & Management")
-//               by equal edge tiles over the active out-edges (the balanced
-//               objective of Section "Workload Balancing").
+// SSSP / CC superstep k (A_k = vertices active in superstep k):
 //   k_push    : every workgroup tile relaxes exactly PUSH_TILE active
 //               out-edges: Gen = snapshot (+ weight), Merge + Apply =
-//               integer atomicMin on the destination; an improvement sets
-//               the next-frontier bit and the dirty bit.
+//               integer atomicMin on the destination; an improvement marks
+//               the destination in the next frontier and the dirty map
+//               (plain, idempotent byte stores).
+//   k_pull    : for large frontiers instead: equal tiles over all in-edges,
+//               min per destination row in LDS, atomics only for rows that
+//               cross a tile boundary.  The device picks push or pull from
+//               the frontier's out-edge count; no host round trip.
+//   k_compact : frontier byte map A_{k+1} -> active list of (edge offset,
+//               CSR base, snapshot) for active vertices with out-edges; one
+//               64-bit atomic per workgroup reserves list slots and edge
+//               offsets; every PUSH_TILE-edge tile records the entry where it
+//               starts; |A_{k+1}| is the count of vertices superstep k changed.
+//               The frontier stands in for the paper's synchronisation
+//               skipping (Section "Synchronization Skipping") and the equal
+//               edge tiles for its fixed-size edge blocks (Section "Data Flows
+//               & Management") under the balanced objective of Section
+//               "Workload Balancing".
 // PageRank superstep:
 //   k_pr_pull : equal in-edge tiles; contributions are gathered into LDS and
 //               summed per destination row in a fixed order; rows that
@@ -47,8 +53,8 @@ struct gx_state {
     int push_grid = 0;
     // SSSP / CC
     uint32_t *val = nullptr;
-    uint32_t *front[2] = {nullptr, nullptr};
-    uint32_t *dirty = nullptr;
+    uint8_t *front8[2] = {nullptr, nullptr};  // frontier byte maps: A_k lives in front8[k & 1]
+    uint8_t *dirty8 = nullptr;                // changed since the last sync (byte per vertex)
     uint4 *list = nullptr;
     uint32_t *tile_start = nullptr;
     uint32_t *snap = nullptr;      // start-of-superstep values of active vertices (pull)
@@ -89,67 +95,54 @@ namespace {
 
 // ------------------------------------------------------------ SSSP / CC
 
-__global__ __launch_bounds__(256) void k_min_init(uint32_t *val, uint32_t *f0, uint32_t *f1, uint32_t *dirty,
-                                                  const int32_t *l2g, const int32_t *rp, int64_t V, int32_t W,
-                                                  int32_t algo, int32_t source, DevStep *step0) {
+__global__ __launch_bounds__(256) void k_min_init(uint32_t *val, uint8_t *f0, uint8_t *f1, uint8_t *dirty,
+                                                  const int32_t *l2g, const int32_t *rp, int64_t V, int32_t algo,
+                                                  int32_t source, DevStep *step0) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) *step0 = DevStep{0, 0, 0, 0};
-    if (i < W) {
-        uint32_t word = 0;
+    if (i < V) {
+        uint32_t x;
+        uint8_t f;
         if (algo == GX_CC) {
-            for (int b = 0; b < 32; b++) {
-                int64_t v = i * 32 + b;
-                if (v < V && rp[v + 1] > rp[v]) word |= 1u << b;
-            }
-        } else if (source >= 0 && (source >> 5) == i) {
-            word = 1u << (source & 31);
+            x = l2g ? (uint32_t)l2g[i] : (uint32_t)i;
+            f = rp[i + 1] > rp[i];
+        } else {
+            x = (i == source) ? 0u : INF;
+            f = i == source;
         }
-        f0[i] = word;
+        val[i] = x;
+        f0[i] = f;
         f1[i] = 0;
         dirty[i] = 0;
     }
-    if (i < V) {
-        uint32_t x;
-        if (algo == GX_CC) x = l2g ? (uint32_t)l2g[i] : (uint32_t)i;
-        else x = (i == source) ? 0u : INF;
-        val[i] = x;
-    }
 }
 
-// Frontier bitmap -> active list, one thread per vertex (256 vertices = 8
-// bitmap words per workgroup; a workgroup whose words are all zero leaves at
-// once).  Active vertices with out-edges get a list entry (edge offset, CSR
-// base, snapshot) in one 64-bit atomic per workgroup; the tiles that start
-// inside an entry's edges record it.  The workgroup also clears its words of
-// the bitmap this superstep's relaxation fills (it held F_{k-1}) and stores
-// the snapshot of its active vertices for the pull.
-__global__ __launch_bounds__(256) void k_compact(const uint32_t *__restrict__ front, uint32_t *__restrict__ front_clear,
+// Frontier byte map -> active list, one thread per vertex, 256 vertices per
+// workgroup (a workgroup without an active vertex leaves at once).  Active
+// vertices with out-edges get a list entry (edge offset, CSR base, snapshot)
+// in one 64-bit atomic per workgroup; the tiles that start inside an entry's
+// edges record it.  It also clears the byte map the next relaxation fills (it
+// held A_{k-1}), stores the snapshot of active vertices for the pull, and
+// counts |A_k|, which is also the number of vertices the previous superstep
+// changed.
+__global__ __launch_bounds__(256) void k_compact(const uint8_t *__restrict__ front, uint8_t *__restrict__ front_clear,
                                                  const int32_t *__restrict__ rp, const uint32_t *__restrict__ val,
-                                                 uint32_t *__restrict__ snap, int64_t V, int32_t W,
+                                                 uint32_t *__restrict__ snap, int64_t V,
                                                  uint4 *__restrict__ list, uint32_t *__restrict__ tile_start,
-                                                 DevStep *__restrict__ step, DevStep *__restrict__ next_step) {
+                                                 DevStep *__restrict__ step, DevStep *__restrict__ prev_step,
+                                                 DevStep *__restrict__ next_step) {
     __shared__ unsigned long long s_scan[4];
     __shared__ unsigned long long s_base;
-    __shared__ uint32_t s_words[8];
     __shared__ int s_nf[4];
     const int tid = threadIdx.x;
-    const int32_t w0 = blockIdx.x * 8;
     if (blockIdx.x == 0 && tid == 0) *next_step = DevStep{0, 0, 0, 0};
-    if (tid < 8) {
-        const int32_t wi = w0 + tid;
-        uint32_t word = 0u;
-        if (wi < W) {
-            word = front[wi];
-            front_clear[wi] = 0u;
-        }
-        s_words[tid] = word;
+    const int64_t u = (int64_t)blockIdx.x * 256 + tid;
+    bool act = false;
+    if (u < V) {
+        act = front[u] != 0;
+        front_clear[u] = 0;
     }
-    __syncthreads();
-    const uint32_t any = s_words[0] | s_words[1] | s_words[2] | s_words[3] | s_words[4] | s_words[5] | s_words[6] |
-                         s_words[7];
-    if (!any) return;  // uniform: every thread read the same words
-    const int64_t u = (int64_t)w0 * 32 + tid;
-    const bool act = u < V && ((s_words[tid >> 5] >> (tid & 31)) & 1u);
+    if (!__syncthreads_or(act)) return;
     int32_t r0 = 0, d = 0;
     if (act) {
         r0 = rp[u];
@@ -165,8 +158,9 @@ __global__ __launch_bounds__(256) void k_compact(const uint32_t *__restrict__ fr
     if (tid == 0) s_base = total ? atomicAdd(&step->list, total) : 0ull;
     __syncthreads();
     if (tid == 0) {
-        const int t = s_nf[0] + s_nf[1] + s_nf[2] + s_nf[3];
-        if (t) atomicAdd(&step->frontier, (unsigned long long)t);
+        const unsigned long long t = s_nf[0] + s_nf[1] + s_nf[2] + s_nf[3];
+        atomicAdd(&step->frontier, t);
+        if (prev_step) atomicAdd(&prev_step->changed, t);
     }
     if (!has) return;
     const unsigned long long pos = s_base + pre;
@@ -184,19 +178,17 @@ template <bool WEIGHTED>
 __global__ __launch_bounds__(PUSH_BLOCK) void k_push(const uint4 *__restrict__ list,
                                                      const uint32_t *__restrict__ tile_start,
                                                      const void *__restrict__ adj, uint32_t *__restrict__ val,
-                                                     uint32_t *__restrict__ front_next, uint32_t *__restrict__ dirty,
-                                                     DevStep *__restrict__ step, uint32_t pull_edges) {
+                                                     uint8_t *__restrict__ front_next, uint8_t *__restrict__ dirty,
+                                                     const DevStep *__restrict__ step, uint32_t pull_edges) {
     __shared__ uint32_t s_base[PUSH_TILE + 1];
     __shared__ uint32_t s_snap[PUSH_TILE + 1];
     __shared__ int32_t s_own[PUSH_TILE];
     __shared__ int32_t s_red[4];
-    __shared__ unsigned long long s_cnt[4];
     const int tid = threadIdx.x;
     const unsigned long long le = step->list;
     const uint32_t L = (uint32_t)(le >> 32), EF = (uint32_t)le;
     if (EF >= pull_edges) return;  // this superstep pulls
     const uint32_t ntiles = (EF + PUSH_TILE - 1) / PUSH_TILE;
-    unsigned long long changed = 0;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const uint32_t e0 = t * PUSH_TILE;
         const int n = (int)min((uint32_t)PUSH_TILE, EF - e0);
@@ -214,45 +206,41 @@ __global__ __launch_bounds__(PUSH_BLOCK) void k_push(const uint4 *__restrict__ l
         }
         __syncthreads();
         block_max_scan<PUSH_VT>(s_own, n, s_red);
-        for (int p = tid; p < n; p += PUSH_BLOCK) {
-            const int j = s_own[p];
-            const uint32_t idx = s_base[j] + (uint32_t)p;
-            uint32_t dst, cand;
-            if (WEIGHTED) {
-                uint2 a = static_cast<const uint2 *>(adj)[idx];
-                dst = a.x;
-                cand = sat_add(s_snap[j], a.y);
-            } else {
-                dst = (uint32_t) static_cast<const int32_t *>(adj)[idx];
-                cand = s_snap[j];
+        // Batched memory access: all edge loads of this thread first, then all
+        // destination reads, then the relaxations (no load waits on another
+        // edge's atomic).
+        uint32_t dst[PUSH_VT], cand[PUSH_VT], cur[PUSH_VT];
+#pragma unroll
+        for (int i = 0; i < PUSH_VT; i++) {
+            const int p = tid + i * PUSH_BLOCK;
+            dst[i] = 0u;
+            cand[i] = INF;
+            if (p < n) {
+                const int j = s_own[p];
+                const uint32_t idx = s_base[j] + (uint32_t)p;
+                if (WEIGHTED) {
+                    const uint2 a = static_cast<const uint2 *>(adj)[idx];
+                    dst[i] = a.x;
+                    cand[i] = sat_add(s_snap[j], a.y);
+                } else {
+                    dst[i] = (uint32_t) static_cast<const int32_t *>(adj)[idx];
+                    cand[i] = s_snap[j];
+                }
             }
-            if (cand < val[dst]) {
-                uint32_t old = atomicMin(&val[dst], cand);
-                if (cand < old) {
-                    const uint32_t bit = 1u << (dst & 31);
-                    uint32_t prev = atomicOr(&front_next[dst >> 5], bit);
-                    if (!(prev & bit)) {
-                        changed++;
-                        atomicOr(&dirty[dst >> 5], bit);
-                    }
+        }
+#pragma unroll
+        for (int i = 0; i < PUSH_VT; i++) cur[i] = cand[i] != INF ? val[dst[i]] : 0u;
+#pragma unroll
+        for (int i = 0; i < PUSH_VT; i++) {
+            if (cand[i] < cur[i]) {
+                const uint32_t old = atomicMin(&val[dst[i]], cand[i]);
+                if (cand[i] < old) {  // improved in this superstep: idempotent plain stores
+                    front_next[dst[i]] = 1;
+                    dirty[dst[i]] = 1;
                 }
             }
         }
         __syncthreads();
-    }
-    unsigned long long tot = block_sum<unsigned long long>(changed, s_cnt);
-    if (tid == 0 && tot) atomicAdd(&step->changed, tot);
-}
-
-// Marks v as changed in this superstep: next-frontier bit and dirty bit;
-// counts it once.
-__device__ __forceinline__ void mark_changed(uint32_t v, uint32_t *front_next, uint32_t *dirty,
-                                             unsigned long long &changed) {
-    const uint32_t bit = 1u << (v & 31);
-    uint32_t prev = atomicOr(&front_next[v >> 5], bit);
-    if (!(prev & bit)) {
-        changed++;
-        atomicOr(&dirty[v >> 5], bit);
     }
 }
 
@@ -267,37 +255,51 @@ __device__ __forceinline__ void mark_changed(uint32_t v, uint32_t *front_next, u
 template <bool WEIGHTED>
 __global__ __launch_bounds__(PR_BLOCK) void k_pull(const int32_t *__restrict__ rp, const void *__restrict__ adj,
                                                    const int32_t *__restrict__ tile_row, int32_t ntiles, int64_t E,
-                                                   const uint32_t *__restrict__ front_cur,
+                                                   const uint8_t *__restrict__ front_cur,
                                                    const uint32_t *__restrict__ snap, uint32_t *__restrict__ val,
-                                                   uint32_t *__restrict__ front_next, uint32_t *__restrict__ dirty,
+                                                   uint8_t *__restrict__ front_next, uint8_t *__restrict__ dirty,
                                                    DevStep *__restrict__ step, uint32_t pull_edges) {
     __shared__ uint32_t s_val[PR_TILE];
     __shared__ int32_t s_own[PR_TILE];
     __shared__ uint32_t s_last[PR_BLOCK];
     __shared__ int32_t s_last_start[PR_BLOCK];
     __shared__ int32_t s_red[4];
-    __shared__ unsigned long long s_c[4];
     const uint32_t EF = (uint32_t)step->list;
     if (EF < pull_edges) return;
     const int tid = threadIdx.x;
     if (blockIdx.x == 0 && tid == 0) step->pad = 1;
-    unsigned long long changed = 0;
     for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int64_t e0 = (int64_t)t * PR_TILE;
         const int n = (int)max((int64_t)0, min((int64_t)PR_TILE, E - e0));
         const int32_t r_lo = tile_row[t], r_hi = tile_row[t + 1];
-        for (int p = tid; p < n; p += PR_BLOCK) {
-            uint32_t u, w = 0, m = INF;
-            if (WEIGHTED) {
-                uint2 a = static_cast<const uint2 *>(adj)[e0 + p];
-                u = a.x;
-                w = a.y;
-            } else {
-                u = (uint32_t) static_cast<const int32_t *>(adj)[e0 + p];
+        {  // messages into LDS: edge loads, then frontier bytes, then snapshots
+            uint32_t u[PR_VT], w[PR_VT], f[PR_VT];
+#pragma unroll
+            for (int i = 0; i < PR_VT; i++) {
+                const int p = tid + i * PR_BLOCK;
+                u[i] = 0u;
+                w[i] = 0u;
+                if (p < n) {
+                    if (WEIGHTED) {
+                        const uint2 a = static_cast<const uint2 *>(adj)[e0 + p];
+                        u[i] = a.x;
+                        w[i] = a.y;
+                    } else {
+                        u[i] = (uint32_t) static_cast<const int32_t *>(adj)[e0 + p];
+                    }
+                }
             }
-            if ((front_cur[u >> 5] >> (u & 31)) & 1u) m = WEIGHTED ? sat_add(snap[u], w) : snap[u];
-            s_val[p] = m;
-            s_own[p] = 0;
+#pragma unroll
+            for (int i = 0; i < PR_VT; i++) f[i] = (tid + i * PR_BLOCK < n) ? front_cur[u[i]] : 0u;
+#pragma unroll
+            for (int i = 0; i < PR_VT; i++) {
+                const int p = tid + i * PR_BLOCK;
+                if (p >= n) continue;
+                uint32_t m = INF;
+                if (f[i]) m = WEIGHTED ? sat_add(snap[u[i]], w[i]) : snap[u[i]];
+                s_val[p] = m;
+                s_own[p] = 0;
+            }
         }
         __syncthreads();
         for (int32_t r = r_lo + tid; r < r_hi; r += PR_BLOCK) {
@@ -318,7 +320,10 @@ __global__ __launch_bounds__(PR_BLOCK) void k_pull(const int32_t *__restrict__ r
                 old = val[r];
                 if (m < old) val[r] = m;
             }
-            if (m < old) mark_changed((uint32_t)r, front_next, dirty, changed);
+            if (m < old) {
+                front_next[r] = 1;
+                dirty[r] = 1;
+            }
         };
         const int c0 = tid * PR_VT, c1 = min(c0 + PR_VT, n);
         int own = -1, first_own = -1;
@@ -370,8 +375,6 @@ __global__ __launch_bounds__(PR_BLOCK) void k_pull(const int32_t *__restrict__ r
         }
         __syncthreads();
     }
-    unsigned long long tot = block_sum<unsigned long long>(changed, s_c);
-    if (tid == 0 && tot) atomicAdd(&step->changed, tot);
 }
 
 // ------------------------------------------------------------ PageRank
@@ -440,9 +443,21 @@ __global__ __launch_bounds__(PR_BLOCK) void k_pr_pull(const int32_t *__restrict_
     const int32_t r_lo = tile_row[t], r_hi = tile_row[t + 1];
     ap.dD = ap.d * (*Dp) * inv_V;
     if (tid == 0) spill_row[t] = -1;
-    for (int p = tid; p < n; p += PR_BLOCK) {
-        s_val[p] = c_in[in_col[e0 + p]];
-        s_own[p] = 0;
+    {  // contributions into LDS: source ids first, then the gathers
+        int32_t u[PR_VT];
+#pragma unroll
+        for (int i = 0; i < PR_VT; i++) {
+            const int p = tid + i * PR_BLOCK;
+            u[i] = p < n ? in_col[e0 + p] : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < PR_VT; i++) {
+            const int p = tid + i * PR_BLOCK;
+            if (p < n) {
+                s_val[p] = c_in[u[i]];
+                s_own[p] = 0;
+            }
+        }
     }
     __syncthreads();
     for (int32_t r = r_lo + tid; r < r_hi; r += PR_BLOCK) {
@@ -566,12 +581,22 @@ __global__ __launch_bounds__(1024) void k_pr_fix(const int32_t *__restrict__ in_
 // ------------------------------------------------------------ sync set
 
 __device__ __forceinline__ uint32_t delta_word(int32_t w, int64_t V, const uint32_t *remote, bool all,
-                                               const uint32_t *dirty, const uint32_t *vals,
+                                               const uint8_t *dirty, const uint32_t *vals,
                                                const uint32_t *synced) {
     uint32_t valid = (int64_t)(w + 1) * 32 <= V ? 0xFFFFFFFFu : ((1u << (V - (int64_t)w * 32)) - 1u);
     uint32_t mask = (all ? 0xFFFFFFFFu : (remote ? remote[w] : 0u)) & valid;
     if (!mask) return 0;
-    if (dirty) return dirty[w] & mask;
+    if (dirty) {
+        uint32_t bits = 0;
+        const uint32_t *d4 = reinterpret_cast<const uint32_t *>(dirty + (int64_t)w * 32);
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            const uint32_t x = d4[q];
+            bits |= (uint32_t)((x & 0xFFu) != 0) << (4 * q) | (uint32_t)((x & 0xFF00u) != 0) << (4 * q + 1) |
+                    (uint32_t)((x & 0xFF0000u) != 0) << (4 * q + 2) | (uint32_t)((x & 0xFF000000u) != 0) << (4 * q + 3);
+        }
+        return bits & mask;
+    }
     uint32_t out = 0;
     for (uint32_t m = mask; m; m &= m - 1) {
         int b = __ffs(m) - 1;
@@ -582,7 +607,7 @@ __device__ __forceinline__ uint32_t delta_word(int32_t w, int64_t V, const uint3
 }
 
 __global__ __launch_bounds__(256) void k_delta_count(int32_t W, int64_t V, const uint32_t *remote, int all,
-                                                     const uint32_t *dirty, const uint32_t *vals,
+                                                     const uint8_t *dirty, const uint32_t *vals,
                                                      const uint32_t *synced, uint32_t *blk_cnt) {
     __shared__ unsigned long long s[4];
     int32_t w = blockIdx.x * blockDim.x + threadIdx.x;
@@ -592,7 +617,7 @@ __global__ __launch_bounds__(256) void k_delta_count(int32_t W, int64_t V, const
 }
 
 __global__ __launch_bounds__(256) void k_delta_emit(int32_t W, int64_t V, const uint32_t *remote, int all,
-                                                    uint32_t *dirty, const uint32_t *vals, uint32_t *synced,
+                                                    uint8_t *dirty, const uint32_t *vals, uint32_t *synced,
                                                     const int32_t *l2g, const uint32_t *__restrict__ blk_cnt,
                                                     int nblk, uint32_t cap, int32_t *gid_out, uint32_t *val_out,
                                                     uint32_t *total_out) {
@@ -637,7 +662,11 @@ __global__ __launch_bounds__(256) void k_delta_emit(int32_t W, int64_t V, const 
         pos++;
         if (commit && synced) synced[v] = vals[v];
     }
-    if (commit && dirty && w < W) dirty[w] = 0u;
+    if (commit && dirty && w < W) {  // the dirty bytes of this word's vertices are cleared
+        uint32_t *d4 = reinterpret_cast<uint32_t *>(dirty + (int64_t)w * 32);
+#pragma unroll
+        for (int q = 0; q < 8; q++) d4[q] = 0u;
+    }
 }
 
 template <class T>
@@ -676,9 +705,10 @@ static size_t state_layout(gx_graph *g, const gx_params *p, Carver &c, gx_state 
     } else {
         int64_t Eimg = p->algo == GX_SSSP ? d.E : d.E_sym;
         s->val = c.take<uint32_t>(V);
-        s->front[0] = c.take<uint32_t>(W);
-        s->front[1] = c.take<uint32_t>(W);
-        s->dirty = c.take<uint32_t>(W);
+        // byte maps padded to whole 32-vertex words (the sync set reads 32 at a time)
+        s->front8[0] = c.take<uint8_t>((size_t)W * 32);
+        s->front8[1] = c.take<uint8_t>((size_t)W * 32);
+        s->dirty8 = c.take<uint8_t>((size_t)W * 32);
         s->list = c.take<uint4>(V);
         s->tile_start = c.take<uint32_t>(Eimg / PUSH_TILE + 2);
         s->snap = c.take<uint32_t>(V);
@@ -762,8 +792,20 @@ extern "C" gx_status gx_state_init(gx_graph *g, const gx_params *p, void *dev_st
     } else {
         int64_t n = std::max<int64_t>(V, d.W);
         const int32_t *rp = p->algo == GX_CC ? d.sym_rp : d.out_rp;
-        hipLaunchKernelGGL(k_min_init, dim3(grid_for<int64_t>(n, 256)), dim3(256), 0, hs, s->val, s->front[0],
-                           s->front[1], s->dirty, d.l2g, rp, V, d.W, p->algo, p->source, s->steps);
+        // (padding bytes of the maps beyond V are cleared too)
+        hipLaunchKernelGGL(k_min_init, dim3(grid_for<int64_t>(n, 256)), dim3(256), 0, hs, s->val, s->front8[0],
+                           s->front8[1], s->dirty8, d.l2g, rp, V, p->algo, p->source, s->steps);
+        if ((int64_t)d.W * 32 > V) {
+            size_t pad = (size_t)d.W * 32 - (size_t)V;
+            (void)hipMemsetAsync(s->front8[0] + V, 0, pad, hs);
+            (void)hipMemsetAsync(s->front8[1] + V, 0, pad, hs);
+            (void)hipMemsetAsync(s->dirty8 + V, 0, pad, hs);
+        }
+        // compaction of superstep 0 (each superstep then relaxes and compacts the next)
+        if (V > 0)
+            hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(V, 256)), dim3(256), 0, hs, s->front8[0], s->front8[1],
+                               rp, s->val, s->snap, V, s->list, s->tile_start, s->steps, (DevStep *)nullptr,
+                               s->steps + 1);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
@@ -792,7 +834,7 @@ extern "C" gx_status gx_state_frontier(gx_state *s, void **dev_bitmap) {
     clear_error();
     GX_REQUIRE(s && dev_bitmap, GX_EINVAL, "NULL argument");
     GX_REQUIRE(s->p.algo != GX_PAGERANK, GX_EINVAL, "PageRank has no frontier");
-    *dev_bitmap = s->front[s->k & 1];
+    *dev_bitmap = s->front8[s->k & 1];
     return GX_OK;
 }
 
@@ -840,30 +882,35 @@ static gx_status enqueue_superstep(gx_state *s, hipStream_t hs) {
                                s->spill_row, s->dpart, ap, s->Dval, inv_V, step, next);
         }
     } else {
-        int cur = (int)(s->k & 1);
+        // superstep k: relax A_k (list built by the previous compaction), then
+        // compact A_{k+1} for superstep k+1
+        const int cur = (int)(s->k & 1);
         const bool cc = p.algo == GX_CC;
         const int32_t *rp = cc ? d.sym_rp : d.out_rp;
-        if (d.W > 0) {
-            hipLaunchKernelGGL(k_compact, dim3(grid_for<int32_t>(d.W, 8)), dim3(256), 0, hs, s->front[cur],
-                               s->front[cur ^ 1], rp, s->val, s->snap, d.V, d.W, s->list, s->tile_start, step, next);
+        DevStep *next2 = s->steps + ((s->k + 2) % STEP_RING);
+        if (d.V > 0) {
             if (e0) (void)hipEventRecord(e0, hs);
             if (!cc) {
                 hipLaunchKernelGGL(k_push<true>, dim3(s->push_grid), dim3(PUSH_BLOCK), 0, hs, s->list, s->tile_start,
-                                   (const void *)d.out_adj, s->val, s->front[cur ^ 1], s->dirty, step, s->pull_edges);
-                if (s->pull_edges != 0xFFFFFFFFu)
-                    hipLaunchKernelGGL(k_pull<true>, dim3(s->pull_grid), dim3(PR_BLOCK), 0, hs, d.in_rp,
-                                       (const void *)d.in_adj, d.pr_tile_row, d.pr_ntiles, d.E, s->front[cur],
-                                       s->snap, s->val, s->front[cur ^ 1], s->dirty, step, s->pull_edges);
-            } else {
-                hipLaunchKernelGGL(k_push<false>, dim3(s->push_grid), dim3(PUSH_BLOCK), 0, hs, s->list,
-                                   s->tile_start, (const void *)d.sym_col, s->val, s->front[cur ^ 1], s->dirty, step,
+                                   (const void *)d.out_adj, s->val, s->front8[cur ^ 1], s->dirty8, step,
                                    s->pull_edges);
                 if (s->pull_edges != 0xFFFFFFFFu)
+                    hipLaunchKernelGGL(k_pull<true>, dim3(s->pull_grid), dim3(PR_BLOCK), 0, hs, d.in_rp,
+                                       (const void *)d.in_adj, d.pr_tile_row, d.pr_ntiles, d.E, s->front8[cur],
+                                       s->snap, s->val, s->front8[cur ^ 1], s->dirty8, step, s->pull_edges);
+            } else {
+                hipLaunchKernelGGL(k_push<false>, dim3(s->push_grid), dim3(PUSH_BLOCK), 0, hs, s->list,
+                                   s->tile_start, (const void *)d.sym_col, s->val, s->front8[cur ^ 1], s->dirty8,
+                                   step, s->pull_edges);
+                if (s->pull_edges != 0xFFFFFFFFu)
                     hipLaunchKernelGGL(k_pull<false>, dim3(s->pull_grid), dim3(PR_BLOCK), 0, hs, d.sym_rp,
-                                       (const void *)d.sym_col, d.sym_tile_row, d.sym_ntiles, d.E_sym, s->front[cur],
-                                       s->snap, s->val, s->front[cur ^ 1], s->dirty, step, s->pull_edges);
+                                       (const void *)d.sym_col, d.sym_tile_row, d.sym_ntiles, d.E_sym,
+                                       s->front8[cur], s->snap, s->val, s->front8[cur ^ 1], s->dirty8, step,
+                                       s->pull_edges);
             }
             if (e1) (void)hipEventRecord(e1, hs);
+            hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(d.V, 256)), dim3(256), 0, hs, s->front8[cur ^ 1],
+                               s->front8[cur], rp, s->val, s->snap, d.V, s->list, s->tile_start, next, step, next2);
         }
     }
     hipError_t e = hipGetLastError();
@@ -1019,7 +1066,7 @@ extern "C" gx_status gx_sync_delta(gx_state *s, int32_t *dev_gid, uint32_t *dev_
     const uint32_t *remote = s->p.algo == GX_CC ? d.remote_any : d.remote_out;
     bool pr = s->p.algo == GX_PAGERANK;
     const uint32_t *vals = pr ? reinterpret_cast<const uint32_t *>(s->x[s->k & 1]) : s->val;
-    uint32_t *dirty = pr ? nullptr : s->dirty;
+    uint8_t *dirty = pr ? nullptr : s->dirty8;
     uint32_t *synced = pr ? s->synced : nullptr;
     hipLaunchKernelGGL(k_delta_count, dim3(s->delta_blocks), dim3(256), 0, hs, d.W, d.V, remote, (int)all, dirty,
                        vals, synced, s->blk_cnt);

@@ -90,3 +90,27 @@ def test_null_handles_are_einval():
     n = ctypes.c_uint32()
     assert b.lib.gx_sync_delta(None, None, None, 0, ctypes.byref(n), None, None) == b.GX_EINVAL
     assert b.lib.gx_version().startswith(b"gx")
+
+
+def test_server_config_validation_on_host():
+    from paper_2203_13005_amd import binding as b
+    h = ctypes.c_void_p()
+    cfg = b._ServerConfig(None, 0, 0, 0, 0, 0.0, 0)
+    assert b.lib.gx_server_create(ctypes.byref(cfg), ctypes.byref(h)) == b.GX_EINVAL  # no arena
+    cfg = b._ServerConfig(ctypes.c_void_p(1 << 20), 1 << 20, 48, 0, 0, 0.0, 0)  # lanes not a multiple of 32
+    assert b.lib.gx_server_create(ctypes.byref(cfg), ctypes.byref(h)) == b.GX_EINVAL
+    cfg = b._ServerConfig(ctypes.c_void_p(1 << 20), 1 << 20, 64, 0, 65, 0.0, 0)  # epoch too long
+    assert b.lib.gx_server_create(ctypes.byref(cfg), ctypes.byref(h)) == b.GX_EINVAL
+    cfg = b._ServerConfig(ctypes.c_void_p(1 << 20), 1 << 20, 64, 0, 0, 1.5, 0)  # damping out of range
+    assert b.lib.gx_server_create(ctypes.byref(cfg), ctypes.byref(h)) == b.GX_EINVAL
+    n = ctypes.c_uint32()
+    assert b.lib.gx_server_poll(None, None, 0, ctypes.byref(n), 0) == b.GX_EINVAL
+    qid = ctypes.c_int64()
+    assert b.lib.gx_server_submit(None, 0, 1, 0, None, ctypes.byref(qid)) == b.GX_EINVAL
+
+
+def test_batch_and_server_null_graph():
+    from paper_2203_13005_amd import binding as b
+    n = ctypes.c_size_t()
+    assert b.lib.gx_batch_bytes(None, b.GX_SSSP, 32, ctypes.byref(n)) == b.GX_EINVAL
+    assert b.lib.gx_server_bytes_per_lane(None, b.GX_SSSP, ctypes.byref(n)) == b.GX_EINVAL

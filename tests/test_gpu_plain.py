@@ -338,3 +338,30 @@ def test_sssp_full_scale22_source0(gx, mode):
     steps = np.array(steps)
     assert np.array_equal(steps[:, 1], ref.msgs)
     assert np.array_equal(steps[:, 2], ref.changed)
+
+
+@pytest.mark.slow
+def test_partition_scale25_pagerank30_and_cc(gx):
+    """One worker's part (1 of 8) of a hash vertex-cut of R-MAT scale 25:
+    30 PageRank supersteps and label-propagation CC to convergence, with the
+    sync set of the final CC state checked against the oracle's."""
+    p = gen.rmat_part(25, seed=3, part=0)
+    dg = load(gx, p, gx.GX_NEED_IN | gx.GX_NEED_SYM)
+    ref = oracle.pagerank(p, 30, 0.85)
+    st = gx.State(dg, gx.GX_PAGERANK, damping=0.85)
+    st.run(30)
+    x = st.values_numpy().astype(np.float64)
+    assert np.max(np.abs(x - ref)) <= PR_TOL
+    assert np.max(np.abs(x - ref) / ref) < 1e-4
+    del st
+    ref_cc = oracle.cc(p)
+    st = gx.State(dg, gx.GX_CC)
+    rs, steps = st.run(100_000, per_step=True)
+    assert rs.supersteps == ref_cc.K
+    assert np.array_equal(st.values_numpy(), ref_cc.state)
+    assert np.array_equal(np.array(steps)[:, 2], ref_cc.changed)
+    rem = oracle.remote_mask(p, "cc")
+    synced = p.l2g.astype(np.uint32).copy()
+    rg, rv, _ = oracle.delta(p, rem, ref_cc.state, synced)
+    gids, vals, skip = st.sync_delta()
+    assert np.array_equal(gids, rg) and np.array_equal(vals, rv) and not skip

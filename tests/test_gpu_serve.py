@@ -1,0 +1,119 @@
+"""Serving loop on MI355X: queries over several resident graphs, admitted as
+lanes free up, must each match the oracle and match their own result when
+run alone."""
+import time
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2203_13005_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def graphs():
+    return [gen.rmat(10, seed=100), gen.rmat(11, seed=101), gen.rmat(12, seed=102)]
+
+
+def serve(gx, graphs, queries, budget=1 << 30, lanes=32, epoch=3, stagger_s=0.0):
+    dgs = [gx.DeviceGraph(g, gx.GX_NEED_OUT | gx.GX_NEED_IN) for g in graphs]
+    srv = gx.Server(budget, lanes_per_pool=lanes, max_pools=4, epoch_supersteps=epoch, ppr_iters=50)
+    ids = [srv.add_graph(d) for d in dgs]
+    qids = {}
+    for i, (gi, algo, s) in enumerate(queries):
+        qids[srv.submit(ids[gi], algo, s)] = i
+        if stagger_s:
+            time.sleep(stagger_s)
+    done = {}
+    t0 = time.time()
+    while len(done) < len(queries):
+        for c in srv.poll(wait_ms=50):
+            assert c.status == 0
+            done[qids[c.id]] = c
+        assert time.time() - t0 < 120, "serving did not finish"
+    srv.close()
+    return done
+
+
+def mixed_queries(graphs, n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        gi = int(rng.integers(0, len(graphs)))
+        g = graphs[gi]
+        cand = np.nonzero(np.diff(g.row_ptr) > 0)[0]
+        algo = 1 if i % 2 == 0 else 3  # GX_SSSP / GX_PPR
+        out.append((gi, algo, int(rng.choice(cand))))
+    return out
+
+
+def check(gx, graphs, q, c):
+    gi, algo, s = q
+    g = graphs[gi]
+    if algo == gx.GX_SSSP:
+        ref = oracle.sssp(g, s)
+        assert np.array_equal(c.result, ref.state)
+        assert c.supersteps == ref.K
+    else:
+        ref = oracle.ppr(g, s, 50)
+        assert np.max(np.abs(c.result.astype(np.float64) - ref)) <= 1e-6
+
+
+def test_serving_mixed_matches_oracle_and_alone(gx, graphs):
+    queries = mixed_queries(graphs, 48, seed=5)
+    done = serve(gx, graphs, queries, stagger_s=0.002)
+    for i, q in enumerate(queries):
+        check(gx, graphs, q, done[i])
+    # the same query alone gives the same bits
+    for i in (0, 1, 6, 13):
+        alone = serve(gx, graphs, [queries[i]])
+        assert np.array_equal(alone[0].result.view(np.uint32), done[i].result.view(np.uint32)), i
+
+
+def test_serving_admits_while_running(gx, graphs):
+    # queries arriving while others run join at superstep boundaries
+    queries = [(2, gx.GX_PPR, int(s)) for s in gen.pick_sources(graphs[2], 20, seed=9)]
+    done = serve(gx, graphs, queries, lanes=32, epoch=2, stagger_s=0.01)
+    starts = sorted(c.start_s for c in done.values())
+    ends = sorted(c.done_s for c in done.values())
+    # some query started after another had started but before it finished
+    assert any(starts[0] < s < ends[0] for s in starts[1:])
+    for i, q in enumerate(queries):
+        check(gx, graphs, q, done[i])
+
+
+def test_serving_small_budget_queues(gx, graphs):
+    g = graphs[0]
+    queries = mixed_queries([g], 12, seed=11)
+    dg = gx.DeviceGraph(g, gx.GX_NEED_OUT | gx.GX_NEED_IN)
+    import ctypes
+    b_sssp, b_ppr = ctypes.c_size_t(), ctypes.c_size_t()
+    gx.binding.lib.gx_server_bytes_per_lane(dg.handle, gx.GX_SSSP, ctypes.byref(b_sssp))
+    gx.binding.lib.gx_server_bytes_per_lane(dg.handle, gx.GX_PPR, ctypes.byref(b_ppr))
+    # the bytes of one 64-lane pool of the larger kind: a 32-lane pool always
+    # fits, the two kinds may have to take turns (idle empty pools are evicted)
+    budget = int(max(b_sssp.value, b_ppr.value) * 64)
+    done = serve(gx, [g], queries, budget=budget, lanes=32)
+    for i, q in enumerate(queries):
+        check(gx, [g], q, done[i])
+
+
+def test_serving_rejects_budget_below_one_pool(gx, graphs):
+    dg = gx.DeviceGraph(graphs[2], gx.GX_NEED_OUT | gx.GX_NEED_IN)
+    srv = gx.Server(1 << 16, lanes_per_pool=32)
+    gid = srv.add_graph(dg)
+    with pytest.raises(gx.GxError) as ei:
+        srv.submit(gid, gx.GX_SSSP, 0)
+    assert ei.value.status == 2  # GX_ENOMEM
+    srv.close()
