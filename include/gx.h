@@ -104,7 +104,7 @@ typedef struct gx_params {
     uint32_t timing;          /* nonzero: time the edge kernels of every superstep with HIP events */
     float    pull_fraction;   /* SSSP/CC: a superstep whose active out-edges exceed this fraction of
                                  all edges pulls over in-edge tiles instead of pushing; 0 = default
-                                 (0.15), >= 1 = always push */
+                                 (0.3), >= 1 = always push */
 } gx_params;
 
 /* Statistics of one superstep (counts are exact). */

@@ -53,7 +53,8 @@ struct BsVariant {
 struct BpArgs {
     const int32_t *in_rp, *in_col, *outdeg, *trow;
     int64_t ntiles, V, E;
-    uint32_t B;
+    uint32_t B;   // lane stride of the tiles
+    uint32_t Bw;  // lanes processed (0..Bw-1); the rest keep their values untouched
     float d;
     const int32_t *seed;  // per lane; -1 = free lane
     float *x[2], *c[2];
@@ -72,7 +73,7 @@ struct BpWork {
 };
 
 const BsVariant *bs_variants(int *n);
-const void *bp_kernel(uint32_t B);
+const void *bp_kernel(uint32_t Bw);
 int coop_grid(const void *kernel, int block, int num_cus, int want);
 void bs_layout(const DevGraph &d, uint32_t B, Carver &c, BsWork *w);
 void bp_layout(const DevGraph &d, uint32_t B, Carver &c, BpWork *w);

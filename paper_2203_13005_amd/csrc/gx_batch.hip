@@ -285,7 +285,7 @@ __device__ __forceinline__ void ppr_apply(const BpArgs &a, int32_t r, const doub
 #pragma unroll
     for (int i = 0; i < LPT; i++) {
         const uint32_t b = lane + 64 * i;
-        if (b >= a.B) continue;
+        if (b >= a.Bw) continue;
         double v = (double)a.d * acc[i];
         if (a.seed[b] == r) v += (1.0 - (double)a.d) + (double)a.d * Dcur[b];
         float xn = (float)v;
@@ -307,7 +307,7 @@ __device__ __forceinline__ void ppr_gather(const BpArgs &a, const float *c_in, i
 #pragma unroll
         for (int i = 0; i < LPT; i++) {
             const uint32_t b = lane + 64 * i;
-            if (b < a.B) acc[i] += (double)row[b];
+            if (b < a.Bw) acc[i] += (double)row[b];
         }
     }
 }
@@ -336,7 +336,7 @@ __device__ __forceinline__ void bp_pull(const BpArgs &a, uint32_t k, const doubl
             ppr_gather<LPT>(a, c_in, e0, std::min(first_start, e1), acc, lane);
 #pragma unroll
             for (int i = 0; i < LPT; i++)
-                if (lane + 64 * i < (int)a.B) a.head[t * a.B + lane + 64 * i] = acc[i];
+                if (lane + 64 * i < (int)a.Bw) a.head[t * a.B + lane + 64 * i] = acc[i];
         }
         for (int32_t r = r_lo; r < r_hi; r++) {
             const int32_t rs = a.in_rp[r], re = a.in_rp[r + 1];
@@ -344,7 +344,7 @@ __device__ __forceinline__ void bp_pull(const BpArgs &a, uint32_t k, const doubl
                 ppr_gather<LPT>(a, c_in, rs, e1, acc, lane);
 #pragma unroll
                 for (int i = 0; i < LPT; i++)
-                    if (lane + 64 * i < (int)a.B) a.tailp[t * a.B + lane + 64 * i] = acc[i];
+                    if (lane + 64 * i < (int)a.Bw) a.tailp[t * a.B + lane + 64 * i] = acc[i];
                 if (lane == 0) a.spill[t] = r;
             } else {
                 ppr_gather<LPT>(a, c_in, rs, re, acc, lane);
@@ -353,7 +353,7 @@ __device__ __forceinline__ void bp_pull(const BpArgs &a, uint32_t k, const doubl
         }
 #pragma unroll
         for (int i = 0; i < LPT; i++)
-            if (lane + 64 * i < (int)a.B) a.dsum[t * a.B + lane + 64 * i] = dang[i];
+            if (lane + 64 * i < (int)a.Bw) a.dsum[t * a.B + lane + 64 * i] = dang[i];
     }
 }
 
@@ -376,7 +376,7 @@ __device__ __forceinline__ void bp_fix(const BpArgs &a, uint32_t k, const double
             dang[i] = 0.0;
             acc[i] = 0.0;
             const uint32_t b = lane + 64 * i;
-            if (b >= a.B) continue;
+            if (b >= a.Bw) continue;
             double s = a.tailp[t * a.B + b];
             for (int32_t t2 = (int32_t)t + 1; t2 <= t_end; t2++) s += a.head[(int64_t)t2 * a.B + b];
             acc[i] = s;
@@ -384,7 +384,7 @@ __device__ __forceinline__ void bp_fix(const BpArgs &a, uint32_t k, const double
         ppr_apply<LPT>(a, r, acc, Dcur, x_in, x_out, c_out, dang, lane);
 #pragma unroll
         for (int i = 0; i < LPT; i++)
-            if (lane + 64 * i < (int)a.B) a.dsum[t * a.B + lane + 64 * i] += dang[i];
+            if (lane + 64 * i < (int)a.Bw) a.dsum[t * a.B + lane + 64 * i] += dang[i];
     }
 }
 
@@ -394,11 +394,11 @@ __device__ __forceinline__ void bp_dang1(const BpArgs &a) {
     const int64_t gwave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
     const int64_t nchunks = (a.ntiles + BP_DCHUNK - 1) / BP_DCHUNK;
-    const int64_t lgroups = (a.B + 63) / 64;
+    const int64_t lgroups = (a.Bw + 63) / 64;
     for (int64_t w = gwave; w < nchunks * lgroups; w += nwaves) {
         const int64_t ch = w / lgroups;
         const uint32_t b = (uint32_t)((w % lgroups) * 64 + lane);
-        if (b >= a.B) continue;
+        if (b >= a.Bw) continue;
         const int64_t t0 = ch * BP_DCHUNK, t1 = std::min<int64_t>(t0 + BP_DCHUNK, a.ntiles);
         double s = 0.0;
         for (int64_t t = t0; t < t1; t++) s += a.dsum[t * a.B + b];
@@ -412,9 +412,9 @@ __device__ __forceinline__ void bp_dang2(const BpArgs &a, double *Dnext) {
     const int64_t gwave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
     const int64_t nchunks = (a.ntiles + BP_DCHUNK - 1) / BP_DCHUNK;
-    for (int64_t lg = gwave; lg * 64 < (int64_t)a.B; lg += nwaves) {
+    for (int64_t lg = gwave; lg * 64 < (int64_t)a.Bw; lg += nwaves) {
         const uint32_t b = (uint32_t)(lg * 64 + lane);
-        if (b >= a.B) continue;
+        if (b >= a.Bw) continue;
         double s = 0.0;
         for (int64_t ch = 0; ch < nchunks; ch++) s += a.dpart[ch * a.B + b];
         Dnext[b] = s;
@@ -513,8 +513,8 @@ const BsVariant *bs_variants(int *n) {
     return v;
 }
 
-const void *bp_kernel(uint32_t B) {
-    uint32_t lpt = (B + 63) / 64;
+const void *bp_kernel(uint32_t Bw) {
+    uint32_t lpt = (Bw + 63) / 64;
     switch (lpt) {
         case 1: return (const void *)k_bppr<1>;
         case 2: return (const void *)k_bppr<2>;
@@ -527,10 +527,7 @@ const void *bp_kernel(uint32_t B) {
 // bound is not trusted to the last workgroup: at most 2 per CU and at most
 // half of the reported bound, so every workgroup is resident at once.
 int coop_grid(const void *kernel, int block, int num_cus, int want) {
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu <= 0)
-        per_cu = 1;
-    per_cu = std::max(1, std::min(2, per_cu / 2));
+    int per_cu = std::max(1, std::min(2, occupancy_per_cu(kernel, block) / 2));
     int cap = per_cu * num_cus;
     if (want > 0) return std::min(want, cap);
     return cap;
@@ -686,6 +683,7 @@ gx_status run_bppr(gx_graph *g, const int32_t *dev_seed, uint32_t B, BpWork &w, 
     a.V = d.V;
     a.E = d.E;
     a.B = B;
+    a.Bw = B;
     a.d = d_;
     a.seed = w.seed;
     a.x[0] = w.x[0];
@@ -726,7 +724,7 @@ hipError_t bs_launch_superstep(const BsArgs &a, uint32_t k, uint32_t it, int gri
 }
 
 hipError_t bp_launch_superstep(const BpArgs &a, uint32_t k, int grid, hipStream_t s) {
-    const uint32_t lpt = (a.B + 63) / 64;
+    const uint32_t lpt = (a.Bw + 63) / 64;
 #define GX_BP_PHASES(L)                                                              \
     hipLaunchKernelGGL(k_bp_pull<L>, dim3(grid), dim3(256), 0, s, a, k);             \
     hipLaunchKernelGGL(k_bp_fix<L>, dim3(grid), dim3(256), 0, s, a, k);

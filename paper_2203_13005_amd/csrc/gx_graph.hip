@@ -7,7 +7,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <functional>
+#include <map>
+#include <mutex>
 #include <thread>
+#include <tuple>
 
 #include "gx_internal.h"
 
@@ -31,6 +34,22 @@ int device_cus(int device) {
     return n;
 }
 
+int occupancy_per_cu(const void *kernel, int block) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, const void *, int>, int> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(mu);
+    auto key = std::make_tuple(dev, kernel, block);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu <= 0)
+        per_cu = 1;
+    cache[key] = per_cu;
+    return per_cu;
+}
+
 template <class F>
 static void parallel_for(int64_t n, F f) {
     unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
@@ -48,9 +67,9 @@ static void parallel_for(int64_t n, F f) {
 
 // Host images built from the description before upload.
 struct HostImages {
-    std::vector<int32_t> in_rp, in_col, outdeg, tile_row;
+    std::vector<int32_t> in_rp, in_col, outdeg, tile_row, in_wrow;
     std::vector<uint32_t> in_w;
-    std::vector<int32_t> sym_rp, sym_col, sym_tile_row;
+    std::vector<int32_t> sym_rp, sym_col, sym_tile_row, sym_wrow;
     std::vector<uint32_t> rem_out, rem_any;
 };
 
@@ -109,14 +128,14 @@ static void build_in_csr(const gx_graph_desc *d, HostImages &h) {
 // Pull tiles: tile t covers edges [t*T, (t+1)*T) of a CSR and owns the rows
 // whose first edge position falls in that range (the last tile also owns the
 // rows starting at E).
-static int64_t ntiles_for(int64_t E) { return std::max<int64_t>(1, (E + PR_TILE - 1) / PR_TILE); }
+static int64_t ntiles_for(int64_t E, int64_t T = PR_TILE) { return std::max<int64_t>(1, (E + T - 1) / T); }
 
-static void build_tiles(const std::vector<int32_t> &rp, std::vector<int32_t> &tile_row) {
+static void build_tiles(const std::vector<int32_t> &rp, std::vector<int32_t> &tile_row, int64_t T = PR_TILE) {
     int64_t V = (int64_t)rp.size() - 1, E = rp.back();
-    int64_t nt = ntiles_for(E);
+    int64_t nt = ntiles_for(E, T);
     tile_row.resize(nt + 1);
     for (int64_t t = 0; t < nt; t++)
-        tile_row[t] = (int32_t)(std::lower_bound(rp.begin(), rp.end() - 1, (int32_t)(t * PR_TILE)) - rp.begin());
+        tile_row[t] = (int32_t)(std::lower_bound(rp.begin(), rp.end() - 1, (int32_t)(t * T)) - rp.begin());
     tile_row[0] = 0;
     tile_row[nt] = (int32_t)V;
 }
@@ -183,12 +202,18 @@ static void layout(const gx_graph_desc *desc, int64_t E_sym, Carver &c, DevGraph
         d->in_col = c.take<int32_t>(E);
         d->outdeg = c.take<int32_t>(V);
     }
-    if (desc->needs & GX_NEED_OUT) d->in_adj = c.take<uint2>(E);
+    if (desc->needs & GX_NEED_OUT) {
+        d->in_adj = c.take<uint2>(E);
+        d->in_nwt = (int32_t)ntiles_for(E, PULL_WT);
+        d->in_wrow = c.take<int32_t>(d->in_nwt + 1);
+    }
     if (desc->needs & GX_NEED_SYM) {
         d->sym_rp = c.take<int32_t>(V + 1);
         d->sym_col = c.take<int32_t>(E_sym);
         d->sym_ntiles = (int32_t)ntiles_for(E_sym);
         d->sym_tile_row = c.take<int32_t>(d->sym_ntiles + 1);
+        d->sym_nwt = (int32_t)ntiles_for(E_sym, PULL_WT);
+        d->sym_wrow = c.take<int32_t>(d->sym_nwt + 1);
     }
     if (desc->l2g) d->l2g = c.take<int32_t>(V);
     if (desc->flags) {
@@ -296,9 +321,11 @@ extern "C" gx_status gx_graph_load(const gx_graph_desc *desc, void *dev_arena, s
     try {
         build_in_csr(desc, h);
         build_tiles(h.in_rp, h.tile_row);
+        if (desc->needs & GX_NEED_OUT) build_tiles(h.in_rp, h.in_wrow, PULL_WT);
         if (desc->needs & GX_NEED_SYM) {
             build_sym(desc, h);
             build_tiles(h.sym_rp, h.sym_tile_row);
+            build_tiles(h.sym_rp, h.sym_wrow, PULL_WT);
         }
         build_flags(desc, W, h);
     } catch (const std::bad_alloc &) {
@@ -350,12 +377,14 @@ extern "C" gx_status gx_graph_load(const gx_graph_desc *desc, void *dev_arena, s
             size_t e0 = off / sizeof(uint2), cnt = n / sizeof(uint2);
             for (size_t i = 0; i < cnt; i++) o[i] = make_uint2((uint32_t)ic[e0 + i], iw[e0 + i]);
         });
+        if (e == hipSuccess) e = up.put_array((void *)d.in_wrow, h.in_wrow.data(), h.in_wrow.size() * 4);
     }
     if (e == hipSuccess && d.sym_rp) {
         e = up.put_array((void *)d.sym_rp, h.sym_rp.data(), (V + 1) * 4);
         if (e == hipSuccess) e = up.put_array((void *)d.sym_col, h.sym_col.data(), h.sym_col.size() * 4);
         if (e == hipSuccess)
             e = up.put_array((void *)d.sym_tile_row, h.sym_tile_row.data(), h.sym_tile_row.size() * 4);
+        if (e == hipSuccess) e = up.put_array((void *)d.sym_wrow, h.sym_wrow.data(), h.sym_wrow.size() * 4);
     }
     if (e == hipSuccess && d.l2g) e = up.put_array((void *)d.l2g, desc->l2g, V * 4);
     if (e == hipSuccess && d.remote_out) {

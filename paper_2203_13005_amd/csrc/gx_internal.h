@@ -60,6 +60,8 @@ struct Carver {
 constexpr int PR_BLOCK = 256;
 constexpr int PR_VT = 8;
 constexpr int PR_TILE = PR_BLOCK * PR_VT;
+// Wave tile of the SSSP / CC pull (in-edges per wavefront tile).
+constexpr int PULL_WT = 512;
 
 struct DevGraph {
     int64_t V = 0, E = 0, E_sym = 0;
@@ -75,11 +77,15 @@ struct DevGraph {
     const int32_t *outdeg = nullptr;
     int32_t pr_ntiles = 0;
     const int32_t *pr_tile_row = nullptr;  // [pr_ntiles + 1]
+    int32_t in_nwt = 0;                    // wave tiles of PULL_WT in-edges
+    const int32_t *in_wrow = nullptr;      // [in_nwt + 1]
     // symmetric adjacency (CC push and pull) and its equal edge tiles
     const int32_t *sym_rp = nullptr;
     const int32_t *sym_col = nullptr;
     int32_t sym_ntiles = 0;
     const int32_t *sym_tile_row = nullptr;
+    int32_t sym_nwt = 0;
+    const int32_t *sym_wrow = nullptr;
     // partition metadata
     const int32_t *l2g = nullptr;          // nullptr = identity
     const uint32_t *remote_out = nullptr;  // bitmaps of W words (nullptr = none remote)
@@ -119,5 +125,9 @@ constexpr int PUSH_VT = 8;
 constexpr int PUSH_TILE = PUSH_BLOCK * PUSH_VT;
 
 int device_cus(int device);
+
+// Workgroups per CU the occupancy query reports for (kernel, block size) on
+// the current device; cached, because the query is slow.
+int occupancy_per_cu(const void *kernel, int block);
 
 }  // namespace gx

@@ -39,6 +39,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <mutex>
 
 #include "gx_device.h"
 #include "gx_internal.h"
@@ -82,14 +83,21 @@ struct gx_state {
     std::vector<Pending> ev_pending;
     double kernel_ms = 0;
     int64_t kernel_launches = 0;
-    ~gx_state() {
-        for (auto e : ev_pool) (void)hipEventDestroy(e);
-        for (auto &pr : ev_pending) {
-            (void)hipEventDestroy(pr.a);
-            (void)hipEventDestroy(pr.b);
-        }
-    }
+    DevStep *host_steps = nullptr;  // pinned, HOST_STEPS entries (from a process-wide pool)
+    ~gx_state();
 };
+
+static void pool_return(hipEvent_t e);
+static void host_steps_return(gx::DevStep *p);
+
+gx_state::~gx_state() {
+    for (auto e : ev_pool) pool_return(e);
+    for (auto &pr : ev_pending) {
+        pool_return(pr.a);
+        pool_return(pr.b);
+    }
+    if (host_steps) host_steps_return(host_steps);
+}
 
 namespace {
 
@@ -117,59 +125,76 @@ __global__ __launch_bounds__(256) void k_min_init(uint32_t *val, uint8_t *f0, ui
     }
 }
 
-// Frontier byte map -> active list, one thread per vertex, 256 vertices per
-// workgroup (a workgroup without an active vertex leaves at once).  Active
-// vertices with out-edges get a list entry (edge offset, CSR base, snapshot)
-// in one 64-bit atomic per workgroup; the tiles that start inside an entry's
-// edges record it.  It also clears the byte map the next relaxation fills (it
-// held A_{k-1}), stores the snapshot of active vertices for the pull, and
-// counts |A_k|, which is also the number of vertices the previous superstep
+// Frontier byte map -> active list.  Each thread takes CVT vertices strided
+// by the block size (coalesced byte and row-pointer loads), so a workgroup
+// covers 256*CVT vertices and the whole grid issues few counter atomics (one
+// per workgroup for the list, one for |A|).  Active vertices with out-edges
+// get a list entry (edge offset, CSR base, snapshot); the tiles that start
+// inside an entry's edges record it.  The kernel also clears the byte map the
+// next relaxation fills (it held A_{k-1}) and stores the snapshot of active
+// vertices for the pull.  |A_{k+1}| is the number of vertices superstep k
 // changed.
+constexpr int CVT = 16;
+
 __global__ __launch_bounds__(256) void k_compact(const uint8_t *__restrict__ front, uint8_t *__restrict__ front_clear,
                                                  const int32_t *__restrict__ rp, const uint32_t *__restrict__ val,
                                                  uint32_t *__restrict__ snap, int64_t V,
                                                  uint4 *__restrict__ list, uint32_t *__restrict__ tile_start,
-                                                 DevStep *__restrict__ step, DevStep *__restrict__ prev_step,
-                                                 DevStep *__restrict__ next_step) {
+                                                 DevStep *__restrict__ step, DevStep *__restrict__ next_step) {
     __shared__ unsigned long long s_scan[4];
     __shared__ unsigned long long s_base;
     __shared__ int s_nf[4];
     const int tid = threadIdx.x;
     if (blockIdx.x == 0 && tid == 0) *next_step = DevStep{0, 0, 0, 0};
-    const int64_t u = (int64_t)blockIdx.x * 256 + tid;
-    bool act = false;
-    if (u < V) {
-        act = front[u] != 0;
-        front_clear[u] = 0;
+    const int64_t v0 = (int64_t)blockIdx.x * 256 * CVT + tid;
+    uint32_t actmask = 0;
+#pragma unroll
+    for (int i = 0; i < CVT; i++) {
+        const int64_t u = v0 + (int64_t)i * 256;
+        if (u < V) {
+            if (front[u]) actmask |= 1u << i;
+            front_clear[u] = 0;
+        }
     }
-    if (!__syncthreads_or(act)) return;
-    int32_t r0 = 0, d = 0;
-    if (act) {
-        r0 = rp[u];
-        d = rp[u + 1] - r0;
+    if (!__syncthreads_or(actmask != 0)) return;
+    int32_t r0[CVT], dg[CVT];
+    uint32_t cnt = 0, edges = 0;
+#pragma unroll
+    for (int i = 0; i < CVT; i++) {
+        r0[i] = 0;
+        dg[i] = 0;
+        if ((actmask >> i) & 1u) {
+            const int64_t u = v0 + (int64_t)i * 256;
+            r0[i] = rp[u];
+            dg[i] = rp[u + 1] - r0[i];
+            if (dg[i] > 0) {
+                cnt++;
+                edges += (uint32_t)dg[i];
+            }
+        }
     }
-    const bool has = act && d > 0;
-    unsigned long long mine = has ? ((1ull << 32) | (uint32_t)d) : 0ull, total;
+    unsigned long long mine = ((unsigned long long)cnt << 32) | edges, total;
     unsigned long long pre = block_excl_scan_u64(mine, &total, s_scan);
-    int nf = act ? 1 : 0;
+    int nf = __popc(actmask);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) nf += __shfl_down(nf, o, 64);
     if ((tid & 63) == 0) s_nf[tid >> 6] = nf;
     if (tid == 0) s_base = total ? atomicAdd(&step->list, total) : 0ull;
     __syncthreads();
-    if (tid == 0) {
-        const unsigned long long t = s_nf[0] + s_nf[1] + s_nf[2] + s_nf[3];
-        atomicAdd(&step->frontier, t);
-        if (prev_step) atomicAdd(&prev_step->changed, t);
+    if (tid == 0) atomicAdd(&step->frontier, (unsigned long long)(s_nf[0] + s_nf[1] + s_nf[2] + s_nf[3]));
+    unsigned long long pos = s_base + pre;
+#pragma unroll
+    for (int i = 0; i < CVT; i++) {
+        if (dg[i] <= 0) continue;
+        const int64_t u = v0 + (int64_t)i * 256;
+        const uint32_t idx = (uint32_t)(pos >> 32), off = (uint32_t)pos;
+        const uint32_t x = val[u];
+        snap[u] = x;
+        list[idx] = make_uint4(off, (uint32_t)(r0[i] - (int32_t)off), x, (uint32_t)u);
+        const uint32_t t0 = (off + PUSH_TILE - 1) / PUSH_TILE, t1 = (off + (uint32_t)dg[i] - 1) / PUSH_TILE;
+        for (uint32_t t = t0; t <= t1; t++) tile_start[t] = idx;
+        pos += (1ull << 32) + (uint32_t)dg[i];
     }
-    if (!has) return;
-    const unsigned long long pos = s_base + pre;
-    const uint32_t idx = (uint32_t)(pos >> 32), off = (uint32_t)pos;
-    const uint32_t x = val[u];
-    snap[u] = x;
-    list[idx] = make_uint4(off, (uint32_t)(r0 - (int32_t)off), x, (uint32_t)u);
-    const uint32_t t0 = (off + PUSH_TILE - 1) / PUSH_TILE, t1 = (off + (uint32_t)d - 1) / PUSH_TILE;
-    for (uint32_t t = t0; t <= t1; t++) tile_start[t] = idx;
 }
 
 // Relaxes the active out-edges, PUSH_TILE per workgroup tile (persistent
@@ -680,10 +705,7 @@ inline unsigned grid_for(T n, unsigned block) {
 
 template <class K>
 static int persistent_grid(gx_graph *g, K kernel, int block) {
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu <= 0)
-        per_cu = 2;
-    return g->num_cus * per_cu;
+    return g->num_cus * occupancy_per_cu(reinterpret_cast<const void *>(kernel), block);
 }
 
 static size_t state_layout(gx_graph *g, const gx_params *p, Carver &c, gx_state *s) {
@@ -775,8 +797,8 @@ extern "C" gx_status gx_state_init(gx_graph *g, const gx_params *p, void *dev_st
     s->pull_grid = persistent_grid(g, k_pull<true>, PR_BLOCK);
     if (p->algo != GX_PAGERANK) {
         const DevGraph &dg = g->d;
-        bool can_pull = p->algo == GX_SSSP ? (dg.in_adj != nullptr) : (dg.sym_tile_row != nullptr);
-        double frac = p->pull_fraction > 0.f ? (double)p->pull_fraction : 0.15;
+        bool can_pull = p->algo == GX_SSSP ? (dg.in_adj != nullptr) : (dg.sym_wrow != nullptr);
+        double frac = p->pull_fraction > 0.f ? (double)p->pull_fraction : 0.3;
         double Eimg = (double)(p->algo == GX_SSSP ? dg.E : dg.E_sym);
         s->pull_edges = (!can_pull || frac >= 1.0) ? 0xFFFFFFFFu : (uint32_t)std::max(1.0, std::ceil(frac * Eimg));
     }
@@ -803,8 +825,8 @@ extern "C" gx_status gx_state_init(gx_graph *g, const gx_params *p, void *dev_st
         }
         // compaction of superstep 0 (each superstep then relaxes and compacts the next)
         if (V > 0)
-            hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(V, 256)), dim3(256), 0, hs, s->front8[0], s->front8[1],
-                               rp, s->val, s->snap, V, s->list, s->tile_start, s->steps, (DevStep *)nullptr,
+            hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(V, 256 * CVT)), dim3(256), 0, hs, s->front8[0],
+                               s->front8[1], rp, s->val, s->snap, V, s->list, s->tile_start, s->steps,
                                s->steps + 1);
     }
     hipError_t e = hipGetLastError();
@@ -845,15 +867,56 @@ extern "C" gx_status gx_state_superstep(gx_state *s, int64_t *k) {
     return GX_OK;
 }
 
+// Process-wide pool of timing events (creating events per superstep costs
+// more than the short supersteps themselves).
+static std::mutex g_ev_mu;
+static std::vector<hipEvent_t> g_ev_free;
+
 static hipEvent_t pool_event(gx_state *s) {
     if (!s->ev_pool.empty()) {
         hipEvent_t e = s->ev_pool.back();
         s->ev_pool.pop_back();
         return e;
     }
+    {
+        std::lock_guard<std::mutex> lk(g_ev_mu);
+        if (!g_ev_free.empty()) {
+            hipEvent_t e = g_ev_free.back();
+            g_ev_free.pop_back();
+            return e;
+        }
+    }
     hipEvent_t e = nullptr;
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
+}
+
+static void pool_return(hipEvent_t e) {
+    std::lock_guard<std::mutex> lk(g_ev_mu);
+    g_ev_free.push_back(e);
+}
+
+// Process-wide pool of pinned buffers for reading superstep counters back.
+constexpr int HOST_STEPS = 256;
+static std::vector<DevStep *> g_hs_free;
+
+static DevStep *host_steps_take() {
+    {
+        std::lock_guard<std::mutex> lk(g_ev_mu);
+        if (!g_hs_free.empty()) {
+            DevStep *p = g_hs_free.back();
+            g_hs_free.pop_back();
+            return p;
+        }
+    }
+    void *p = nullptr;
+    if (hipHostMalloc(&p, HOST_STEPS * sizeof(DevStep), hipHostMallocDefault) != hipSuccess) return nullptr;
+    return static_cast<DevStep *>(p);
+}
+
+static void host_steps_return(DevStep *p) {
+    std::lock_guard<std::mutex> lk(g_ev_mu);
+    g_hs_free.push_back(p);
 }
 
 // Enqueues superstep s->k on `hs` and advances s->k.
@@ -909,8 +972,9 @@ static gx_status enqueue_superstep(gx_state *s, hipStream_t hs) {
                                        s->pull_edges);
             }
             if (e1) (void)hipEventRecord(e1, hs);
-            hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(d.V, 256)), dim3(256), 0, hs, s->front8[cur ^ 1],
-                               s->front8[cur], rp, s->val, s->snap, d.V, s->list, s->tile_start, next, step, next2);
+            hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(d.V, 256 * CVT)), dim3(256), 0, hs,
+                               s->front8[cur ^ 1], s->front8[cur], rp, s->val, s->snap, d.V, s->list, s->tile_start,
+                               next, next2);
         }
     }
     hipError_t e = hipGetLastError();
@@ -940,19 +1004,24 @@ static void collect_timings(gx_state *s, gx_step_stats *per_step = nullptr, int6
     s->ev_pending.clear();
 }
 
-static void to_stats(const gx_state *s, const DevStep &ds, gx_step_stats *o) {
+// `next` is the slot of the following superstep: for SSSP/CC the number of
+// vertices a superstep changed is the size of the next frontier.
+static void to_stats(const gx_state *s, const DevStep &ds, const DevStep &next, gx_step_stats *o) {
     if (s->p.algo == GX_PAGERANK) {
         o->frontier = s->g->d.V;
         o->edges = s->g->d.E;
         o->pulled = 1;
+        o->changed = (int64_t)ds.changed;
     } else {
         o->frontier = (int64_t)ds.frontier;
         o->edges = (int64_t)(uint32_t)ds.list;
         o->pulled = ds.pad ? 1 : 0;
+        o->changed = (int64_t)next.frontier;
     }
-    o->changed = (int64_t)ds.changed;
     o->kernel_ms = 0.0;
 }
+
+static gx_status read_steps(gx_state *s, int64_t kfirst, uint32_t n, hipStream_t hs, std::vector<DevStep> &out);
 
 extern "C" gx_status gx_superstep(gx_state *s, void *stream, gx_step_stats *stats) {
     clear_error();
@@ -963,11 +1032,36 @@ extern "C" gx_status gx_superstep(gx_state *s, void *stream, gx_step_stats *stat
     gx_status st = enqueue_superstep(s, hs);
     if (st != GX_OK) return st;
     if (stats) {
-        DevStep ds;
-        GX_CHECK_HIP(hipMemcpyAsync(&ds, s->steps + (k % STEP_RING), sizeof ds, hipMemcpyDeviceToHost, hs), s);
-        GX_CHECK_HIP(hipStreamSynchronize(hs), s);
-        to_stats(s, ds, stats);
+        std::vector<DevStep> ds;
+        st = read_steps(s, k, 2, hs, ds);
+        if (st != GX_OK) return st;
+        to_stats(s, ds[0], ds[1], stats);
         collect_timings(s, stats, k, 1);
+    }
+    return GX_OK;
+}
+
+// Copies the counters of supersteps [kfirst, kfirst + n) to out[] through the
+// state's pinned buffer (ring-contiguous pieces, one synchronisation).
+static gx_status read_steps(gx_state *s, int64_t kfirst, uint32_t n, hipStream_t hs, std::vector<DevStep> &out) {
+    out.resize(n);
+    if (!s->host_steps) s->host_steps = host_steps_take();
+    GX_REQUIRE(s->host_steps, GX_ENOMEM, "pinned host allocation failed");
+    for (uint32_t done = 0; done < n;) {
+        uint32_t chunk = std::min<uint32_t>(n - done, HOST_STEPS);
+        uint32_t copied = 0;
+        while (copied < chunk) {
+            int64_t k = kfirst + done + copied;
+            uint32_t slot = (uint32_t)(k % STEP_RING);
+            uint32_t run = std::min<uint32_t>(chunk - copied, STEP_RING - slot);
+            GX_CHECK_HIP(hipMemcpyAsync(s->host_steps + copied, s->steps + slot, run * sizeof(DevStep),
+                                        hipMemcpyDeviceToHost, hs),
+                         s);
+            copied += run;
+        }
+        GX_CHECK_HIP(hipStreamSynchronize(hs), s);
+        std::memcpy(out.data() + done, s->host_steps, chunk * sizeof(DevStep));
+        done += chunk;
     }
     return GX_OK;
 }
@@ -982,7 +1076,7 @@ extern "C" gx_status gx_run_until_converged(gx_state *s, uint32_t max_supersteps
     double ms0 = s->kernel_ms;
     int64_t l0 = s->kernel_launches;
     gx_run_stats rs{};
-    std::vector<DevStep> host(64);
+    std::vector<DevStep> host;
     gx_status result = GX_OK;
     const int64_t k_begin = s->k;
     if (s->p.algo == GX_PAGERANK) {
@@ -991,21 +1085,20 @@ extern "C" gx_status gx_run_until_converged(gx_state *s, uint32_t max_supersteps
             gx_status st = enqueue_superstep(s, hs);
             if (st != GX_OK) return st;
         }
-        host.resize(std::max<size_t>(host.size(), max_supersteps));
-        for (uint32_t i = 0; i < max_supersteps; i++)
-            GX_CHECK_HIP(hipMemcpyAsync(&host[i], s->steps + ((kfirst + i) % STEP_RING), sizeof(DevStep),
-                                        hipMemcpyDeviceToHost, hs),
-                         s);
-        GX_CHECK_HIP(hipStreamSynchronize(hs), s);
+        gx_status st = read_steps(s, kfirst, max_supersteps + 1, hs, host);
+        if (st != GX_OK) return st;
         for (uint32_t i = 0; i < max_supersteps; i++) {
             gx_step_stats o;
-            to_stats(s, host[i], &o);
+            to_stats(s, host[i], host[i + 1], &o);
             if (per_step) per_step[i] = o;
             rs.edges += o.edges;
         }
         rs.supersteps = max_supersteps;
         rs.converged = 0;
     } else {
+        // Supersteps are enqueued in growing speculative groups (2, 4, 8) and
+        // the host synchronises once per group; supersteps enqueued after
+        // convergence find an empty frontier and change nothing.
         uint32_t done = 0, spec = 2;
         bool conv = false;
         while (done < max_supersteps && !conv) {
@@ -1015,21 +1108,16 @@ extern "C" gx_status gx_run_until_converged(gx_state *s, uint32_t max_supersteps
                 gx_status st = enqueue_superstep(s, hs);
                 if (st != GX_OK) return st;
             }
-            if (host.size() < g) host.resize(g);
-            for (uint32_t i = 0; i < g; i++)
-                GX_CHECK_HIP(hipMemcpyAsync(&host[i], s->steps + ((kfirst + i) % STEP_RING), sizeof(DevStep),
-                                            hipMemcpyDeviceToHost, hs),
-                             s);
-            GX_CHECK_HIP(hipStreamSynchronize(hs), s);
+            gx_status st = read_steps(s, kfirst, g + 1, hs, host);
+            if (st != GX_OK) return st;
             for (uint32_t i = 0; i < g; i++) {
                 gx_step_stats o;
-                to_stats(s, host[i], &o);
+                to_stats(s, host[i], host[i + 1], &o);
                 if (per_step) per_step[done] = o;
                 rs.edges += o.edges;
                 done++;
                 if (o.changed == 0) {
                     conv = true;
-                    // supersteps enqueued after this one found an empty frontier and changed nothing
                     s->k = kfirst + i + 1;
                     break;
                 }

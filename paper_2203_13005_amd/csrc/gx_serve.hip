@@ -284,6 +284,7 @@ struct gx_server {
         a.V = d.V;
         a.E = d.E;
         a.B = p.B;
+        a.Bw = p.B;
         a.d = cfg.damping;
         a.seed = p.pw.seed;
         a.x[0] = p.pw.x[0];
@@ -386,6 +387,11 @@ struct gx_server {
                 if (p.lane_q[b] >= 0) left = std::min<int64_t>(left, (int64_t)cfg.ppr_iters - p.lane_age[b]);
             p.epoch_len = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(left, epoch_max()));
             BpArgs a = bp_args(p);
+            // only the occupied prefix of lanes (lowest free lanes are taken first)
+            uint32_t hi = 0;
+            for (uint32_t b = 0; b < p.B; b++)
+                if (p.lane_q[b] >= 0) hi = b + 1;
+            a.Bw = std::min<uint32_t>(p.B, (hi + 31) / 32 * 32);
             for (uint32_t it = 0; it < p.epoch_len; it++)
                 if (bp_launch_superstep(a, p.k + it, grid, p.stream) != hipSuccess) return false;
         }
