@@ -246,6 +246,62 @@ def bench_partition(gx, torch, np, gen, reps=3):
                                  for d in steps]}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sssp_rmat22_relaxation_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2203_13005_amd", "csrc", "gx_plain.hip")
+
+
+def kernel_source_hash():
+    import hashlib
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+
+
+def summarize_pmc(fetch_dir, write_dir, solves):
+    """Turns two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) over
+    `bench.py --copy-calibration` into the traffic record bench.py reports.
+    Each counter is scaled so the 1 GiB device copy reads (writes) 1 GiB."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        rows = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            rows += [r for r in csv.DictReader(open(f)) if r.get("Counter_Name") == counter]
+        return rows
+
+    out = {"source_sha256_16": kernel_source_hash(), "solves_profiled": None}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = load(d, counter)
+        copy = [float(r["Counter_Value"]) for r in rows if "copy" in r["Kernel_Name"].lower() and
+                float(r["Counter_Value"]) > 500_000]
+        relax = [float(r["Counter_Value"]) for r in rows if "k_push" in r["Kernel_Name"] or "k_pull" in r["Kernel_Name"]]
+        if not copy or not relax:
+            raise SystemExit(f"{counter}: no calibration copy or no relaxation dispatches in {d}")
+        factor = (1 << 30) / 1024.0 / max(copy)  # KiB of a 1 GiB copy / measured
+        out[counter] = {"calibration_copy_kib": max(copy), "factor": factor,
+                        "relaxation_dispatches": len(relax), "relaxation_kib_total": sum(relax),
+                        "relaxation_bytes_total_calibrated": sum(relax) * 1024.0 * factor}
+    out["solves_profiled"] = solves
+    out["note"] = ("push and pull dispatches of every solve in the profiled run (validation, warm-up, detail "
+                   "and timed solves, all identical) summed and divided by the number of solves")
+    out["bytes_per_solve"] = (out["FETCH_SIZE"]["relaxation_bytes_total_calibrated"] +
+                              out["WRITE_SIZE"]["relaxation_bytes_total_calibrated"]) / solves
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    json.dump(out, open(TRAFFIC_FILE, "w"), indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def load_traffic():
+    """Measured HBM bytes per relaxation launch, or None when absent or
+    taken on a different kernel source."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256_16") != kernel_source_hash():
+        return None
+    return t
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -260,9 +316,16 @@ def main():
     ap.add_argument("--no-pagerank", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-queries", type=int, default=2000)
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the traffic record from two rocprofv3 --pmc output folders and exit")
+    ap.add_argument("--pmc-solves", type=int, default=0,
+                    help="solves in the profiled run (1 validation + warmup + 1 detail + steps)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.pmc_solves)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU exchange is not built.",
               file=sys.stderr)
@@ -283,7 +346,8 @@ def main():
     dg = gx.DeviceGraph(g, gx.GX_NEED_OUT, device=dev)  # out-CSR (push) + in-CSR (pull)
     torch.cuda.synchronize()
     load_s = time.perf_counter() - t0
-    log(f"loaded in {load_s:.2f}s ({(g.E * 8 + g.V * 4) / load_s / 1e9:.2f} GB/s host->device incl. packaging)")
+    load_bytes = dg.arena_bytes
+    log(f"loaded in {load_s:.2f}s ({load_bytes / load_s / 1e9:.2f} GB/s of device images, host packaging included)")
 
     # Untimed validation pass: per-superstep frontiers for the byte model.
     st = gx.State(dg, gx.GX_SSSP, source=0, pull_fraction=args.pull_fraction)
@@ -347,6 +411,7 @@ def main():
         log("copy calibration: 1 GiB device-to-device copy done")
 
     achieved = bytes_per_solve * args.steps / (kern_ms / 1e3) / 1e9
+    traffic = load_traffic()
     out = {
         "metric": "GTEPS per superstep and % HBM roofline; batched-vs-plain SSSP queries/s, p50/p99",
         "value": edges / dt / 1e9,
@@ -367,6 +432,9 @@ def main():
             "V": g.V, "E": g.E, "supersteps": K, "messages_per_solve": edges_per_solve,
             "parallelism": "single GPU",
         },
+        "load": {"what": "gx_graph_load: host validation and packaging (out-CSR, in-edge records), "
+                         "16 MiB blocks through three rotating pinned buffers on a copy stream",
+                 "seconds": load_s, "device_bytes": load_bytes, "GBps": load_bytes / load_s / 1e9},
         "roofline": {
             "bound": "hbm",
             "kernel": "relaxation: k_push<true> / k_pull<true> (one of the two works per superstep)",
@@ -374,7 +442,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": None if traffic is None else traffic["bytes_per_solve"],
+            "traffic_unit": "HBM bytes of the relaxation kernels per solve (FETCH_SIZE + WRITE_SIZE, "
+                            "copy-calibrated); achieved = algorithmic bytes per solve / their time per solve",
             "algorithmic_bytes_per_solve": bytes_per_solve,
             "kernel_ms_per_solve": kern_ms / args.steps,
             "launches_per_solve": launches / args.steps,

@@ -67,9 +67,10 @@ static void parallel_for(int64_t n, F f) {
 
 // Host images built from the description before upload.
 struct HostImages {
-    std::vector<int32_t> in_rp, in_col, outdeg, tile_row, in_wrow;
+    std::vector<int32_t> in_rp, in_col, outdeg, tile_row;
     std::vector<uint32_t> in_w;
-    std::vector<int32_t> sym_rp, sym_col, sym_tile_row, sym_wrow;
+    std::vector<int32_t> sym_rp, sym_col;
+    std::vector<uint2> pull_w, pull_sym;
     std::vector<uint32_t> rem_out, rem_any;
 };
 
@@ -140,6 +141,31 @@ static void build_tiles(const std::vector<int32_t> &rp, std::vector<int32_t> &ti
     tile_row[nt] = (int32_t)V;
 }
 
+// Banded pull records from a CSR over destinations (rows) listing sources in
+// ascending order: a stable split by source band keeps (destination,
+// source) order inside every band.  `w` may be null (records {dst, src}).
+static void build_banded(const std::vector<int32_t> &rp, const int32_t *src, const uint32_t *w,
+                         std::vector<uint2> &out) {
+    const int64_t V = (int64_t)rp.size() - 1, E = rp.back();
+    const int64_t nb = (V >> PULL_BAND_BITS) + 1;
+    std::vector<int64_t> pos(nb + 1, 0);
+    for (int64_t e = 0; e < E; e++) pos[(src[e] >> PULL_BAND_BITS) + 1]++;
+    for (int64_t b = 0; b < nb; b++) pos[b + 1] += pos[b];
+    out.resize(E);
+    for (int64_t v = 0; v < V; v++)
+        for (int32_t e = rp[v]; e < rp[v + 1]; e++) {
+            const uint32_t u = (uint32_t)src[e];
+            out[pos[u >> PULL_BAND_BITS]++] = make_uint2((uint32_t)v, w ? ((u << 8) | w[e]) : u);
+        }
+}
+
+static bool banded_weights_fit(const gx_graph_desc *d) {
+    if (d->V >= (int64_t(1) << 24)) return false;
+    for (int64_t e = 0; e < d->E; e++)
+        if (d->w[e] > 255u) return false;
+    return true;
+}
+
 // Symmetric adjacency: sorted union of out- and in-neighbours, self
 // excluded, duplicates removed (needs the in-CSR).
 static void build_sym(const gx_graph_desc *d, HostImages &h) {
@@ -202,18 +228,11 @@ static void layout(const gx_graph_desc *desc, int64_t E_sym, Carver &c, DevGraph
         d->in_col = c.take<int32_t>(E);
         d->outdeg = c.take<int32_t>(V);
     }
-    if (desc->needs & GX_NEED_OUT) {
-        d->in_adj = c.take<uint2>(E);
-        d->in_nwt = (int32_t)ntiles_for(E, PULL_WT);
-        d->in_wrow = c.take<int32_t>(d->in_nwt + 1);
-    }
+    if ((desc->needs & GX_NEED_OUT) && (desc->E == 0 || banded_weights_fit(desc))) d->pull_w = c.take<uint2>(E);
     if (desc->needs & GX_NEED_SYM) {
         d->sym_rp = c.take<int32_t>(V + 1);
         d->sym_col = c.take<int32_t>(E_sym);
-        d->sym_ntiles = (int32_t)ntiles_for(E_sym);
-        d->sym_tile_row = c.take<int32_t>(d->sym_ntiles + 1);
-        d->sym_nwt = (int32_t)ntiles_for(E_sym, PULL_WT);
-        d->sym_wrow = c.take<int32_t>(d->sym_nwt + 1);
+        d->pull_sym = c.take<uint2>(E_sym);
     }
     if (desc->l2g) d->l2g = c.take<int32_t>(V);
     if (desc->flags) {
@@ -321,11 +340,11 @@ extern "C" gx_status gx_graph_load(const gx_graph_desc *desc, void *dev_arena, s
     try {
         build_in_csr(desc, h);
         build_tiles(h.in_rp, h.tile_row);
-        if (desc->needs & GX_NEED_OUT) build_tiles(h.in_rp, h.in_wrow, PULL_WT);
+        if ((desc->needs & GX_NEED_OUT) && (desc->E == 0 || banded_weights_fit(desc)))
+            build_banded(h.in_rp, h.in_col.data(), h.in_w.data(), h.pull_w);
         if (desc->needs & GX_NEED_SYM) {
             build_sym(desc, h);
-            build_tiles(h.sym_rp, h.sym_tile_row);
-            build_tiles(h.sym_rp, h.sym_wrow, PULL_WT);
+            build_banded(h.sym_rp, h.sym_col.data(), nullptr, h.pull_sym);
         }
         build_flags(desc, W, h);
     } catch (const std::bad_alloc &) {
@@ -369,22 +388,12 @@ extern "C" gx_status gx_graph_load(const gx_graph_desc *desc, void *dev_arena, s
         e = up.put_array((void *)d.in_col, h.in_col.data(), E * 4);
         if (e == hipSuccess) e = up.put_array((void *)d.outdeg, g->host_outdeg.data(), V * 4);
     }
-    if (e == hipSuccess && d.in_adj) {
-        const int32_t *ic = h.in_col.data();
-        const uint32_t *iw = h.in_w.data();
-        e = up.put((void *)d.in_adj, E * sizeof(uint2), [ic, iw](char *dst, size_t off, size_t n) {
-            uint2 *o = reinterpret_cast<uint2 *>(dst);
-            size_t e0 = off / sizeof(uint2), cnt = n / sizeof(uint2);
-            for (size_t i = 0; i < cnt; i++) o[i] = make_uint2((uint32_t)ic[e0 + i], iw[e0 + i]);
-        });
-        if (e == hipSuccess) e = up.put_array((void *)d.in_wrow, h.in_wrow.data(), h.in_wrow.size() * 4);
-    }
+    if (e == hipSuccess && d.pull_w) e = up.put_array((void *)d.pull_w, h.pull_w.data(), E * sizeof(uint2));
     if (e == hipSuccess && d.sym_rp) {
         e = up.put_array((void *)d.sym_rp, h.sym_rp.data(), (V + 1) * 4);
         if (e == hipSuccess) e = up.put_array((void *)d.sym_col, h.sym_col.data(), h.sym_col.size() * 4);
         if (e == hipSuccess)
-            e = up.put_array((void *)d.sym_tile_row, h.sym_tile_row.data(), h.sym_tile_row.size() * 4);
-        if (e == hipSuccess) e = up.put_array((void *)d.sym_wrow, h.sym_wrow.data(), h.sym_wrow.size() * 4);
+            e = up.put_array((void *)d.pull_sym, h.pull_sym.data(), h.pull_sym.size() * sizeof(uint2));
     }
     if (e == hipSuccess && d.l2g) e = up.put_array((void *)d.l2g, desc->l2g, V * 4);
     if (e == hipSuccess && d.remote_out) {

@@ -60,8 +60,10 @@ struct Carver {
 constexpr int PR_BLOCK = 256;
 constexpr int PR_VT = 8;
 constexpr int PR_TILE = PR_BLOCK * PR_VT;
-// Wave tile of the SSSP / CC pull (in-edges per wavefront tile).
-constexpr int PULL_WT = 512;
+// Source bands of the SSSP / CC pull: in-edges are ordered by
+// (source >> PULL_BAND_BITS, destination, source), so a sweep over the edge
+// records touches one band of source snapshots (2^18 vertices) at a time.
+constexpr int PULL_BAND_BITS = 18;
 
 struct DevGraph {
     int64_t V = 0, E = 0, E_sym = 0;
@@ -73,19 +75,17 @@ struct DevGraph {
     // (SSSP pull); out-degree; equal in-edge tiles shared by both pulls
     const int32_t *in_rp = nullptr;
     const int32_t *in_col = nullptr;
-    const uint2 *in_adj = nullptr;
     const int32_t *outdeg = nullptr;
     int32_t pr_ntiles = 0;
     const int32_t *pr_tile_row = nullptr;  // [pr_ntiles + 1]
-    int32_t in_nwt = 0;                    // wave tiles of PULL_WT in-edges
-    const int32_t *in_wrow = nullptr;      // [in_nwt + 1]
+    // banded in-edge records for the SSSP pull: {dst, (src << 8) | w}; null
+    // when V >= 2^24 or a weight exceeds 255 (the engine then only pushes)
+    const uint2 *pull_w = nullptr;
     // symmetric adjacency (CC push and pull) and its equal edge tiles
     const int32_t *sym_rp = nullptr;
     const int32_t *sym_col = nullptr;
-    int32_t sym_ntiles = 0;
-    const int32_t *sym_tile_row = nullptr;
-    int32_t sym_nwt = 0;
-    const int32_t *sym_wrow = nullptr;
+    // banded symmetric records for the CC pull: {dst, src}
+    const uint2 *pull_sym = nullptr;
     // partition metadata
     const int32_t *l2g = nullptr;          // nullptr = identity
     const uint32_t *remote_out = nullptr;  // bitmaps of W words (nullptr = none remote)

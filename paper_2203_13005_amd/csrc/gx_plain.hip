@@ -269,136 +269,84 @@ __global__ __launch_bounds__(PUSH_BLOCK) void k_push(const uint4 *__restrict__ l
     }
 }
 
-// Pull form of the same superstep, for large frontiers: equal tiles over the
-// in-edges (static, built at load).  Every in-edge whose source is active
-// carries the source's snapshot (+ weight); the merge is a min per
-// destination row computed in LDS (each thread sums a contiguous chunk, rows
-// spanning threads are combined by walking back over the threads' trailing
-// pieces).  A row inside one tile is written by one thread with a plain
-// store; only rows that cross a tile boundary (the high-degree tail) use
-// atomicMin.  Runs only when the frontier's out-edges reach pull_edges.
+// Pull form of the same superstep, for large frontiers.  The in-edges are
+// stored as records {dst, (src << 8) | w} (CC: {dst, src}) ordered by
+// (source band, dst, src), built at load.  Every thread takes PULL_VT
+// consecutive records (the grid sweeps the array front to back, so at any
+// time the source snapshots being gathered come from one band of 2^18
+// vertices and stay cache resident); an active source's record carries its
+// snapshot (+ weight); the thread folds runs of equal destination to their
+// minimum and applies each by integer atomicMin after a plain read
+// filters out non-improving candidates.  Runs only when the frontier's
+// out-edges reach pull_edges.
+constexpr int PULL_VT = 8;
+
 template <bool WEIGHTED>
-__global__ __launch_bounds__(PR_BLOCK) void k_pull(const int32_t *__restrict__ rp, const void *__restrict__ adj,
-                                                   const int32_t *__restrict__ tile_row, int32_t ntiles, int64_t E,
-                                                   const uint8_t *__restrict__ front_cur,
-                                                   const uint32_t *__restrict__ snap, uint32_t *__restrict__ val,
-                                                   uint8_t *__restrict__ front_next, uint8_t *__restrict__ dirty,
-                                                   DevStep *__restrict__ step, uint32_t pull_edges) {
-    __shared__ uint32_t s_val[PR_TILE];
-    __shared__ int32_t s_own[PR_TILE];
-    __shared__ uint32_t s_last[PR_BLOCK];
-    __shared__ int32_t s_last_start[PR_BLOCK];
-    __shared__ int32_t s_red[4];
+__global__ __launch_bounds__(256) void k_pull(const uint2 *__restrict__ rec, int64_t E,
+                                              const uint8_t *__restrict__ front_cur,
+                                              const uint32_t *__restrict__ snap, uint32_t *__restrict__ val,
+                                              uint8_t *__restrict__ front_next, uint8_t *__restrict__ dirty,
+                                              DevStep *__restrict__ step, uint32_t pull_edges) {
     const uint32_t EF = (uint32_t)step->list;
     if (EF < pull_edges) return;
-    const int tid = threadIdx.x;
-    if (blockIdx.x == 0 && tid == 0) step->pad = 1;
-    for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const int64_t e0 = (int64_t)t * PR_TILE;
-        const int n = (int)max((int64_t)0, min((int64_t)PR_TILE, E - e0));
-        const int32_t r_lo = tile_row[t], r_hi = tile_row[t + 1];
-        {  // messages into LDS: edge loads, then frontier bytes, then snapshots
-            uint32_t u[PR_VT], w[PR_VT], f[PR_VT];
+    if (blockIdx.x == 0 && threadIdx.x == 0) step->pad = 1;
+    const int64_t nchunks = (E + PULL_VT - 1) / PULL_VT;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nchunks;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e0 = c * PULL_VT;
+        const int n = (int)min((int64_t)PULL_VT, E - e0);
+        uint32_t dst[PULL_VT], src[PULL_VT], m[PULL_VT];
+        if (n == PULL_VT) {
+            const uint4 *r4 = reinterpret_cast<const uint4 *>(rec + e0);
 #pragma unroll
-            for (int i = 0; i < PR_VT; i++) {
-                const int p = tid + i * PR_BLOCK;
-                u[i] = 0u;
-                w[i] = 0u;
-                if (p < n) {
-                    if (WEIGHTED) {
-                        const uint2 a = static_cast<const uint2 *>(adj)[e0 + p];
-                        u[i] = a.x;
-                        w[i] = a.y;
-                    } else {
-                        u[i] = (uint32_t) static_cast<const int32_t *>(adj)[e0 + p];
-                    }
-                }
+            for (int i = 0; i < PULL_VT / 2; i++) {
+                const uint4 q = r4[i];
+                dst[2 * i] = q.x;
+                src[2 * i] = q.y;
+                dst[2 * i + 1] = q.z;
+                src[2 * i + 1] = q.w;
             }
+        } else {
 #pragma unroll
-            for (int i = 0; i < PR_VT; i++) f[i] = (tid + i * PR_BLOCK < n) ? front_cur[u[i]] : 0u;
-#pragma unroll
-            for (int i = 0; i < PR_VT; i++) {
-                const int p = tid + i * PR_BLOCK;
-                if (p >= n) continue;
-                uint32_t m = INF;
-                if (f[i]) m = WEIGHTED ? sat_add(snap[u[i]], w[i]) : snap[u[i]];
-                s_val[p] = m;
-                s_own[p] = 0;
+            for (int i = 0; i < PULL_VT; i++) {
+                const uint2 q = i < n ? rec[e0 + i] : make_uint2(0xFFFFFFFFu, 0u);
+                dst[i] = q.x;
+                src[i] = q.y;
             }
         }
-        __syncthreads();
-        for (int32_t r = r_lo + tid; r < r_hi; r += PR_BLOCK) {
-            int32_t a = rp[r], b = rp[r + 1];
-            if (b > a) s_own[a - e0] = r - r_lo + 1;
+#pragma unroll
+        for (int i = 0; i < PULL_VT; i++) {
+            const uint32_t u = WEIGHTED ? (src[i] >> 8) : src[i];
+            m[i] = (i < n && front_cur[u]) ? 1u : 0u;
         }
-        __syncthreads();
-        block_max_scan<PR_VT>(s_own, n, s_red);
-
-        auto finish = [&](int o, uint32_t m, bool ends_tile) {
-            if (m == INF) return;
-            const int32_t r = o == 0 ? r_lo - 1 : r_lo + o - 1;  // owner 0: row begun in an earlier tile
-            const bool crossing = (o == 0) || (ends_tile && rp[r + 1] > e0 + n);
-            uint32_t old;
-            if (crossing) {
-                old = atomicMin(&val[r], m);
+#pragma unroll
+        for (int i = 0; i < PULL_VT; i++) {
+            if (m[i]) {
+                const uint32_t u = WEIGHTED ? (src[i] >> 8) : src[i];
+                m[i] = WEIGHTED ? sat_add(snap[u], src[i] & 0xFFu) : snap[u];
             } else {
-                old = val[r];
-                if (m < old) val[r] = m;
+                m[i] = INF;
             }
-            if (m < old) {
-                front_next[r] = 1;
-                dirty[r] = 1;
-            }
-        };
-        const int c0 = tid * PR_VT, c1 = min(c0 + PR_VT, n);
-        int own = -1, first_own = -1;
-        bool started = false, first = true, defer = false, defer_end = false;
-        uint32_t mn = INF, first_mn = INF;
-        for (int p = c0; p < c1; p++) {
-            int o = s_own[p];
-            if (o != own) {
-                if (own >= 0) {
-                    if (first && !started) {
-                        defer = true;
-                        first_mn = mn;
-                        first_own = own;
-                    } else {
-                        finish(own, mn, false);
+        }
+        uint32_t run_dst = dst[0], run_min = m[0];
+#pragma unroll
+        for (int i = 1; i <= PULL_VT; i++) {
+            const bool more = i < n;
+            if (!more || dst[i] != run_dst) {  // the run of run_dst ends here
+                if (run_min != INF && run_min < val[run_dst]) {
+                    const uint32_t old = atomicMin(&val[run_dst], run_min);
+                    if (run_min < old) {
+                        front_next[run_dst] = 1;
+                        dirty[run_dst] = 1;
                     }
-                    first = false;
                 }
-                own = o;
-                mn = INF;
-                started = (p == 0) ? (o != 0) : (p > c0 || s_own[p - 1] != o);
-            }
-            mn = min(mn, s_val[p]);
-        }
-        bool last_ends_here = false;
-        if (own >= 0) {
-            last_ends_here = (c1 == n) || (s_own[c1] != own);
-            if (last_ends_here) {
-                if (first && !started) {
-                    defer = true;
-                    defer_end = (c1 == n);
-                    first_mn = mn;
-                    first_own = own;
-                } else {
-                    finish(own, mn, c1 == n);
-                }
+                if (!more) break;
+                run_dst = dst[i];
+                run_min = m[i];
+            } else {
+                run_min = min(run_min, m[i]);
             }
         }
-        s_last[tid] = (own >= 0 && !last_ends_here) ? mn : INF;
-        s_last_start[tid] = started ? 1 : 0;
-        __syncthreads();
-        if (defer) {
-            uint32_t tot = first_mn;
-            for (int j = tid - 1; j >= 0; j--) {
-                tot = min(tot, s_last[j]);
-                if (s_last_start[j]) break;
-            }
-            finish(first_own, tot, defer_end);
-        }
-        __syncthreads();
     }
 }
 
@@ -794,10 +742,10 @@ extern "C" gx_status gx_state_init(gx_graph *g, const gx_params *p, void *dev_st
     Carver c(dev_state, bytes);
     state_layout(g, p, c, s);
     s->push_grid = persistent_grid(g, k_push<true>, PUSH_BLOCK);
-    s->pull_grid = persistent_grid(g, k_pull<true>, PR_BLOCK);
+    s->pull_grid = persistent_grid(g, k_pull<true>, 256);
     if (p->algo != GX_PAGERANK) {
         const DevGraph &dg = g->d;
-        bool can_pull = p->algo == GX_SSSP ? (dg.in_adj != nullptr) : (dg.sym_wrow != nullptr);
+        bool can_pull = p->algo == GX_SSSP ? (dg.pull_w != nullptr) : (dg.pull_sym != nullptr);
         double frac = p->pull_fraction > 0.f ? (double)p->pull_fraction : 0.3;
         double Eimg = (double)(p->algo == GX_SSSP ? dg.E : dg.E_sym);
         s->pull_edges = (!can_pull || frac >= 1.0) ? 0xFFFFFFFFu : (uint32_t)std::max(1.0, std::ceil(frac * Eimg));
@@ -958,16 +906,15 @@ static gx_status enqueue_superstep(gx_state *s, hipStream_t hs) {
                                    (const void *)d.out_adj, s->val, s->front8[cur ^ 1], s->dirty8, step,
                                    s->pull_edges);
                 if (s->pull_edges != 0xFFFFFFFFu)
-                    hipLaunchKernelGGL(k_pull<true>, dim3(s->pull_grid), dim3(PR_BLOCK), 0, hs, d.in_rp,
-                                       (const void *)d.in_adj, d.pr_tile_row, d.pr_ntiles, d.E, s->front8[cur],
-                                       s->snap, s->val, s->front8[cur ^ 1], s->dirty8, step, s->pull_edges);
+                    hipLaunchKernelGGL(k_pull<true>, dim3(s->pull_grid), dim3(256), 0, hs, d.pull_w, d.E,
+                                       s->front8[cur], s->snap, s->val, s->front8[cur ^ 1], s->dirty8, step,
+                                       s->pull_edges);
             } else {
                 hipLaunchKernelGGL(k_push<false>, dim3(s->push_grid), dim3(PUSH_BLOCK), 0, hs, s->list,
                                    s->tile_start, (const void *)d.sym_col, s->val, s->front8[cur ^ 1], s->dirty8,
                                    step, s->pull_edges);
                 if (s->pull_edges != 0xFFFFFFFFu)
-                    hipLaunchKernelGGL(k_pull<false>, dim3(s->pull_grid), dim3(PR_BLOCK), 0, hs, d.sym_rp,
-                                       (const void *)d.sym_col, d.sym_tile_row, d.sym_ntiles, d.E_sym,
+                    hipLaunchKernelGGL(k_pull<false>, dim3(s->pull_grid), dim3(256), 0, hs, d.pull_sym, d.E_sym,
                                        s->front8[cur], s->snap, s->val, s->front8[cur ^ 1], s->dirty8, step,
                                        s->pull_edges);
             }
