@@ -57,6 +57,7 @@ struct BpArgs {
     uint32_t Bw;  // lanes processed (0..Bw-1); the rest keep their values untouched
     float d;
     const int32_t *seed;  // per lane; -1 = free lane
+    const int32_t *end;   // per lane: first superstep it no longer runs (NULL: every lane runs every superstep)
     float *x[2], *c[2];
     double *head, *tailp, *dsum, *dpart, *D[2];  // D[k & 1]: dangling mass of superstep k
     int32_t *spill;
@@ -68,7 +69,7 @@ struct BpWork {
     int64_t ntiles;
     float *x[2], *c[2];
     double *head, *tailp, *dsum, *dpart, *D[2];
-    int32_t *spill, *trow, *seed;
+    int32_t *spill, *trow, *seed, *end;
     GridBar *bar;
 };
 

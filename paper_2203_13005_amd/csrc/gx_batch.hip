@@ -14,8 +14,9 @@
 //     start.
 //   relaxation: 8 threads per work unit handle the unit's 32 lanes (4 each,
 //     one 16-byte load of the destination's group); improvements are
-//     folded by atomicMin per lane, and the group's improved-lane bits by one
-//     atomicOr into the next mask.
+//     folded by atomicMin per lane (no result awaited: a candidate below a
+//     value read during the superstep already proves the lane changes), and
+//     the group's improved-lane bits by one atomicOr into the next mask.
 //   A grid barrier separates the phases; the loop ends when a superstep
 //   activates no (vertex, lane) pair.
 // PPR (k_bppr): per superstep a pull over equal in-edge tiles (one wave per
@@ -137,70 +138,68 @@ __device__ __forceinline__ void bs_relax(const BsArgs &a, uint32_t k, uint32_t i
         __syncthreads();
         block_max_scan<VT>(sh.own, n, sh.red);
         // UB work units per 8-thread group at a time: their edge loads, then
-        // their snapshot and destination loads, then the relaxations.
+        // their snapshot and destination loads, then the relaxations, all
+        // loads unconditional (units past the tile's end repeat its last
+        // unit with no lanes).  The lane minima go out as atomics whose
+        // results are not awaited; only the mask atomics return, once.
         constexpr int UB = 4;
         for (int p0 = tid >> 3; p0 < n; p0 += UNITS * UB) {
             uint2 ed[UB];
             uint32_t my4[UB], gq[UB], jq[UB];
 #pragma unroll
             for (int q = 0; q < UB; q++) {
-                const int p = p0 + q * UNITS;
-                ed[q] = make_uint2(0u, 0u);
-                my4[q] = 0u;
-                gq[q] = 0u;
-                jq[q] = 0u;
-                if (p < n) {
-                    const int j = sh.own[p];
-                    jq[q] = (uint32_t)j;
-                    gq[q] = sh.g[j];
-                    my4[q] = (sh.mask[j] >> (sub * 4)) & 15u;
-                    ed[q] = a.adj[sh.base[j] + (uint32_t)p];
-                }
+                const int p = min(p0 + q * UNITS, n - 1);
+                const int j = sh.own[p];
+                jq[q] = (uint32_t)j;
+                gq[q] = sh.g[j];
+                my4[q] = (p0 + q * UNITS < n) ? (sh.mask[j] >> (sub * 4)) & 15u : 0u;
+                ed[q] = a.adj[sh.base[j] + (uint32_t)p];
             }
             uint4 sn[UB], cur[UB];
 #pragma unroll
             for (int q = 0; q < UB; q++) {
-                if (my4[q]) {
-                    sn[q] = a.S[(size_t)(s0 + jq[q]) * 8 + sub];
-                    cur[q] = *reinterpret_cast<const uint4 *>(a.D + (size_t)ed[q].x * a.B + a.l0 + gq[q] * 32 +
-                                                              sub * 4);
-                } else {
-                    sn[q] = make_uint4(INF, INF, INF, INF);
-                    cur[q] = make_uint4(0u, 0u, 0u, 0u);
+                sn[q] = a.S[(size_t)(s0 + jq[q]) * 8 + sub];
+                cur[q] = *reinterpret_cast<const uint4 *>(a.D + (size_t)ed[q].x * a.B + a.l0 + gq[q] * 32 + sub * 4);
+            }
+            uint32_t cand[UB][4], word[UB];
+#pragma unroll
+            for (int q = 0; q < UB; q++) {
+                const uint32_t snv[4] = {sn[q].x, sn[q].y, sn[q].z, sn[q].w};
+                const uint32_t cv[4] = {cur[q].x, cur[q].y, cur[q].z, cur[q].w};
+                uint32_t imp = 0;
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    cand[q][r] = sat_add(snv[r], ed[q].y);
+                    // below a value read this superstep: the lane changes
+                    if (((my4[q] >> r) & 1u) && cand[q][r] < cv[r]) imp |= 1u << r;
                 }
+                uint32_t w = imp << (sub * 4);
+                w |= __shfl_xor(w, 1, 8);
+                w |= __shfl_xor(w, 2, 8);
+                w |= __shfl_xor(w, 4, 8);
+                word[q] = w;
             }
 #pragma unroll
             for (int q = 0; q < UB; q++) {
-                const int p = p0 + q * UNITS;
-                uint32_t imp = 0;
-                if (my4[q]) {
-                    uint32_t *dp = a.D + (size_t)ed[q].x * a.B + a.l0 + gq[q] * 32 + sub * 4;
-                    const uint32_t snv[4] = {sn[q].x, sn[q].y, sn[q].z, sn[q].w};
-                    const uint32_t cv[4] = {cur[q].x, cur[q].y, cur[q].z, cur[q].w};
+                const uint32_t imp = (word[q] >> (sub * 4)) & 15u;
+                uint32_t *dp = a.D + (size_t)ed[q].x * a.B + a.l0 + gq[q] * 32 + sub * 4;
 #pragma unroll
-                    for (int r = 0; r < 4; r++) {
-                        if (!((my4[q] >> r) & 1u)) continue;
-                        const uint32_t cand = sat_add(snv[r], ed[q].y);
-                        if (cand < cv[r]) {
-                            uint32_t old = atomicMin(dp + r, cand);
-                            if (cand < old) imp |= 1u << r;
-                        }
-                    }
-                }
-                if (p < n) {  // uniform within the 8-thread group
-                    uint32_t word = imp << (sub * 4);
-                    word |= __shfl_xor(word, 1, 8);
-                    word |= __shfl_xor(word, 2, 8);
-                    word |= __shfl_xor(word, 4, 8);
-                    if (sub == 0 && word) {
-                        const uint32_t v = ed[q].x, g = gq[q];
-                        uint32_t prev = atomicOr(&Mn[(size_t)v * a.G + g], word);
-                        uint32_t nb = word & ~prev;
-                        changed += __popc(nb);
-                        if (a.lane_cnt)
-                            for (uint32_t mm = nb; mm; mm &= mm - 1)
-                                atomicAdd(&sh.lane[g * 32 + __ffs(mm) - 1], 1u);
-                    }
+                for (int r = 0; r < 4; r++)
+                    if ((imp >> r) & 1u) atomicMin(dp + r, cand[q][r]);
+            }
+            // The group leader ORs all UB words (a zero word changes nothing)
+            // under one branch, so the returns are awaited once.
+            if (sub == 0 && (word[0] | word[1] | word[2] | word[3])) {
+                static_assert(UB == 4, "the branch above names the UB words");
+                uint32_t prev[UB];
+#pragma unroll
+                for (int q = 0; q < UB; q++) prev[q] = atomicOr(&Mn[(size_t)ed[q].x * a.G + gq[q]], word[q]);
+#pragma unroll
+                for (int q = 0; q < UB; q++) {
+                    const uint32_t nb = word[q] & ~prev[q];
+                    changed += __popc(nb);
+                    if (a.lane_cnt)
+                        for (uint32_t mm = nb; mm; mm &= mm - 1) atomicAdd(&sh.lane[gq[q] * 32 + __ffs(mm) - 1], 1u);
                 }
             }
         }
@@ -277,52 +276,91 @@ __global__ __launch_bounds__(256) void k_bs_lane_reset(uint32_t *D, uint32_t *Mc
 
 // ------------------------------------------------------------------ PPR
 
+// Per-lane constants of one PPR superstep, held in registers: lane b =
+// lane + 64 i is live when it is inside the processed width, holds a query
+// and has not reached its end superstep (a finished lane is frozen: its
+// values stay as they were after its last superstep, in x[end & 1]).
 template <int LPT>
-__device__ __forceinline__ void ppr_apply(const BpArgs &a, int32_t r, const double (&acc)[LPT], const double *Dcur,
-                                          const float *x_in, float *x_out, float *c_out, double (&dang)[LPT],
+struct PprLanes {
+    uint32_t bl[LPT];  // load column (clamped into the processed width)
+    bool live[LPT];
+    int32_t seed[LPT];
+    double dc[LPT];    // dangling mass of the lane at the start of the superstep
+    __device__ PprLanes(const BpArgs &a, uint32_t k, const double *Dcur, int lane) {
+#pragma unroll
+        for (int i = 0; i < LPT; i++) {
+            const uint32_t b = lane + 64 * i;
+            bl[i] = min(b, a.Bw - 1);
+            const int32_t sd = b < a.Bw ? a.seed[b] : -1;
+            live[i] = sd >= 0 && (!a.end || (int32_t)((uint32_t)a.end[b] - k) > 0);
+            seed[i] = sd;
+            dc[i] = b < a.Bw ? Dcur[b] : 0.0;
+        }
+    }
+};
+
+template <int LPT>
+__device__ __forceinline__ void ppr_apply(const BpArgs &a, int32_t r, int od, const double (&acc)[LPT],
+                                          const PprLanes<LPT> &L, float *x_out, float *c_out, double (&dang)[LPT],
                                           int lane) {
-    const int od = a.outdeg[r];
 #pragma unroll
     for (int i = 0; i < LPT; i++) {
+        if (!L.live[i]) continue;
         const uint32_t b = lane + 64 * i;
-        if (b >= a.Bw) continue;
         double v = (double)a.d * acc[i];
-        if (a.seed[b] == r) v += (1.0 - (double)a.d) + (double)a.d * Dcur[b];
-        float xn = (float)v;
-        if (a.seed[b] < 0) xn = x_in[(size_t)r * a.B + b];  // free lane: keep whatever it holds
+        if (L.seed[i] == r) v += (1.0 - (double)a.d) + (double)a.d * L.dc[i];
+        const float xn = (float)v;
         x_out[(size_t)r * a.B + b] = xn;
         c_out[(size_t)r * a.B + b] = od > 0 ? xn / (float)od : 0.0f;
         if (od == 0) dang[i] += (double)xn;
     }
 }
 
+// Sum over in-edges e_lo..e_hi-1 (in edge order) of the sources' lane
+// contributions.  The wave loads 64 source ids at a time (one per lane) and
+// broadcasts them; the contribution rows of EB edges are loaded before any
+// is added, so a row's loads overlap instead of waiting one by one.
 template <int LPT>
 __device__ __forceinline__ void ppr_gather(const BpArgs &a, const float *c_in, int32_t e_lo, int32_t e_hi,
-                                           double (&acc)[LPT], int lane) {
+                                           double (&acc)[LPT], const PprLanes<LPT> &L, int lane) {
+    constexpr int EB = 8;
 #pragma unroll
     for (int i = 0; i < LPT; i++) acc[i] = 0.0;
-    for (int32_t e = e_lo; e < e_hi; e++) {
-        const int32_t u = a.in_col[e];
-        const float *row = c_in + (size_t)u * a.B;
+    for (int32_t eb = e_lo; eb < e_hi; eb += 64) {
+        const int cnt = min(64, e_hi - eb);
+        const int32_t myu = a.in_col[eb + min(lane, cnt - 1)];
+        for (int j0 = 0; j0 < cnt; j0 += EB) {
+            const int nb = min(EB, cnt - j0);
+            float v[EB][LPT];
 #pragma unroll
-        for (int i = 0; i < LPT; i++) {
-            const uint32_t b = lane + 64 * i;
-            if (b < a.Bw) acc[i] += (double)row[b];
+            for (int jj = 0; jj < EB; jj++) {
+                const int32_t u = __shfl(myu, j0 + min(jj, nb - 1), 64);
+                const float *row = c_in + (size_t)u * a.B;
+#pragma unroll
+                for (int i = 0; i < LPT; i++) v[jj][i] = row[L.bl[i]];
+            }
+#pragma unroll
+            for (int jj = 0; jj < EB; jj++)
+                if (jj < nb)
+#pragma unroll
+                    for (int i = 0; i < LPT; i++) acc[i] += (double)v[jj][i];
         }
     }
 }
 
-// PPR phase P of superstep k: pull tiles, one wave per tile.
+// PPR phase P of superstep k: pull tiles, one wave per tile.  The row
+// pointers and out-degrees of up to 64 rows are loaded at once (one per
+// lane) and broadcast.
 template <int LPT>
 __device__ __forceinline__ void bp_pull(const BpArgs &a, uint32_t k, const double *Dcur) {
     const int lane = threadIdx.x & 63;
     const int64_t gwave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
     const int32_t TP = BP_TILE;
-    const float *x_in = a.x[k & 1];
     float *x_out = a.x[(k + 1) & 1];
     const float *c_in = a.c[k & 1];
     float *c_out = a.c[(k + 1) & 1];
+    const PprLanes<LPT> L(a, k, Dcur, lane);
     for (int64_t t = gwave; t < a.ntiles; t += nwaves) {
         const int32_t e0 = (int32_t)(t * TP);
         const int32_t e1 = (int32_t)std::min<int64_t>((int64_t)e0 + TP, a.E);
@@ -333,22 +371,30 @@ __device__ __forceinline__ void bp_pull(const BpArgs &a, uint32_t k, const doubl
         if (lane == 0) a.spill[t] = -1;
         const int32_t first_start = r_lo < a.V ? a.in_rp[r_lo] : (int32_t)a.E;
         if (e0 < e1 && first_start > e0) {  // row begun in an earlier tile
-            ppr_gather<LPT>(a, c_in, e0, std::min(first_start, e1), acc, lane);
+            ppr_gather<LPT>(a, c_in, e0, std::min(first_start, e1), acc, L, lane);
 #pragma unroll
             for (int i = 0; i < LPT; i++)
                 if (lane + 64 * i < (int)a.Bw) a.head[t * a.B + lane + 64 * i] = acc[i];
         }
-        for (int32_t r = r_lo; r < r_hi; r++) {
-            const int32_t rs = a.in_rp[r], re = a.in_rp[r + 1];
-            if (re > e1) {  // continues into later tiles
-                ppr_gather<LPT>(a, c_in, rs, e1, acc, lane);
+        int32_t rs = first_start;
+        for (int32_t rb = r_lo; rb < r_hi; rb += 64) {
+            const int nr = std::min<int32_t>(64, r_hi - rb);
+            const int32_t rq = rb + std::min(lane, nr - 1);
+            const int32_t my_re = a.in_rp[rq + 1], my_od = a.outdeg[rq];
+            for (int j = 0; j < nr; j++) {
+                const int32_t r = rb + j;
+                const int32_t re = __shfl(my_re, j, 64);
+                if (re > e1) {  // continues into later tiles
+                    ppr_gather<LPT>(a, c_in, rs, e1, acc, L, lane);
 #pragma unroll
-                for (int i = 0; i < LPT; i++)
-                    if (lane + 64 * i < (int)a.Bw) a.tailp[t * a.B + lane + 64 * i] = acc[i];
-                if (lane == 0) a.spill[t] = r;
-            } else {
-                ppr_gather<LPT>(a, c_in, rs, re, acc, lane);
-                ppr_apply<LPT>(a, r, acc, Dcur, x_in, x_out, c_out, dang, lane);
+                    for (int i = 0; i < LPT; i++)
+                        if (lane + 64 * i < (int)a.Bw) a.tailp[t * a.B + lane + 64 * i] = acc[i];
+                    if (lane == 0) a.spill[t] = r;
+                } else {
+                    ppr_gather<LPT>(a, c_in, rs, re, acc, L, lane);
+                    ppr_apply<LPT>(a, r, __shfl(my_od, j, 64), acc, L, x_out, c_out, dang, lane);
+                }
+                rs = re;
             }
         }
 #pragma unroll
@@ -363,9 +409,9 @@ __device__ __forceinline__ void bp_fix(const BpArgs &a, uint32_t k, const double
     const int lane = threadIdx.x & 63;
     const int64_t gwave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    const float *x_in = a.x[k & 1];
     float *x_out = a.x[(k + 1) & 1];
     float *c_out = a.c[(k + 1) & 1];
+    const PprLanes<LPT> L(a, k, Dcur, lane);
     for (int64_t t = gwave; t < a.ntiles; t += nwaves) {
         const int32_t r = a.spill[t];
         if (r < 0) continue;
@@ -381,7 +427,7 @@ __device__ __forceinline__ void bp_fix(const BpArgs &a, uint32_t k, const double
             for (int32_t t2 = (int32_t)t + 1; t2 <= t_end; t2++) s += a.head[(int64_t)t2 * a.B + b];
             acc[i] = s;
         }
-        ppr_apply<LPT>(a, r, acc, Dcur, x_in, x_out, c_out, dang, lane);
+        ppr_apply<LPT>(a, r, a.outdeg[r], acc, L, x_out, c_out, dang, lane);
 #pragma unroll
         for (int i = 0; i < LPT; i++)
             if (lane + 64 * i < (int)a.Bw) a.dsum[t * a.B + lane + 64 * i] += dang[i];
@@ -561,7 +607,8 @@ void bp_layout(const DevGraph &d, uint32_t B, Carver &c, BpWork *w) {
     w->D[1] = c.take<double>(B);
     w->spill = c.take<int32_t>(nt);
     w->trow = c.take<int32_t>(nt + 1);
-    w->seed = c.take<int32_t>(B);
+    w->seed = c.take<int32_t>(2 * (size_t)B);  // seeds, then per-lane end supersteps
+    w->end = w->seed + B;
     w->bar = c.take<GridBar>(1);
 }
 

@@ -11,13 +11,16 @@
 // SSSP / CC superstep k (A_k = vertices active in superstep k):
 //   k_push    : every workgroup tile relaxes exactly PUSH_TILE active
 //               out-edges: Gen = snapshot (+ weight), Merge + Apply =
-//               integer atomicMin on the destination; an improvement marks
-//               the destination in the next frontier and the dirty map
-//               (plain, idempotent byte stores).
-//   k_pull    : for large frontiers instead: equal tiles over all in-edges,
-//               min per destination row in LDS, atomics only for rows that
-//               cross a tile boundary.  The device picks push or pull from
-//               the frontier's out-edge count; no host round trip.
+//               integer atomicMin on the destination, filtered by a plain
+//               read; a candidate that passes marks the destination in the
+//               next frontier and the dirty map (plain, idempotent byte
+//               stores).
+//   k_pull    : for large frontiers instead: one streaming sweep over all
+//               in-edge records, grouped by source band so the gathered
+//               snapshots stay cache resident, min per run of equal
+//               destination, the same filtered atomics.  The device picks
+//               push or pull from the frontier's out-edge count; no host
+//               round trip.
 //   k_compact : frontier byte map A_{k+1} -> active list of (edge offset,
 //               CSR base, snapshot) for active vertices with out-edges; one
 //               64-bit atomic per workgroup reserves list slots and edge
@@ -125,15 +128,16 @@ __global__ __launch_bounds__(256) void k_min_init(uint32_t *val, uint8_t *f0, ui
     }
 }
 
-// Frontier byte map -> active list.  Each thread takes CVT vertices strided
-// by the block size (coalesced byte and row-pointer loads), so a workgroup
-// covers 256*CVT vertices and the whole grid issues few counter atomics (one
-// per workgroup for the list, one for |A|).  Active vertices with out-edges
-// get a list entry (edge offset, CSR base, snapshot); the tiles that start
-// inside an entry's edges record it.  The kernel also clears the byte map the
-// next relaxation fills (it held A_{k-1}) and stores the snapshot of active
-// vertices for the pull.  |A_{k+1}| is the number of vertices superstep k
-// changed.
+// Frontier byte map -> active list.  Each thread takes CVT consecutive
+// vertices: one 16-byte load of their frontier bytes (and one 16-byte store
+// clearing the byte map the next relaxation fills, which held A_{k-1}); a
+// thread with an active vertex loads its CVT+1 row pointers and CVT values
+// as whole vectors, so no load waits on another.  A workgroup covers
+// 256*CVT vertices and issues two counter atomics (list, |A|).  Active
+// vertices with out-edges get a list entry (edge offset, CSR base,
+// snapshot, vertex), their snapshot is stored for the pull, and the tiles
+// that start inside an entry's edges record it.  |A_{k+1}| is the number of
+// vertices superstep k changed.
 constexpr int CVT = 16;
 
 __global__ __launch_bounds__(256) void k_compact(const uint8_t *__restrict__ front, uint8_t *__restrict__ front_clear,
@@ -146,31 +150,55 @@ __global__ __launch_bounds__(256) void k_compact(const uint8_t *__restrict__ fro
     __shared__ int s_nf[4];
     const int tid = threadIdx.x;
     if (blockIdx.x == 0 && tid == 0) *next_step = DevStep{0, 0, 0, 0};
-    const int64_t v0 = (int64_t)blockIdx.x * 256 * CVT + tid;
+    const int64_t u0 = ((int64_t)blockIdx.x * 256 + tid) * CVT;
     uint32_t actmask = 0;
+    if (u0 < V) {  // byte maps are padded to whole 32-vertex words: the 16 bytes at u0 exist
+        const uint4 f = *reinterpret_cast<const uint4 *>(front + u0);
+        *reinterpret_cast<uint4 *>(front_clear + u0) = make_uint4(0u, 0u, 0u, 0u);
+        const uint32_t fw[4] = {f.x, f.y, f.z, f.w};
 #pragma unroll
-    for (int i = 0; i < CVT; i++) {
-        const int64_t u = v0 + (int64_t)i * 256;
-        if (u < V) {
-            if (front[u]) actmask |= 1u << i;
-            front_clear[u] = 0;
-        }
+        for (int q = 0; q < 4; q++)
+#pragma unroll
+            for (int b = 0; b < 4; b++)
+                if ((fw[q] >> (8 * b)) & 0xFFu) actmask |= 1u << (4 * q + b);
+        if (V - u0 < CVT) actmask &= (1u << (V - u0)) - 1u;  // padding bytes are no vertices
     }
     if (!__syncthreads_or(actmask != 0)) return;
-    int32_t r0[CVT], dg[CVT];
+    int32_t r[CVT + 1];
+    uint32_t x[CVT];
+#pragma unroll
+    for (int i = 0; i < CVT; i++) {
+        r[i] = 0;
+        x[i] = 0;
+    }
+    r[CVT] = 0;
+    if (actmask) {
+        if (u0 + CVT <= V) {  // rows u0 .. u0+CVT of the V+1 row pointers
+            const int4 *r4 = reinterpret_cast<const int4 *>(rp + u0);
+            const uint4 *x4 = reinterpret_cast<const uint4 *>(val + u0);
+#pragma unroll
+            for (int q = 0; q < CVT / 4; q++) {
+                const int4 a = r4[q];
+                const uint4 b = x4[q];
+                r[4 * q] = a.x, r[4 * q + 1] = a.y, r[4 * q + 2] = a.z, r[4 * q + 3] = a.w;
+                x[4 * q] = b.x, x[4 * q + 1] = b.y, x[4 * q + 2] = b.z, x[4 * q + 3] = b.w;
+            }
+            r[CVT] = rp[u0 + CVT];
+        } else {
+#pragma unroll
+            for (int i = 0; i < CVT; i++) {
+                if (u0 + i < V) x[i] = val[u0 + i];
+                if (u0 + i <= V) r[i] = rp[u0 + i];
+            }
+        }
+    }
     uint32_t cnt = 0, edges = 0;
 #pragma unroll
     for (int i = 0; i < CVT; i++) {
-        r0[i] = 0;
-        dg[i] = 0;
-        if ((actmask >> i) & 1u) {
-            const int64_t u = v0 + (int64_t)i * 256;
-            r0[i] = rp[u];
-            dg[i] = rp[u + 1] - r0[i];
-            if (dg[i] > 0) {
-                cnt++;
-                edges += (uint32_t)dg[i];
-            }
+        const int32_t dg = r[i + 1] - r[i];
+        if (((actmask >> i) & 1u) && dg > 0) {
+            cnt++;
+            edges += (uint32_t)dg;
         }
     }
     unsigned long long mine = ((unsigned long long)cnt << 32) | edges, total;
@@ -185,15 +213,15 @@ __global__ __launch_bounds__(256) void k_compact(const uint8_t *__restrict__ fro
     unsigned long long pos = s_base + pre;
 #pragma unroll
     for (int i = 0; i < CVT; i++) {
-        if (dg[i] <= 0) continue;
-        const int64_t u = v0 + (int64_t)i * 256;
+        const int32_t dg = r[i + 1] - r[i];
+        if (!((actmask >> i) & 1u) || dg <= 0) continue;
+        const int64_t u = u0 + i;
         const uint32_t idx = (uint32_t)(pos >> 32), off = (uint32_t)pos;
-        const uint32_t x = val[u];
-        snap[u] = x;
-        list[idx] = make_uint4(off, (uint32_t)(r0[i] - (int32_t)off), x, (uint32_t)u);
-        const uint32_t t0 = (off + PUSH_TILE - 1) / PUSH_TILE, t1 = (off + (uint32_t)dg[i] - 1) / PUSH_TILE;
+        snap[u] = x[i];
+        list[idx] = make_uint4(off, (uint32_t)(r[i] - (int32_t)off), x[i], (uint32_t)u);
+        const uint32_t t0 = (off + PUSH_TILE - 1) / PUSH_TILE, t1 = (off + (uint32_t)dg - 1) / PUSH_TILE;
         for (uint32_t t = t0; t <= t1; t++) tile_start[t] = idx;
-        pos += (1ull << 32) + (uint32_t)dg[i];
+        pos += (1ull << 32) + (uint32_t)dg;
     }
 }
 
@@ -231,38 +259,47 @@ __global__ __launch_bounds__(PUSH_BLOCK) void k_push(const uint4 *__restrict__ l
         }
         __syncthreads();
         block_max_scan<PUSH_VT>(s_own, n, s_red);
-        // Batched memory access: all edge loads of this thread first, then all
-        // destination reads, then the relaxations (no load waits on another
-        // edge's atomic).
+        // Batched memory access: every load is unconditional (slots past the
+        // tile's end repeat its last edge and are dropped at the end), so the
+        // thread issues all its edge loads, then all destination reads, with
+        // one wait each and no load behind another edge's atomic.
+        uint32_t idx[PUSH_VT], sv[PUSH_VT];
+#pragma unroll
+        for (int i = 0; i < PUSH_VT; i++) {
+            const int p = min(tid + i * PUSH_BLOCK, n - 1);
+            const int j = s_own[p];
+            idx[i] = s_base[j] + (uint32_t)p;
+            sv[i] = s_snap[j];
+        }
         uint32_t dst[PUSH_VT], cand[PUSH_VT], cur[PUSH_VT];
 #pragma unroll
         for (int i = 0; i < PUSH_VT; i++) {
-            const int p = tid + i * PUSH_BLOCK;
-            dst[i] = 0u;
-            cand[i] = INF;
-            if (p < n) {
-                const int j = s_own[p];
-                const uint32_t idx = s_base[j] + (uint32_t)p;
-                if (WEIGHTED) {
-                    const uint2 a = static_cast<const uint2 *>(adj)[idx];
-                    dst[i] = a.x;
-                    cand[i] = sat_add(s_snap[j], a.y);
-                } else {
-                    dst[i] = (uint32_t) static_cast<const int32_t *>(adj)[idx];
-                    cand[i] = s_snap[j];
-                }
+            if (WEIGHTED) {
+                const uint2 a = static_cast<const uint2 *>(adj)[idx[i]];
+                dst[i] = a.x;
+                cand[i] = a.y;
+            } else {
+                dst[i] = (uint32_t) static_cast<const int32_t *>(adj)[idx[i]];
             }
         }
 #pragma unroll
-        for (int i = 0; i < PUSH_VT; i++) cur[i] = cand[i] != INF ? val[dst[i]] : 0u;
+        for (int i = 0; i < PUSH_VT; i++) cur[i] = val[dst[i]];
+#pragma unroll
+        for (int i = 0; i < PUSH_VT; i++) {
+            cand[i] = WEIGHTED ? sat_add(sv[i], cand[i]) : sv[i];
+            if (tid + i * PUSH_BLOCK >= n) cand[i] = INF;
+        }
+        // A candidate below a value read during this superstep is below the
+        // destination's start-of-superstep value (values only fall), so the
+        // destination changes in this superstep whichever atomic lands last:
+        // mark it with idempotent plain stores and let the atomic go without
+        // waiting for its result.
 #pragma unroll
         for (int i = 0; i < PUSH_VT; i++) {
             if (cand[i] < cur[i]) {
-                const uint32_t old = atomicMin(&val[dst[i]], cand[i]);
-                if (cand[i] < old) {  // improved in this superstep: idempotent plain stores
-                    front_next[dst[i]] = 1;
-                    dirty[dst[i]] = 1;
-                }
+                atomicMin(&val[dst[i]], cand[i]);
+                front_next[dst[i]] = 1;
+                dirty[dst[i]] = 1;
             }
         }
         __syncthreads();
@@ -309,42 +346,45 @@ __global__ __launch_bounds__(256) void k_pull(const uint2 *__restrict__ rec, int
         } else {
 #pragma unroll
             for (int i = 0; i < PULL_VT; i++) {
-                const uint2 q = i < n ? rec[e0 + i] : make_uint2(0xFFFFFFFFu, 0u);
+                const uint2 q = i < n ? rec[e0 + i] : make_uint2(0xFFFFFFFFu, 0u);  // pad: source 0, no run
                 dst[i] = q.x;
                 src[i] = q.y;
             }
         }
+        // Source flags and snapshots are read unconditionally (one wait for
+        // both; the band's slice is cache resident) and selected afterwards.
+        uint32_t f[PULL_VT];
 #pragma unroll
         for (int i = 0; i < PULL_VT; i++) {
             const uint32_t u = WEIGHTED ? (src[i] >> 8) : src[i];
-            m[i] = (i < n && front_cur[u]) ? 1u : 0u;
+            f[i] = front_cur[u];
+            m[i] = snap[u];
         }
 #pragma unroll
         for (int i = 0; i < PULL_VT; i++) {
-            if (m[i]) {
-                const uint32_t u = WEIGHTED ? (src[i] >> 8) : src[i];
-                m[i] = WEIGHTED ? sat_add(snap[u], src[i] & 0xFFu) : snap[u];
-            } else {
-                m[i] = INF;
-            }
+            const uint32_t c = WEIGHTED ? sat_add(m[i], src[i] & 0xFFu) : m[i];
+            m[i] = (i < n && f[i]) ? c : INF;
         }
-        uint32_t run_dst = dst[0], run_min = m[0];
+        // Minimum of each run of equal destination, kept at the run's last
+        // record; then one batched read of those destinations, then the
+        // filtered atomics (no result awaited, as in the push).
+        uint32_t cur[PULL_VT];
 #pragma unroll
-        for (int i = 1; i <= PULL_VT; i++) {
-            const bool more = i < n;
-            if (!more || dst[i] != run_dst) {  // the run of run_dst ends here
-                if (run_min != INF && run_min < val[run_dst]) {
-                    const uint32_t old = atomicMin(&val[run_dst], run_min);
-                    if (run_min < old) {
-                        front_next[run_dst] = 1;
-                        dirty[run_dst] = 1;
-                    }
-                }
-                if (!more) break;
-                run_dst = dst[i];
-                run_min = m[i];
-            } else {
-                run_min = min(run_min, m[i]);
+        for (int i = 1; i < PULL_VT; i++)
+            if (dst[i] == dst[i - 1]) m[i] = min(m[i], m[i - 1]);
+#pragma unroll
+        for (int i = 0; i < PULL_VT; i++) {
+            const bool last = i < n && (i + 1 == n || dst[i + 1] != dst[i]);
+            if (!last) m[i] = INF;
+        }
+#pragma unroll
+        for (int i = 0; i < PULL_VT; i++) cur[i] = val[m[i] != INF ? dst[i] : dst[0]];
+#pragma unroll
+        for (int i = 0; i < PULL_VT; i++) {
+            if (m[i] < cur[i]) {
+                atomicMin(&val[dst[i]], m[i]);
+                front_next[dst[i]] = 1;
+                dirty[dst[i]] = 1;
             }
         }
     }
@@ -416,18 +456,19 @@ __global__ __launch_bounds__(PR_BLOCK) void k_pr_pull(const int32_t *__restrict_
     const int32_t r_lo = tile_row[t], r_hi = tile_row[t + 1];
     ap.dD = ap.d * (*Dp) * inv_V;
     if (tid == 0) spill_row[t] = -1;
-    {  // contributions into LDS: source ids first, then the gathers
+    if (n > 0) {  // contributions into LDS: all source ids, then all gathers
+        // (unconditional loads: slots past the tile's end repeat its last edge)
         int32_t u[PR_VT];
+        float cv[PR_VT];
 #pragma unroll
-        for (int i = 0; i < PR_VT; i++) {
-            const int p = tid + i * PR_BLOCK;
-            u[i] = p < n ? in_col[e0 + p] : 0;
-        }
+        for (int i = 0; i < PR_VT; i++) u[i] = in_col[e0 + min(tid + i * PR_BLOCK, n - 1)];
+#pragma unroll
+        for (int i = 0; i < PR_VT; i++) cv[i] = c_in[u[i]];
 #pragma unroll
         for (int i = 0; i < PR_VT; i++) {
             const int p = tid + i * PR_BLOCK;
             if (p < n) {
-                s_val[p] = c_in[u[i]];
+                s_val[p] = cv[i];
                 s_own[p] = 0;
             }
         }

@@ -103,10 +103,11 @@ struct Pool {
     // result staging
     uint32_t *stage = nullptr;
     uint32_t *host_stage = nullptr;  // pinned, V words
-    uint32_t *host_cnt = nullptr;    // pinned, epoch x B activation counts
+    uint32_t *host_cnt = nullptr;    // pinned: SSSP epoch x B activation counts; PPR seeds and ends
     std::vector<int64_t> lane_q;     // query id per lane, -1 = free
     std::vector<int64_t> lane_age;   // supersteps since the lane joined
     std::vector<int32_t> seeds;      // PPR seed per lane (-1 = free)
+    std::vector<uint32_t> ends;      // PPR: first superstep the lane no longer runs (mod 2^32)
     uint32_t k = 0;                  // supersteps run (buffer parity)
     bool in_flight = false;
     uint32_t epoch_len = 0;
@@ -205,13 +206,14 @@ struct gx_server {
         p->lane_q.assign(B, -1);
         p->lane_age.assign(B, 0);
         p->seeds.assign(B, -1);
+        p->ends.assign(B, 0u);
         const DevGraph &d = g->d;
         Carver c(mem, bytes);
         bool ok = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) == hipSuccess &&
                   hipEventCreateWithFlags(&p->done, hipEventDisableTiming) == hipSuccess &&
                   hipHostMalloc((void **)&p->host_stage, std::max<size_t>(4, d.V * 4), hipHostMallocDefault) ==
                       hipSuccess &&
-                  hipHostMalloc((void **)&p->host_cnt, std::max<size_t>(4, (size_t)epoch_max() * B * 4),
+                  hipHostMalloc((void **)&p->host_cnt, std::max<size_t>((size_t)epoch_max(), 2) * B * 4,
                                 hipHostMallocDefault) == hipSuccess;
         if (algo == GX_SSSP) {
             p->D = c.take<uint32_t>((size_t)d.V * B);
@@ -237,8 +239,8 @@ struct gx_server {
                      hipMemsetAsync(p->pw.c[1], 0, n, s) == hipSuccess &&
                      hipMemsetAsync(p->pw.D[0], 0, B * 8, s) == hipSuccess &&
                      hipMemsetAsync(p->pw.D[1], 0, B * 8, s) == hipSuccess &&
-                     bp_make_tiles(d.in_rp, d.V, p->pw.ntiles, p->pw.trow, s) == hipSuccess &&
-                     hipMemcpyAsync(p->pw.seed, p->seeds.data(), B * 4, hipMemcpyHostToDevice, s) == hipSuccess;
+                     hipMemsetAsync(p->pw.seed, 0xFF, B * 4, s) == hipSuccess &&
+                     bp_make_tiles(d.in_rp, d.V, p->pw.ntiles, p->pw.trow, s) == hipSuccess;
             }
             ok = ok && hipStreamSynchronize(s) == hipSuccess;
         }
@@ -287,6 +289,7 @@ struct gx_server {
         a.Bw = p.B;
         a.d = cfg.damping;
         a.seed = p.pw.seed;
+        a.end = p.pw.end;
         a.x[0] = p.pw.x[0];
         a.x[1] = p.pw.x[1];
         a.c[0] = p.pw.c[0];
@@ -309,11 +312,12 @@ struct gx_server {
             e = bs_lane_reset(p.D, p.bw.M[p.k & 1], p.bw.M[(p.k + 1) & 1], d.V, p.B, p.B / 32, lane, q.source,
                               p.stream);
         } else {
+            // the lane runs supersteps k .. k + iterations - 1; its seed and end
+            // reach the device with the next epoch's lane table
             p.seeds[lane] = q.source;
+            p.ends[lane] = p.k + (uint32_t)cfg.ppr_iters;
             e = bp_lane_reset(p.pw.x[p.k & 1], p.pw.c[p.k & 1], p.pw.D[p.k & 1], d.outdeg, d.V, p.B, lane, q.source,
                               p.stream);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(p.pw.seed + lane, &p.seeds[lane], 4, hipMemcpyHostToDevice, p.stream);
         }
         if (e != hipSuccess) return false;
         p.lane_q[lane] = q.id;
@@ -328,7 +332,9 @@ struct gx_server {
         auto it = running.find(p.lane_q[lane]);
         if (it == running.end()) return;
         SQuery &q = it->second;
-        const uint32_t *tile = p.algo == GX_SSSP ? p.D : reinterpret_cast<const uint32_t *>(p.pw.x[p.k & 1]);
+        // a PPR lane froze after its last superstep: its values are in x[end & 1]
+        const uint32_t *tile =
+            p.algo == GX_SSSP ? p.D : reinterpret_cast<const uint32_t *>(p.pw.x[p.ends[lane] & 1]);
         hipError_t e = lane_extract(tile, d.V, p.B, lane, p.stage, p.stream);
         if (e == hipSuccess) e = hipMemcpyAsync(p.host_stage, p.stage, d.V * 4, hipMemcpyDeviceToHost, p.stream);
         if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
@@ -366,7 +372,7 @@ struct gx_server {
             for (uint32_t b = 0; b < B; b++) {
                 if (p.lane_q[b] < 0) continue;
                 p.lane_age[b] += p.epoch_len;
-                if (p.lane_age[b] >= (int64_t)cfg.ppr_iters) retire(p, b, p.lane_age[b]);
+                if ((int32_t)(p.ends[b] - p.k) <= 0) retire(p, b, (int64_t)cfg.ppr_iters);
             }
         }
     }
@@ -382,10 +388,19 @@ struct gx_server {
                                p.stream) != hipSuccess)
                 return false;
         } else {
-            int64_t left = cfg.ppr_iters;
+            // Lanes that reach their end inside the epoch freeze on the device;
+            // the epoch runs until the last lane's end or the epoch limit.
+            int64_t left = 1;
             for (uint32_t b = 0; b < p.B; b++)
-                if (p.lane_q[b] >= 0) left = std::min<int64_t>(left, (int64_t)cfg.ppr_iters - p.lane_age[b]);
-            p.epoch_len = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(left, epoch_max()));
+                if (p.lane_q[b] >= 0) left = std::max<int64_t>(left, (int32_t)(p.ends[b] - p.k));
+            p.epoch_len = (uint32_t)std::min<int64_t>(left, epoch_max());
+            int32_t *lt = reinterpret_cast<int32_t *>(p.host_cnt);  // idle pool: the last epoch's copies are done
+            for (uint32_t b = 0; b < p.B; b++) {
+                lt[b] = p.lane_q[b] >= 0 ? p.seeds[b] : -1;
+                lt[p.B + b] = (int32_t)p.ends[b];
+            }
+            if (hipMemcpyAsync(p.pw.seed, lt, (size_t)p.B * 8, hipMemcpyHostToDevice, p.stream) != hipSuccess)
+                return false;
             BpArgs a = bp_args(p);
             // only the occupied prefix of lanes (lowest free lanes are taken first)
             uint32_t hi = 0;
