@@ -67,9 +67,14 @@ def cpu_baseline(g, edges_per_solve, budget_s=20.0):
     times.sort()
     med = times[len(times) // 2]
     assert int(r.msgs.sum()) == edges_per_solve
+    t0 = time.perf_counter()
+    dist = oracle.dijkstra(g, 0)  # the work-efficient sequential solve, for scale
+    t_dij = time.perf_counter() - t0
+    assert (dist == r.state).all()
     return {"value": edges_per_solve / med / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
             "sample": f"full single-source solve from vertex 0 ({r.K} supersteps, {edges_per_solve} messages), "
                       f"single-threaded C oracle, median of {len(times)} runs ({med:.2f} s each)",
+            "dijkstra_single_core_s": t_dij,
             "host_cpu": platform.processor() or platform.machine(), "host_nproc": os.cpu_count()}
 
 

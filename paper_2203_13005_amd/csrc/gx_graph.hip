@@ -71,6 +71,7 @@ struct HostImages {
     std::vector<uint32_t> in_w;
     std::vector<int32_t> sym_rp, sym_col;
     std::vector<uint2> pull_w, pull_sym;
+    PullSlices pull_w_off{}, pull_sym_off{};
     std::vector<uint32_t> rem_out, rem_any;
 };
 
@@ -141,22 +142,50 @@ static void build_tiles(const std::vector<int32_t> &rp, std::vector<int32_t> &ti
     tile_row[nt] = (int32_t)V;
 }
 
-// Banded pull records from a CSR over destinations (rows) listing sources in
-// ascending order: a stable split by source band keeps (destination,
-// source) order inside every band.  `w` may be null (records {dst, src}).
-static void build_banded(const std::vector<int32_t> &rp, const int32_t *src, const uint32_t *w,
-                         std::vector<uint2> &out) {
+// Pull records from a CSR over destinations (rows) listing sources in
+// ascending order.  Destinations are taken in blocks of
+// 2^PULL_SLICE_SHIFT; the blocks are dealt to the PULL_SLICES slices
+// greedily, heaviest in-edge count first, each to the lightest slice so
+// far (degree skew would otherwise pile most edges onto one slice).  Within
+// a slice the records are grouped by source band, keeping the (destination,
+// source) order of the CSR inside a group.  `w` may be null (records
+// {dst, src}).  The array is padded to whole PULL_VT groups (the padding is
+// never a valid record).
+static void build_pull(const std::vector<int32_t> &rp, const int32_t *src, const uint32_t *w,
+                       std::vector<uint2> &out, PullSlices &sl) {
     const int64_t V = (int64_t)rp.size() - 1, E = rp.back();
     const int64_t nb = (V >> PULL_BAND_BITS) + 1;
-    std::vector<int64_t> pos(nb + 1, 0);
-    for (int64_t e = 0; e < E; e++) pos[(src[e] >> PULL_BAND_BITS) + 1]++;
-    for (int64_t b = 0; b < nb; b++) pos[b + 1] += pos[b];
-    out.resize(E);
-    for (int64_t v = 0; v < V; v++)
+    const int64_t nblk = (V + (1 << PULL_SLICE_SHIFT) - 1) >> PULL_SLICE_SHIFT;
+    std::vector<int64_t> bcnt((size_t)nblk, 0);
+    for (int64_t v = 0; v < V; v++) bcnt[v >> PULL_SLICE_SHIFT] += rp[v + 1] - rp[v];
+    std::vector<int64_t> order((size_t)nblk);
+    for (int64_t i = 0; i < nblk; i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return bcnt[a] > bcnt[b]; });
+    std::vector<uint8_t> slice((size_t)nblk, 0);
+    int64_t load[PULL_SLICES] = {};
+    for (int64_t b : order) {
+        int x = 0;
+        for (int y = 1; y < PULL_SLICES; y++)
+            if (load[y] < load[x]) x = y;
+        slice[b] = (uint8_t)x;
+        load[x] += bcnt[b];
+    }
+    std::vector<int64_t> pos((size_t)PULL_SLICES * nb + 1, 0);
+    for (int64_t v = 0; v < V; v++) {
+        const int64_t g0 = (int64_t)slice[v >> PULL_SLICE_SHIFT] * nb + 1;
+        for (int32_t e = rp[v]; e < rp[v + 1]; e++) pos[g0 + (src[e] >> PULL_BAND_BITS)]++;
+    }
+    for (size_t g = 0; g + 1 < pos.size(); g++) pos[g + 1] += pos[g];
+    for (int x = 0; x < PULL_SLICES; x++) sl.off[x] = pos[(size_t)x * nb];
+    sl.off[PULL_SLICES] = E;
+    out.assign((size_t)pull_padded(E), make_uint2(0xFFFFFFFFu, 0u));
+    for (int64_t v = 0; v < V; v++) {
+        const int64_t g0 = (int64_t)slice[v >> PULL_SLICE_SHIFT] * nb;
         for (int32_t e = rp[v]; e < rp[v + 1]; e++) {
             const uint32_t u = (uint32_t)src[e];
-            out[pos[u >> PULL_BAND_BITS]++] = make_uint2((uint32_t)v, w ? ((u << 8) | w[e]) : u);
+            out[pos[g0 + (u >> PULL_BAND_BITS)]++] = make_uint2((uint32_t)v, w ? ((u << 8) | w[e]) : u);
         }
+    }
 }
 
 static bool banded_weights_fit(const gx_graph_desc *d) {
@@ -228,11 +257,12 @@ static void layout(const gx_graph_desc *desc, int64_t E_sym, Carver &c, DevGraph
         d->in_col = c.take<int32_t>(E);
         d->outdeg = c.take<int32_t>(V);
     }
-    if ((desc->needs & GX_NEED_OUT) && (desc->E == 0 || banded_weights_fit(desc))) d->pull_w = c.take<uint2>(E);
+    if ((desc->needs & GX_NEED_OUT) && (desc->E == 0 || banded_weights_fit(desc)))
+        d->pull_w = c.take<uint2>(pull_padded(E));
     if (desc->needs & GX_NEED_SYM) {
         d->sym_rp = c.take<int32_t>(V + 1);
         d->sym_col = c.take<int32_t>(E_sym);
-        d->pull_sym = c.take<uint2>(E_sym);
+        d->pull_sym = c.take<uint2>(pull_padded(E_sym));
     }
     if (desc->l2g) d->l2g = c.take<int32_t>(V);
     if (desc->flags) {
@@ -341,10 +371,10 @@ extern "C" gx_status gx_graph_load(const gx_graph_desc *desc, void *dev_arena, s
         build_in_csr(desc, h);
         build_tiles(h.in_rp, h.tile_row);
         if ((desc->needs & GX_NEED_OUT) && (desc->E == 0 || banded_weights_fit(desc)))
-            build_banded(h.in_rp, h.in_col.data(), h.in_w.data(), h.pull_w);
+            build_pull(h.in_rp, h.in_col.data(), h.in_w.data(), h.pull_w, h.pull_w_off);
         if (desc->needs & GX_NEED_SYM) {
             build_sym(desc, h);
-            build_banded(h.sym_rp, h.sym_col.data(), nullptr, h.pull_sym);
+            build_pull(h.sym_rp, h.sym_col.data(), nullptr, h.pull_sym, h.pull_sym_off);
         }
         build_flags(desc, W, h);
     } catch (const std::bad_alloc &) {
@@ -356,6 +386,8 @@ extern "C" gx_status gx_graph_load(const gx_graph_desc *desc, void *dev_arena, s
     GX_REQUIRE(g, GX_ENOMEM, "host allocation failed");
     Carver c(dev_arena, arena_bytes);
     layout(desc, (int64_t)h.sym_col.size(), c, &g->d);
+    g->d.pull_w_off = h.pull_w_off;
+    g->d.pull_sym_off = h.pull_sym_off;
     g->needs = desc->needs;
     g->arena = dev_arena;
     g->arena_bytes = arena_bytes;
@@ -388,7 +420,8 @@ extern "C" gx_status gx_graph_load(const gx_graph_desc *desc, void *dev_arena, s
         e = up.put_array((void *)d.in_col, h.in_col.data(), E * 4);
         if (e == hipSuccess) e = up.put_array((void *)d.outdeg, g->host_outdeg.data(), V * 4);
     }
-    if (e == hipSuccess && d.pull_w) e = up.put_array((void *)d.pull_w, h.pull_w.data(), E * sizeof(uint2));
+    if (e == hipSuccess && d.pull_w)
+        e = up.put_array((void *)d.pull_w, h.pull_w.data(), h.pull_w.size() * sizeof(uint2));
     if (e == hipSuccess && d.sym_rp) {
         e = up.put_array((void *)d.sym_rp, h.sym_rp.data(), (V + 1) * 4);
         if (e == hipSuccess) e = up.put_array((void *)d.sym_col, h.sym_col.data(), h.sym_col.size() * 4);

@@ -60,10 +60,21 @@ struct Carver {
 constexpr int PR_BLOCK = 256;
 constexpr int PR_VT = 8;
 constexpr int PR_TILE = PR_BLOCK * PR_VT;
-// Source bands of the SSSP / CC pull: in-edges are ordered by
-// (source >> PULL_BAND_BITS, destination, source), so a sweep over the edge
-// records touches one band of source snapshots (2^18 vertices) at a time.
-constexpr int PULL_BAND_BITS = 18;
+// Records of the SSSP / CC pull.  Destinations are dealt to PULL_SLICES
+// slices in blocks of 2^PULL_SLICE_SHIFT vertices, balanced by in-edge
+// count; a slice's records are ordered by
+// (source >> PULL_BAND_BITS, destination, source).  Workgroup b sweeps slice
+// b mod PULL_SLICES, and workgroups are dealt round-robin to the 8 XCDs, so
+// each XCD's L2 holds one slice's destination values and one band of source
+// snapshots (2^16 vertices) at a time.
+constexpr int PULL_SLICES = 8;
+constexpr int PULL_SLICE_SHIFT = 6;
+constexpr int PULL_BAND_BITS = 16;
+constexpr int PULL_VT = 8;  // records per thread; slices are swept in aligned groups of PULL_VT
+inline int64_t pull_padded(int64_t n) { return (n + PULL_VT - 1) / PULL_VT * PULL_VT; }
+struct PullSlices {
+    int64_t off[PULL_SLICES + 1];  // slice x holds records off[x] .. off[x+1]-1
+};
 
 struct DevGraph {
     int64_t V = 0, E = 0, E_sym = 0;
@@ -78,14 +89,17 @@ struct DevGraph {
     const int32_t *outdeg = nullptr;
     int32_t pr_ntiles = 0;
     const int32_t *pr_tile_row = nullptr;  // [pr_ntiles + 1]
-    // banded in-edge records for the SSSP pull: {dst, (src << 8) | w}; null
-    // when V >= 2^24 or a weight exceeds 255 (the engine then only pushes)
+    // sliced, banded in-edge records for the SSSP pull: {dst, (src << 8) | w}
+    // (padded to whole PULL_VT groups); null when V >= 2^24 or a weight
+    // exceeds 255 (the engine then only pushes)
     const uint2 *pull_w = nullptr;
+    PullSlices pull_w_off{};
     // symmetric adjacency (CC push and pull) and its equal edge tiles
     const int32_t *sym_rp = nullptr;
     const int32_t *sym_col = nullptr;
-    // banded symmetric records for the CC pull: {dst, src}
+    // sliced, banded symmetric records for the CC pull: {dst, src}
     const uint2 *pull_sym = nullptr;
+    PullSlices pull_sym_off{};
     // partition metadata
     const int32_t *l2g = nullptr;          // nullptr = identity
     const uint32_t *remote_out = nullptr;  // bitmaps of W words (nullptr = none remote)

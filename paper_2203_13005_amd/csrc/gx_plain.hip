@@ -135,16 +135,18 @@ __global__ __launch_bounds__(256) void k_min_init(uint32_t *val, uint8_t *f0, ui
 // as whole vectors, so no load waits on another.  A workgroup covers
 // 256*CVT vertices and issues two counter atomics (list, |A|).  Active
 // vertices with out-edges get a list entry (edge offset, CSR base,
-// snapshot, vertex), their snapshot is stored for the pull, and the tiles
-// that start inside an entry's edges record it.  |A_{k+1}| is the number of
-// vertices superstep k changed.
+// snapshot, vertex) and the tiles that start inside an entry's edges record
+// it.  When the next superstep may pull (snap_all), the snapshot array is
+// written for every vertex, INF for inactive ones, so the pull reads one
+// word per record.  |A_{k+1}| is the number of vertices superstep k changed.
 constexpr int CVT = 16;
 
 __global__ __launch_bounds__(256) void k_compact(const uint8_t *__restrict__ front, uint8_t *__restrict__ front_clear,
                                                  const int32_t *__restrict__ rp, const uint32_t *__restrict__ val,
                                                  uint32_t *__restrict__ snap, int64_t V,
                                                  uint4 *__restrict__ list, uint32_t *__restrict__ tile_start,
-                                                 DevStep *__restrict__ step, DevStep *__restrict__ next_step) {
+                                                 DevStep *__restrict__ step, DevStep *__restrict__ next_step,
+                                                 int snap_all) {
     __shared__ unsigned long long s_scan[4];
     __shared__ unsigned long long s_base;
     __shared__ int s_nf[4];
@@ -163,7 +165,18 @@ __global__ __launch_bounds__(256) void k_compact(const uint8_t *__restrict__ fro
                 if ((fw[q] >> (8 * b)) & 0xFFu) actmask |= 1u << (4 * q + b);
         if (V - u0 < CVT) actmask &= (1u << (V - u0)) - 1u;  // padding bytes are no vertices
     }
-    if (!__syncthreads_or(actmask != 0)) return;
+    if (!__syncthreads_or(actmask != 0)) {
+        if (snap_all && u0 < V) {
+            if (u0 + CVT <= V) {
+                uint4 *s4 = reinterpret_cast<uint4 *>(snap + u0);
+#pragma unroll
+                for (int q = 0; q < CVT / 4; q++) s4[q] = make_uint4(INF, INF, INF, INF);
+            } else {
+                for (int i = 0; u0 + i < V; i++) snap[u0 + i] = INF;
+            }
+        }
+        return;
+    }
     int32_t r[CVT + 1];
     uint32_t x[CVT];
 #pragma unroll
@@ -192,6 +205,20 @@ __global__ __launch_bounds__(256) void k_compact(const uint8_t *__restrict__ fro
             }
         }
     }
+    if (snap_all && u0 < V) {
+        uint32_t sv[CVT];
+#pragma unroll
+        for (int i = 0; i < CVT; i++) sv[i] = ((actmask >> i) & 1u) ? x[i] : INF;
+        if (u0 + CVT <= V) {
+            uint4 *s4 = reinterpret_cast<uint4 *>(snap + u0);
+#pragma unroll
+            for (int q = 0; q < CVT / 4; q++) s4[q] = make_uint4(sv[4 * q], sv[4 * q + 1], sv[4 * q + 2], sv[4 * q + 3]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < CVT; i++)
+                if (u0 + i < V) snap[u0 + i] = sv[i];
+        }
+    }
     uint32_t cnt = 0, edges = 0;
 #pragma unroll
     for (int i = 0; i < CVT; i++) {
@@ -217,7 +244,7 @@ __global__ __launch_bounds__(256) void k_compact(const uint8_t *__restrict__ fro
         if (!((actmask >> i) & 1u) || dg <= 0) continue;
         const int64_t u = u0 + i;
         const uint32_t idx = (uint32_t)(pos >> 32), off = (uint32_t)pos;
-        snap[u] = x[i];
+        if (!snap_all) snap[u] = x[i];
         list[idx] = make_uint4(off, (uint32_t)(r[i] - (int32_t)off), x[i], (uint32_t)u);
         const uint32_t t0 = (off + PUSH_TILE - 1) / PUSH_TILE, t1 = (off + (uint32_t)dg - 1) / PUSH_TILE;
         for (uint32_t t = t0; t <= t1; t++) tile_start[t] = idx;
@@ -307,78 +334,77 @@ __global__ __launch_bounds__(PUSH_BLOCK) void k_push(const uint4 *__restrict__ l
 }
 
 // Pull form of the same superstep, for large frontiers.  The in-edges are
-// stored as records {dst, (src << 8) | w} (CC: {dst, src}) ordered by
-// (source band, dst, src), built at load.  Every thread takes PULL_VT
-// consecutive records (the grid sweeps the array front to back, so at any
-// time the source snapshots being gathered come from one band of 2^18
-// vertices and stay cache resident); an active source's record carries its
-// snapshot (+ weight); the thread folds runs of equal destination to their
-// minimum and applies each by integer atomicMin after a plain read
-// filters out non-improving candidates.  Runs only when the frontier's
-// out-edges reach pull_edges.
-constexpr int PULL_VT = 8;
-
+// stored as records {dst, (src << 8) | w} (CC: {dst, src}) in
+// PULL_SLICES destination slices, each ordered by (source band, dst, src),
+// built at load.  Workgroup b sweeps slice b mod PULL_SLICES, PULL_VT
+// consecutive records per thread; since workgroups are dealt round-robin to
+// the XCDs, each XCD's L2 holds its slice's destination values and the
+// current band of source snapshots.  The compaction stored INF as the
+// snapshot of every inactive vertex, so a record costs one snapshot read;
+// the thread folds runs of equal destination to their minimum and applies
+// each with the filtered atomics of the push.  Runs only when the
+// frontier's out-edges reach pull_edges.
 template <bool WEIGHTED>
-__global__ __launch_bounds__(256) void k_pull(const uint2 *__restrict__ rec, int64_t E,
-                                              const uint8_t *__restrict__ front_cur,
+__global__ __launch_bounds__(256) void k_pull(const uint2 *__restrict__ rec, PullSlices sl, uint32_t vmax,
                                               const uint32_t *__restrict__ snap, uint32_t *__restrict__ val,
                                               uint8_t *__restrict__ front_next, uint8_t *__restrict__ dirty,
                                               DevStep *__restrict__ step, uint32_t pull_edges) {
     const uint32_t EF = (uint32_t)step->list;
     if (EF < pull_edges) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) step->pad = 1;
-    const int64_t nchunks = (E + PULL_VT - 1) / PULL_VT;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nchunks;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t e0 = c * PULL_VT;
-        const int n = (int)min((int64_t)PULL_VT, E - e0);
-        uint32_t dst[PULL_VT], src[PULL_VT], m[PULL_VT];
-        if (n == PULL_VT) {
-            const uint4 *r4 = reinterpret_cast<const uint4 *>(rec + e0);
+    const int x = (int)(blockIdx.x % PULL_SLICES);
+    const int64_t lo = sl.off[x], hi = sl.off[x + 1];
+    // An empty slice has no record to sweep; a non-empty one guarantees
+    // that every visited group holds one of its records (the anchor below).
+    if (lo >= hi) return;
+    const int64_t base = lo / PULL_VT * PULL_VT;  // aligned groups; records outside [lo, hi) are masked
+    const int64_t stride = (int64_t)(gridDim.x / PULL_SLICES) * blockDim.x * PULL_VT;
+    for (int64_t e0 = base + ((int64_t)(blockIdx.x / PULL_SLICES) * blockDim.x + threadIdx.x) * PULL_VT; e0 < hi;
+         e0 += stride) {
+        uint32_t dst[PULL_VT], src[PULL_VT], m[PULL_VT], cur[PULL_VT];
+        const uint4 *r4 = reinterpret_cast<const uint4 *>(rec + e0);  // the array is padded to whole groups
 #pragma unroll
-            for (int i = 0; i < PULL_VT / 2; i++) {
-                const uint4 q = r4[i];
-                dst[2 * i] = q.x;
-                src[2 * i] = q.y;
-                dst[2 * i + 1] = q.z;
-                src[2 * i + 1] = q.w;
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < PULL_VT; i++) {
-                const uint2 q = i < n ? rec[e0 + i] : make_uint2(0xFFFFFFFFu, 0u);  // pad: source 0, no run
-                dst[i] = q.x;
-                src[i] = q.y;
-            }
+        for (int i = 0; i < PULL_VT / 2; i++) {
+            const uint4 q = r4[i];
+            dst[2 * i] = q.x;
+            src[2 * i] = q.y;
+            dst[2 * i + 1] = q.z;
+            src[2 * i + 1] = q.w;
         }
-        // Source flags and snapshots are read unconditionally (one wait for
-        // both; the band's slice is cache resident) and selected afterwards.
-        uint32_t f[PULL_VT];
+        const int i0 = (int)max((int64_t)0, lo - e0);  // first record of this slice in the chunk
+        uint32_t anchor = dst[0];
+#pragma unroll
+        for (int i = 1; i < PULL_VT; i++)
+            if (i == i0) anchor = dst[i];
+        anchor = min(anchor, vmax);
 #pragma unroll
         for (int i = 0; i < PULL_VT; i++) {
-            const uint32_t u = WEIGHTED ? (src[i] >> 8) : src[i];
-            f[i] = front_cur[u];
-            m[i] = snap[u];
+            if (e0 + i < lo || e0 + i >= hi) {  // another slice's record or padding
+                dst[i] = 0xFFFFFFFFu;
+                src[i] = 0u;
+            }
+            m[i] = snap[WEIGHTED ? (src[i] >> 8) : src[i]];
         }
 #pragma unroll
         for (int i = 0; i < PULL_VT; i++) {
-            const uint32_t c = WEIGHTED ? sat_add(m[i], src[i] & 0xFFu) : m[i];
-            m[i] = (i < n && f[i]) ? c : INF;
+            m[i] = WEIGHTED ? sat_add(m[i], src[i] & 0xFFu) : m[i];
+            if (dst[i] == 0xFFFFFFFFu) m[i] = INF;
         }
         // Minimum of each run of equal destination, kept at the run's last
         // record; then one batched read of those destinations, then the
         // filtered atomics (no result awaited, as in the push).
-        uint32_t cur[PULL_VT];
 #pragma unroll
         for (int i = 1; i < PULL_VT; i++)
             if (dst[i] == dst[i - 1]) m[i] = min(m[i], m[i - 1]);
 #pragma unroll
-        for (int i = 0; i < PULL_VT; i++) {
-            const bool last = i < n && (i + 1 == n || dst[i + 1] != dst[i]);
-            if (!last) m[i] = INF;
-        }
+        for (int i = 0; i + 1 < PULL_VT; i++)
+            if (dst[i + 1] == dst[i]) m[i] = INF;
+        // records without a candidate read the destination of the chunk's
+        // first record of this slice instead (in the slice, so cache
+        // resident, and different per lane: one dummy address shared by
+        // every idle lane would become a single hot line)
 #pragma unroll
-        for (int i = 0; i < PULL_VT; i++) cur[i] = val[m[i] != INF ? dst[i] : dst[0]];
+        for (int i = 0; i < PULL_VT; i++) cur[i] = val[m[i] != INF ? dst[i] : anchor];
 #pragma unroll
         for (int i = 0; i < PULL_VT; i++) {
             if (m[i] < cur[i]) {
@@ -783,7 +809,8 @@ extern "C" gx_status gx_state_init(gx_graph *g, const gx_params *p, void *dev_st
     Carver c(dev_state, bytes);
     state_layout(g, p, c, s);
     s->push_grid = persistent_grid(g, k_push<true>, PUSH_BLOCK);
-    s->pull_grid = persistent_grid(g, k_pull<true>, 256);
+    // whole multiples of the slice count (workgroup b sweeps slice b mod PULL_SLICES)
+    s->pull_grid = std::max(PULL_SLICES, persistent_grid(g, k_pull<true>, 256) / PULL_SLICES * PULL_SLICES);
     if (p->algo != GX_PAGERANK) {
         const DevGraph &dg = g->d;
         bool can_pull = p->algo == GX_SSSP ? (dg.pull_w != nullptr) : (dg.pull_sym != nullptr);
@@ -816,7 +843,7 @@ extern "C" gx_status gx_state_init(gx_graph *g, const gx_params *p, void *dev_st
         if (V > 0)
             hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(V, 256 * CVT)), dim3(256), 0, hs, s->front8[0],
                                s->front8[1], rp, s->val, s->snap, V, s->list, s->tile_start, s->steps,
-                               s->steps + 1);
+                               s->steps + 1, (int)(s->pull_edges != 0xFFFFFFFFu));
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
@@ -947,22 +974,21 @@ static gx_status enqueue_superstep(gx_state *s, hipStream_t hs) {
                                    (const void *)d.out_adj, s->val, s->front8[cur ^ 1], s->dirty8, step,
                                    s->pull_edges);
                 if (s->pull_edges != 0xFFFFFFFFu)
-                    hipLaunchKernelGGL(k_pull<true>, dim3(s->pull_grid), dim3(256), 0, hs, d.pull_w, d.E,
-                                       s->front8[cur], s->snap, s->val, s->front8[cur ^ 1], s->dirty8, step,
-                                       s->pull_edges);
+                    hipLaunchKernelGGL(k_pull<true>, dim3(s->pull_grid), dim3(256), 0, hs, d.pull_w, d.pull_w_off,
+                                       (uint32_t)(d.V - 1), s->snap, s->val, s->front8[cur ^ 1], s->dirty8, step, s->pull_edges);
             } else {
                 hipLaunchKernelGGL(k_push<false>, dim3(s->push_grid), dim3(PUSH_BLOCK), 0, hs, s->list,
                                    s->tile_start, (const void *)d.sym_col, s->val, s->front8[cur ^ 1], s->dirty8,
                                    step, s->pull_edges);
                 if (s->pull_edges != 0xFFFFFFFFu)
-                    hipLaunchKernelGGL(k_pull<false>, dim3(s->pull_grid), dim3(256), 0, hs, d.pull_sym, d.E_sym,
-                                       s->front8[cur], s->snap, s->val, s->front8[cur ^ 1], s->dirty8, step,
+                    hipLaunchKernelGGL(k_pull<false>, dim3(s->pull_grid), dim3(256), 0, hs, d.pull_sym,
+                                       d.pull_sym_off, (uint32_t)(d.V - 1), s->snap, s->val, s->front8[cur ^ 1], s->dirty8, step,
                                        s->pull_edges);
             }
             if (e1) (void)hipEventRecord(e1, hs);
             hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(d.V, 256 * CVT)), dim3(256), 0, hs,
                                s->front8[cur ^ 1], s->front8[cur], rp, s->val, s->snap, d.V, s->list, s->tile_start,
-                               next, next2);
+                               next, next2, (int)(s->pull_edges != 0xFFFFFFFFu));
         }
     }
     hipError_t e = hipGetLastError();
