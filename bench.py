@@ -263,12 +263,19 @@ def bench_partition(gx, torch, np, gen, reps=3):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sssp_rmat22_relaxation_traffic.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2203_13005_amd", "csrc", "gx_plain.hip")
+KERNEL_SOURCES = os.path.join(ROOT, "paper_2203_13005_amd", "csrc")
 
 
 def kernel_source_hash():
+    """Hash of the device library's sources (kernels, layouts, launch code):
+    a traffic record taken on other sources is not reported."""
+    import glob
     import hashlib
-    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(KERNEL_SOURCES, "*.hip")) + glob.glob(os.path.join(KERNEL_SOURCES, "*.h"))):
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def summarize_pmc(fetch_dir, write_dir, solves):

@@ -63,7 +63,7 @@ typedef enum {
 } gx_algo;
 
 /* Which device images gx_graph_load builds (bitmask). */
-#define GX_NEED_OUT 1u  /* out-CSR (dst, weight) + in-CSR (src, weight): SSSP push and pull */
+#define GX_NEED_OUT 1u  /* out-CSR (dst, weight) + in-edge records (dst, src, weight): SSSP push and pull */
 #define GX_NEED_IN  2u  /* in-CSR (sources ascending) + out-degree: PageRank, PPR */
 #define GX_NEED_SYM 4u  /* symmetric deduplicated adjacency: CC */
 
@@ -103,8 +103,8 @@ typedef struct gx_params {
     uint32_t delta_mode;      /* GX_DELTA_REMOTE or GX_DELTA_ALL */
     uint32_t timing;          /* nonzero: time the edge kernels of every superstep with HIP events */
     float    pull_fraction;   /* SSSP/CC: a superstep whose active out-edges exceed this fraction of
-                                 all edges pulls over in-edge tiles instead of pushing; 0 = default
-                                 (0.3), >= 1 = always push */
+                                 all edges pulls (one sweep over every in-edge record) instead of
+                                 pushing; 0 = default (0.3), >= 1 = always push */
 } gx_params;
 
 /* Statistics of one superstep (counts are exact). */
@@ -112,7 +112,7 @@ typedef struct gx_step_stats {
     int64_t frontier;      /* |F_k|: active vertices (PageRank: V) */
     int64_t edges;         /* messages generated: out-edges of F_k (PageRank: E) */
     int64_t changed;       /* vertices whose value changed (|F_{k+1}| for SSSP/CC) */
-    int64_t pulled;        /* 1 if the superstep ran as a pull over in-edge tiles */
+    int64_t pulled;        /* 1 if the superstep ran as a pull over all in-edge records */
     double  kernel_ms;     /* with gx_params.timing: HIP-event time of its edge kernels, else 0 */
 } gx_step_stats;
 
@@ -166,7 +166,7 @@ gx_status gx_state_free(gx_state *s);
 gx_status gx_state_values(gx_state *s, void **dev_values);
 /* Device pointer to the current frontier as a byte map (uint8 per vertex,
  * nonzero = vertex v is active in the next superstep); SSSP/CC only. */
-gx_status gx_state_frontier(gx_state *s, void **dev_bitmap);
+gx_status gx_state_frontier(gx_state *s, void **dev_bytemap);
 /* Supersteps executed since init. */
 gx_status gx_state_superstep(gx_state *s, int64_t *k);
 
@@ -174,9 +174,10 @@ gx_status gx_state_superstep(gx_state *s, int64_t *k);
  * requestGen() -> requestMerge() -> requestApply() in BSP order: one
  * superstep.  SSSP/CC: relax the active list (built with start-of-superstep
  * snapshots by the previous call or by gx_state_init) over equal tiles of
- * active out-edges (push) or of all in-edges (pull, for large frontiers),
- * merge by integer min, mark changed vertices in the next frontier and the
- * dirty map, then compact the next frontier.  PageRank: pull over the
+ * active out-edges (push) or as one sweep over all in-edge records (pull,
+ * for large frontiers; the device picks), merge by integer min, mark
+ * changed vertices in the next frontier and the dirty map, then compact the
+ * next frontier.  PageRank: pull over the
  * in-CSR in equal edge tiles with a fixed summation order.
  * With stats == NULL the call is asynchronous; otherwise it synchronises
  * `stream` and fills *stats.
