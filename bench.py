@@ -121,7 +121,28 @@ def bench_batched(gx, torch, np, gen, steps=3):
             "plain_queries_per_s": 256 / t_plain, "plain_ms_total": t_plain * 1e3,
             "speedup_vs_plain": t_plain / t_batch, "lane_messages_per_batch": int(plain_edges),
             "lane_gteps": plain_edges / t_batch / 1e9,
-            "tune": {"block": best.block, "tile": best.tile, "width": best.width}}
+            "tune": {"block": best.block, "tile": best.tile, "width": best.width},
+            "ppr": bench_batched_ppr(gx, torch, g, dg, src)}
+
+
+def bench_batched_ppr(gx, torch, g, dg, src, iters=50, reps=3):
+    """Personalised PageRank lanes (50 iterations) on the same graph: 64 and
+    256 seeds in one persistent launch each."""
+    out = {}
+    for B in (64, 256):
+        seeds = src[:B]
+        gx.batch_run(dg, gx.GX_PPR, seeds, iters=iters)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            gx.batch_run(dg, gx.GX_PPR, seeds, iters=iters)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+        log(f"batched PPR: {B} lanes x {iters} iterations in {t * 1e3:.2f} ms "
+            f"({t * 1e6 / iters:.1f} us per superstep)")
+        out[f"lanes_{B}"] = {"ms_per_batch": t * 1e3, "us_per_superstep": t * 1e6 / iters,
+                             "queries_per_s": B / t, "lane_edge_gathers_per_s": B * g.E * iters / t}
+    return out
 
 
 def bench_serving(gx, torch, np, gen, n_queries=2000, qps_frac=0.7, budget_gib=64.0, lanes=64, max_pools=32):
@@ -397,10 +418,10 @@ def main():
         state.run(100_000)
         state.sync_delta(cap=cap)
     torch.cuda.synchronize()
-    assert np.array_equal(state.values_numpy(), dist_ref)
 
     state.reset()
     _, detail = state.run(100_000, per_step=True, detail=True)
+    assert np.array_equal(state.values_numpy(), dist_ref)
     for i, d in enumerate(detail):
         log(f"  superstep {i:2d}: |F|={d['frontier']:>8d} edges={d['edges']:>9d} changed={d['changed']:>8d} "
             f"{'pull' if d['pulled'] else 'push'} {d['kernel_ms'] * 1e3:8.1f} us")

@@ -89,6 +89,9 @@ typedef struct gx_graph_desc {
     const int32_t *l2g;
     const uint8_t *flags;
     uint32_t needs;
+    uint32_t pr_tile_edges;  /* in-edges per PageRank workgroup tile: 0 = automatic (the largest of
+                                2048, 1024, 512 that still gives 2048 tiles, else 256), or one of
+                                256, 512, 1024, 2048 */
 } gx_graph_desc;
 
 /* Sync-set selection (gx_params.delta_mode). */

@@ -29,7 +29,7 @@ class GxError(RuntimeError):
 class _GraphDesc(ctypes.Structure):
     _fields_ = [("V", ctypes.c_int64), ("E", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
                 ("col", ctypes.c_void_p), ("w", ctypes.c_void_p), ("l2g", ctypes.c_void_p),
-                ("flags", ctypes.c_void_p), ("needs", ctypes.c_uint32)]
+                ("flags", ctypes.c_void_p), ("needs", ctypes.c_uint32), ("pr_tile_edges", ctypes.c_uint32)]
 
 
 class _Params(ctypes.Structure):
@@ -169,7 +169,7 @@ class DeviceGraph:
     """A worker's graph resident in HBM.  ``host`` is any object with V, E,
     row_ptr, col, w and optional l2g / flags numpy arrays (out-CSR)."""
 
-    def __init__(self, host, needs: int, device="cuda:0", stream=None):
+    def __init__(self, host, needs: int, device="cuda:0", stream=None, pr_tile_edges: int = 0):
         import torch
         self.device = torch.device(device)
         self._keep = [np.ascontiguousarray(host.row_ptr, np.int32), np.ascontiguousarray(host.col, np.int32),
@@ -178,7 +178,7 @@ class DeviceGraph:
                       None if getattr(host, "flags", None) is None else np.ascontiguousarray(host.flags, np.uint8)]
         rp, col, w, l2g, flags = self._keep
         self.desc = _GraphDesc(int(host.V), int(host.E), _np_ptr(rp), _np_ptr(col), _np_ptr(w), _np_ptr(l2g),
-                               _np_ptr(flags), int(needs))
+                               _np_ptr(flags), int(needs), int(pr_tile_edges))
         nbytes = ctypes.c_size_t(0)
         _check(lib.gx_graph_bytes(ctypes.byref(self.desc), ctypes.byref(nbytes)))
         self.arena_bytes = nbytes.value

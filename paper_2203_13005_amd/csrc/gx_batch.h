@@ -75,7 +75,7 @@ struct BpWork {
 
 const BsVariant *bs_variants(int *n);
 const void *bp_kernel(uint32_t Bw);
-int coop_grid(const void *kernel, int block, int num_cus, int want);
+int coop_grid(const void *kernel, int block, int num_cus, int want, int max_per_cu);
 void bs_layout(const DevGraph &d, uint32_t B, Carver &c, BsWork *w);
 void bp_layout(const DevGraph &d, uint32_t B, Carver &c, BpWork *w);
 hipError_t launch_coop(const void *kernel, int grid, int block, void *args, hipStream_t s);

@@ -316,87 +316,127 @@ __device__ __forceinline__ void ppr_apply(const BpArgs &a, int32_t r, int od, co
     }
 }
 
-// Sum over in-edges e_lo..e_hi-1 (in edge order) of the sources' lane
-// contributions.  The wave loads 64 source ids at a time (one per lane) and
-// broadcasts them; the contribution rows of EB edges are loaded before any
-// is added, so a row's loads overlap instead of waiting one by one.
-template <int LPT>
-__device__ __forceinline__ void ppr_gather(const BpArgs &a, const float *c_in, int32_t e_lo, int32_t e_hi,
-                                           double (&acc)[LPT], const PprLanes<LPT> &L, int lane) {
-    constexpr int EB = 8;
-#pragma unroll
-    for (int i = 0; i < LPT; i++) acc[i] = 0.0;
-    for (int32_t eb = e_lo; eb < e_hi; eb += 64) {
-        const int cnt = min(64, e_hi - eb);
-        const int32_t myu = a.in_col[eb + min(lane, cnt - 1)];
-        for (int j0 = 0; j0 < cnt; j0 += EB) {
-            const int nb = min(EB, cnt - j0);
-            float v[EB][LPT];
-#pragma unroll
-            for (int jj = 0; jj < EB; jj++) {
-                const int32_t u = __shfl(myu, j0 + min(jj, nb - 1), 64);
-                const float *row = c_in + (size_t)u * a.B;
-#pragma unroll
-                for (int i = 0; i < LPT; i++) v[jj][i] = row[L.bl[i]];
-            }
-#pragma unroll
-            for (int jj = 0; jj < EB; jj++)
-                if (jj < nb)
-#pragma unroll
-                    for (int i = 0; i < LPT; i++) acc[i] += (double)v[jj][i];
-        }
-    }
-}
-
-// PPR phase P of superstep k: pull tiles, one wave per tile.  The row
-// pointers and out-degrees of up to 64 rows are loaded at once (one per
-// lane) and broadcast.
+// PPR phase P of superstep k: pull tiles, one wave per tile, lanes across
+// the wave.  The tile's edges are streamed in order: the wave loads the
+// tile's source ids at once (edge position p sits in lane p mod 64 of
+// register p / 64), then loads the contribution rows of EB edges at a time
+// before adding any, so the row loads of consecutive edges overlap whatever
+// rows they belong to.  A running segment (the head of a row begun in an earlier
+// tile, then the rows that start in this tile) closes when the position
+// passes its end; row ends and out-degrees come from a window of 64 rows
+// loaded one per lane.  Each lane adds its row's contributions in edge
+// order, so results do not depend on the batching.
 template <int LPT>
 __device__ __forceinline__ void bp_pull(const BpArgs &a, uint32_t k, const double *Dcur) {
-    const int lane = threadIdx.x & 63;
+    constexpr int EB = 16 / (LPT == 3 ? 4 : LPT);  // edges whose rows are loaded before any is added
+    constexpr int CR = BP_TILE / 64;               // source-id registers per lane
+    __shared__ int2 s_win[4][64];        // per wave (blocks of 256 threads)
+    const int lane = threadIdx.x & 63, wv = (threadIdx.x >> 6) & 3;
     const int64_t gwave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    const int32_t TP = BP_TILE;
     float *x_out = a.x[(k + 1) & 1];
     const float *c_in = a.c[k & 1];
     float *c_out = a.c[(k + 1) & 1];
     const PprLanes<LPT> L(a, k, Dcur, lane);
     for (int64_t t = gwave; t < a.ntiles; t += nwaves) {
-        const int32_t e0 = (int32_t)(t * TP);
-        const int32_t e1 = (int32_t)std::min<int64_t>((int64_t)e0 + TP, a.E);
+        const int32_t e0 = (int32_t)(t * BP_TILE);
+        const int32_t e1 = (int32_t)std::min<int64_t>((int64_t)e0 + BP_TILE, a.E);
+        const int n = e1 - e0;  // 0 only when E == 0
         const int32_t r_lo = a.trow[t], r_hi = a.trow[t + 1];
+        const int nrows = r_hi - r_lo;
+        if (lane == 0) a.spill[t] = -1;
+        int32_t col[CR];
+#pragma unroll
+        for (int q = 0; q < CR; q++) col[q] = n > 0 ? a.in_col[e0 + min(lane + 64 * q, n - 1)] : 0;
+        const int32_t first_start = r_lo < a.V ? a.in_rp[r_lo] : (int32_t)a.E;
+        // Row window in LDS: entry j holds the end and out-degree of row
+        // r_lo + wb + j.  (Values in LDS are waited for on their own counter;
+        // a register loaded from global memory would make every later use wait
+        // for all row loads in flight.)
+        int wb = 0;
+        auto load_window = [&]() {
+            const int32_t rq = r_lo + wb + min(lane, nrows - wb - 1);
+            const int32_t re = a.in_rp[rq + 1], od = a.outdeg[rq];
+            s_win[wv][lane] = make_int2(re, od);
+            __builtin_amdgcn_wave_barrier();
+        };
+        if (nrows > 0) load_window();
         double acc[LPT], dang[LPT];
 #pragma unroll
-        for (int i = 0; i < LPT; i++) dang[i] = 0.0;
-        if (lane == 0) a.spill[t] = -1;
-        const int32_t first_start = r_lo < a.V ? a.in_rp[r_lo] : (int32_t)a.E;
-        if (e0 < e1 && first_start > e0) {  // row begun in an earlier tile
-            ppr_gather<LPT>(a, c_in, e0, std::min(first_start, e1), acc, L, lane);
-#pragma unroll
-            for (int i = 0; i < LPT; i++)
-                if (lane + 64 * i < (int)a.Bw) a.head[t * a.B + lane + 64 * i] = acc[i];
+        for (int i = 0; i < LPT; i++) {
+            acc[i] = 0.0;
+            dang[i] = 0.0;
         }
-        int32_t rs = first_start;
-        for (int32_t rb = r_lo; rb < r_hi; rb += 64) {
-            const int nr = std::min<int32_t>(64, r_hi - rb);
-            const int32_t rq = rb + std::min(lane, nr - 1);
-            const int32_t my_re = a.in_rp[rq + 1], my_od = a.outdeg[rq];
-            for (int j = 0; j < nr; j++) {
-                const int32_t r = rb + j;
-                const int32_t re = __shfl(my_re, j, 64);
-                if (re > e1) {  // continues into later tiles
-                    ppr_gather<LPT>(a, c_in, rs, e1, acc, L, lane);
+        // seg = -1: the head (positions before first_start); seg >= 0: row r_lo + seg
+        int seg = -1;
+        const int head_end = std::min(first_start, e1) - e0;
+        int seg_end = head_end;
+        auto close = [&]() {  // closes segment `seg` with the sum in acc, then moves to the next one
+            if (seg < 0) {
+                if (head_end > 0)
+#pragma unroll
+                    for (int i = 0; i < LPT; i++)
+                        if (lane + 64 * i < (int)a.Bw) a.head[t * a.B + lane + 64 * i] = acc[i];
+            } else {
+                const int32_t r = r_lo + seg;
+                const int2 w = s_win[wv][seg - wb];
+                const int32_t re = w.x;
+                if (re > e1) {  // continues into later tiles: a partial for the fix phase
 #pragma unroll
                     for (int i = 0; i < LPT; i++)
                         if (lane + 64 * i < (int)a.Bw) a.tailp[t * a.B + lane + 64 * i] = acc[i];
                     if (lane == 0) a.spill[t] = r;
                 } else {
-                    ppr_gather<LPT>(a, c_in, rs, re, acc, L, lane);
-                    ppr_apply<LPT>(a, r, __shfl(my_od, j, 64), acc, L, x_out, c_out, dang, lane);
+                    ppr_apply<LPT>(a, r, w.y, acc, L, x_out, c_out, dang, lane);
                 }
-                rs = re;
+            }
+#pragma unroll
+            for (int i = 0; i < LPT; i++) acc[i] = 0.0;
+            seg++;
+            if (seg < nrows) {
+                if (seg - wb == 64) {  // next window of rows
+                    wb = seg;
+                    __builtin_amdgcn_wave_barrier();
+                    load_window();
+                }
+                seg_end = std::min(s_win[wv][seg - wb].x, e1) - e0;
+            } else {
+                seg_end = 0x7FFFFFFF;
+            }
+        };
+        // Chunks of EB edges: the chunk's contribution rows are loaded at
+        // once, then added segment by segment (one predicated pass over the
+        // chunk's registers per segment, closes in between), so the loads of
+        // a chunk overlap whatever rows they belong to and the adds keep
+        // edge order.
+        for (int p0 = 0; p0 < n; p0 += EB) {
+            const int cnt = min(EB, n - p0);
+            float v[EB][LPT];
+#pragma unroll
+            for (int jj = 0; jj < EB; jj++) {
+                const int p = p0 + min(jj, cnt - 1);
+                int32_t c = col[0];
+#pragma unroll
+                for (int q = 1; q < CR; q++)
+                    if ((p >> 6) == q) c = col[q];
+                const int32_t u = __shfl(c, p & 63, 64);
+                const float *row = c_in + (size_t)u * a.B;
+#pragma unroll
+                for (int i = 0; i < LPT; i++) v[jj][i] = row[L.bl[i]];
+            }
+            int j = 0;
+            while (j < cnt) {
+                while (p0 + j >= seg_end) close();
+                const int jend = min(seg_end - p0, cnt);
+#pragma unroll
+                for (int jj = 0; jj < EB; jj++)
+                    if (jj >= j && jj < jend)
+#pragma unroll
+                        for (int i = 0; i < LPT; i++) acc[i] += (double)v[jj][i];
+                j = jend;
             }
         }
+        while (seg < nrows) close();  // the open segment, then rows with no edges left in this tile
 #pragma unroll
         for (int i = 0; i < LPT; i++)
             if (lane + 64 * i < (int)a.Bw) a.dsum[t * a.B + lane + 64 * i] = dang[i];
@@ -434,6 +474,21 @@ __device__ __forceinline__ void bp_fix(const BpArgs &a, uint32_t k, const double
     }
 }
 
+// Sum of p[i * stride] over i = 0 .. n-1 (n >= 1) in index order; the
+// loads go out 16 at a time, the adds stay in order.
+__device__ __forceinline__ double ordered_sum(const double *p, int64_t stride, int64_t n) {
+    double s = 0.0;
+    for (int64_t i0 = 0; i0 < n; i0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int j = 0; j < 16; j++) v[j] = p[std::min<int64_t>(i0 + j, n - 1) * stride];
+#pragma unroll
+        for (int j = 0; j < 16; j++)
+            if (i0 + j < n) s += v[j];
+    }
+    return s;
+}
+
 // Phase D1: dangling partial per fixed chunk of BP_DCHUNK tiles.
 __device__ __forceinline__ void bp_dang1(const BpArgs &a) {
     const int lane = threadIdx.x & 63;
@@ -446,9 +501,7 @@ __device__ __forceinline__ void bp_dang1(const BpArgs &a) {
         const uint32_t b = (uint32_t)((w % lgroups) * 64 + lane);
         if (b >= a.Bw) continue;
         const int64_t t0 = ch * BP_DCHUNK, t1 = std::min<int64_t>(t0 + BP_DCHUNK, a.ntiles);
-        double s = 0.0;
-        for (int64_t t = t0; t < t1; t++) s += a.dsum[t * a.B + b];
-        a.dpart[ch * a.B + b] = s;
+        a.dpart[ch * a.B + b] = ordered_sum(a.dsum + t0 * a.B + b, a.B, t1 - t0);
     }
 }
 
@@ -461,9 +514,7 @@ __device__ __forceinline__ void bp_dang2(const BpArgs &a, double *Dnext) {
     for (int64_t lg = gwave; lg * 64 < (int64_t)a.Bw; lg += nwaves) {
         const uint32_t b = (uint32_t)(lg * 64 + lane);
         if (b >= a.Bw) continue;
-        double s = 0.0;
-        for (int64_t ch = 0; ch < nchunks; ch++) s += a.dpart[ch * a.B + b];
-        Dnext[b] = s;
+        Dnext[b] = ordered_sum(a.dpart + b, a.B, nchunks);
     }
 }
 
@@ -569,11 +620,14 @@ const void *bp_kernel(uint32_t Bw) {
     }
 }
 
-// Workgroups of a cooperative (grid-barrier) launch.  The occupancy query's
-// bound is not trusted to the last workgroup: at most 2 per CU and at most
-// half of the reported bound, so every workgroup is resident at once.
-int coop_grid(const void *kernel, int block, int num_cus, int want) {
-    int per_cu = std::max(1, std::min(2, occupancy_per_cu(kernel, block) / 2));
+// Workgroups of a cooperative (grid-barrier) launch.  By default at most
+// max_per_cu per CU and at most half of the occupancy bound; a kernel whose
+// phases run for milliseconds (batched PPR) passes max_per_cu = 0 to use
+// the whole bound (the cooperative launch itself refuses a grid that cannot
+// be resident at once).
+int coop_grid(const void *kernel, int block, int num_cus, int want, int max_per_cu) {
+    const int occ = occupancy_per_cu(kernel, block);
+    int per_cu = max_per_cu > 0 ? std::max(1, std::min(max_per_cu, occ / 2)) : std::max(1, occ);
     int cap = per_cu * num_cus;
     if (want > 0) return std::min(want, cap);
     return cap;
@@ -669,7 +723,7 @@ gx_status run_bsssp(gx_graph *g, const int32_t *dev_src, uint32_t B, BsWork &w, 
     const size_t n = (size_t)d.V * B;
     hipLaunchKernelGGL(k_bs_fill, dim3(std::min<size_t>(4096, (n + 255) / 256 + 1)), dim3(256), 0, s, D, n, INF);
     int64_t steps_max = 0;
-    const int grid = coop_grid(var->fn, var->block, g->num_cus, (int)tn.grid);
+    const int grid = coop_grid(var->fn, var->block, g->num_cus, (int)tn.grid, 2);
     for (uint32_t l0 = 0; l0 < B; l0 += tn.width) {
         const uint32_t G = tn.width / 32;
         GX_CHECK_HIP(hipMemsetAsync(w.M[0], 0, (size_t)d.V * G * 4, s), g);
@@ -748,7 +802,7 @@ gx_status run_bppr(gx_graph *g, const int32_t *dev_seed, uint32_t B, BpWork &w, 
     a.k0 = 0;
     a.steps = iters;
     const void *fn = bp_kernel(B);
-    const int grid = coop_grid(fn, 256, g->num_cus, grid_want);
+    const int grid = coop_grid(fn, 256, g->num_cus, grid_want, 0);
     if (iters > 0) GX_CHECK_HIP(launch_coop(fn, grid, 256, &a, s), g);
     GX_CHECK_HIP(hipMemcpyAsync(out, w.x[iters & 1], n * 4, hipMemcpyDeviceToDevice, s), g);
     GridBar bar;
@@ -772,8 +826,14 @@ hipError_t bs_launch_superstep(const BsArgs &a, uint32_t k, uint32_t it, int gri
 
 hipError_t bp_launch_superstep(const BpArgs &a, uint32_t k, int grid, hipStream_t s) {
     const uint32_t lpt = (a.Bw + 63) / 64;
-#define GX_BP_PHASES(L)                                                              \
-    hipLaunchKernelGGL(k_bp_pull<L>, dim3(grid), dim3(256), 0, s, a, k);             \
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const int cus = device_cus(dev);
+    // the pull keeps its row gathers in flight from every wave the CUs hold
+#define GX_BP_PHASES(L)                                                                                  \
+    hipLaunchKernelGGL(k_bp_pull<L>,                                                                     \
+                       dim3(std::max(grid, cus * occupancy_per_cu((const void *)k_bp_pull<L>, 256))),  \
+                       dim3(256), 0, s, a, k);                                                          \
     hipLaunchKernelGGL(k_bp_fix<L>, dim3(grid), dim3(256), 0, s, a, k);
     switch (lpt) {
         case 1: GX_BP_PHASES(1) break;

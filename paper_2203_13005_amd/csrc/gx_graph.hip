@@ -78,7 +78,11 @@ struct HostImages {
 static gx_status validate(const gx_graph_desc *d) {
     GX_REQUIRE(d, GX_EINVAL, "desc is NULL");
     GX_REQUIRE(d->V >= 0 && d->V < (int64_t(1) << 31) - 64, GX_EINVAL, "V=%lld out of range", (long long)d->V);
-    GX_REQUIRE(d->E >= 0 && d->E < (int64_t(1) << 31) - PR_TILE, GX_EINVAL, "E=%lld out of range", (long long)d->E);
+    GX_REQUIRE(d->E >= 0 && d->E < (int64_t(1) << 31) - PR_TILE_MAX, GX_EINVAL, "E=%lld out of range",
+               (long long)d->E);
+    GX_REQUIRE(d->pr_tile_edges == 0 || d->pr_tile_edges == 256 || d->pr_tile_edges == 512 ||
+                   d->pr_tile_edges == 1024 || d->pr_tile_edges == 2048,
+               GX_EINVAL, "pr_tile_edges=%u not 0, 256, 512, 1024 or 2048", d->pr_tile_edges);
     GX_REQUIRE(d->needs != 0 && (d->needs & ~7u) == 0, GX_EINVAL, "needs=%u invalid", d->needs);
     GX_REQUIRE(d->row_ptr || d->V == 0, GX_EINVAL, "row_ptr is NULL");
     GX_REQUIRE(d->col || d->E == 0, GX_EINVAL, "col is NULL");
@@ -130,9 +134,18 @@ static void build_in_csr(const gx_graph_desc *d, HostImages &h) {
 // Pull tiles: tile t covers edges [t*T, (t+1)*T) of a CSR and owns the rows
 // whose first edge position falls in that range (the last tile also owns the
 // rows starting at E).
-static int64_t ntiles_for(int64_t E, int64_t T = PR_TILE) { return std::max<int64_t>(1, (E + T - 1) / T); }
+static int64_t ntiles_for(int64_t E, int64_t T) { return std::max<int64_t>(1, (E + T - 1) / T); }
 
-static void build_tiles(const std::vector<int32_t> &rp, std::vector<int32_t> &tile_row, int64_t T = PR_TILE) {
+// PageRank tile size: the caller's choice, else the largest size that still
+// gives 2048 tiles (eight per CU), else the smallest.
+static int32_t pr_tile_for(const gx_graph_desc *d) {
+    if (d->pr_tile_edges) return (int32_t)d->pr_tile_edges;
+    for (int32_t T = PR_TILE_MAX; T > PR_BLOCK; T /= 2)
+        if (ntiles_for(d->E, T) >= 2048) return T;
+    return PR_BLOCK;
+}
+
+static void build_tiles(const std::vector<int32_t> &rp, std::vector<int32_t> &tile_row, int64_t T) {
     int64_t V = (int64_t)rp.size() - 1, E = rp.back();
     int64_t nt = ntiles_for(E, T);
     tile_row.resize(nt + 1);
@@ -144,10 +157,12 @@ static void build_tiles(const std::vector<int32_t> &rp, std::vector<int32_t> &ti
 
 // Pull records from a CSR over destinations (rows) listing sources in
 // ascending order.  Destinations are taken in blocks of
-// 2^PULL_SLICE_SHIFT; the blocks are dealt to the PULL_SLICES slices
-// greedily, heaviest in-edge count first, each to the lightest slice so
-// far (degree skew would otherwise pile most edges onto one slice).  Within
-// a slice the records are grouped by source band, keeping the (destination,
+// 2^PULL_SLICE_SHIFT and dealt to PULL_SLICES * S bins greedily, heaviest
+// in-edge count first, each to the lightest bin so far (degree skew would
+// otherwise pile most edges onto one bin).  Bin j belongs to XCD slice
+// j mod PULL_SLICES; S is chosen so a bin's destination values fit
+// PULL_BIN_BYTES, and an XCD sweeps its S bins one after another.  Within a
+// bin the records are grouped by source band, keeping the (destination,
 // source) order of the CSR inside a group.  `w` may be null (records
 // {dst, src}).  The array is padded to whole PULL_VT groups (the padding is
 // never a valid record).
@@ -155,32 +170,35 @@ static void build_pull(const std::vector<int32_t> &rp, const int32_t *src, const
                        std::vector<uint2> &out, PullSlices &sl) {
     const int64_t V = (int64_t)rp.size() - 1, E = rp.back();
     const int64_t nb = (V >> PULL_BAND_BITS) + 1;
+    const int64_t S = std::max<int64_t>(1, (V * 4 + PULL_SLICES * PULL_BIN_BYTES - 1) / (PULL_SLICES * PULL_BIN_BYTES));
+    const int64_t nbin = PULL_SLICES * S;
     const int64_t nblk = (V + (1 << PULL_SLICE_SHIFT) - 1) >> PULL_SLICE_SHIFT;
     std::vector<int64_t> bcnt((size_t)nblk, 0);
     for (int64_t v = 0; v < V; v++) bcnt[v >> PULL_SLICE_SHIFT] += rp[v + 1] - rp[v];
     std::vector<int64_t> order((size_t)nblk);
     for (int64_t i = 0; i < nblk; i++) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return bcnt[a] > bcnt[b]; });
-    std::vector<uint8_t> slice((size_t)nblk, 0);
-    int64_t load[PULL_SLICES] = {};
+    // group index of block b's bin: slices are contiguous, their bins in order
+    std::vector<int32_t> group((size_t)nblk, 0);
+    std::vector<int64_t> load((size_t)nbin, 0);
     for (int64_t b : order) {
-        int x = 0;
-        for (int y = 1; y < PULL_SLICES; y++)
-            if (load[y] < load[x]) x = y;
-        slice[b] = (uint8_t)x;
-        load[x] += bcnt[b];
+        int64_t j = 0;
+        for (int64_t y = 1; y < nbin; y++)
+            if (load[y] < load[j]) j = y;
+        load[j] += bcnt[b];
+        group[b] = (int32_t)((j % PULL_SLICES) * S + j / PULL_SLICES);
     }
-    std::vector<int64_t> pos((size_t)PULL_SLICES * nb + 1, 0);
+    std::vector<int64_t> pos((size_t)nbin * nb + 1, 0);
     for (int64_t v = 0; v < V; v++) {
-        const int64_t g0 = (int64_t)slice[v >> PULL_SLICE_SHIFT] * nb + 1;
+        const int64_t g0 = (int64_t)group[v >> PULL_SLICE_SHIFT] * nb + 1;
         for (int32_t e = rp[v]; e < rp[v + 1]; e++) pos[g0 + (src[e] >> PULL_BAND_BITS)]++;
     }
     for (size_t g = 0; g + 1 < pos.size(); g++) pos[g + 1] += pos[g];
-    for (int x = 0; x < PULL_SLICES; x++) sl.off[x] = pos[(size_t)x * nb];
+    for (int x = 0; x < PULL_SLICES; x++) sl.off[x] = pos[(size_t)x * S * nb];
     sl.off[PULL_SLICES] = E;
     out.assign((size_t)pull_padded(E), make_uint2(0xFFFFFFFFu, 0u));
     for (int64_t v = 0; v < V; v++) {
-        const int64_t g0 = (int64_t)slice[v >> PULL_SLICE_SHIFT] * nb;
+        const int64_t g0 = (int64_t)group[v >> PULL_SLICE_SHIFT] * nb;
         for (int32_t e = rp[v]; e < rp[v + 1]; e++) {
             const uint32_t u = (uint32_t)src[e];
             out[pos[g0 + (u >> PULL_BAND_BITS)]++] = make_uint2((uint32_t)v, w ? ((u << 8) | w[e]) : u);
@@ -250,7 +268,8 @@ static void layout(const gx_graph_desc *desc, int64_t E_sym, Carver &c, DevGraph
     }
     if (desc->needs & (GX_NEED_IN | GX_NEED_OUT)) {
         d->in_rp = c.take<int32_t>(V + 1);
-        d->pr_ntiles = (int32_t)ntiles_for(E);
+        d->pr_tile = pr_tile_for(desc);
+        d->pr_ntiles = (int32_t)ntiles_for(E, d->pr_tile);
         d->pr_tile_row = c.take<int32_t>(d->pr_ntiles + 1);
     }
     if (desc->needs & GX_NEED_IN) {
@@ -369,7 +388,7 @@ extern "C" gx_status gx_graph_load(const gx_graph_desc *desc, void *dev_arena, s
     int32_t W = (int32_t)((desc->V + 31) / 32);
     try {
         build_in_csr(desc, h);
-        build_tiles(h.in_rp, h.tile_row);
+        build_tiles(h.in_rp, h.tile_row, pr_tile_for(desc));
         if ((desc->needs & GX_NEED_OUT) && (desc->E == 0 || banded_weights_fit(desc)))
             build_pull(h.in_rp, h.in_col.data(), h.in_w.data(), h.pull_w, h.pull_w_off);
         if (desc->needs & GX_NEED_SYM) {

@@ -56,19 +56,21 @@ struct Carver {
 };
 
 // ---------------------------------------------------------------- graph
-// Edge tile of the PageRank pull (in-edges per workgroup tile).
+// Edge tile of the PageRank pull (in-edges per workgroup tile): PR_BLOCK
+// threads times 1, 2, 4 or 8 edges, chosen per graph at load.
 constexpr int PR_BLOCK = 256;
-constexpr int PR_VT = 8;
-constexpr int PR_TILE = PR_BLOCK * PR_VT;
+constexpr int PR_TILE_MAX = PR_BLOCK * 8;
 // Records of the SSSP / CC pull.  Destinations are dealt to PULL_SLICES
 // slices in blocks of 2^PULL_SLICE_SHIFT vertices, balanced by in-edge
-// count; a slice's records are ordered by
+// count; a slice is a sequence of bins of at most PULL_BIN_BYTES of
+// destination values, each ordered by
 // (source >> PULL_BAND_BITS, destination, source).  Workgroup b sweeps slice
 // b mod PULL_SLICES, and workgroups are dealt round-robin to the 8 XCDs, so
-// each XCD's L2 holds one slice's destination values and one band of source
+// each XCD's L2 holds one bin's destination values and one band of source
 // snapshots (2^16 vertices) at a time.
 constexpr int PULL_SLICES = 8;
 constexpr int PULL_SLICE_SHIFT = 6;
+constexpr int64_t PULL_BIN_BYTES = int64_t(2) << 20;  // destination values an XCD sweeps at a time
 constexpr int PULL_BAND_BITS = 16;
 constexpr int PULL_VT = 8;  // records per thread; slices are swept in aligned groups of PULL_VT
 inline int64_t pull_padded(int64_t n) { return (n + PULL_VT - 1) / PULL_VT * PULL_VT; }
@@ -87,6 +89,7 @@ struct DevGraph {
     const int32_t *in_rp = nullptr;
     const int32_t *in_col = nullptr;
     const int32_t *outdeg = nullptr;
+    int32_t pr_tile = PR_TILE_MAX;  // in-edges per PageRank tile
     int32_t pr_ntiles = 0;
     const int32_t *pr_tile_row = nullptr;  // [pr_ntiles + 1]
     // sliced, banded in-edge records for the SSSP pull: {dst, (src << 8) | w}

@@ -460,6 +460,7 @@ struct PrApply {
     }
 };
 
+template <int VT>
 __global__ __launch_bounds__(PR_BLOCK) void k_pr_pull(const int32_t *__restrict__ in_rp,
                                                       const int32_t *__restrict__ in_col,
                                                       const int32_t *__restrict__ tile_row, int64_t E,
@@ -468,30 +469,32 @@ __global__ __launch_bounds__(PR_BLOCK) void k_pr_pull(const int32_t *__restrict_
                                                       double *__restrict__ head, double *__restrict__ tailp,
                                                       int32_t *__restrict__ spill_row, double *__restrict__ dpart,
                                                       DevStep *__restrict__ step) {
-    __shared__ float s_val[PR_TILE];
-    __shared__ int32_t s_own[PR_TILE];
+    constexpr int TILE = PR_BLOCK * VT;
+    __shared__ float s_val[TILE];
+    __shared__ int32_t s_own[TILE];
     __shared__ double s_last[PR_BLOCK];
-    __shared__ int32_t s_last_start[PR_BLOCK];
+    __shared__ double s_wy[PR_BLOCK / 64];
+    __shared__ int s_wf[PR_BLOCK / 64];
     __shared__ int32_t s_red[4];
     __shared__ double s_d[4];
     __shared__ unsigned long long s_c[4];
     const int tid = threadIdx.x;
     const int32_t t = blockIdx.x;
-    const int64_t e0 = (int64_t)t * PR_TILE;
-    const int n = (int)max((int64_t)0, min((int64_t)PR_TILE, E - e0));
+    const int64_t e0 = (int64_t)t * TILE;
+    const int n = (int)max((int64_t)0, min((int64_t)TILE, E - e0));
     const int32_t r_lo = tile_row[t], r_hi = tile_row[t + 1];
     ap.dD = ap.d * (*Dp) * inv_V;
     if (tid == 0) spill_row[t] = -1;
     if (n > 0) {  // contributions into LDS: all source ids, then all gathers
         // (unconditional loads: slots past the tile's end repeat its last edge)
-        int32_t u[PR_VT];
-        float cv[PR_VT];
+        int32_t u[VT];
+        float cv[VT];
 #pragma unroll
-        for (int i = 0; i < PR_VT; i++) u[i] = in_col[e0 + min(tid + i * PR_BLOCK, n - 1)];
+        for (int i = 0; i < VT; i++) u[i] = in_col[e0 + min(tid + i * PR_BLOCK, n - 1)];
 #pragma unroll
-        for (int i = 0; i < PR_VT; i++) cv[i] = c_in[u[i]];
+        for (int i = 0; i < VT; i++) cv[i] = c_in[u[i]];
 #pragma unroll
-        for (int i = 0; i < PR_VT; i++) {
+        for (int i = 0; i < VT; i++) {
             const int p = tid + i * PR_BLOCK;
             if (p < n) {
                 s_val[p] = cv[i];
@@ -505,12 +508,12 @@ __global__ __launch_bounds__(PR_BLOCK) void k_pr_pull(const int32_t *__restrict_
         if (b > a) s_own[a - e0] = r - r_lo + 1;
     }
     __syncthreads();
-    block_max_scan<PR_VT>(s_own, n, s_red);
+    block_max_scan<VT>(s_own, n, s_red);
 
     // Per-thread contiguous chunk: sequential sums per destination row.
     double dsum = 0.0;
     int chg = 0;
-    const int c0 = tid * PR_VT, c1 = min(c0 + PR_VT, n);
+    const int c0 = tid * VT, c1 = min(c0 + VT, n);
     int own = -1;
     bool started = false, first = true;
     double sum = 0.0, first_sum = 0.0;
@@ -562,17 +565,38 @@ __global__ __launch_bounds__(PR_BLOCK) void k_pr_pull(const int32_t *__restrict_
             }
         }
     }
-    s_last[tid] = (own >= 0 && !last_ends_here) ? sum : 0.0;
-    s_last_start[tid] = started ? 1 : 0;
-    __syncthreads();
-    if (defer_first) {  // walk back over the threads holding earlier pieces of this row
-        double total = first_sum;
-        for (int j = tid - 1; j >= 0; j--) {
-            total += s_last[j];
-            if (s_last_start[j]) break;
+    // Pieces of rows that run past a chunk: an inclusive segmented scan over
+    // the threads, a segment starting at the thread where a row's trailing
+    // piece starts (or where a row ends).  Fixed order: a shuffle scan inside
+    // each wave, then the wave totals folded in wave order; a deferred first
+    // piece then adds the scan value of the thread before it.
+    {
+        double y = (own >= 0 && !last_ends_here) ? sum : 0.0;
+        int f = (own < 0 || started || last_ends_here) ? 1 : 0;
+        const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const double yp = __shfl_up(y, d, 64);
+            const int fp = __shfl_up(f, d, 64);
+            if (lane >= d) {
+                if (!f) y = yp + y;
+                f |= fp;
+            }
         }
-        finish(first_own, total, defer_ends_tile);
+        if (lane == 63) {
+            s_wy[wv] = y;
+            s_wf[wv] = f;
+        }
+        __syncthreads();
+        if (!f) {
+            double c = 0.0;
+            for (int v = 0; v < wv; v++) c = s_wf[v] ? s_wy[v] : c + s_wy[v];
+            y = c + y;
+        }
+        s_last[tid] = y;
     }
+    __syncthreads();
+    if (defer_first) finish(first_own, tid > 0 ? first_sum + s_last[tid - 1] : first_sum, defer_ends_tile);
     // Rows of this tile without in-edges.
     for (int32_t r = r_lo + tid; r < r_hi; r += PR_BLOCK)
         if (in_rp[r + 1] == in_rp[r]) ap(r, 0.0, dsum, chg);
@@ -585,8 +609,10 @@ __global__ __launch_bounds__(PR_BLOCK) void k_pr_pull(const int32_t *__restrict_
 }
 
 // Completes the rows that cross tile boundaries (in tile order) and reduces
-// the dangling mass of the new ranks for the next superstep.  One block.
-__global__ __launch_bounds__(1024) void k_pr_fix(const int32_t *__restrict__ in_rp, int32_t ntiles,
+// the dangling mass of the new ranks for the next superstep in a fixed
+// order.  One workgroup; the kernel boundary makes every pull workgroup's
+// partials visible to it.
+__global__ __launch_bounds__(1024) void k_pr_fix(const int32_t *__restrict__ in_rp, int32_t ntiles, int32_t tile,
                                                  const double *__restrict__ head, const double *__restrict__ tailp,
                                                  const int32_t *__restrict__ spill_row,
                                                  const double *__restrict__ dpart, PrApply ap, double *Dp,
@@ -598,18 +624,18 @@ __global__ __launch_bounds__(1024) void k_pr_fix(const int32_t *__restrict__ in_
     double dsum = 0.0;
     int chg = 0;
     for (int32_t t = threadIdx.x; t < ntiles; t += blockDim.x) {
-        int32_t r = spill_row[t];
+        const int32_t r = spill_row[t];
         if (r >= 0) {
             double total = tailp[t];
-            int32_t t_end = (in_rp[r + 1] - 1) / PR_TILE;
+            const int32_t t_end = (in_rp[r + 1] - 1) / tile;
             for (int32_t t2 = t + 1; t2 <= t_end; t2++) total += head[t2];
             ap(r, total, dsum, chg);
         }
         dsum += dpart[t];
     }
     __syncthreads();
-    double td = block_sum<double>(dsum, s_d);
-    unsigned long long tc = block_sum<unsigned long long>((unsigned long long)chg, s_c);
+    const double td = block_sum<double>(dsum, s_d);
+    const unsigned long long tc = block_sum<unsigned long long>((unsigned long long)chg, s_c);
     if (threadIdx.x == 0) {
         *Dp = td;  // dangling mass of x_{t+1}
         if (tc) atomicAdd(&step->changed, tc);
@@ -953,12 +979,14 @@ static gx_status enqueue_superstep(gx_state *s, hipStream_t hs) {
         double inv_V = d.V > 0 ? 1.0 / (double)d.V : 0.0;
         if (d.V > 0) {
             if (e0) (void)hipEventRecord(e0, hs);
-            hipLaunchKernelGGL(k_pr_pull, dim3(d.pr_ntiles), dim3(PR_BLOCK), 0, hs, d.in_rp, d.in_col, d.pr_tile_row,
+            auto pull = d.pr_tile == 256 ? k_pr_pull<1> : d.pr_tile == 512 ? k_pr_pull<2>
+                      : d.pr_tile == 1024 ? k_pr_pull<4> : k_pr_pull<8>;
+            hipLaunchKernelGGL(pull, dim3(d.pr_ntiles), dim3(PR_BLOCK), 0, hs, d.in_rp, d.in_col, d.pr_tile_row,
                                d.E, s->contrib[cur], ap, s->Dval, inv_V, s->head, s->tailp, s->spill_row, s->dpart,
                                step);
             if (e1) (void)hipEventRecord(e1, hs);
-            hipLaunchKernelGGL(k_pr_fix, dim3(1), dim3(1024), 0, hs, d.in_rp, d.pr_ntiles, s->head, s->tailp,
-                               s->spill_row, s->dpart, ap, s->Dval, inv_V, step, next);
+            hipLaunchKernelGGL(k_pr_fix, dim3(1), dim3(1024), 0, hs, d.in_rp, d.pr_ntiles, d.pr_tile, s->head,
+                               s->tailp, s->spill_row, s->dpart, ap, s->Dval, inv_V, step, next);
         }
     } else {
         // superstep k: relax A_k (list built by the previous compaction), then

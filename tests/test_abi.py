@@ -64,6 +64,11 @@ def test_graph_bytes_and_validation():
         assert b.lib.gx_last_error()
     d, keep = _desc(b, g, 0)
     assert b.lib.gx_graph_bytes(ctypes.byref(d), ctypes.byref(n)) == b.GX_EINVAL
+    for tile, ok in ((0, True), (256, True), (2048, True), (128, False), (300, False), (4096, False)):
+        d, keep = _desc(b, g, b.GX_NEED_IN)
+        d.pr_tile_edges = tile
+        st = b.lib.gx_graph_bytes(ctypes.byref(d), ctypes.byref(n))
+        assert st == (b.GX_OK if ok else b.GX_EINVAL), tile
 
 
 def test_load_rejects_small_arena_before_touching_device():

@@ -201,9 +201,9 @@ def test_cc_rmat_partition(gx, scale, seed, mode):
 
 # ------------------------------------------------------------------ PageRank
 
-def check_pr(gx, g, T, d=0.85, tol=PR_TOL):
+def check_pr(gx, g, T, d=0.85, tol=PR_TOL, tile=0):
     ref = oracle.pagerank(g, T, d)
-    st = gx.State(load(gx, g, gx.GX_NEED_IN), gx.GX_PAGERANK, damping=d)
+    st = gx.State(gx.DeviceGraph(g, gx.GX_NEED_IN, pr_tile_edges=tile), gx.GX_PAGERANK, damping=d)
     rs, steps = st.run(T, per_step=True)
     x = st.values_numpy().astype(np.float64)
     err = np.max(np.abs(x - ref)) if g.V else 0.0
@@ -219,35 +219,42 @@ def test_pagerank_rmat_scale14_20_steps(gx):
     assert rel < 1e-4
 
 
+PR_TILES = [0, 256, 512, 1024, 2048]  # 0 = the size the library picks
+
+
+@pytest.mark.parametrize("tile", PR_TILES)
 @pytest.mark.parametrize("V,E,seed", [(50, 100, 1), (3000, 9000, 2), (10000, 300, 3)])
-def test_pagerank_random(gx, V, E, seed):
-    check_pr(gx, random_graph(V, E, seed), 15)
+def test_pagerank_random(gx, V, E, seed, tile):
+    check_pr(gx, random_graph(V, E, seed), 15, tile=tile)
 
 
-def test_pagerank_hub_rows_span_tiles(gx):
+@pytest.mark.parametrize("tile", PR_TILES)
+def test_pagerank_hub_rows_span_tiles(gx, tile):
     # in-degree 9000 at vertex 0 and 3000 at vertex 1: rows cross several
-    # 2048-edge tiles; plus rows ending exactly on a tile boundary
+    # tiles; plus rows ending exactly on a tile boundary
     V = 9001
     src = np.r_[np.arange(1, V), np.arange(2, 3002)]
     dst = np.r_[np.zeros(V - 1, int), np.ones(3000, int)]
     g = gen.from_edges(V, src, dst)
-    check_pr(gx, g, 10)
-    g = star_into(2049)  # E = 2048: exactly one full tile
-    check_pr(gx, g, 10)
+    check_pr(gx, g, 10, tile=tile)
+    g = star_into(2049)  # E = 2048: a whole number of tiles of every size
+    check_pr(gx, g, 10, tile=tile)
     g = star_into(4097, hub=4096)  # E = 4096, the hub is the last row
-    check_pr(gx, g, 10)
+    check_pr(gx, g, 10, tile=tile)
 
 
-def test_pagerank_edge_cases(gx):
-    check_pr(gx, gen.from_edges(1, [], []), 5)
-    check_pr(gx, gen.from_edges(7, [], []), 5)
+@pytest.mark.parametrize("tile", PR_TILES)
+def test_pagerank_edge_cases(gx, tile):
+    check_pr(gx, gen.from_edges(1, [], []), 5, tile=tile)
+    check_pr(gx, gen.from_edges(7, [], []), 5, tile=tile)
     g = gen.from_edges(2, [0], [1])
-    check_pr(gx, g, 12)
+    check_pr(gx, g, 12, tile=tile)
 
 
-def test_pagerank_deterministic_and_checkpoint(gx):
+@pytest.mark.parametrize("tile", [0, 2048])
+def test_pagerank_deterministic_and_checkpoint(gx, tile):
     g = gen.rmat(15, seed=4)
-    dg = load(gx, g, gx.GX_NEED_IN)
+    dg = gx.DeviceGraph(g, gx.GX_NEED_IN, pr_tile_edges=tile)
     a = gx.State(dg, gx.GX_PAGERANK)
     a.run(20)
     b = gx.State(dg, gx.GX_PAGERANK)

@@ -82,13 +82,16 @@ def test_serving_mixed_matches_oracle_and_alone(gx, graphs):
 
 
 def test_serving_admits_while_running(gx, graphs):
-    # queries arriving while others run join at superstep boundaries
+    # queries arriving while others run join at superstep boundaries; the
+    # arrival gap is an eighth of one query's own time on the device, so
+    # several arrive during each query's life whatever the speed
     queries = [(2, gx.GX_PPR, int(s)) for s in gen.pick_sources(graphs[2], 20, seed=9)]
-    done = serve(gx, graphs, queries, lanes=32, epoch=2, stagger_s=0.01)
-    starts = sorted(c.start_s for c in done.values())
-    ends = sorted(c.done_s for c in done.values())
-    # some query started after another had started but before it finished
-    assert any(starts[0] < s < ends[0] for s in starts[1:])
+    one = serve(gx, graphs, queries[:1], epoch=2)[0]
+    gap = max((one.done_s - one.start_s) / 8, 1e-4)
+    done = serve(gx, graphs, queries, lanes=32, epoch=2, stagger_s=gap)
+    spans = [(c.start_s, c.done_s) for c in done.values()]
+    # some query was admitted after another had started but before it finished
+    assert any(a0 < b0 < a1 for a0, a1 in spans for b0, _ in spans), (gap, sorted(spans)[:4])
     for i, q in enumerate(queries):
         check(gx, graphs, q, done[i])
 
