@@ -61,8 +61,6 @@ struct BpArgs {
     float *x[2], *c[2];
     double *head, *tailp, *dsum, *dpart, *D[2];  // D[k & 1]: dangling mass of superstep k
     int32_t *spill;
-    GridBar *bar;
-    uint32_t k0, steps;
 };
 
 struct BpWork {
@@ -70,11 +68,9 @@ struct BpWork {
     float *x[2], *c[2];
     double *head, *tailp, *dsum, *dpart, *D[2];
     int32_t *spill, *trow, *seed, *end;
-    GridBar *bar;
 };
 
 const BsVariant *bs_variants(int *n);
-const void *bp_kernel(uint32_t Bw);
 int coop_grid(const void *kernel, int block, int num_cus, int want, int max_per_cu);
 void bs_layout(const DevGraph &d, uint32_t B, Carver &c, BsWork *w);
 void bp_layout(const DevGraph &d, uint32_t B, Carver &c, BpWork *w);

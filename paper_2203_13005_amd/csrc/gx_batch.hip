@@ -19,11 +19,11 @@
 //     the group's improved-lane bits by one atomicOr into the next mask.
 //   A grid barrier separates the phases; the loop ends when a superstep
 //   activates no (vertex, lane) pair.
-// PPR (k_bppr): per superstep a pull over equal in-edge tiles (one wave per
-//   tile, lanes across the wave), rows crossing tiles completed in tile
-//   order, and the per-lane dangling mass reduced in a fixed two-level order,
-//   so every lane's arithmetic is independent of the other lanes and of the
-//   launch shape.
+// PPR: per superstep four ordinary launches: a pull over equal in-edge
+//   tiles (one wave per tile, lanes across the wave), rows crossing tiles
+//   completed in tile order, and the per-lane dangling mass reduced in a
+//   fixed two-level order, so every lane's arithmetic is independent of the
+//   other lanes and of the launch shape.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -518,26 +518,7 @@ __device__ __forceinline__ void bp_dang2(const BpArgs &a, double *Dnext) {
     }
 }
 
-// Persistent cooperative form: `steps` supersteps with grid barriers
-// between the phases.  The dangling mass of superstep k lives in D[k & 1].
-template <int LPT>
-__global__ __launch_bounds__(256) void k_bppr(BpArgs a) {
-    __shared__ unsigned int s_flag;
-    for (uint32_t it = 0; it < a.steps; it++) {
-        const uint32_t k = a.k0 + it;
-        const double *Dcur = a.D[k & 1];
-        bp_pull<LPT>(a, k, Dcur);
-        if (!grid_sync(a.bar, gridDim.x, &s_flag)) return;
-        bp_fix<LPT>(a, k, Dcur);
-        if (!grid_sync(a.bar, gridDim.x, &s_flag)) return;
-        bp_dang1(a);
-        if (!grid_sync(a.bar, gridDim.x, &s_flag)) return;
-        bp_dang2(a, a.D[(k + 1) & 1]);
-        if (!grid_sync(a.bar, gridDim.x, &s_flag)) return;
-    }
-}
-
-// Ordinary-launch form of the four phases (serving).
+// The four phases as ordinary launches (batched runs and serving).
 template <int LPT>
 __global__ __launch_bounds__(256) void k_bp_pull(BpArgs a, uint32_t k) { bp_pull<LPT>(a, k, a.D[k & 1]); }
 template <int LPT>
@@ -610,15 +591,6 @@ const BsVariant *bs_variants(int *n) {
     return v;
 }
 
-const void *bp_kernel(uint32_t Bw) {
-    uint32_t lpt = (Bw + 63) / 64;
-    switch (lpt) {
-        case 1: return (const void *)k_bppr<1>;
-        case 2: return (const void *)k_bppr<2>;
-        case 3: return (const void *)k_bppr<3>;
-        default: return (const void *)k_bppr<4>;
-    }
-}
 
 // Workgroups of a cooperative (grid-barrier) launch.  By default at most
 // max_per_cu per CU and at most half of the occupancy bound; a kernel whose
@@ -663,7 +635,6 @@ void bp_layout(const DevGraph &d, uint32_t B, Carver &c, BpWork *w) {
     w->trow = c.take<int32_t>(nt + 1);
     w->seed = c.take<int32_t>(2 * (size_t)B);  // seeds, then per-lane end supersteps
     w->end = w->seed + B;
-    w->bar = c.take<GridBar>(1);
 }
 
 hipError_t launch_coop(const void *kernel, int grid, int block, void *args, hipStream_t s) {
@@ -774,7 +745,6 @@ gx_status run_bppr(gx_graph *g, const int32_t *dev_seed, uint32_t B, BpWork &w, 
     const size_t n = (size_t)d.V * B;
     hipLaunchKernelGGL(k_bp_init, dim3((unsigned)std::min<size_t>(8192, (n + 255) / 256 + 1)), dim3(256), 0, s,
                        w.x[0], w.c[0], w.D[0], w.seed, d.outdeg, d.V, B);
-    GX_CHECK_HIP(hipMemsetAsync(w.bar, 0, sizeof(GridBar), s), g);
     BpArgs a{};
     a.in_rp = d.in_rp;
     a.in_col = d.in_col;
@@ -798,21 +768,13 @@ gx_status run_bppr(gx_graph *g, const int32_t *dev_seed, uint32_t B, BpWork &w, 
     a.D[0] = w.D[0];
     a.D[1] = w.D[1];
     a.spill = w.spill;
-    a.bar = w.bar;
-    a.k0 = 0;
-    a.steps = iters;
-    const void *fn = bp_kernel(B);
-    const int grid = coop_grid(fn, 256, g->num_cus, grid_want, 0);
-    if (iters > 0) GX_CHECK_HIP(launch_coop(fn, grid, 256, &a, s), g);
+    // four ordinary launches per superstep (measured faster than one
+    // persistent kernel with grid barriers: each phase then runs at its own
+    // full occupancy)
+    const int grid = grid_want > 0 ? grid_want : 2 * g->num_cus;
+    for (uint32_t k = 0; k < iters; k++) GX_CHECK_HIP(bp_launch_superstep(a, k, grid, s), g);
     GX_CHECK_HIP(hipMemcpyAsync(out, w.x[iters & 1], n * 4, hipMemcpyDeviceToDevice, s), g);
-    GridBar bar;
-    GX_CHECK_HIP(hipMemcpyAsync(&bar, w.bar, sizeof bar, hipMemcpyDeviceToHost, s), g);
     GX_CHECK_HIP(hipStreamSynchronize(s), g);
-    if (bar.error) {
-        set_error("grid barrier timed out in batched PPR");
-        g->dev_error = true;
-        return GX_EDEVICE;
-    }
     return GX_OK;
 }
 

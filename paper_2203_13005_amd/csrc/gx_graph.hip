@@ -71,6 +71,7 @@ struct HostImages {
     std::vector<uint32_t> in_w;
     std::vector<int32_t> sym_rp, sym_col;
     std::vector<uint2> pull_w, pull_sym;
+    std::vector<uint4> pull_w_units, pull_sym_units;
     PullSlices pull_w_off{}, pull_sym_off{};
     std::vector<uint32_t> rem_out, rem_any;
 };
@@ -163,15 +164,15 @@ static void build_tiles(const std::vector<int32_t> &rp, std::vector<int32_t> &ti
 // j mod PULL_SLICES; S is chosen so a bin's destination values fit
 // PULL_BIN_BYTES, and an XCD sweeps its S bins one after another.  Within a
 // bin the records are grouped by source band, keeping the (destination,
-// source) order of the CSR inside a group.  `w` may be null (records
-// {dst, src}).  The array is padded to whole PULL_VT groups (the padding is
-// never a valid record).
+// source) order of the CSR inside a group; every group is padded to whole
+// PULL_VT records with sentinels (destination PULL_SENTINEL, source the band
+// base) and cut into units of at most PULL_UNIT records.  `w` may be null
+// (records {dst, src}).
 static void build_pull(const std::vector<int32_t> &rp, const int32_t *src, const uint32_t *w,
-                       std::vector<uint2> &out, PullSlices &sl) {
-    const int64_t V = (int64_t)rp.size() - 1, E = rp.back();
+                       std::vector<uint2> &out, std::vector<uint4> &units, PullSlices &sl) {
+    const int64_t V = (int64_t)rp.size() - 1;
     const int64_t nb = (V >> PULL_BAND_BITS) + 1;
-    const int64_t S = std::max<int64_t>(1, (V * 4 + PULL_SLICES * PULL_BIN_BYTES - 1) / (PULL_SLICES * PULL_BIN_BYTES));
-    const int64_t nbin = PULL_SLICES * S;
+    const int64_t nbin = pull_bins(V), S = nbin / PULL_SLICES;
     const int64_t nblk = (V + (1 << PULL_SLICE_SHIFT) - 1) >> PULL_SLICE_SHIFT;
     std::vector<int64_t> bcnt((size_t)nblk, 0);
     for (int64_t v = 0; v < V; v++) bcnt[v >> PULL_SLICE_SHIFT] += rp[v + 1] - rp[v];
@@ -188,22 +189,36 @@ static void build_pull(const std::vector<int32_t> &rp, const int32_t *src, const
         load[j] += bcnt[b];
         group[b] = (int32_t)((j % PULL_SLICES) * S + j / PULL_SLICES);
     }
-    std::vector<int64_t> pos((size_t)nbin * nb + 1, 0);
+    const int64_t ng = nbin * nb;
+    std::vector<int64_t> cnt((size_t)ng, 0);
     for (int64_t v = 0; v < V; v++) {
-        const int64_t g0 = (int64_t)group[v >> PULL_SLICE_SHIFT] * nb + 1;
-        for (int32_t e = rp[v]; e < rp[v + 1]; e++) pos[g0 + (src[e] >> PULL_BAND_BITS)]++;
+        const int64_t g0 = (int64_t)group[v >> PULL_SLICE_SHIFT] * nb;
+        for (int32_t e = rp[v]; e < rp[v + 1]; e++) cnt[g0 + (src[e] >> PULL_BAND_BITS)]++;
     }
-    for (size_t g = 0; g + 1 < pos.size(); g++) pos[g + 1] += pos[g];
-    for (int x = 0; x < PULL_SLICES; x++) sl.off[x] = pos[(size_t)x * S * nb];
-    sl.off[PULL_SLICES] = E;
-    out.assign((size_t)pull_padded(E), make_uint2(0xFFFFFFFFu, 0u));
+    std::vector<int64_t> pos((size_t)ng + 1, 0);
+    for (int64_t g = 0; g < ng; g++) pos[g + 1] = pos[g] + (cnt[g] + PULL_VT - 1) / PULL_VT * PULL_VT;
+    out.assign((size_t)pos[ng], make_uint2(PULL_SENTINEL, 0u));
+    for (int64_t g = 0; g < ng; g++) {  // sentinels carry their band's base as the source
+        const uint32_t bb = (uint32_t)((g % nb) << PULL_BAND_BITS);
+        for (int64_t i = pos[g] + cnt[g]; i < pos[g + 1]; i++) out[i].y = w ? (bb << 8) : bb;
+    }
+    std::vector<int64_t> fill(pos.begin(), pos.end() - 1);
     for (int64_t v = 0; v < V; v++) {
         const int64_t g0 = (int64_t)group[v >> PULL_SLICE_SHIFT] * nb;
         for (int32_t e = rp[v]; e < rp[v + 1]; e++) {
             const uint32_t u = (uint32_t)src[e];
-            out[pos[g0 + (u >> PULL_BAND_BITS)]++] = make_uint2((uint32_t)v, w ? ((u << 8) | w[e]) : u);
+            out[fill[g0 + (u >> PULL_BAND_BITS)]++] = make_uint2((uint32_t)v, w ? ((u << 8) | w[e]) : u);
         }
     }
+    units.clear();
+    for (int x = 0; x < PULL_SLICES; x++) {
+        sl.uoff[x] = (int64_t)units.size();
+        for (int64_t g = x * S * nb; g < (x + 1) * S * nb; g++)
+            for (int64_t s0 = pos[g]; s0 < pos[g + 1]; s0 += PULL_UNIT)
+                units.push_back(make_uint4((uint32_t)s0, (uint32_t)std::min<int64_t>(PULL_UNIT, pos[g + 1] - s0),
+                                           (uint32_t)((g % nb) << PULL_BAND_BITS), 0u));
+    }
+    sl.uoff[PULL_SLICES] = (int64_t)units.size();
 }
 
 static bool banded_weights_fit(const gx_graph_desc *d) {
@@ -276,12 +291,15 @@ static void layout(const gx_graph_desc *desc, int64_t E_sym, Carver &c, DevGraph
         d->in_col = c.take<int32_t>(E);
         d->outdeg = c.take<int32_t>(V);
     }
-    if ((desc->needs & GX_NEED_OUT) && (desc->E == 0 || banded_weights_fit(desc)))
-        d->pull_w = c.take<uint2>(pull_padded(E));
+    if ((desc->needs & GX_NEED_OUT) && (desc->E == 0 || banded_weights_fit(desc))) {
+        d->pull_w = c.take<uint2>(pull_rec_cap(V, E));
+        d->pull_w_units = c.take<uint4>(pull_unit_cap(V, E));
+    }
     if (desc->needs & GX_NEED_SYM) {
         d->sym_rp = c.take<int32_t>(V + 1);
         d->sym_col = c.take<int32_t>(E_sym);
-        d->pull_sym = c.take<uint2>(pull_padded(E_sym));
+        d->pull_sym = c.take<uint2>(pull_rec_cap(V, E_sym));
+        d->pull_sym_units = c.take<uint4>(pull_unit_cap(V, E_sym));
     }
     if (desc->l2g) d->l2g = c.take<int32_t>(V);
     if (desc->flags) {
@@ -390,10 +408,10 @@ extern "C" gx_status gx_graph_load(const gx_graph_desc *desc, void *dev_arena, s
         build_in_csr(desc, h);
         build_tiles(h.in_rp, h.tile_row, pr_tile_for(desc));
         if ((desc->needs & GX_NEED_OUT) && (desc->E == 0 || banded_weights_fit(desc)))
-            build_pull(h.in_rp, h.in_col.data(), h.in_w.data(), h.pull_w, h.pull_w_off);
+            build_pull(h.in_rp, h.in_col.data(), h.in_w.data(), h.pull_w, h.pull_w_units, h.pull_w_off);
         if (desc->needs & GX_NEED_SYM) {
             build_sym(desc, h);
-            build_pull(h.sym_rp, h.sym_col.data(), nullptr, h.pull_sym, h.pull_sym_off);
+            build_pull(h.sym_rp, h.sym_col.data(), nullptr, h.pull_sym, h.pull_sym_units, h.pull_sym_off);
         }
         build_flags(desc, W, h);
     } catch (const std::bad_alloc &) {
@@ -439,13 +457,19 @@ extern "C" gx_status gx_graph_load(const gx_graph_desc *desc, void *dev_arena, s
         e = up.put_array((void *)d.in_col, h.in_col.data(), E * 4);
         if (e == hipSuccess) e = up.put_array((void *)d.outdeg, g->host_outdeg.data(), V * 4);
     }
-    if (e == hipSuccess && d.pull_w)
+    if (e == hipSuccess && d.pull_w) {
         e = up.put_array((void *)d.pull_w, h.pull_w.data(), h.pull_w.size() * sizeof(uint2));
+        if (e == hipSuccess)
+            e = up.put_array((void *)d.pull_w_units, h.pull_w_units.data(), h.pull_w_units.size() * sizeof(uint4));
+    }
     if (e == hipSuccess && d.sym_rp) {
         e = up.put_array((void *)d.sym_rp, h.sym_rp.data(), (V + 1) * 4);
         if (e == hipSuccess) e = up.put_array((void *)d.sym_col, h.sym_col.data(), h.sym_col.size() * 4);
         if (e == hipSuccess)
             e = up.put_array((void *)d.pull_sym, h.pull_sym.data(), h.pull_sym.size() * sizeof(uint2));
+        if (e == hipSuccess)
+            e = up.put_array((void *)d.pull_sym_units, h.pull_sym_units.data(),
+                             h.pull_sym_units.size() * sizeof(uint4));
     }
     if (e == hipSuccess && d.l2g) e = up.put_array((void *)d.l2g, desc->l2g, V * 4);
     if (e == hipSuccess && d.remote_out) {

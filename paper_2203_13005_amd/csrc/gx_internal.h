@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstring>
 #include <string>
@@ -63,20 +64,33 @@ constexpr int PR_TILE_MAX = PR_BLOCK * 8;
 // Records of the SSSP / CC pull.  Destinations are dealt to PULL_SLICES
 // slices in blocks of 2^PULL_SLICE_SHIFT vertices, balanced by in-edge
 // count; a slice is a sequence of bins of at most PULL_BIN_BYTES of
-// destination values, each ordered by
-// (source >> PULL_BAND_BITS, destination, source).  Workgroup b sweeps slice
-// b mod PULL_SLICES, and workgroups are dealt round-robin to the 8 XCDs, so
-// each XCD's L2 holds one bin's destination values and one band of source
-// snapshots (2^16 vertices) at a time.
+// destination values; a bin's records are grouped by source band
+// (source >> PULL_BAND_BITS) and ordered by (destination, source) inside a
+// group.  Groups are padded to whole PULL_VT records with sentinels and cut
+// into work units of at most PULL_UNIT records.  Workgroup b takes the units
+// of slice b mod PULL_SLICES in order; workgroups are dealt round-robin to
+// the 8 XCDs, so each XCD's L2 holds one bin's destination values, and a
+// unit's band of source snapshots (PULL_BAND words) is staged in LDS.
 constexpr int PULL_SLICES = 8;
 constexpr int PULL_SLICE_SHIFT = 6;
 constexpr int64_t PULL_BIN_BYTES = int64_t(2) << 20;  // destination values an XCD sweeps at a time
-constexpr int PULL_BAND_BITS = 16;
-constexpr int PULL_VT = 8;  // records per thread; slices are swept in aligned groups of PULL_VT
-inline int64_t pull_padded(int64_t n) { return (n + PULL_VT - 1) / PULL_VT * PULL_VT; }
+constexpr int PULL_BAND_BITS = 12;
+constexpr int PULL_BAND = 1 << PULL_BAND_BITS;
+constexpr int PULL_VT = 8;       // records per thread and group padding
+constexpr int PULL_UNIT = 8192;  // records per work unit at most (a multiple of PULL_VT)
+constexpr uint32_t PULL_SENTINEL = 0xFFFFFFFFu;  // destination of a padding record
 struct PullSlices {
-    int64_t off[PULL_SLICES + 1];  // slice x holds records off[x] .. off[x+1]-1
+    int64_t uoff[PULL_SLICES + 1];  // slice x owns work units uoff[x] .. uoff[x+1]-1
 };
+// Capacity of the record array and of the unit table (upper bounds, known
+// before the layout is built).
+inline int64_t pull_bins(int64_t V) {
+    return PULL_SLICES *
+           std::max<int64_t>(1, (V * 4 + PULL_SLICES * PULL_BIN_BYTES - 1) / (PULL_SLICES * PULL_BIN_BYTES));
+}
+inline int64_t pull_groups(int64_t V) { return pull_bins(V) * ((V >> PULL_BAND_BITS) + 1); }
+inline int64_t pull_rec_cap(int64_t V, int64_t E) { return E + (PULL_VT - 1) * pull_groups(V) + PULL_VT; }
+inline int64_t pull_unit_cap(int64_t V, int64_t E) { return pull_rec_cap(V, E) / PULL_UNIT + pull_groups(V) + 1; }
 
 struct DevGraph {
     int64_t V = 0, E = 0, E_sym = 0;
@@ -96,12 +110,14 @@ struct DevGraph {
     // (padded to whole PULL_VT groups); null when V >= 2^24 or a weight
     // exceeds 255 (the engine then only pushes)
     const uint2 *pull_w = nullptr;
+    const uint4 *pull_w_units = nullptr;  // {first record, records, band base, 0}
     PullSlices pull_w_off{};
     // symmetric adjacency (CC push and pull) and its equal edge tiles
     const int32_t *sym_rp = nullptr;
     const int32_t *sym_col = nullptr;
     // sliced, banded symmetric records for the CC pull: {dst, src}
     const uint2 *pull_sym = nullptr;
+    const uint4 *pull_sym_units = nullptr;
     PullSlices pull_sym_off{};
     // partition metadata
     const int32_t *l2g = nullptr;          // nullptr = identity

@@ -334,83 +334,83 @@ __global__ __launch_bounds__(PUSH_BLOCK) void k_push(const uint4 *__restrict__ l
 }
 
 // Pull form of the same superstep, for large frontiers.  The in-edges are
-// stored as records {dst, (src << 8) | w} (CC: {dst, src}) in
-// PULL_SLICES destination slices, each ordered by (source band, dst, src),
-// built at load.  Workgroup b sweeps slice b mod PULL_SLICES, PULL_VT
-// consecutive records per thread; since workgroups are dealt round-robin to
-// the XCDs, each XCD's L2 holds its slice's destination values and the
-// current band of source snapshots.  The compaction stored INF as the
-// snapshot of every inactive vertex, so a record costs one snapshot read;
-// the thread folds runs of equal destination to their minimum and applies
-// each with the filtered atomics of the push.  Runs only when the
+// stored as records {dst, (src << 8) | w} (CC: {dst, src}) in work units of
+// one destination slice and one band of PULL_BAND sources (layout built at
+// load).  Workgroup b takes the units of slice b mod PULL_SLICES in order;
+// since workgroups are dealt round-robin to the XCDs, each XCD's L2 holds
+// its slice's destination values.  A unit's band of snapshots is staged in
+// LDS (the compaction stored INF as the snapshot of every inactive vertex),
+// so a record's gather is an LDS read; the thread folds runs of equal
+// destination in its PULL_VT consecutive records to their minimum and
+// applies each with the filtered atomics of the push.  Runs only when the
 // frontier's out-edges reach pull_edges.
 template <bool WEIGHTED>
-__global__ __launch_bounds__(256) void k_pull(const uint2 *__restrict__ rec, PullSlices sl, uint32_t vmax,
-                                              const uint32_t *__restrict__ snap, uint32_t *__restrict__ val,
-                                              uint8_t *__restrict__ front_next, uint8_t *__restrict__ dirty,
-                                              DevStep *__restrict__ step, uint32_t pull_edges) {
+__global__ __launch_bounds__(256) void k_pull(const uint2 *__restrict__ rec, const uint4 *__restrict__ units,
+                                              PullSlices sl, int64_t V, const uint32_t *__restrict__ snap,
+                                              uint32_t *__restrict__ val, uint8_t *__restrict__ front_next,
+                                              uint8_t *__restrict__ dirty, DevStep *__restrict__ step,
+                                              uint32_t pull_edges) {
+    __shared__ uint32_t s_snap[PULL_BAND];
     const uint32_t EF = (uint32_t)step->list;
     if (EF < pull_edges) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) step->pad = 1;
+    const int tid = threadIdx.x;
+    if (blockIdx.x == 0 && tid == 0) step->pad = 1;
     const int x = (int)(blockIdx.x % PULL_SLICES);
-    const int64_t lo = sl.off[x], hi = sl.off[x + 1];
-    // An empty slice has no record to sweep; a non-empty one guarantees
-    // that every visited group holds one of its records (the anchor below).
-    if (lo >= hi) return;
-    const int64_t base = lo / PULL_VT * PULL_VT;  // aligned groups; records outside [lo, hi) are masked
-    const int64_t stride = (int64_t)(gridDim.x / PULL_SLICES) * blockDim.x * PULL_VT;
-    for (int64_t e0 = base + ((int64_t)(blockIdx.x / PULL_SLICES) * blockDim.x + threadIdx.x) * PULL_VT; e0 < hi;
-         e0 += stride) {
-        uint32_t dst[PULL_VT], src[PULL_VT], m[PULL_VT], cur[PULL_VT];
-        const uint4 *r4 = reinterpret_cast<const uint4 *>(rec + e0);  // the array is padded to whole groups
+    const int64_t nblk = gridDim.x / PULL_SLICES;
+    for (int64_t ui = sl.uoff[x] + blockIdx.x / PULL_SLICES; ui < sl.uoff[x + 1]; ui += nblk) {
+        const uint4 un = units[ui];
+        const uint32_t start = un.x, cnt = un.y, bb = un.z;
+        __syncthreads();  // the previous unit's gathers are done
+        if ((int64_t)bb + PULL_BAND <= V) {
+            const uint4 *s4 = reinterpret_cast<const uint4 *>(snap + bb);
 #pragma unroll
-        for (int i = 0; i < PULL_VT / 2; i++) {
-            const uint4 q = r4[i];
-            dst[2 * i] = q.x;
-            src[2 * i] = q.y;
-            dst[2 * i + 1] = q.z;
-            src[2 * i + 1] = q.w;
+            for (int q = 0; q < PULL_BAND / 4 / 256; q++)
+                reinterpret_cast<uint4 *>(s_snap)[q * 256 + tid] = s4[q * 256 + tid];
+        } else {  // the last band ends at V
+            for (int i = tid; i < PULL_BAND; i += 256) s_snap[i] = bb + i < V ? snap[bb + i] : INF;
         }
-        const int i0 = (int)max((int64_t)0, lo - e0);  // first record of this slice in the chunk
-        uint32_t anchor = dst[0];
+        __syncthreads();
+        for (uint32_t e0 = start + (uint32_t)tid * PULL_VT; e0 < start + cnt; e0 += 256 * PULL_VT) {
+            uint32_t dst[PULL_VT], src[PULL_VT], m[PULL_VT], cur[PULL_VT];
+            const uint4 *r4 = reinterpret_cast<const uint4 *>(rec + e0);  // units are whole groups of PULL_VT
 #pragma unroll
-        for (int i = 1; i < PULL_VT; i++)
-            if (i == i0) anchor = dst[i];
-        anchor = min(anchor, vmax);
-#pragma unroll
-        for (int i = 0; i < PULL_VT; i++) {
-            if (e0 + i < lo || e0 + i >= hi) {  // another slice's record or padding
-                dst[i] = 0xFFFFFFFFu;
-                src[i] = 0u;
+            for (int i = 0; i < PULL_VT / 2; i++) {
+                const uint4 q = r4[i];
+                dst[2 * i] = q.x;
+                src[2 * i] = q.y;
+                dst[2 * i + 1] = q.z;
+                src[2 * i + 1] = q.w;
             }
-            m[i] = snap[WEIGHTED ? (src[i] >> 8) : src[i]];
-        }
+            // the first record of a group of PULL_VT is never padding
+            const uint32_t anchor = dst[0];
 #pragma unroll
-        for (int i = 0; i < PULL_VT; i++) {
-            m[i] = WEIGHTED ? sat_add(m[i], src[i] & 0xFFu) : m[i];
-            if (dst[i] == 0xFFFFFFFFu) m[i] = INF;
-        }
-        // Minimum of each run of equal destination, kept at the run's last
-        // record; then one batched read of those destinations, then the
-        // filtered atomics (no result awaited, as in the push).
+            for (int i = 0; i < PULL_VT; i++) {
+                const uint32_t u = WEIGHTED ? (src[i] >> 8) : src[i];
+                const uint32_t sv = s_snap[(u - bb) & (PULL_BAND - 1)];
+                m[i] = WEIGHTED ? sat_add(sv, src[i] & 0xFFu) : sv;
+                if (dst[i] == PULL_SENTINEL) m[i] = INF;
+            }
+            // Minimum of each run of equal destination, kept at the run's
+            // last record; then one batched read of those destinations (a
+            // record without a candidate reads the group's first destination,
+            // a line of this slice, instead of one shared hot line), then the
+            // filtered atomics (no result awaited, as in the push).
 #pragma unroll
-        for (int i = 1; i < PULL_VT; i++)
-            if (dst[i] == dst[i - 1]) m[i] = min(m[i], m[i - 1]);
+            for (int i = 1; i < PULL_VT; i++)
+                if (dst[i] == dst[i - 1]) m[i] = min(m[i], m[i - 1]);
 #pragma unroll
-        for (int i = 0; i + 1 < PULL_VT; i++)
-            if (dst[i + 1] == dst[i]) m[i] = INF;
-        // records without a candidate read the destination of the chunk's
-        // first record of this slice instead (in the slice, so cache
-        // resident, and different per lane: one dummy address shared by
-        // every idle lane would become a single hot line)
+            for (int i = 0; i + 1 < PULL_VT; i++)
+                if (dst[i + 1] == dst[i]) m[i] = INF;
 #pragma unroll
-        for (int i = 0; i < PULL_VT; i++) cur[i] = val[m[i] != INF ? dst[i] : anchor];
+            for (int i = 0; i < PULL_VT; i++) cur[i] = val[m[i] != INF ? dst[i] : anchor];
+            __builtin_amdgcn_sched_barrier(0);  // every read above is issued before the first compare
 #pragma unroll
-        for (int i = 0; i < PULL_VT; i++) {
-            if (m[i] < cur[i]) {
-                atomicMin(&val[dst[i]], m[i]);
-                front_next[dst[i]] = 1;
-                dirty[dst[i]] = 1;
+            for (int i = 0; i < PULL_VT; i++) {
+                if (m[i] < cur[i]) {
+                    atomicMin(&val[dst[i]], m[i]);
+                    front_next[dst[i]] = 1;
+                    dirty[dst[i]] = 1;
+                }
             }
         }
     }
@@ -1002,15 +1002,15 @@ static gx_status enqueue_superstep(gx_state *s, hipStream_t hs) {
                                    (const void *)d.out_adj, s->val, s->front8[cur ^ 1], s->dirty8, step,
                                    s->pull_edges);
                 if (s->pull_edges != 0xFFFFFFFFu)
-                    hipLaunchKernelGGL(k_pull<true>, dim3(s->pull_grid), dim3(256), 0, hs, d.pull_w, d.pull_w_off,
-                                       (uint32_t)(d.V - 1), s->snap, s->val, s->front8[cur ^ 1], s->dirty8, step, s->pull_edges);
+                    hipLaunchKernelGGL(k_pull<true>, dim3(s->pull_grid), dim3(256), 0, hs, d.pull_w, d.pull_w_units,
+                                       d.pull_w_off, d.V, s->snap, s->val, s->front8[cur ^ 1], s->dirty8, step, s->pull_edges);
             } else {
                 hipLaunchKernelGGL(k_push<false>, dim3(s->push_grid), dim3(PUSH_BLOCK), 0, hs, s->list,
                                    s->tile_start, (const void *)d.sym_col, s->val, s->front8[cur ^ 1], s->dirty8,
                                    step, s->pull_edges);
                 if (s->pull_edges != 0xFFFFFFFFu)
                     hipLaunchKernelGGL(k_pull<false>, dim3(s->pull_grid), dim3(256), 0, hs, d.pull_sym,
-                                       d.pull_sym_off, (uint32_t)(d.V - 1), s->snap, s->val, s->front8[cur ^ 1], s->dirty8, step,
+                                       d.pull_sym_units, d.pull_sym_off, d.V, s->snap, s->val, s->front8[cur ^ 1], s->dirty8, step,
                                        s->pull_edges);
             }
             if (e1) (void)hipEventRecord(e1, hs);

@@ -301,7 +301,6 @@ struct gx_server {
         a.D[0] = p.pw.D[0];
         a.D[1] = p.pw.D[1];
         a.spill = p.pw.spill;
-        a.bar = nullptr;
         return a;
     }
 
