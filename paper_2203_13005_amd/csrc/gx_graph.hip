@@ -4,6 +4,7 @@
 // block i is in flight on the copy stream, block i+1 is packaged into the
 // next buffer; pointers rotate instead of data being copied between stages).
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <functional>
@@ -113,23 +114,51 @@ static gx_status validate(const gx_graph_desc *d) {
     return GX_OK;
 }
 
+static unsigned host_threads() { return std::max(1u, std::min(16u, std::thread::hardware_concurrency())); }
+
 // Stable counting sort of the edges by destination: in-rows list their
-// sources in ascending order.
+// sources in ascending order.  Each thread owns a range of destinations
+// (equal in-edge counts for the scatter) and scans every edge in source
+// order, keeping only its own: no shared counters, the same result as one
+// sequential pass.
 static void build_in_csr(const gx_graph_desc *d, HostImages &h) {
-    int64_t V = d->V, E = d->E;
+    const int64_t V = d->V, E = d->E;
     h.in_rp.assign(V + 1, 0);
     h.in_col.resize(E);
-    for (int64_t e = 0; e < E; e++) h.in_rp[d->col[e] + 1]++;
-    for (int64_t v = 0; v < V; v++) h.in_rp[v + 1] += h.in_rp[v];
-    std::vector<int32_t> pos(h.in_rp.begin(), h.in_rp.end() - 1);
-    bool wts = d->w && (d->needs & GX_NEED_OUT);
+    const bool wts = d->w && (d->needs & GX_NEED_OUT);
     if (wts) h.in_w.resize(E);
-    for (int64_t u = 0; u < V; u++)
-        for (int32_t e = d->row_ptr[u]; e < d->row_ptr[u + 1]; e++) {
-            int32_t p = pos[d->col[e]]++;
-            h.in_col[p] = (int32_t)u;
-            if (wts) h.in_w[p] = d->w[e];
-        }
+    const unsigned nt = E < 4096 ? 1u : host_threads();
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; t++)  // counts: equal destination ranges
+        th.emplace_back([&, t] {
+            const int64_t lo = V * t / nt, hi = V * (t + 1) / nt;
+            for (int64_t e = 0; e < E; e++) {
+                const int64_t v = d->col[e];
+                if (v >= lo && v < hi) h.in_rp[v + 1]++;
+            }
+        });
+    for (auto &x : th) x.join();
+    th.clear();
+    for (int64_t v = 0; v < V; v++) h.in_rp[v + 1] += h.in_rp[v];
+    std::vector<int64_t> cut(nt + 1, V);  // destination ranges of equal in-edge counts
+    cut[0] = 0;
+    for (unsigned t = 1; t < nt; t++)
+        cut[t] = std::lower_bound(h.in_rp.begin(), h.in_rp.end() - 1, (int32_t)(E * t / nt)) - h.in_rp.begin();
+    for (unsigned t = 0; t < nt; t++)
+        th.emplace_back([&, t] {
+            const int64_t lo = cut[t], hi = cut[t + 1];
+            if (lo >= hi) return;
+            std::vector<int32_t> pos(h.in_rp.begin() + lo, h.in_rp.begin() + hi);
+            for (int64_t u = 0; u < V; u++)
+                for (int32_t e = d->row_ptr[u]; e < d->row_ptr[u + 1]; e++) {
+                    const int64_t v = d->col[e];
+                    if (v < lo || v >= hi) continue;
+                    const int32_t p = pos[v - lo]++;
+                    h.in_col[p] = (int32_t)u;
+                    if (wts) h.in_w[p] = d->w[e];
+                }
+        });
+    for (auto &x : th) x.join();
 }
 
 // Pull tiles: tile t covers edges [t*T, (t+1)*T) of a CSR and owns the rows
@@ -191,10 +220,23 @@ static void build_pull(const std::vector<int32_t> &rp, const int32_t *src, const
     }
     const int64_t ng = nbin * nb;
     std::vector<int64_t> cnt((size_t)ng, 0);
-    for (int64_t v = 0; v < V; v++) {
-        const int64_t g0 = (int64_t)group[v >> PULL_SLICE_SHIFT] * nb;
+    // one thread per slice: it owns the groups of its bins, so the counts and
+    // the fill below need no shared counters
+    auto per_slice = [&](auto &&body) {
+        std::vector<std::thread> th;
+        for (int x = 0; x < PULL_SLICES; x++)
+            th.emplace_back([&, x] {
+                const int64_t glo = x * S, ghi = (x + 1) * S;
+                for (int64_t v = 0; v < V; v++) {
+                    const int64_t gb = group[v >> PULL_SLICE_SHIFT];
+                    if (gb >= glo && gb < ghi) body(v, gb * nb);
+                }
+            });
+        for (auto &t : th) t.join();
+    };
+    per_slice([&](int64_t v, int64_t g0) {
         for (int32_t e = rp[v]; e < rp[v + 1]; e++) cnt[g0 + (src[e] >> PULL_BAND_BITS)]++;
-    }
+    });
     std::vector<int64_t> pos((size_t)ng + 1, 0);
     for (int64_t g = 0; g < ng; g++) pos[g + 1] = pos[g] + (cnt[g] + PULL_VT - 1) / PULL_VT * PULL_VT;
     out.assign((size_t)pos[ng], make_uint2(PULL_SENTINEL, 0u));
@@ -203,13 +245,12 @@ static void build_pull(const std::vector<int32_t> &rp, const int32_t *src, const
         for (int64_t i = pos[g] + cnt[g]; i < pos[g + 1]; i++) out[i].y = w ? (bb << 8) : bb;
     }
     std::vector<int64_t> fill(pos.begin(), pos.end() - 1);
-    for (int64_t v = 0; v < V; v++) {
-        const int64_t g0 = (int64_t)group[v >> PULL_SLICE_SHIFT] * nb;
+    per_slice([&](int64_t v, int64_t g0) {
         for (int32_t e = rp[v]; e < rp[v + 1]; e++) {
             const uint32_t u = (uint32_t)src[e];
             out[fill[g0 + (u >> PULL_BAND_BITS)]++] = make_uint2((uint32_t)v, w ? ((u << 8) | w[e]) : u);
         }
-    }
+    });
     units.clear();
     for (int x = 0; x < PULL_SLICES; x++) {
         sl.uoff[x] = (int64_t)units.size();
@@ -223,9 +264,15 @@ static void build_pull(const std::vector<int32_t> &rp, const int32_t *src, const
 
 static bool banded_weights_fit(const gx_graph_desc *d) {
     if (d->V >= (int64_t(1) << 24)) return false;
-    for (int64_t e = 0; e < d->E; e++)
-        if (d->w[e] > 255u) return false;
-    return true;
+    std::atomic<bool> ok{true};
+    parallel_for(d->E, [&](int64_t lo, int64_t hi) {
+        for (int64_t e = lo; e < hi; e++)
+            if (d->w[e] > 255u) {
+                ok = false;
+                return;
+            }
+    });
+    return ok;
 }
 
 // Symmetric adjacency: sorted union of out- and in-neighbours, self
@@ -445,8 +492,10 @@ extern "C" gx_status gx_graph_load(const gx_graph_desc *desc, void *dev_arena, s
         // Package (destination, weight) pairs block by block.
         e = up.put((void *)d.out_adj, E * sizeof(uint2), [col, w](char *dst, size_t off, size_t n) {
             uint2 *o = reinterpret_cast<uint2 *>(dst);
-            size_t e0 = off / sizeof(uint2), cnt = n / sizeof(uint2);
-            for (size_t i = 0; i < cnt; i++) o[i] = make_uint2((uint32_t)col[e0 + i], w[e0 + i]);
+            const size_t e0 = off / sizeof(uint2), cnt = n / sizeof(uint2);
+            parallel_for((int64_t)cnt, [&](int64_t lo, int64_t hi) {
+                for (int64_t i = lo; i < hi; i++) o[i] = make_uint2((uint32_t)col[e0 + i], w[e0 + i]);
+            });
         });
     }
     if (e == hipSuccess && d.in_rp) {
