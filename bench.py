@@ -242,6 +242,64 @@ def bench_pagerank_small(gx, torch, np, gen, reps=20):
             "pull_kernel_us_per_superstep": kern * 1e3 / reps / 20}
 
 
+def bench_exchange(gx, torch, np, gen, scale=22, nparts=8, reps=3):
+    """All parts of an 8-way hash vertex-cut of R-MAT scale 22 (seed 2)
+    resident on the GPU: SSSP from vertex 0 superstep by superstep, every part
+    emitting its sync set and merging the other parts' pairs; checked against
+    the plain solve of the whole graph."""
+    t0 = time.perf_counter()
+    parts = [gen.rmat_part(scale, seed=2, part=p) for p in range(nparts)]
+    log(f"exchange: {nparts} parts of R-MAT scale {scale} generated in {time.perf_counter() - t0:.1f}s")
+    dgs = [gx.DeviceGraph(p, gx.GX_NEED_OUT) for p in parts]
+
+    def solve():
+        states = []
+        for p, dg in zip(parts, dgs):
+            loc = int(np.searchsorted(p.l2g, 0))
+            src = loc if loc < p.V and p.l2g[loc] == 0 else -1
+            states.append(gx.State(dg, gx.GX_SSSP, source=src, delta_mode=gx.GX_DELTA_ALL))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        K, pairs = 0, 0
+        while True:
+            K += 1
+            for st in states:
+                st.superstep(stats=False)
+            sent = [st.sync_delta(on_device=True) for st in states]
+            pairs += sum(int(x[0].numel()) for x in sent)
+            active = 0
+            for q, st in enumerate(states):
+                others = [x for i, x in enumerate(sent) if i != q and x[0].numel()]
+                gid = torch.cat([o[0] for o in others]) if others else sent[q][0][:0]
+                val = torch.cat([o[1] for o in others]) if others else sent[q][1][:0]
+                active += st.apply_delta(gid, val)
+            if active == 0:
+                break
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, K, pairs, states
+
+    solve()
+    times = []
+    for _ in range(reps):
+        dt, K, pairs, states = solve()
+        times.append(dt)
+    g = gen.rmat(scale, seed=2)
+    ref = gx.State(gx.DeviceGraph(g, gx.GX_NEED_OUT), gx.GX_SSSP, source=0)
+    rs, _ = ref.run(100_000)
+    dist = ref.values_numpy()
+    for p, st in zip(parts, states):
+        assert np.array_equal(st.values_numpy(), dist[p.l2g]), "exchange differs from the whole-graph solve"
+    assert K == rs.supersteps
+    dt = sorted(times)[len(times) // 2]
+    log(f"exchange: {nparts} parts, K={K}, {pairs} pairs exchanged, {dt * 1e3:.1f} ms per solve")
+    return {"workload": f"all {nparts} parts of a hash vertex-cut of R-MAT scale {scale} (seed 2) resident, "
+                        "SSSP from vertex 0 with the sync sets exchanged every superstep (gx_sync_delta / "
+                        "gx_apply_delta), equal to the whole-graph solve",
+            "parts": nparts, "replicas": int(sum(p.V for p in parts)), "edges": int(sum(p.E for p in parts)),
+            "supersteps": K, "pairs_exchanged_per_solve": pairs, "ms_per_solve": dt * 1e3,
+            "whole_graph_messages_per_solve": int(rs.edges), "gteps": rs.edges / dt / 1e9}
+
+
 def bench_partition(gx, torch, np, gen, reps=3):
     """One part (1 of 8) of a hash vertex-cut of R-MAT scale 25 (seed 3):
     30 PageRank supersteps and min-label CC to convergence."""
@@ -500,6 +558,7 @@ def main():
         out["pagerank_scale14"] = bench_pagerank_small(gx, torch, np, gen)
     if args.partition:
         out["partition_scale25"] = bench_partition(gx, torch, np, gen)
+        out["exchange_8parts_scale22"] = bench_exchange(gx, torch, np, gen)
     if not args.no_batched:
         out["batched"] = bench_batched(gx, torch, np, gen)
     if not args.no_serving:

@@ -14,7 +14,7 @@
  *   requestGen/Merge/Apply()         -> gx_superstep
  *   iteration control                -> gx_run_until_converged
  *     (Section "Iteration Control")
- *   update(): lazy upload + skip     -> gx_sync_delta
+ *   update(): lazy upload + skip     -> gx_sync_delta (send), gx_apply_delta (receive)
  *     (Sections "Synchronization Caching", "Synchronization Skipping")
  *   disconnect()                     -> gx_graph_free / gx_state_free
  *
@@ -101,7 +101,7 @@ typedef struct gx_graph_desc {
 typedef struct gx_params {
     int32_t  algo;            /* gx_algo: GX_PAGERANK, GX_SSSP or GX_CC */
     float    damping;         /* PageRank damping d, in [0, 1) */
-    int32_t  source;          /* SSSP source (local id) */
+    int32_t  source;          /* SSSP source (local id); -1 = no source in this part (another part holds it) */
     uint32_t max_supersteps;  /* cap used by gx_run_until_converged (PageRank: exactly this many) */
     uint32_t delta_mode;      /* GX_DELTA_REMOTE or GX_DELTA_ALL */
     uint32_t timing;          /* nonzero: time the edge kernels of every superstep with HIP events */
@@ -208,6 +208,23 @@ gx_status gx_run_until_converged(gx_state *s, uint32_t max_supersteps, void *str
  */
 gx_status gx_sync_delta(gx_state *s, int32_t *dev_gid, uint32_t *dev_val, uint32_t cap,
                         uint32_t *count, int32_t *skippable, void *stream);
+
+/*
+ * The receiving side of update(): merges the (global id, value) pairs that
+ * other parts emitted with gx_sync_delta into this part's replicas, for
+ * SSSP and CC (integer min; Section "Operation Interfaces", Section
+ * "Synchronization Caching": mirrors and masters exchange only changed
+ * values).  dev_gid / dev_val are device arrays of n pairs in any order;
+ * ids this part does not hold are ignored.  A replica whose value falls
+ * becomes active in the next superstep (it is not marked dirty: the parts
+ * that emitted the value already sent it to every other part).  Call it
+ * between gx_superstep calls: it rebuilds the active list of the next
+ * superstep.  *active_next (optional) receives the next superstep's active
+ * vertex count and then the call synchronises `stream`; otherwise it is
+ * asynchronous.  GX_EINVAL for PageRank or NULL buffers with n > 0.
+ */
+gx_status gx_apply_delta(gx_state *s, const int32_t *dev_gid, const uint32_t *dev_val, uint32_t n,
+                         int64_t *active_next, void *stream);
 
 /* ---------------------------------------------------------------------
  * Batched lanes: B independent single-source SSSP (or personalised

@@ -97,6 +97,7 @@ _SIGS = {
                                                 ctypes.POINTER(StepStats)]),
     "gx_sync_delta": (ctypes.c_int32, [_P, _P, _P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
                                        ctypes.POINTER(ctypes.c_int32), _P]),
+    "gx_apply_delta": (ctypes.c_int32, [_P, _P, _P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int64), _P]),
     "gx_batch_bytes": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_size_t)]),
     "gx_batch_run": (ctypes.c_int32, [_P, ctypes.c_int32, _P, ctypes.c_uint32, ctypes.c_float, ctypes.c_uint32,
                                       _P, ctypes.c_size_t, _P, ctypes.POINTER(Tune), _P,
@@ -283,8 +284,9 @@ class State:
             steps = [(ps[i].as_dict() if detail else ps[i].as_tuple()) for i in range(rs.supersteps)]
         return rs, steps
 
-    def sync_delta(self, cap: int | None = None, stream=None):
-        """Returns (gids int32, value bits uint32, skippable) as numpy arrays."""
+    def sync_delta(self, cap: int | None = None, stream=None, on_device: bool = False):
+        """Returns (gids int32, value bits uint32, skippable) as numpy arrays, or
+        as device tensors (int32 bit patterns) with on_device=True."""
         import torch
         cap = self.graph.V if cap is None else int(cap)
         gid = torch.empty(max(cap, 1), dtype=torch.int32, device=self.graph.device)
@@ -294,7 +296,20 @@ class State:
         _check(lib.gx_sync_delta(self.handle, ctypes.c_void_p(gid.data_ptr()), ctypes.c_void_p(val.data_ptr()),
                                  cap, ctypes.byref(n), ctypes.byref(sk), _stream_handle(stream)))
         c = n.value
+        if on_device:
+            return gid[:c], val[:c], bool(sk.value)
         return gid[:c].cpu().numpy(), val[:c].cpu().numpy().view(np.uint32), bool(sk.value)
+
+    def apply_delta(self, gids, vals, stream=None) -> int:
+        """Merges (global id, value) pairs that other parts emitted (device int32
+        tensors, values as bit patterns) into this part's replicas; returns the
+        number of vertices active in the next superstep."""
+        n = int(gids.numel())
+        act = ctypes.c_int64()
+        _check(lib.gx_apply_delta(self.handle, ctypes.c_void_p(gids.data_ptr()) if n else None,
+                                  ctypes.c_void_p(vals.data_ptr()) if n else None, n, ctypes.byref(act),
+                                  _stream_handle(stream)))
+        return act.value
 
     def close(self):
         if getattr(self, "handle", None):

@@ -735,6 +735,40 @@ __global__ __launch_bounds__(256) void k_delta_emit(int32_t W, int64_t V, const 
     }
 }
 
+// Receiving side of the sync set: values other parts emitted for vertices
+// this part holds (global id -> local id by binary search in the ascending
+// l2g map; ids it does not hold are ignored) are merged by integer min; a
+// replica whose value falls becomes active in the next superstep.
+__global__ __launch_bounds__(256) void k_apply_delta(const int32_t *__restrict__ gid,
+                                                     const uint32_t *__restrict__ vals, uint32_t n,
+                                                     const int32_t *__restrict__ l2g, int64_t V,
+                                                     uint32_t *__restrict__ val, uint8_t *__restrict__ front_next) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t g = gid[i];
+    int64_t x;
+    if (l2g) {
+        int64_t lo = 0, hi = V;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) / 2;
+            if (l2g[mid] < g) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo >= V || l2g[lo] != g) return;
+        x = lo;
+    } else {
+        if (g < 0 || g >= V) return;
+        x = g;
+    }
+    const uint32_t v = vals[i];
+    if (v < val[x]) {  // below the value before the merge: the replica changes
+        atomicMin(&val[x], v);
+        front_next[x] = 1;
+    }
+}
+
+__global__ void k_zero_step(DevStep *step) { *step = DevStep{0, 0, 0, 0}; }
+
 template <class T>
 inline unsigned grid_for(T n, unsigned block) {
     return (unsigned)std::max<T>(1, (n + block - 1) / block);
@@ -796,7 +830,7 @@ static gx_status check_params(const gx_graph *g, const gx_params *p) {
     }
     if (p->algo == GX_SSSP) {
         GX_REQUIRE(g->needs & GX_NEED_OUT, GX_EINVAL, "SSSP needs GX_NEED_OUT");
-        GX_REQUIRE(p->source >= 0 && p->source < g->d.V, GX_EINVAL, "source %d out of [0,V)", p->source);
+        GX_REQUIRE(p->source >= -1 && p->source < g->d.V, GX_EINVAL, "source %d out of [-1,V)", p->source);
     }
     if (p->algo == GX_CC) GX_REQUIRE(g->needs & GX_NEED_SYM, GX_EINVAL, "CC needs GX_NEED_SYM");
     return GX_OK;
@@ -1211,6 +1245,42 @@ extern "C" gx_status gx_sync_delta(gx_state *s, int32_t *dev_gid, uint32_t *dev_
     if (total > cap) {
         set_error("sync set has %u entries, capacity %u", total, cap);
         return GX_ENOMEM;
+    }
+    return GX_OK;
+}
+
+extern "C" gx_status gx_apply_delta(gx_state *s, const int32_t *dev_gid, const uint32_t *dev_val, uint32_t n,
+                                    int64_t *active_next, void *stream) {
+    clear_error();
+    GX_REQUIRE(s, GX_EINVAL, "state is NULL");
+    GX_REQUIRE(n == 0 || (dev_gid && dev_val), GX_EINVAL, "input buffers are NULL");
+    GX_REQUIRE(s->p.algo == GX_SSSP || s->p.algo == GX_CC, GX_EINVAL, "gx_apply_delta merges SSSP / CC values only");
+    GX_REQUIRE(!s->dev_error && !s->g->dev_error, GX_EDEVICE, "sticky device error");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const DevGraph &d = s->g->d;
+    if (d.V > 0) {
+        // A_{k+1} (the frontier of the superstep about to run) and its counter slot
+        uint8_t *front = s->front8[s->k & 1];
+        DevStep *slot = s->steps + (s->k % STEP_RING), *slot2 = s->steps + ((s->k + 1) % STEP_RING);
+        if (n > 0)
+            hipLaunchKernelGGL(k_apply_delta, dim3(grid_for<uint32_t>(n, 256)), dim3(256), 0, hs, dev_gid, dev_val, n,
+                               d.l2g, d.V, s->val, front);
+        // rebuild the active list of A_{k+1} from the merged values
+        hipLaunchKernelGGL(k_zero_step, dim3(1), dim3(1), 0, hs, slot);
+        const int32_t *rp = s->p.algo == GX_CC ? d.sym_rp : d.out_rp;
+        hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(d.V, 256 * CVT)), dim3(256), 0, hs, front,
+                           s->front8[(s->k & 1) ^ 1], rp, s->val, s->snap, d.V, s->list, s->tile_start, slot, slot2,
+                           (int)(s->pull_edges != 0xFFFFFFFFu));
+        GX_CHECK_HIP(hipGetLastError(), s);
+    }
+    if (active_next) {
+        *active_next = 0;
+        if (d.V > 0) {
+            DevStep ds{};
+            GX_CHECK_HIP(hipMemcpyAsync(&ds, s->steps + (s->k % STEP_RING), sizeof ds, hipMemcpyDeviceToHost, hs), s);
+            GX_CHECK_HIP(hipStreamSynchronize(hs), s);
+            *active_next = (int64_t)ds.frontier;
+        }
     }
     return GX_OK;
 }

@@ -1,0 +1,98 @@
+"""All eight parts of a hash vertex-cut resident on one GPU, run superstep by
+superstep with the sync sets exchanged between the parts (gx_sync_delta on
+every part, gx_apply_delta of the other parts' pairs on every part): the
+replicas must end with the global oracle's values, bit for bit, after as
+many supersteps as the oracle takes on the whole graph."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+NPARTS = 8
+
+
+@pytest.fixture(scope="module")
+def gx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2203_13005_amd as m
+    return m
+
+
+def run_exchange(gx, parts, algo, gsource=None):
+    import torch
+    needs = gx.GX_NEED_OUT if algo == gx.GX_SSSP else gx.GX_NEED_SYM
+    dgs = [gx.DeviceGraph(p, needs) for p in parts]
+    states = []
+    for p, dg in zip(parts, dgs):
+        if algo == gx.GX_SSSP:
+            loc = np.searchsorted(p.l2g, gsource)
+            src = int(loc) if loc < p.V and p.l2g[loc] == gsource else -1
+            states.append(gx.State(dg, algo, source=src, delta_mode=gx.GX_DELTA_ALL))
+        else:
+            states.append(gx.State(dg, algo, delta_mode=gx.GX_DELTA_ALL))
+    K = 0
+    while True:
+        K += 1
+        for st in states:
+            st.superstep(stats=False)
+        sent = [st.sync_delta(on_device=True) for st in states]
+        active = 0
+        for q, st in enumerate(states):
+            others = [s for p, s in enumerate(sent) if p != q and s[0].numel()]
+            gid = torch.cat([o[0] for o in others]) if others else sent[q][0][:0]
+            val = torch.cat([o[1] for o in others]) if others else sent[q][1][:0]
+            active += st.apply_delta(gid, val)
+        if active == 0 or K > 10_000:
+            break
+    return K, [st.values_numpy() for st in states]
+
+
+@pytest.mark.parametrize("scale,seed", [(10, 3), (12, 5)])
+def test_exchange_sssp_equals_global_oracle(gx, scale, seed):
+    g = gen.rmat(scale, seed=seed)
+    parts = [gen.rmat_part(scale, seed=seed, part=p) for p in range(NPARTS)]
+    src = int(np.nonzero(np.diff(g.row_ptr) > 0)[0][0])
+    ref = oracle.sssp(g, src)
+    K, vals = run_exchange(gx, parts, gx.GX_SSSP, src)
+    assert K == ref.K
+    for p, v in zip(parts, vals):
+        assert np.array_equal(v, ref.state[p.l2g])
+
+
+@pytest.mark.parametrize("scale,seed", [(10, 3), (12, 5)])
+def test_exchange_cc_equals_global_oracle(gx, scale, seed):
+    g = gen.rmat(scale, seed=seed)
+    parts = [gen.rmat_part(scale, seed=seed, part=p) for p in range(NPARTS)]
+    ref = oracle.cc(g)
+    K, vals = run_exchange(gx, parts, gx.GX_CC)
+    assert K == ref.K
+    for p, v in zip(parts, vals):
+        assert np.array_equal(v, ref.state[p.l2g])
+
+
+def test_apply_delta_merges_min_and_ignores_foreign_ids(gx):
+    import torch
+    part = gen.rmat_part(10, seed=3, part=2)
+    st = gx.State(gx.DeviceGraph(part, gx.GX_NEED_OUT), gx.GX_SSSP, source=-1)
+    assert st.apply_delta(torch.empty(0, dtype=torch.int32, device="cuda:0"),
+                          torch.empty(0, dtype=torch.int32, device="cuda:0")) == 0
+    held = part.l2g[[0, 5, 9]].astype(np.int32)
+    foreign = np.setdiff1d(np.arange(part.l2g.max() + 2, dtype=np.int32), part.l2g)[:3]
+    gids = torch.tensor(np.r_[held, foreign], dtype=torch.int32, device="cuda:0")
+    vals = torch.tensor(np.array([7, 3, 11, 1, 1, 1], np.uint32).view(np.int32), device="cuda:0")
+    act = st.apply_delta(gids, vals)
+    v = st.values_numpy()
+    assert v[0] == 7 and v[5] == 3 and v[9] == 11
+    assert (v == 0xFFFFFFFF).sum() == part.V - 3
+    # every lowered replica is in the next frontier and counted active
+    fr = st.frontier_numpy()
+    assert set(np.nonzero(fr)[0]) == {0, 5, 9}
+    assert act == 3
+    # a larger value changes nothing
+    st.apply_delta(gids[:1], torch.tensor(np.array([9], np.uint32).view(np.int32), device="cuda:0"))
+    assert st.values_numpy()[0] == 7
