@@ -342,8 +342,12 @@ __global__ __launch_bounds__(PUSH_BLOCK) void k_push(const uint4 *__restrict__ l
 // LDS (the compaction stored INF as the snapshot of every inactive vertex),
 // so a record's gather is an LDS read; the thread folds runs of equal
 // destination in its PULL_VT consecutive records to their minimum and
-// applies each with the filtered atomics of the push.  Runs only when the
-// frontier's out-edges reach pull_edges.
+// applies each with the filtered atomics of the push.  A record without a
+// candidate (inactive source, padding, or not the end of its run) reads
+// nothing: the destination reads are buffer loads whose offset for such
+// lanes lies past the buffer, which fetches nothing and returns 0.  Runs only
+// when the frontier's out-edges reach pull_edges (V * 4 must fit the 32-bit
+// buffer range; the host enables the pull only then).
 template <bool WEIGHTED>
 __global__ __launch_bounds__(256) void k_pull(const uint2 *__restrict__ rec, const uint4 *__restrict__ units,
                                               PullSlices sl, int64_t V, const uint32_t *__restrict__ snap,
@@ -355,6 +359,7 @@ __global__ __launch_bounds__(256) void k_pull(const uint2 *__restrict__ rec, con
     if (EF < pull_edges) return;
     const int tid = threadIdx.x;
     if (blockIdx.x == 0 && tid == 0) step->pad = 1;
+    const __amdgpu_buffer_rsrc_t vrs = __builtin_amdgcn_make_buffer_rsrc(val, (short)0, (int)(uint32_t)(V * 4), 0x00020000);
     const int x = (int)(blockIdx.x % PULL_SLICES);
     const int64_t nblk = gridDim.x / PULL_SLICES;
     for (int64_t ui = sl.uoff[x] + blockIdx.x / PULL_SLICES; ui < sl.uoff[x + 1]; ui += nblk) {
@@ -381,8 +386,6 @@ __global__ __launch_bounds__(256) void k_pull(const uint2 *__restrict__ rec, con
                 dst[2 * i + 1] = q.z;
                 src[2 * i + 1] = q.w;
             }
-            // the first record of a group of PULL_VT is never padding
-            const uint32_t anchor = dst[0];
 #pragma unroll
             for (int i = 0; i < PULL_VT; i++) {
                 const uint32_t u = WEIGHTED ? (src[i] >> 8) : src[i];
@@ -391,10 +394,9 @@ __global__ __launch_bounds__(256) void k_pull(const uint2 *__restrict__ rec, con
                 if (dst[i] == PULL_SENTINEL) m[i] = INF;
             }
             // Minimum of each run of equal destination, kept at the run's
-            // last record; then one batched read of those destinations (a
-            // record without a candidate reads the group's first destination,
-            // a line of this slice, instead of one shared hot line), then the
-            // filtered atomics (no result awaited, as in the push).
+            // last record; then one batched read of those destinations (only
+            // records with a candidate fetch), then the filtered atomics (no
+            // result awaited, as in the push).
 #pragma unroll
             for (int i = 1; i < PULL_VT; i++)
                 if (dst[i] == dst[i - 1]) m[i] = min(m[i], m[i - 1]);
@@ -402,7 +404,8 @@ __global__ __launch_bounds__(256) void k_pull(const uint2 *__restrict__ rec, con
             for (int i = 0; i + 1 < PULL_VT; i++)
                 if (dst[i + 1] == dst[i]) m[i] = INF;
 #pragma unroll
-            for (int i = 0; i < PULL_VT; i++) cur[i] = val[m[i] != INF ? dst[i] : anchor];
+            for (int i = 0; i < PULL_VT; i++)
+                cur[i] = __builtin_amdgcn_raw_buffer_load_b32(vrs, m[i] != INF ? dst[i] * 4u : 0x80000000u, 0, 0);
             __builtin_amdgcn_sched_barrier(0);  // every read above is issued before the first compare
 #pragma unroll
             for (int i = 0; i < PULL_VT; i++) {
@@ -873,7 +876,9 @@ extern "C" gx_status gx_state_init(gx_graph *g, const gx_params *p, void *dev_st
     s->pull_grid = std::max(PULL_SLICES, persistent_grid(g, k_pull<true>, 256) / PULL_SLICES * PULL_SLICES);
     if (p->algo != GX_PAGERANK) {
         const DevGraph &dg = g->d;
-        bool can_pull = p->algo == GX_SSSP ? (dg.pull_w != nullptr) : (dg.pull_sym != nullptr);
+        // (the pull addresses values through a 32-bit buffer range)
+        bool can_pull = dg.V < (int64_t(1) << 30) &&
+                        (p->algo == GX_SSSP ? (dg.pull_w != nullptr) : (dg.pull_sym != nullptr));
         double frac = p->pull_fraction > 0.f ? (double)p->pull_fraction : 0.3;
         double Eimg = (double)(p->algo == GX_SSSP ? dg.E : dg.E_sym);
         s->pull_edges = (!can_pull || frac >= 1.0) ? 0xFFFFFFFFu : (uint32_t)std::max(1.0, std::ceil(frac * Eimg));

@@ -125,6 +125,45 @@ def test_sssp_in_hub_spanning_many_pull_tiles(gx, mode):
     check_sssp_stepwise(gx, g, 0, mode)
 
 
+@pytest.mark.parametrize("mode", [1e-9, 0.0])
+def test_sssp_pull_rmat20(gx, mode):
+    # scale 20: 16384 destination blocks dealt over the XCD slices
+    g = gen.rmat(20, seed=5)
+    ref = oracle.sssp(g, 0)
+    st = gx.State(load(gx, g, gx.GX_NEED_OUT), gx.GX_SSSP, source=0, pull_fraction=mode)
+    rs, steps = st.run(10_000, per_step=True)
+    assert rs.supersteps == ref.K
+    assert np.array_equal(st.values_numpy(), ref.state)
+    steps = np.array(steps)
+    assert np.array_equal(steps[:, 1], ref.msgs)
+    assert np.array_equal(steps[:, 2], ref.changed)
+
+
+@pytest.mark.parametrize("mode", [1e-9, 0.0])
+def test_sssp_pull_large_distances(gx, mode):
+    # a weight-255 chain of 2000 vertices with leaves hanging off it:
+    # distances reach ~5e5 and some vertices stay unreached
+    L, leaves = 2000, 30000
+    rng = np.random.default_rng(11)
+    V = L + leaves
+    chain_s, chain_d = np.arange(L - 1), np.arange(1, L)
+    ls = rng.integers(0, L, 4 * leaves)
+    ld = rng.integers(L, V, 4 * leaves)
+    xs, xd = rng.integers(L, V, leaves), rng.integers(L, V, leaves)
+    src = np.r_[chain_s, ls, xs]
+    dst = np.r_[chain_d, ld, xd]
+    w = np.r_[np.full(L - 1, 255), rng.integers(1, 256, 4 * leaves), rng.integers(1, 256, leaves)]
+    g = gen.from_edges(V, src, dst, w)
+    ref = oracle.sssp(g, 0)
+    assert ref.state[L - 1] == 255 * (L - 1)
+    st = gx.State(load(gx, g, gx.GX_NEED_OUT), gx.GX_SSSP, source=0, pull_fraction=mode)
+    rs, steps = st.run(100_000, per_step=True)
+    assert rs.supersteps == ref.K
+    assert np.array_equal(st.values_numpy(), ref.state)
+    steps = np.array(steps)
+    assert np.array_equal(steps[:, 2], ref.changed)
+
+
 def test_sssp_edge_cases(gx):
     g = gen.from_edges(1, [], [])
     st = gx.State(load(gx, g, gx.GX_NEED_OUT), gx.GX_SSSP, source=0)
