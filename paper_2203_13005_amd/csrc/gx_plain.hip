@@ -146,12 +146,16 @@ __global__ __launch_bounds__(256) void k_compact(const uint8_t *__restrict__ fro
                                                  uint32_t *__restrict__ snap, int64_t V,
                                                  uint4 *__restrict__ list, uint32_t *__restrict__ tile_start,
                                                  DevStep *__restrict__ step, DevStep *__restrict__ next_step,
-                                                 int snap_all) {
+                                                 int snap_all, const DevStep *__restrict__ prev) {
     __shared__ unsigned long long s_scan[4];
     __shared__ unsigned long long s_base;
     __shared__ int s_nf[4];
     const int tid = threadIdx.x;
     if (blockIdx.x == 0 && tid == 0) *next_step = DevStep{0, 0, 0, 0};
+    // The previous superstep had no active vertex: nothing was relaxed, the
+    // map read here is still the cleared one and the map cleared here is
+    // empty, so A_{k+1} is empty without a sweep (its counters stay zero).
+    if (prev != nullptr && prev->frontier == 0) return;
     const int64_t u0 = ((int64_t)blockIdx.x * 256 + tid) * CVT;
     uint32_t actmask = 0;
     if (u0 < V) {  // byte maps are padded to whole 32-vertex words: the 16 bytes at u0 exist
@@ -908,7 +912,7 @@ extern "C" gx_status gx_state_init(gx_graph *g, const gx_params *p, void *dev_st
         if (V > 0)
             hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(V, 256 * CVT)), dim3(256), 0, hs, s->front8[0],
                                s->front8[1], rp, s->val, s->snap, V, s->list, s->tile_start, s->steps,
-                               s->steps + 1, (int)(s->pull_edges != 0xFFFFFFFFu));
+                               s->steps + 1, (int)(s->pull_edges != 0xFFFFFFFFu), nullptr);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
@@ -1055,7 +1059,7 @@ static gx_status enqueue_superstep(gx_state *s, hipStream_t hs) {
             if (e1) (void)hipEventRecord(e1, hs);
             hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(d.V, 256 * CVT)), dim3(256), 0, hs,
                                s->front8[cur ^ 1], s->front8[cur], rp, s->val, s->snap, d.V, s->list, s->tile_start,
-                               next, next2, (int)(s->pull_edges != 0xFFFFFFFFu));
+                               next, next2, (int)(s->pull_edges != 0xFFFFFFFFu), step);
         }
     }
     hipError_t e = hipGetLastError();
@@ -1275,7 +1279,7 @@ extern "C" gx_status gx_apply_delta(gx_state *s, const int32_t *dev_gid, const u
         const int32_t *rp = s->p.algo == GX_CC ? d.sym_rp : d.out_rp;
         hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(d.V, 256 * CVT)), dim3(256), 0, hs, front,
                            s->front8[(s->k & 1) ^ 1], rp, s->val, s->snap, d.V, s->list, s->tile_start, slot, slot2,
-                           (int)(s->pull_edges != 0xFFFFFFFFu));
+                           (int)(s->pull_edges != 0xFFFFFFFFu), nullptr);
         GX_CHECK_HIP(hipGetLastError(), s);
     }
     if (active_next) {
