@@ -144,12 +144,18 @@ namespace gx {
 gx_status graph_layout(const gx_graph_desc *desc, Carver &c, DevGraph *d);
 
 // Per-superstep statistics slot kept in device memory.
+// The compaction's workgroups each add to `list` and to `frontier`; adds to
+// one address serialise, so the two counters live on different 128-byte
+// lines and do not queue behind each other.
 struct DevStep {
     unsigned long long list;      // (entries << 32) | edges, via one 64-bit add per workgroup
+    unsigned long long changed;   // PageRank changed values
+    unsigned long long pad;       // 1 when the superstep pulled
+    unsigned long long spare0[13];
     unsigned long long frontier;  // |F_k|
-    unsigned long long changed;   // |F_{k+1}| (or PageRank changed values)
-    unsigned long long pad;
+    unsigned long long spare1[15];
 };
+static_assert(sizeof(DevStep) == 256, "DevStep spans two 128-byte lines");
 constexpr int STEP_RING = 4096;
 
 // Tiles of the push relaxation (active out-edges per workgroup tile).

@@ -71,6 +71,7 @@ struct gx_state {
     double *head = nullptr, *tailp = nullptr;
     int32_t *spill_row = nullptr;
     double *dpart = nullptr;
+    uint32_t *cpart = nullptr;   // per-tile changed counts (PageRank)
     double *Dval = nullptr;
     // shared
     DevStep *steps = nullptr;
@@ -110,7 +111,7 @@ __global__ __launch_bounds__(256) void k_min_init(uint32_t *val, uint8_t *f0, ui
                                                   const int32_t *l2g, const int32_t *rp, int64_t V, int32_t algo,
                                                   int32_t source, DevStep *step0) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) *step0 = DevStep{0, 0, 0, 0};
+    if (i == 0) *step0 = DevStep{};
     if (i < V) {
         uint32_t x;
         uint8_t f;
@@ -151,7 +152,7 @@ __global__ __launch_bounds__(256) void k_compact(const uint8_t *__restrict__ fro
     __shared__ unsigned long long s_base;
     __shared__ int s_nf[4];
     const int tid = threadIdx.x;
-    if (blockIdx.x == 0 && tid == 0) *next_step = DevStep{0, 0, 0, 0};
+    if (blockIdx.x == 0 && tid == 0) *next_step = DevStep{};
     // The previous superstep had no active vertex: nothing was relaxed, the
     // map read here is still the cleared one and the map cleared here is
     // empty, so A_{k+1} is empty without a sweep (its counters stay zero).
@@ -430,7 +431,7 @@ __global__ __launch_bounds__(256) void k_pr_init(float *x, float *contrib, uint3
                                                  double *dpart, DevStep *step0) {
     __shared__ double s_d[4];
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v == 0) *step0 = DevStep{0, 0, 0, 0};
+    if (v == 0) *step0 = DevStep{};
     double dl = 0.0;
     if (v < V) {
         int od = outdeg[v];
@@ -475,7 +476,7 @@ __global__ __launch_bounds__(PR_BLOCK) void k_pr_pull(const int32_t *__restrict_
                                                       const double *__restrict__ Dp, double inv_V,
                                                       double *__restrict__ head, double *__restrict__ tailp,
                                                       int32_t *__restrict__ spill_row, double *__restrict__ dpart,
-                                                      DevStep *__restrict__ step) {
+                                                      uint32_t *__restrict__ cpart) {
     constexpr int TILE = PR_BLOCK * VT;
     __shared__ float s_val[TILE];
     __shared__ int32_t s_own[TILE];
@@ -609,9 +610,9 @@ __global__ __launch_bounds__(PR_BLOCK) void k_pr_pull(const int32_t *__restrict_
         if (in_rp[r + 1] == in_rp[r]) ap(r, 0.0, dsum, chg);
     double td = block_sum<double>(dsum, s_d);
     unsigned long long tc = block_sum<unsigned long long>((unsigned long long)chg, s_c);
-    if (tid == 0) {
+    if (tid == 0) {  // per-tile partials, summed by k_pr_fix (no atomics on one shared counter)
         dpart[t] = td;
-        if (tc) atomicAdd(&step->changed, tc);
+        cpart[t] = (uint32_t)tc;
     }
 }
 
@@ -622,7 +623,8 @@ __global__ __launch_bounds__(PR_BLOCK) void k_pr_pull(const int32_t *__restrict_
 __global__ __launch_bounds__(1024) void k_pr_fix(const int32_t *__restrict__ in_rp, int32_t ntiles, int32_t tile,
                                                  const double *__restrict__ head, const double *__restrict__ tailp,
                                                  const int32_t *__restrict__ spill_row,
-                                                 const double *__restrict__ dpart, PrApply ap, double *Dp,
+                                                 const double *__restrict__ dpart,
+                                                 const uint32_t *__restrict__ cpart, PrApply ap, double *Dp,
                                                  double inv_V, DevStep *__restrict__ step,
                                                  DevStep *__restrict__ next_step) {
     __shared__ double s_d[16];
@@ -630,6 +632,7 @@ __global__ __launch_bounds__(1024) void k_pr_fix(const int32_t *__restrict__ in_
     ap.dD = ap.d * (*Dp) * inv_V;
     double dsum = 0.0;
     int chg = 0;
+    unsigned long long csum = 0;
     for (int32_t t = threadIdx.x; t < ntiles; t += blockDim.x) {
         const int32_t r = spill_row[t];
         if (r >= 0) {
@@ -639,15 +642,16 @@ __global__ __launch_bounds__(1024) void k_pr_fix(const int32_t *__restrict__ in_
             ap(r, total, dsum, chg);
         }
         dsum += dpart[t];
+        csum += cpart[t];
     }
     __syncthreads();
     const double td = block_sum<double>(dsum, s_d);
-    const unsigned long long tc = block_sum<unsigned long long>((unsigned long long)chg, s_c);
+    const unsigned long long tc = block_sum<unsigned long long>(csum + (unsigned long long)chg, s_c);
     if (threadIdx.x == 0) {
         *Dp = td;  // dangling mass of x_{t+1}
-        if (tc) atomicAdd(&step->changed, tc);
+        step->changed = tc;
         step->frontier = 0;
-        *next_step = DevStep{0, 0, 0, 0};
+        *next_step = DevStep{};
     }
 }
 
@@ -774,7 +778,7 @@ __global__ __launch_bounds__(256) void k_apply_delta(const int32_t *__restrict__
     }
 }
 
-__global__ void k_zero_step(DevStep *step) { *step = DevStep{0, 0, 0, 0}; }
+__global__ void k_zero_step(DevStep *step) { *step = DevStep{}; }
 
 template <class T>
 inline unsigned grid_for(T n, unsigned block) {
@@ -805,6 +809,7 @@ static size_t state_layout(gx_graph *g, const gx_params *p, Carver &c, gx_state 
         s->tailp = c.take<double>(nt);
         s->spill_row = c.take<int32_t>(nt);
         s->dpart = c.take<double>(std::max<int64_t>(nt, grid_for<int64_t>(V, 256)));
+        s->cpart = c.take<uint32_t>(std::max<int64_t>(nt, 1));
         s->Dval = c.take<double>(1);
     } else {
         int64_t Eimg = p->algo == GX_SSSP ? d.E : d.E_sym;
@@ -1026,10 +1031,10 @@ static gx_status enqueue_superstep(gx_state *s, hipStream_t hs) {
                       : d.pr_tile == 1024 ? k_pr_pull<4> : k_pr_pull<8>;
             hipLaunchKernelGGL(pull, dim3(d.pr_ntiles), dim3(PR_BLOCK), 0, hs, d.in_rp, d.in_col, d.pr_tile_row,
                                d.E, s->contrib[cur], ap, s->Dval, inv_V, s->head, s->tailp, s->spill_row, s->dpart,
-                               step);
+                               s->cpart);
             if (e1) (void)hipEventRecord(e1, hs);
             hipLaunchKernelGGL(k_pr_fix, dim3(1), dim3(1024), 0, hs, d.in_rp, d.pr_ntiles, d.pr_tile, s->head,
-                               s->tailp, s->spill_row, s->dpart, ap, s->Dval, inv_V, step, next);
+                               s->tailp, s->spill_row, s->dpart, s->cpart, ap, s->Dval, inv_V, step, next);
         }
     } else {
         // superstep k: relax A_k (list built by the previous compaction), then
