@@ -134,30 +134,34 @@ __global__ __launch_bounds__(256) void k_min_init(uint32_t *val, uint8_t *f0, ui
 // clearing the byte map the next relaxation fills, which held A_{k-1}); a
 // thread with an active vertex loads its CVT+1 row pointers and CVT values
 // as whole vectors, so no load waits on another.  A workgroup covers
-// 256*CVT vertices and issues two counter atomics (list, |A|).  Active
+// CBLOCK*CVT vertices and issues two counter atomics (list, |A|).  Active
 // vertices with out-edges get a list entry (edge offset, CSR base,
 // snapshot, vertex) and the tiles that start inside an entry's edges record
 // it.  When the next superstep may pull (snap_all), the snapshot array is
 // written for every vertex, INF for inactive ones, so the pull reads one
 // word per record.  |A_{k+1}| is the number of vertices superstep k changed.
 constexpr int CVT = 16;
+// Threads per compaction workgroup: each workgroup makes one list
+// reservation (an add with return on a single counter, which serialises
+// across workgroups), so fewer, larger workgroups shorten that chain.
+constexpr int CBLOCK = 1024;
 
-__global__ __launch_bounds__(256) void k_compact(const uint8_t *__restrict__ front, uint8_t *__restrict__ front_clear,
+__global__ __launch_bounds__(CBLOCK) void k_compact(const uint8_t *__restrict__ front, uint8_t *__restrict__ front_clear,
                                                  const int32_t *__restrict__ rp, const uint32_t *__restrict__ val,
                                                  uint32_t *__restrict__ snap, int64_t V,
                                                  uint4 *__restrict__ list, uint32_t *__restrict__ tile_start,
                                                  DevStep *__restrict__ step, DevStep *__restrict__ next_step,
                                                  int snap_all, const DevStep *__restrict__ prev) {
-    __shared__ unsigned long long s_scan[4];
+    __shared__ unsigned long long s_scan[CBLOCK / 64];
     __shared__ unsigned long long s_base;
-    __shared__ int s_nf[4];
+    __shared__ int s_nf[CBLOCK / 64];
     const int tid = threadIdx.x;
     if (blockIdx.x == 0 && tid == 0) *next_step = DevStep{};
     // The previous superstep had no active vertex: nothing was relaxed, the
     // map read here is still the cleared one and the map cleared here is
     // empty, so A_{k+1} is empty without a sweep (its counters stay zero).
     if (prev != nullptr && prev->frontier == 0) return;
-    const int64_t u0 = ((int64_t)blockIdx.x * 256 + tid) * CVT;
+    const int64_t u0 = ((int64_t)blockIdx.x * CBLOCK + tid) * CVT;
     uint32_t actmask = 0;
     if (u0 < V) {  // byte maps are padded to whole 32-vertex words: the 16 bytes at u0 exist
         const uint4 f = *reinterpret_cast<const uint4 *>(front + u0);
@@ -241,7 +245,12 @@ __global__ __launch_bounds__(256) void k_compact(const uint8_t *__restrict__ fro
     if ((tid & 63) == 0) s_nf[tid >> 6] = nf;
     if (tid == 0) s_base = total ? atomicAdd(&step->list, total) : 0ull;
     __syncthreads();
-    if (tid == 0) atomicAdd(&step->frontier, (unsigned long long)(s_nf[0] + s_nf[1] + s_nf[2] + s_nf[3]));
+    if (tid == 0) {
+        int nfb = 0;
+#pragma unroll
+        for (int w = 0; w < CBLOCK / 64; w++) nfb += s_nf[w];
+        atomicAdd(&step->frontier, (unsigned long long)nfb);
+    }
     unsigned long long pos = s_base + pre;
 #pragma unroll
     for (int i = 0; i < CVT; i++) {
@@ -915,7 +924,7 @@ extern "C" gx_status gx_state_init(gx_graph *g, const gx_params *p, void *dev_st
         }
         // compaction of superstep 0 (each superstep then relaxes and compacts the next)
         if (V > 0)
-            hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(V, 256 * CVT)), dim3(256), 0, hs, s->front8[0],
+            hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(V, CBLOCK * CVT)), dim3(CBLOCK), 0, hs, s->front8[0],
                                s->front8[1], rp, s->val, s->snap, V, s->list, s->tile_start, s->steps,
                                s->steps + 1, (int)(s->pull_edges != 0xFFFFFFFFu), nullptr);
     }
@@ -1062,7 +1071,7 @@ static gx_status enqueue_superstep(gx_state *s, hipStream_t hs) {
                                        s->pull_edges);
             }
             if (e1) (void)hipEventRecord(e1, hs);
-            hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(d.V, 256 * CVT)), dim3(256), 0, hs,
+            hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(d.V, CBLOCK * CVT)), dim3(CBLOCK), 0, hs,
                                s->front8[cur ^ 1], s->front8[cur], rp, s->val, s->snap, d.V, s->list, s->tile_start,
                                next, next2, (int)(s->pull_edges != 0xFFFFFFFFu), step);
         }
@@ -1282,7 +1291,7 @@ extern "C" gx_status gx_apply_delta(gx_state *s, const int32_t *dev_gid, const u
         // rebuild the active list of A_{k+1} from the merged values
         hipLaunchKernelGGL(k_zero_step, dim3(1), dim3(1), 0, hs, slot);
         const int32_t *rp = s->p.algo == GX_CC ? d.sym_rp : d.out_rp;
-        hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(d.V, 256 * CVT)), dim3(256), 0, hs, front,
+        hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(d.V, CBLOCK * CVT)), dim3(CBLOCK), 0, hs, front,
                            s->front8[(s->k & 1) ^ 1], rp, s->val, s->snap, d.V, s->list, s->tile_start, slot, slot2,
                            (int)(s->pull_edges != 0xFFFFFFFFu), nullptr);
         GX_CHECK_HIP(hipGetLastError(), s);
