@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+VALU_INT32_PEAK_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 lanes x 2.4 GHz
 
 
 def log(msg):
@@ -33,7 +34,9 @@ def log(msg):
 def push_bytes_per_superstep(g, fronts):
     """Algorithmic bytes of the relaxation kernel per superstep: 8 B per
     active out-edge (destination + weight), 16 B per active-list entry, 4 B
-    per distinct destination read, 4 B per vertex that improves."""
+    per distinct destination read, 4 B per vertex that improves (lower
+    bracket); the upper bracket reads 4 B of destination value per edge
+    instead of per distinct destination."""
     import numpy as np
     deg = np.diff(g.row_ptr).astype(np.int64)
     out = []
@@ -49,9 +52,30 @@ def push_bytes_per_superstep(g, fronts):
             nf = int(mark.sum())
         else:
             nf = 0
-        out.append(dict(edges=ef, list=len(f), dests=nf, changed=int(fronts[k + 1].sum()),
-                        bytes=8 * ef + 16 * len(f) + 4 * nf + 4 * int(fronts[k + 1].sum())))
+        ch = int(fronts[k + 1].sum())
+        out.append(dict(edges=ef, list=len(f), dests=nf, changed=ch,
+                        bytes=8 * ef + 16 * len(f) + 4 * nf + 4 * ch,
+                        bytes_upper=12 * ef + 16 * len(f) + 4 * ch))
     return out
+
+
+def copy_ceiling_gbps(torch, nbytes=1 << 30, reps=5):
+    """Device-to-device copy rate (bytes read + bytes written per second):
+    the practical HBM ceiling next to the 8 TB/s peak."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * nbytes / (ms / 1e3) / 1e9
 
 
 def cpu_baseline(g, edges_per_solve, budget_s=20.0):
@@ -121,6 +145,13 @@ def bench_batched(gx, torch, np, gen, steps=3):
             "plain_queries_per_s": 256 / t_plain, "plain_ms_total": t_plain * 1e3,
             "speedup_vs_plain": t_plain / t_batch, "lane_messages_per_batch": int(plain_edges),
             "lane_gteps": plain_edges / t_batch / 1e9,
+            # upper bracket: a 4 B value gather and a 4 B min update per lane message; VALU: an
+            # add and a min per lane message against 256 CUs x 64 lanes x 2.4 GHz int32 ops
+            "roofline": {"hbm_upper_GBps": 8 * plain_edges / t_batch / 1e9,
+                         "hbm_upper_frac": 8 * plain_edges / t_batch / 1e9 / HBM_PEAK_GBS,
+                         "valu_Tops": 2 * plain_edges / t_batch / 1e12,
+                         "valu_frac": 2 * plain_edges / t_batch / VALU_INT32_PEAK_OPS,
+                         "binds": "memory (random lane-row gathers); VALU far from its peak"},
             "tune": {"block": best.block, "tile": best.tile, "width": best.width},
             "ppr": bench_batched_ppr(gx, torch, g, dg, src)}
 
@@ -513,6 +544,10 @@ def main():
         log("copy calibration: 1 GiB device-to-device copy done")
 
     achieved = bytes_per_solve * args.steps / (kern_ms / 1e3) / 1e9
+    bytes_upper = sum(p["bytes_upper"] for p in per_step)
+    achieved_upper = bytes_upper * args.steps / (kern_ms / 1e3) / 1e9
+    copy_gbps = copy_ceiling_gbps(torch)
+    log(f"device copy ceiling {copy_gbps:.0f} GB/s")
     traffic = load_traffic()
     out = {
         "metric": "GTEPS per superstep and % HBM roofline; batched-vs-plain SSSP queries/s, p50/p99",
@@ -548,6 +583,11 @@ def main():
             "traffic_unit": "HBM bytes of the relaxation kernels per solve (FETCH_SIZE + WRITE_SIZE, "
                             "copy-calibrated); achieved = algorithmic bytes per solve / their time per solve",
             "algorithmic_bytes_per_solve": bytes_per_solve,
+            "algorithmic_bytes_upper_per_solve": bytes_upper,
+            "achieved_upper": achieved_upper,
+            "frac_upper": achieved_upper / HBM_PEAK_GBS,
+            "copy_ceiling_GBps": copy_gbps,
+            "frac_of_copy_ceiling": achieved / copy_gbps,
             "kernel_ms_per_solve": kern_ms / args.steps,
             "launches_per_solve": launches / args.steps,
             "per_superstep": [dict(edges=p["edges"], bytes=p["bytes"], pulled=int(d["pulled"]),
