@@ -8,14 +8,15 @@
 // edge triplets of one iteration, Section "Pipeline Shuffling"), so the
 // frontier compaction stores a snapshot of every active vertex's value.
 //
-// SSSP / CC superstep k (A_k = vertices active in superstep k):
-//   k_push    : every workgroup tile relaxes exactly PUSH_TILE active
+// SSSP / CC superstep k (A_k = vertices active in superstep k), one
+// launch of k_relax that runs one of two forms:
+//   push      : every workgroup tile relaxes exactly PUSH_TILE active
 //               out-edges: Gen = snapshot (+ weight), Merge + Apply =
 //               integer atomicMin on the destination, filtered by a plain
 //               read; a candidate that passes marks the destination in the
 //               next frontier and the dirty map (plain, idempotent byte
 //               stores).
-//   k_pull    : for large frontiers instead: one streaming sweep over all
+//   pull      : for large frontiers instead: one streaming sweep over all
 //               in-edge records, grouped by source band so the gathered
 //               snapshots stay cache resident, min per run of equal
 //               destination, the same filtered atomics.  The device picks
@@ -26,6 +27,8 @@
 //               64-bit atomic per workgroup reserves list slots and edge
 //               offsets; every PUSH_TILE-edge tile records the entry where it
 //               starts; |A_{k+1}| is the count of vertices superstep k changed.
+//               It runs after the relaxation, so the next superstep's form
+//               is known on the device when its launch starts.
 //               The frontier stands in for the paper's synchronisation
 //               skipping (Section "Synchronization Skipping") and the equal
 //               edge tiles for its fixed-size edge blocks (Section "Data Flows
@@ -54,7 +57,7 @@ struct gx_state {
     gx_params p{};
     int64_t k = 0;
     bool dev_error = false;
-    int push_grid = 0;
+    int relax_grid = 0;   // persistent grid of the relaxation kernel
     // SSSP / CC
     uint32_t *val = nullptr;
     uint8_t *front8[2] = {nullptr, nullptr};  // frontier byte maps: A_k lives in front8[k & 1]
@@ -63,7 +66,6 @@ struct gx_state {
     uint32_t *tile_start = nullptr;
     uint32_t *snap = nullptr;      // start-of-superstep values of active vertices (pull)
     uint32_t pull_edges = 0xFFFFFFFFu;
-    int pull_grid = 0;
     // PageRank
     float *x[2] = {nullptr, nullptr};
     float *contrib[2] = {nullptr, nullptr};
@@ -268,20 +270,24 @@ __global__ __launch_bounds__(CBLOCK) void k_compact(const uint8_t *__restrict__ 
 
 // Relaxes the active out-edges, PUSH_TILE per workgroup tile (persistent
 // grid; the tile count comes from the compaction's counter).
+struct PushLds {
+    uint32_t base[PUSH_TILE + 1];
+    uint32_t snap[PUSH_TILE + 1];
+    int32_t own[PUSH_TILE];
+    int32_t red[4];
+};
+
 template <bool WEIGHTED>
-__global__ __launch_bounds__(PUSH_BLOCK) void k_push(const uint4 *__restrict__ list,
-                                                     const uint32_t *__restrict__ tile_start,
-                                                     const void *__restrict__ adj, uint32_t *__restrict__ val,
-                                                     uint8_t *__restrict__ front_next, uint8_t *__restrict__ dirty,
-                                                     const DevStep *__restrict__ step, uint32_t pull_edges) {
-    __shared__ uint32_t s_base[PUSH_TILE + 1];
-    __shared__ uint32_t s_snap[PUSH_TILE + 1];
-    __shared__ int32_t s_own[PUSH_TILE];
-    __shared__ int32_t s_red[4];
+__device__ __forceinline__ void push_body(const uint4 *__restrict__ list, const uint32_t *__restrict__ tile_start,
+                                          const void *__restrict__ adj, uint32_t *__restrict__ val,
+                                          uint8_t *__restrict__ front_next, uint8_t *__restrict__ dirty,
+                                          unsigned long long le, PushLds &lds) {
+    uint32_t *s_base = lds.base;
+    uint32_t *s_snap = lds.snap;
+    int32_t *s_own = lds.own;
+    int32_t *s_red = lds.red;
     const int tid = threadIdx.x;
-    const unsigned long long le = step->list;
     const uint32_t L = (uint32_t)(le >> 32), EF = (uint32_t)le;
-    if (EF >= pull_edges) return;  // this superstep pulls
     const uint32_t ntiles = (EF + PUSH_TILE - 1) / PUSH_TILE;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const uint32_t e0 = t * PUSH_TILE;
@@ -363,14 +369,11 @@ __global__ __launch_bounds__(PUSH_BLOCK) void k_push(const uint4 *__restrict__ l
 // when the frontier's out-edges reach pull_edges (V * 4 must fit the 32-bit
 // buffer range; the host enables the pull only then).
 template <bool WEIGHTED>
-__global__ __launch_bounds__(256) void k_pull(const uint2 *__restrict__ rec, const uint4 *__restrict__ units,
-                                              PullSlices sl, int64_t V, const uint32_t *__restrict__ snap,
-                                              uint32_t *__restrict__ val, uint8_t *__restrict__ front_next,
-                                              uint8_t *__restrict__ dirty, DevStep *__restrict__ step,
-                                              uint32_t pull_edges) {
-    __shared__ uint32_t s_snap[PULL_BAND];
-    const uint32_t EF = (uint32_t)step->list;
-    if (EF < pull_edges) return;
+__device__ __forceinline__ void pull_body(const uint2 *__restrict__ rec, const uint4 *__restrict__ units,
+                                          const PullSlices &sl, int64_t V, const uint32_t *__restrict__ snap,
+                                          uint32_t *__restrict__ val, uint8_t *__restrict__ front_next,
+                                          uint8_t *__restrict__ dirty, DevStep *__restrict__ step,
+                                          uint32_t *__restrict__ s_snap) {
     const int tid = threadIdx.x;
     if (blockIdx.x == 0 && tid == 0) step->pad = 1;
     const __amdgpu_buffer_rsrc_t vrs = __builtin_amdgcn_make_buffer_rsrc(val, (short)0, (int)(uint32_t)(V * 4), 0x00020000);
@@ -431,6 +434,33 @@ __global__ __launch_bounds__(256) void k_pull(const uint2 *__restrict__ rec, con
             }
         }
     }
+}
+
+// One launch per superstep: the frontier's edge count, known on the device
+// after the compaction, picks the form (a second, idle launch would cost a
+// dispatch and a sweep of exiting workgroups every superstep).
+struct PullArgs {
+    const uint2 *rec;
+    const uint4 *units;
+    PullSlices sl;
+};
+union RelaxLds {
+    PushLds push;
+    uint32_t pull_snap[PULL_BAND];
+};
+
+template <bool WEIGHTED>
+__global__ __launch_bounds__(256) void k_relax(const uint4 *__restrict__ list, const uint32_t *__restrict__ tile_start,
+                                               const void *__restrict__ adj, PullArgs pa, int64_t V,
+                                               const uint32_t *__restrict__ snap, uint32_t *__restrict__ val,
+                                               uint8_t *__restrict__ front_next, uint8_t *__restrict__ dirty,
+                                               DevStep *__restrict__ step, uint32_t pull_edges) {
+    __shared__ RelaxLds lds;
+    const unsigned long long le = step->list;
+    if ((uint32_t)le >= pull_edges)
+        pull_body<WEIGHTED>(pa.rec, pa.units, pa.sl, V, snap, val, front_next, dirty, step, lds.pull_snap);
+    else
+        push_body<WEIGHTED>(list, tile_start, adj, val, front_next, dirty, le, lds.push);
 }
 
 // ------------------------------------------------------------ PageRank
@@ -889,9 +919,10 @@ extern "C" gx_status gx_state_init(gx_graph *g, const gx_params *p, void *dev_st
     s->p = *p;
     Carver c(dev_state, bytes);
     state_layout(g, p, c, s);
-    s->push_grid = persistent_grid(g, k_push<true>, PUSH_BLOCK);
-    // whole multiples of the slice count (workgroup b sweeps slice b mod PULL_SLICES)
-    s->pull_grid = std::max(PULL_SLICES, persistent_grid(g, k_pull<true>, 256) / PULL_SLICES * PULL_SLICES);
+    // whole multiples of the slice count (a pulling workgroup b sweeps slice b mod PULL_SLICES)
+    s->relax_grid = std::max(PULL_SLICES, (p->algo == GX_CC ? persistent_grid(g, k_relax<false>, 256)
+                                                            : persistent_grid(g, k_relax<true>, 256)) /
+                                              PULL_SLICES * PULL_SLICES);
     if (p->algo != GX_PAGERANK) {
         const DevGraph &dg = g->d;
         // (the pull addresses values through a 32-bit buffer range)
@@ -1055,20 +1086,15 @@ static gx_status enqueue_superstep(gx_state *s, hipStream_t hs) {
         if (d.V > 0) {
             if (e0) (void)hipEventRecord(e0, hs);
             if (!cc) {
-                hipLaunchKernelGGL(k_push<true>, dim3(s->push_grid), dim3(PUSH_BLOCK), 0, hs, s->list, s->tile_start,
-                                   (const void *)d.out_adj, s->val, s->front8[cur ^ 1], s->dirty8, step,
-                                   s->pull_edges);
-                if (s->pull_edges != 0xFFFFFFFFu)
-                    hipLaunchKernelGGL(k_pull<true>, dim3(s->pull_grid), dim3(256), 0, hs, d.pull_w, d.pull_w_units,
-                                       d.pull_w_off, d.V, s->snap, s->val, s->front8[cur ^ 1], s->dirty8, step, s->pull_edges);
-            } else {
-                hipLaunchKernelGGL(k_push<false>, dim3(s->push_grid), dim3(PUSH_BLOCK), 0, hs, s->list,
-                                   s->tile_start, (const void *)d.sym_col, s->val, s->front8[cur ^ 1], s->dirty8,
+                const PullArgs pa{d.pull_w, d.pull_w_units, d.pull_w_off};
+                hipLaunchKernelGGL(k_relax<true>, dim3(s->relax_grid), dim3(256), 0, hs, s->list, s->tile_start,
+                                   (const void *)d.out_adj, pa, d.V, s->snap, s->val, s->front8[cur ^ 1], s->dirty8,
                                    step, s->pull_edges);
-                if (s->pull_edges != 0xFFFFFFFFu)
-                    hipLaunchKernelGGL(k_pull<false>, dim3(s->pull_grid), dim3(256), 0, hs, d.pull_sym,
-                                       d.pull_sym_units, d.pull_sym_off, d.V, s->snap, s->val, s->front8[cur ^ 1], s->dirty8, step,
-                                       s->pull_edges);
+            } else {
+                const PullArgs pa{d.pull_sym, d.pull_sym_units, d.pull_sym_off};
+                hipLaunchKernelGGL(k_relax<false>, dim3(s->relax_grid), dim3(256), 0, hs, s->list, s->tile_start,
+                                   (const void *)d.sym_col, pa, d.V, s->snap, s->val, s->front8[cur ^ 1], s->dirty8,
+                                   step, s->pull_edges);
             }
             if (e1) (void)hipEventRecord(e1, hs);
             hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(d.V, CBLOCK * CVT)), dim3(CBLOCK), 0, hs,
