@@ -14,8 +14,8 @@
 //               out-edges: Gen = snapshot (+ weight), Merge + Apply =
 //               integer atomicMin on the destination, filtered by a plain
 //               read; a candidate that passes marks the destination in the
-//               next frontier and the dirty map (plain, idempotent byte
-//               stores).
+//               next frontier (a plain, idempotent byte store; the next
+//               compaction carries the marks into the dirty map).
 //   pull      : for large frontiers instead: one streaming sweep over all
 //               in-edge records, grouped by source band so the gathered
 //               snapshots stay cache resident, min per run of equal
@@ -153,7 +153,8 @@ __global__ __launch_bounds__(CBLOCK) void k_compact(const uint8_t *__restrict__ 
                                                  uint32_t *__restrict__ snap, int64_t V,
                                                  uint4 *__restrict__ list, uint32_t *__restrict__ tile_start,
                                                  DevStep *__restrict__ step, DevStep *__restrict__ next_step,
-                                                 int snap_all, const DevStep *__restrict__ prev) {
+                                                 int snap_all, const DevStep *__restrict__ prev,
+                                                 uint8_t *__restrict__ dirty) {
     __shared__ unsigned long long s_scan[CBLOCK / 64];
     __shared__ unsigned long long s_base;
     __shared__ int s_nf[CBLOCK / 64];
@@ -168,6 +169,11 @@ __global__ __launch_bounds__(CBLOCK) void k_compact(const uint8_t *__restrict__ 
     if (u0 < V) {  // byte maps are padded to whole 32-vertex words: the 16 bytes at u0 exist
         const uint4 f = *reinterpret_cast<const uint4 *>(front + u0);
         *reinterpret_cast<uint4 *>(front_clear + u0) = make_uint4(0u, 0u, 0u, 0u);
+        if (dirty != nullptr && (f.x | f.y | f.z | f.w)) {  // changed vertices become dirty here
+            uint4 *d4 = reinterpret_cast<uint4 *>(dirty + u0);
+            const uint4 d = *d4;
+            *d4 = make_uint4(d.x | f.x, d.y | f.y, d.z | f.z, d.w | f.w);
+        }
         const uint32_t fw[4] = {f.x, f.y, f.z, f.w};
 #pragma unroll
         for (int q = 0; q < 4; q++)
@@ -280,8 +286,7 @@ struct PushLds {
 template <bool WEIGHTED>
 __device__ __forceinline__ void push_body(const uint4 *__restrict__ list, const uint32_t *__restrict__ tile_start,
                                           const void *__restrict__ adj, uint32_t *__restrict__ val,
-                                          uint8_t *__restrict__ front_next, uint8_t *__restrict__ dirty,
-                                          unsigned long long le, PushLds &lds) {
+                                          uint8_t *__restrict__ front_next, unsigned long long le, PushLds &lds) {
     uint32_t *s_base = lds.base;
     uint32_t *s_snap = lds.snap;
     int32_t *s_own = lds.own;
@@ -346,7 +351,6 @@ __device__ __forceinline__ void push_body(const uint4 *__restrict__ list, const 
             if (cand[i] < cur[i]) {
                 atomicMin(&val[dst[i]], cand[i]);
                 front_next[dst[i]] = 1;
-                dirty[dst[i]] = 1;
             }
         }
         __syncthreads();
@@ -372,8 +376,7 @@ template <bool WEIGHTED>
 __device__ __forceinline__ void pull_body(const uint2 *__restrict__ rec, const uint4 *__restrict__ units,
                                           const PullSlices &sl, int64_t V, const uint32_t *__restrict__ snap,
                                           uint32_t *__restrict__ val, uint8_t *__restrict__ front_next,
-                                          uint8_t *__restrict__ dirty, DevStep *__restrict__ step,
-                                          uint32_t *__restrict__ s_snap) {
+                                          DevStep *__restrict__ step, uint32_t *__restrict__ s_snap) {
     const int tid = threadIdx.x;
     if (blockIdx.x == 0 && tid == 0) step->pad = 1;
     const __amdgpu_buffer_rsrc_t vrs = __builtin_amdgcn_make_buffer_rsrc(val, (short)0, (int)(uint32_t)(V * 4), 0x00020000);
@@ -429,7 +432,6 @@ __device__ __forceinline__ void pull_body(const uint2 *__restrict__ rec, const u
                 if (m[i] < cur[i]) {
                     atomicMin(&val[dst[i]], m[i]);
                     front_next[dst[i]] = 1;
-                    dirty[dst[i]] = 1;
                 }
             }
         }
@@ -453,14 +455,14 @@ template <bool WEIGHTED>
 __global__ __launch_bounds__(256) void k_relax(const uint4 *__restrict__ list, const uint32_t *__restrict__ tile_start,
                                                const void *__restrict__ adj, PullArgs pa, int64_t V,
                                                const uint32_t *__restrict__ snap, uint32_t *__restrict__ val,
-                                               uint8_t *__restrict__ front_next, uint8_t *__restrict__ dirty,
-                                               DevStep *__restrict__ step, uint32_t pull_edges) {
+                                               uint8_t *__restrict__ front_next, DevStep *__restrict__ step,
+                                               uint32_t pull_edges) {
     __shared__ RelaxLds lds;
     const unsigned long long le = step->list;
     if ((uint32_t)le >= pull_edges)
-        pull_body<WEIGHTED>(pa.rec, pa.units, pa.sl, V, snap, val, front_next, dirty, step, lds.pull_snap);
+        pull_body<WEIGHTED>(pa.rec, pa.units, pa.sl, V, snap, val, front_next, step, lds.pull_snap);
     else
-        push_body<WEIGHTED>(list, tile_start, adj, val, front_next, dirty, le, lds.push);
+        push_body<WEIGHTED>(list, tile_start, adj, val, front_next, le, lds.push);
 }
 
 // ------------------------------------------------------------ PageRank
@@ -957,7 +959,7 @@ extern "C" gx_status gx_state_init(gx_graph *g, const gx_params *p, void *dev_st
         if (V > 0)
             hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(V, CBLOCK * CVT)), dim3(CBLOCK), 0, hs, s->front8[0],
                                s->front8[1], rp, s->val, s->snap, V, s->list, s->tile_start, s->steps,
-                               s->steps + 1, (int)(s->pull_edges != 0xFFFFFFFFu), nullptr);
+                               s->steps + 1, (int)(s->pull_edges != 0xFFFFFFFFu), nullptr, nullptr);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
@@ -1088,18 +1090,18 @@ static gx_status enqueue_superstep(gx_state *s, hipStream_t hs) {
             if (!cc) {
                 const PullArgs pa{d.pull_w, d.pull_w_units, d.pull_w_off};
                 hipLaunchKernelGGL(k_relax<true>, dim3(s->relax_grid), dim3(256), 0, hs, s->list, s->tile_start,
-                                   (const void *)d.out_adj, pa, d.V, s->snap, s->val, s->front8[cur ^ 1], s->dirty8,
-                                   step, s->pull_edges);
+                                   (const void *)d.out_adj, pa, d.V, s->snap, s->val, s->front8[cur ^ 1], step,
+                                   s->pull_edges);
             } else {
                 const PullArgs pa{d.pull_sym, d.pull_sym_units, d.pull_sym_off};
                 hipLaunchKernelGGL(k_relax<false>, dim3(s->relax_grid), dim3(256), 0, hs, s->list, s->tile_start,
-                                   (const void *)d.sym_col, pa, d.V, s->snap, s->val, s->front8[cur ^ 1], s->dirty8,
-                                   step, s->pull_edges);
+                                   (const void *)d.sym_col, pa, d.V, s->snap, s->val, s->front8[cur ^ 1], step,
+                                   s->pull_edges);
             }
             if (e1) (void)hipEventRecord(e1, hs);
             hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(d.V, CBLOCK * CVT)), dim3(CBLOCK), 0, hs,
                                s->front8[cur ^ 1], s->front8[cur], rp, s->val, s->snap, d.V, s->list, s->tile_start,
-                               next, next2, (int)(s->pull_edges != 0xFFFFFFFFu), step);
+                               next, next2, (int)(s->pull_edges != 0xFFFFFFFFu), step, s->dirty8);
         }
     }
     hipError_t e = hipGetLastError();
@@ -1319,7 +1321,7 @@ extern "C" gx_status gx_apply_delta(gx_state *s, const int32_t *dev_gid, const u
         const int32_t *rp = s->p.algo == GX_CC ? d.sym_rp : d.out_rp;
         hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(d.V, CBLOCK * CVT)), dim3(CBLOCK), 0, hs, front,
                            s->front8[(s->k & 1) ^ 1], rp, s->val, s->snap, d.V, s->list, s->tile_start, slot, slot2,
-                           (int)(s->pull_edges != 0xFFFFFFFFu), nullptr);
+                           (int)(s->pull_edges != 0xFFFFFFFFu), nullptr, nullptr);
         GX_CHECK_HIP(hipGetLastError(), s);
     }
     if (active_next) {
