@@ -139,9 +139,10 @@ __global__ __launch_bounds__(256) void k_min_init(uint32_t *val, uint8_t *f0, ui
 // CBLOCK*CVT vertices and issues two counter atomics (list, |A|).  Active
 // vertices with out-edges get a list entry (edge offset, CSR base,
 // snapshot, vertex) and the tiles that start inside an entry's edges record
-// it.  When the next superstep may pull (snap_all), the snapshot array is
-// written for every vertex, INF for inactive ones, so the pull reads one
-// word per record.  |A_{k+1}| is the number of vertices superstep k changed.
+// it.  When the next superstep may pull (snap_all), threads with an active
+// vertex also store their vertices' values as snapshots (the pull stages
+// them with the frontier map and treats inactive sources as INF).  |A_{k+1}|
+// is the number of vertices superstep k changed.
 constexpr int CVT = 16;
 // Threads per compaction workgroup: each workgroup makes one list
 // reservation (an add with return on a single counter, which serialises
@@ -182,18 +183,7 @@ __global__ __launch_bounds__(CBLOCK) void k_compact(const uint8_t *__restrict__ 
                 if ((fw[q] >> (8 * b)) & 0xFFu) actmask |= 1u << (4 * q + b);
         if (V - u0 < CVT) actmask &= (1u << (V - u0)) - 1u;  // padding bytes are no vertices
     }
-    if (!__syncthreads_or(actmask != 0)) {
-        if (snap_all && u0 < V) {
-            if (u0 + CVT <= V) {
-                uint4 *s4 = reinterpret_cast<uint4 *>(snap + u0);
-#pragma unroll
-                for (int q = 0; q < CVT / 4; q++) s4[q] = make_uint4(INF, INF, INF, INF);
-            } else {
-                for (int i = 0; u0 + i < V; i++) snap[u0 + i] = INF;
-            }
-        }
-        return;
-    }
+    if (!__syncthreads_or(actmask != 0)) return;
     int32_t r[CVT + 1];
     uint32_t x[CVT];
 #pragma unroll
@@ -222,18 +212,18 @@ __global__ __launch_bounds__(CBLOCK) void k_compact(const uint8_t *__restrict__ 
             }
         }
     }
-    if (snap_all && u0 < V) {
-        uint32_t sv[CVT];
-#pragma unroll
-        for (int i = 0; i < CVT; i++) sv[i] = ((actmask >> i) & 1u) ? x[i] : INF;
+    // Snapshots for the pull: a thread with an active vertex stores the values
+    // of all its CVT vertices (the pull masks inactive sources with the
+    // frontier map, so whatever an inactive entry holds is never used).
+    if (snap_all && actmask) {
         if (u0 + CVT <= V) {
             uint4 *s4 = reinterpret_cast<uint4 *>(snap + u0);
 #pragma unroll
-            for (int q = 0; q < CVT / 4; q++) s4[q] = make_uint4(sv[4 * q], sv[4 * q + 1], sv[4 * q + 2], sv[4 * q + 3]);
+            for (int q = 0; q < CVT / 4; q++) s4[q] = make_uint4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
         } else {
 #pragma unroll
             for (int i = 0; i < CVT; i++)
-                if (u0 + i < V) snap[u0 + i] = sv[i];
+                if (u0 + i < V) snap[u0 + i] = x[i];
         }
     }
     uint32_t cnt = 0, edges = 0;
@@ -266,7 +256,6 @@ __global__ __launch_bounds__(CBLOCK) void k_compact(const uint8_t *__restrict__ 
         if (!((actmask >> i) & 1u) || dg <= 0) continue;
         const int64_t u = u0 + i;
         const uint32_t idx = (uint32_t)(pos >> 32), off = (uint32_t)pos;
-        if (!snap_all) snap[u] = x[i];
         list[idx] = make_uint4(off, (uint32_t)(r[i] - (int32_t)off), x[i], (uint32_t)u);
         const uint32_t t0 = (off + PUSH_TILE - 1) / PUSH_TILE, t1 = (off + (uint32_t)dg - 1) / PUSH_TILE;
         for (uint32_t t = t0; t <= t1; t++) tile_start[t] = idx;
@@ -363,8 +352,8 @@ __device__ __forceinline__ void push_body(const uint4 *__restrict__ list, const 
 // load).  Workgroup b takes the units of slice b mod PULL_SLICES in order;
 // since workgroups are dealt round-robin to the XCDs, each XCD's L2 holds
 // its slice's destination values.  A unit's band of snapshots is staged in
-// LDS (the compaction stored INF as the snapshot of every inactive vertex),
-// so a record's gather is an LDS read; the thread folds runs of equal
+// LDS, INF where the frontier map A_k says the source is inactive, so a
+// record's gather is an LDS read; the thread folds runs of equal
 // destination in its PULL_VT consecutive records to their minimum and
 // applies each with the filtered atomics of the push.  A record without a
 // candidate (inactive source, padding, or not the end of its run) reads
@@ -375,8 +364,9 @@ __device__ __forceinline__ void push_body(const uint4 *__restrict__ list, const 
 template <bool WEIGHTED>
 __device__ __forceinline__ void pull_body(const uint2 *__restrict__ rec, const uint4 *__restrict__ units,
                                           const PullSlices &sl, int64_t V, const uint32_t *__restrict__ snap,
-                                          uint32_t *__restrict__ val, uint8_t *__restrict__ front_next,
-                                          DevStep *__restrict__ step, uint32_t *__restrict__ s_snap) {
+                                          const uint8_t *__restrict__ front_cur, uint32_t *__restrict__ val,
+                                          uint8_t *__restrict__ front_next, DevStep *__restrict__ step,
+                                          uint32_t *__restrict__ s_snap) {
     const int tid = threadIdx.x;
     if (blockIdx.x == 0 && tid == 0) step->pad = 1;
     const __amdgpu_buffer_rsrc_t vrs = __builtin_amdgcn_make_buffer_rsrc(val, (short)0, (int)(uint32_t)(V * 4), 0x00020000);
@@ -386,13 +376,24 @@ __device__ __forceinline__ void pull_body(const uint2 *__restrict__ rec, const u
         const uint4 un = units[ui];
         const uint32_t start = un.x, cnt = un.y, bb = un.z;
         __syncthreads();  // the previous unit's gathers are done
+        // the band's snapshots, INF where the source is not in A_k
         if ((int64_t)bb + PULL_BAND <= V) {
             const uint4 *s4 = reinterpret_cast<const uint4 *>(snap + bb);
+            const uint32_t *f4 = reinterpret_cast<const uint32_t *>(front_cur + bb);
+            uint4 sv[PULL_BAND / 4 / 256];
+            uint32_t fv[PULL_BAND / 4 / 256];
+#pragma unroll
+            for (int q = 0; q < PULL_BAND / 4 / 256; q++) {
+                sv[q] = s4[q * 256 + tid];
+                fv[q] = f4[q * 256 + tid];
+            }
 #pragma unroll
             for (int q = 0; q < PULL_BAND / 4 / 256; q++)
-                reinterpret_cast<uint4 *>(s_snap)[q * 256 + tid] = s4[q * 256 + tid];
+                reinterpret_cast<uint4 *>(s_snap)[q * 256 + tid] =
+                    make_uint4(fv[q] & 0xFFu ? sv[q].x : INF, fv[q] & 0xFF00u ? sv[q].y : INF,
+                               fv[q] & 0xFF0000u ? sv[q].z : INF, fv[q] & 0xFF000000u ? sv[q].w : INF);
         } else {  // the last band ends at V
-            for (int i = tid; i < PULL_BAND; i += 256) s_snap[i] = bb + i < V ? snap[bb + i] : INF;
+            for (int i = tid; i < PULL_BAND; i += 256) s_snap[i] = bb + i < V && front_cur[bb + i] ? snap[bb + i] : INF;
         }
         __syncthreads();
         for (uint32_t e0 = start + (uint32_t)tid * PULL_VT; e0 < start + cnt; e0 += 256 * PULL_VT) {
@@ -455,12 +456,12 @@ template <bool WEIGHTED>
 __global__ __launch_bounds__(256) void k_relax(const uint4 *__restrict__ list, const uint32_t *__restrict__ tile_start,
                                                const void *__restrict__ adj, PullArgs pa, int64_t V,
                                                const uint32_t *__restrict__ snap, uint32_t *__restrict__ val,
-                                               uint8_t *__restrict__ front_next, DevStep *__restrict__ step,
-                                               uint32_t pull_edges) {
+                                               const uint8_t *__restrict__ front_cur, uint8_t *__restrict__ front_next,
+                                               DevStep *__restrict__ step, uint32_t pull_edges) {
     __shared__ RelaxLds lds;
     const unsigned long long le = step->list;
     if ((uint32_t)le >= pull_edges)
-        pull_body<WEIGHTED>(pa.rec, pa.units, pa.sl, V, snap, val, front_next, step, lds.pull_snap);
+        pull_body<WEIGHTED>(pa.rec, pa.units, pa.sl, V, snap, front_cur, val, front_next, step, lds.pull_snap);
     else
         push_body<WEIGHTED>(list, tile_start, adj, val, front_next, le, lds.push);
 }
@@ -1090,13 +1091,13 @@ static gx_status enqueue_superstep(gx_state *s, hipStream_t hs) {
             if (!cc) {
                 const PullArgs pa{d.pull_w, d.pull_w_units, d.pull_w_off};
                 hipLaunchKernelGGL(k_relax<true>, dim3(s->relax_grid), dim3(256), 0, hs, s->list, s->tile_start,
-                                   (const void *)d.out_adj, pa, d.V, s->snap, s->val, s->front8[cur ^ 1], step,
-                                   s->pull_edges);
+                                   (const void *)d.out_adj, pa, d.V, s->snap, s->val, s->front8[cur], s->front8[cur ^ 1],
+                                   step, s->pull_edges);
             } else {
                 const PullArgs pa{d.pull_sym, d.pull_sym_units, d.pull_sym_off};
                 hipLaunchKernelGGL(k_relax<false>, dim3(s->relax_grid), dim3(256), 0, hs, s->list, s->tile_start,
-                                   (const void *)d.sym_col, pa, d.V, s->snap, s->val, s->front8[cur ^ 1], step,
-                                   s->pull_edges);
+                                   (const void *)d.sym_col, pa, d.V, s->snap, s->val, s->front8[cur], s->front8[cur ^ 1],
+                                   step, s->pull_edges);
             }
             if (e1) (void)hipEventRecord(e1, hs);
             hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(d.V, CBLOCK * CVT)), dim3(CBLOCK), 0, hs,
