@@ -472,6 +472,8 @@ extern "C" gx_status gx_graph_load(const gx_graph_desc *desc, void *dev_arena, s
     layout(desc, (int64_t)h.sym_col.size(), c, &g->d);
     g->d.pull_w_off = h.pull_w_off;
     g->d.pull_sym_off = h.pull_sym_off;
+    for (const uint4 &u : h.pull_w_units) g->pull_w_recs.push_back(u.y);
+    for (const uint4 &u : h.pull_sym_units) g->pull_sym_recs.push_back(u.y);
     g->needs = desc->needs;
     g->arena = dev_arena;
     g->arena_bytes = arena_bytes;

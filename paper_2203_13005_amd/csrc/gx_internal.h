@@ -136,6 +136,7 @@ struct gx_graph {
     int num_cus = 0;
     bool dev_error = false;
     std::vector<int32_t> host_outdeg;  // out-degree (host copy, for sources and stats)
+    std::vector<uint32_t> pull_w_recs, pull_sym_recs;  // records of each pull unit (sizes fix-up regions)
 };
 
 namespace gx {

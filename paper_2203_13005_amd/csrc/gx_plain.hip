@@ -58,6 +58,9 @@ struct gx_state {
     int64_t k = 0;
     bool dev_error = false;
     int relax_grid = 0;   // persistent grid of the relaxation kernel
+    uint2 *fix = nullptr;         // fix-up regions, fix_cap entries per relaxation workgroup
+    uint32_t *fixn = nullptr;     // entries recorded per workgroup
+    uint32_t fix_cap = 0;
     // SSSP / CC
     uint32_t *val = nullptr;
     uint8_t *front8[2] = {nullptr, nullptr};  // frontier byte maps: A_k lives in front8[k & 1]
@@ -272,6 +275,59 @@ struct PushLds {
     int32_t red[4];
 };
 
+// Where a pulling workgroup's improving candidates go.  A candidate below a
+// value read during the superstep is below the destination's start value
+// (values only fall), so the destination changes whatever else lands: it is
+// marked in the next frontier, its value is set with a plain store, and the
+// pair (destination, candidate) is appended to the workgroup's fix-up
+// region.  Plain stores racing on one destination may leave a larger
+// candidate; the fix-up kernel then re-applies every recorded candidate
+// still below the stored value with an atomic minimum.  Min atomics cost
+// several times a plain store here.  This is sound because every writer of
+// a destination in the pull, and the fix-up workgroup that reads its
+// entries, run on the XCD that owns the destination's slice (one L2 sees
+// all of its plain stores); regions are sized for every record a workgroup
+// can meet, so no candidate ever bypasses them (plain stores and atomics on
+// one word in one kernel would not be ordered).
+struct FixRegion {
+    uint2 *ent;        // this workgroup's region
+    uint32_t cap;      // its capacity
+    uint32_t *count;   // LDS: candidates offered so far
+};
+
+template <int N>
+__device__ __forceinline__ void apply_hits(const uint32_t (&dst)[N], const uint32_t (&m)[N], uint32_t hits,
+                                           uint32_t *__restrict__ val, uint8_t *__restrict__ front_next,
+                                           const FixRegion &fr) {
+    // one LDS reservation per wave: lane-ordered, contiguous entries
+    const int lane = threadIdx.x & 63;
+    const uint32_t cnt = (uint32_t)__popc(hits);
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    const uint32_t total = __shfl(incl, 63, 64);
+    uint32_t base = 0;
+    if (lane == 63 && total) base = atomicAdd(fr.count, total);
+    base = __shfl(base, 63, 64);
+    uint32_t pos = base + incl - cnt;
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        if ((hits >> i) & 1u) {
+            if (pos < fr.cap) {
+                fr.ent[pos] = make_uint2(dst[i], m[i]);
+                val[dst[i]] = m[i];
+            } else {
+                atomicMin(&val[dst[i]], m[i]);
+            }
+            front_next[dst[i]] = 1;
+            pos++;
+        }
+    }
+}
+
 template <bool WEIGHTED>
 __device__ __forceinline__ void push_body(const uint4 *__restrict__ list, const uint32_t *__restrict__ tile_start,
                                           const void *__restrict__ adj, uint32_t *__restrict__ val,
@@ -333,8 +389,9 @@ __device__ __forceinline__ void push_body(const uint4 *__restrict__ list, const 
         // A candidate below a value read during this superstep is below the
         // destination's start-of-superstep value (values only fall), so the
         // destination changes in this superstep whichever atomic lands last:
-        // mark it with idempotent plain stores and let the atomic go without
-        // waiting for its result.
+        // mark it with an idempotent plain store and let the atomic go
+        // without waiting for its result.  (Destinations here are written
+        // from every XCD, so the merge stays an atomic minimum.)
 #pragma unroll
         for (int i = 0; i < PUSH_VT; i++) {
             if (cand[i] < cur[i]) {
@@ -366,7 +423,7 @@ __device__ __forceinline__ void pull_body(const uint2 *__restrict__ rec, const u
                                           const PullSlices &sl, int64_t V, const uint32_t *__restrict__ snap,
                                           const uint8_t *__restrict__ front_cur, uint32_t *__restrict__ val,
                                           uint8_t *__restrict__ front_next, DevStep *__restrict__ step,
-                                          uint32_t *__restrict__ s_snap) {
+                                          uint32_t *__restrict__ s_snap, const FixRegion &fr) {
     const int tid = threadIdx.x;
     if (blockIdx.x == 0 && tid == 0) step->pad = 1;
     const __amdgpu_buffer_rsrc_t vrs = __builtin_amdgcn_make_buffer_rsrc(val, (short)0, (int)(uint32_t)(V * 4), 0x00020000);
@@ -396,7 +453,12 @@ __device__ __forceinline__ void pull_body(const uint2 *__restrict__ rec, const u
             for (int i = tid; i < PULL_BAND; i += 256) s_snap[i] = bb + i < V && front_cur[bb + i] ? snap[bb + i] : INF;
         }
         __syncthreads();
-        for (uint32_t e0 = start + (uint32_t)tid * PULL_VT; e0 < start + cnt; e0 += 256 * PULL_VT) {
+        // every lane runs every chunk (the hits' reservation is a wave-wide
+        // scan); lanes past the unit's end load its first group and offer nothing
+        for (uint32_t c0 = start; c0 < start + cnt; c0 += 256 * PULL_VT) {
+            const uint32_t ex = c0 + (uint32_t)tid * PULL_VT;
+            const bool live = ex < start + cnt;
+            const uint32_t e0 = live ? ex : start;
             uint32_t dst[PULL_VT], src[PULL_VT], m[PULL_VT], cur[PULL_VT];
             const uint4 *r4 = reinterpret_cast<const uint4 *>(rec + e0);  // units are whole groups of PULL_VT
 #pragma unroll
@@ -412,7 +474,7 @@ __device__ __forceinline__ void pull_body(const uint2 *__restrict__ rec, const u
                 const uint32_t u = WEIGHTED ? (src[i] >> 8) : src[i];
                 const uint32_t sv = s_snap[(u - bb) & (PULL_BAND - 1)];
                 m[i] = WEIGHTED ? sat_add(sv, src[i] & 0xFFu) : sv;
-                if (dst[i] == PULL_SENTINEL) m[i] = INF;
+                if (dst[i] == PULL_SENTINEL || !live) m[i] = INF;
             }
             // Minimum of each run of equal destination, kept at the run's
             // last record; then one batched read of those destinations (only
@@ -428,13 +490,10 @@ __device__ __forceinline__ void pull_body(const uint2 *__restrict__ rec, const u
             for (int i = 0; i < PULL_VT; i++)
                 cur[i] = __builtin_amdgcn_raw_buffer_load_b32(vrs, m[i] != INF ? dst[i] * 4u : 0x80000000u, 0, 0);
             __builtin_amdgcn_sched_barrier(0);  // every read above is issued before the first compare
+            uint32_t hits = 0;
 #pragma unroll
-            for (int i = 0; i < PULL_VT; i++) {
-                if (m[i] < cur[i]) {
-                    atomicMin(&val[dst[i]], m[i]);
-                    front_next[dst[i]] = 1;
-                }
-            }
+            for (int i = 0; i < PULL_VT; i++) hits |= (uint32_t)(m[i] < cur[i]) << i;
+            apply_hits<PULL_VT>(dst, m, hits, val, front_next, fr);
         }
     }
 }
@@ -457,13 +516,32 @@ __global__ __launch_bounds__(256) void k_relax(const uint4 *__restrict__ list, c
                                                const void *__restrict__ adj, PullArgs pa, int64_t V,
                                                const uint32_t *__restrict__ snap, uint32_t *__restrict__ val,
                                                const uint8_t *__restrict__ front_cur, uint8_t *__restrict__ front_next,
-                                               DevStep *__restrict__ step, uint32_t pull_edges) {
+                                               DevStep *__restrict__ step, uint32_t pull_edges,
+                                               uint2 *__restrict__ fix, uint32_t *__restrict__ fixn, uint32_t fix_cap) {
     __shared__ RelaxLds lds;
+    __shared__ uint32_t s_fixn;
+    if (threadIdx.x == 0) s_fixn = 0;
+    __syncthreads();
+    const FixRegion fr{fix + (size_t)blockIdx.x * fix_cap, fix_cap, &s_fixn};
     const unsigned long long le = step->list;
     if ((uint32_t)le >= pull_edges)
-        pull_body<WEIGHTED>(pa.rec, pa.units, pa.sl, V, snap, front_cur, val, front_next, step, lds.pull_snap);
+        pull_body<WEIGHTED>(pa.rec, pa.units, pa.sl, V, snap, front_cur, val, front_next, step, lds.pull_snap, fr);
     else
         push_body<WEIGHTED>(list, tile_start, adj, val, front_next, le, lds.push);
+    __syncthreads();
+    if (threadIdx.x == 0) fixn[blockIdx.x] = min(s_fixn, fix_cap);
+}
+
+// The relaxation's fix-up: workgroup b re-applies the recorded candidates of
+// relaxation workgroup b that are still below the stored value.
+__global__ __launch_bounds__(256) void k_fixup(const uint2 *__restrict__ fix, const uint32_t *__restrict__ fixn,
+                                               uint32_t fix_cap, uint32_t *__restrict__ val) {
+    const uint32_t n = fixn[blockIdx.x];
+    const uint2 *e = fix + (size_t)blockIdx.x * fix_cap;
+    for (uint32_t i = threadIdx.x; i < n; i += 256) {
+        const uint2 q = e[i];
+        if (q.y < val[q.x]) atomicMin(&val[q.x], q.y);
+    }
 }
 
 // ------------------------------------------------------------ PageRank
@@ -836,6 +914,34 @@ static int persistent_grid(gx_graph *g, K kernel, int block) {
     return g->num_cus * occupancy_per_cu(reinterpret_cast<const void *>(kernel), block);
 }
 
+// Persistent grid of the relaxation: whole multiples of the slice count (a
+// pulling workgroup b sweeps slice b mod PULL_SLICES).
+static int relax_grid_for(gx_graph *g, const gx_params *p) {
+    const int pg = p->algo == GX_CC ? persistent_grid(g, k_relax<false>, 256) : persistent_grid(g, k_relax<true>, 256);
+    return std::max(PULL_SLICES, pg / PULL_SLICES * PULL_SLICES);
+}
+
+// Fix-up entries per relaxation workgroup: the records of the pull units the
+// workgroup sweeps (workgroup b takes units b/8, b/8 + nper, ... of slice
+// b mod 8), maximised over workgroups, so a region never overflows.
+static uint32_t fix_cap_for(const gx_graph *g, const gx_params *p, int grid) {
+    const DevGraph &d = g->d;
+    const bool cc = p->algo == GX_CC;
+    const bool has_pull = cc ? d.pull_sym != nullptr : d.pull_w != nullptr;
+    if (!has_pull) return 0;
+    const PullSlices &sl = cc ? d.pull_sym_off : d.pull_w_off;
+    const std::vector<uint32_t> &recs = cc ? g->pull_sym_recs : g->pull_w_recs;
+    const int64_t nper = grid / PULL_SLICES;
+    uint64_t bound = 0;
+    for (int x = 0; x < PULL_SLICES; x++)
+        for (int64_t j = 0; j < nper; j++) {
+            uint64_t sum = 0;
+            for (int64_t u = sl.uoff[x] + j; u < sl.uoff[x + 1]; u += nper) sum += recs[(size_t)u];
+            bound = std::max(bound, sum);
+        }
+    return (uint32_t)bound;
+}
+
 static size_t state_layout(gx_graph *g, const gx_params *p, Carver &c, gx_state *s) {
     const DevGraph &d = g->d;
     int64_t V = d.V;
@@ -863,6 +969,10 @@ static size_t state_layout(gx_graph *g, const gx_params *p, Carver &c, gx_state 
         s->list = c.take<uint4>(V);
         s->tile_start = c.take<uint32_t>(Eimg / PUSH_TILE + 2);
         s->snap = c.take<uint32_t>(V);
+        s->relax_grid = relax_grid_for(g, p);
+        s->fix_cap = fix_cap_for(g, p, s->relax_grid);
+        s->fix = c.take<uint2>((size_t)s->relax_grid * s->fix_cap);
+        s->fixn = c.take<uint32_t>(s->relax_grid);
     }
     s->steps = c.take<DevStep>(STEP_RING);
     s->delta_blocks = (int)grid_for<int64_t>(W, 256);
@@ -922,10 +1032,6 @@ extern "C" gx_status gx_state_init(gx_graph *g, const gx_params *p, void *dev_st
     s->p = *p;
     Carver c(dev_state, bytes);
     state_layout(g, p, c, s);
-    // whole multiples of the slice count (a pulling workgroup b sweeps slice b mod PULL_SLICES)
-    s->relax_grid = std::max(PULL_SLICES, (p->algo == GX_CC ? persistent_grid(g, k_relax<false>, 256)
-                                                            : persistent_grid(g, k_relax<true>, 256)) /
-                                              PULL_SLICES * PULL_SLICES);
     if (p->algo != GX_PAGERANK) {
         const DevGraph &dg = g->d;
         // (the pull addresses values through a 32-bit buffer range)
@@ -1092,13 +1198,14 @@ static gx_status enqueue_superstep(gx_state *s, hipStream_t hs) {
                 const PullArgs pa{d.pull_w, d.pull_w_units, d.pull_w_off};
                 hipLaunchKernelGGL(k_relax<true>, dim3(s->relax_grid), dim3(256), 0, hs, s->list, s->tile_start,
                                    (const void *)d.out_adj, pa, d.V, s->snap, s->val, s->front8[cur], s->front8[cur ^ 1],
-                                   step, s->pull_edges);
+                                   step, s->pull_edges, s->fix, s->fixn, s->fix_cap);
             } else {
                 const PullArgs pa{d.pull_sym, d.pull_sym_units, d.pull_sym_off};
                 hipLaunchKernelGGL(k_relax<false>, dim3(s->relax_grid), dim3(256), 0, hs, s->list, s->tile_start,
                                    (const void *)d.sym_col, pa, d.V, s->snap, s->val, s->front8[cur], s->front8[cur ^ 1],
-                                   step, s->pull_edges);
+                                   step, s->pull_edges, s->fix, s->fixn, s->fix_cap);
             }
+            hipLaunchKernelGGL(k_fixup, dim3(s->relax_grid), dim3(256), 0, hs, s->fix, s->fixn, s->fix_cap, s->val);
             if (e1) (void)hipEventRecord(e1, hs);
             hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(d.V, CBLOCK * CVT)), dim3(CBLOCK), 0, hs,
                                s->front8[cur ^ 1], s->front8[cur], rp, s->val, s->snap, d.V, s->list, s->tile_start,
