@@ -164,6 +164,47 @@ def test_sssp_pull_large_distances(gx, mode):
     assert np.array_equal(steps[:, 2], ref.changed)
 
 
+@pytest.mark.parametrize("mode", [1e-9, 0.0])
+def test_sssp_pull_racing_stores_on_hubs(gx, mode):
+    # Three hubs each receive an in-edge from every vertex: their records
+    # spread over ~49 source bands, so many pull work units store candidates
+    # for one hub at once; the fix-up pass must leave the minimum.  Weights
+    # are chosen so the best candidate is rare and arrives in the same
+    # superstep as many worse ones.
+    V = 200_000
+    rng = np.random.default_rng(23)
+    hubs = np.array([7, 100_003, 199_998])
+    src, dst, w = [], [], []
+    for h in hubs:
+        s_ = np.arange(V)
+        s_ = s_[s_ != h]
+        src.append(s_)
+        dst.append(np.full(len(s_), h))
+        w.append(rng.integers(1, 256, len(s_)))
+    # a random sparse layer so the sources get distinct distances
+    rs = rng.integers(0, V, 4 * V)
+    rd = rng.integers(0, V, 4 * V)
+    src.append(rs); dst.append(rd); w.append(rng.integers(1, 256, 4 * V))
+    g = gen.from_edges(V, np.concatenate(src), np.concatenate(dst), np.concatenate(w))
+    check_sssp_stepwise(gx, g, 0, mode)
+
+
+def test_cc_pull_racing_stores_on_hubs(gx):
+    V = 150_000
+    rng = np.random.default_rng(29)
+    hub = 120_000
+    s_ = np.arange(V)
+    s_ = s_[s_ != hub]
+    src = np.r_[s_, rng.integers(0, V, V)]
+    dst = np.r_[np.full(len(s_), hub), rng.integers(0, V, V)]
+    g = gen.from_edges(V, src, dst)
+    ref = oracle.cc(g)
+    st = gx.State(load(gx, g, gx.GX_NEED_SYM), gx.GX_CC, pull_fraction=1e-9)
+    rs, _ = st.run(10_000)
+    assert rs.supersteps == ref.K
+    assert np.array_equal(st.values_numpy(), ref.state)
+
+
 def test_sssp_edge_cases(gx):
     g = gen.from_edges(1, [], [])
     st = gx.State(load(gx, g, gx.GX_NEED_OUT), gx.GX_SSSP, source=0)
