@@ -355,19 +355,29 @@ def bench_partition(gx, torch, np, gen, reps=3):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     cc_edges = 0
+    t_solve = t_sync = 0.0
     for _ in range(reps):
+        t1 = time.perf_counter()
         cc.reset()
         rs_cc, steps = cc.run(100_000, per_step=True, detail=True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
         cc_edges += rs_cc.edges
-        gids, vals, skip = cc.sync_delta()
-    torch.cuda.synchronize()
+        gids, vals, skip = cc.sync_delta(on_device=True)  # the sync set stays in HBM
+        torch.cuda.synchronize()
+        t_solve += t2 - t1
+        t_sync += time.perf_counter() - t2
     t_cc = (time.perf_counter() - t0) / reps
+    log(f"partition CC: solve {t_solve / reps * 1e3:.2f} ms (kernels {sum(d['kernel_ms'] for d in steps):.2f} ms), "
+        f"sync set {t_sync / reps * 1e3:.2f} ms; PageRank {t_pr * 1e3:.2f} ms")
     return {"workload": f"part 0 of an 8-way hash vertex-cut of R-MAT scale 25 (seed 3): V_p={p.V}, E_p={p.E}; "
                         "PageRank 30 supersteps + min-label CC to convergence + final sync set",
             "pagerank_ms": t_pr * 1e3, "pagerank_gteps": 30 * p.E / t_pr / 1e9,
             "pagerank_pull_roofline_frac": pr_bytes / (kern / reps / 1e3) / 1e9 / HBM_PEAK_GBS,
-            "cc_ms": t_cc * 1e3, "cc_supersteps": int(rs_cc.supersteps), "cc_gteps": cc_edges / reps / t_cc / 1e9,
-            "sync_set_final": int(len(gids)),
+            "cc_ms": t_cc * 1e3, "cc_solve_ms": t_solve / reps * 1e3, "cc_sync_set_ms": t_sync / reps * 1e3,
+            "cc_supersteps": int(rs_cc.supersteps), "cc_gteps": cc_edges / reps / t_cc / 1e9,
+            "cc_kernel_ms": sum(d["kernel_ms"] for d in steps),
+            "sync_set_final": int(gids.numel()),
             "cc_per_superstep": [dict(edges=d["edges"], pulled=d["pulled"], us=round(d["kernel_ms"] * 1e3, 1))
                                  for d in steps]}
 
