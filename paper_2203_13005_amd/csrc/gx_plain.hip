@@ -38,10 +38,11 @@
 //   k_pr_pull : equal in-edge tiles; contributions are gathered into LDS and
 //               summed per destination row in a fixed order; rows that
 //               cross a tile boundary leave fixed partials.
-//   k_pr_fix  : one workgroup completes the crossing rows in tile order and
-//               reduces the dangling mass for the next superstep in a fixed
-//               order.  No floating-point atomics: results are bitwise
-//               reproducible.
+//   k_pr_fix  : completes the crossing rows (each by one thread, in tile
+//               order) and reduces the dangling mass for the next superstep:
+//               per-workgroup partials, then the last workgroup to finish
+//               sums them in workgroup order.  No floating-point atomics:
+//               results are bitwise reproducible.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -78,6 +79,10 @@ struct gx_state {
     double *dpart = nullptr;
     uint32_t *cpart = nullptr;   // per-tile changed counts (PageRank)
     double *Dval = nullptr;
+    int pr_fix_grid = 1;              // workgroups of k_pr_fix
+    double *fix_d = nullptr;          // their dangling-mass partials
+    unsigned long long *fix_c = nullptr;  // and changed counts
+    uint32_t *fix_done = nullptr;     // workgroups finished (the last resets it)
     // shared
     DevStep *steps = nullptr;
     uint32_t *blk_cnt = nullptr;
@@ -736,24 +741,33 @@ __global__ __launch_bounds__(PR_BLOCK) void k_pr_pull(const int32_t *__restrict_
     }
 }
 
-// Completes the rows that cross tile boundaries (in tile order) and reduces
-// the dangling mass of the new ranks for the next superstep in a fixed
-// order.  One workgroup; the kernel boundary makes every pull workgroup's
-// partials visible to it.
-__global__ __launch_bounds__(1024) void k_pr_fix(const int32_t *__restrict__ in_rp, int32_t ntiles, int32_t tile,
-                                                 const double *__restrict__ head, const double *__restrict__ tailp,
-                                                 const int32_t *__restrict__ spill_row,
-                                                 const double *__restrict__ dpart,
-                                                 const uint32_t *__restrict__ cpart, PrApply ap, double *Dp,
-                                                 double inv_V, DevStep *__restrict__ step,
-                                                 DevStep *__restrict__ next_step) {
-    __shared__ double s_d[16];
-    __shared__ unsigned long long s_c[16];
+// Completes the rows that cross tile boundaries (each by one thread, adding
+// the row's partials in tile order) and reduces the dangling mass of the new
+// ranks for the next superstep: every workgroup leaves its partial sums, and
+// the last one to finish adds them up in workgroup order, so the result does
+// not depend on timing.  The kernel boundary makes every pull workgroup's
+// partials visible here; *Dp (the old mass) is read by every workgroup
+// before the last one overwrites it.
+constexpr int PR_FIX_BLOCK = 256;
+constexpr int PR_FIX_MAX_GRID = 1024;
+
+__global__ __launch_bounds__(PR_FIX_BLOCK) void k_pr_fix(const int32_t *__restrict__ in_rp, int32_t ntiles,
+                                                         int32_t tile, const double *__restrict__ head,
+                                                         const double *__restrict__ tailp,
+                                                         const int32_t *__restrict__ spill_row,
+                                                         const double *__restrict__ dpart,
+                                                         const uint32_t *__restrict__ cpart, PrApply ap, double *Dp,
+                                                         double inv_V, DevStep *__restrict__ step,
+                                                         DevStep *__restrict__ next_step, double *fix_d,
+                                                         unsigned long long *fix_c, uint32_t *fix_done) {
+    __shared__ double s_d[PR_FIX_BLOCK / 64];
+    __shared__ unsigned long long s_c[PR_FIX_BLOCK / 64];
+    __shared__ int s_last;
     ap.dD = ap.d * (*Dp) * inv_V;
     double dsum = 0.0;
     int chg = 0;
     unsigned long long csum = 0;
-    for (int32_t t = threadIdx.x; t < ntiles; t += blockDim.x) {
+    for (int32_t t = blockIdx.x * PR_FIX_BLOCK + threadIdx.x; t < ntiles; t += gridDim.x * PR_FIX_BLOCK) {
         const int32_t r = spill_row[t];
         if (r >= 0) {
             double total = tailp[t];
@@ -764,14 +778,32 @@ __global__ __launch_bounds__(1024) void k_pr_fix(const int32_t *__restrict__ in_
         dsum += dpart[t];
         csum += cpart[t];
     }
-    __syncthreads();
     const double td = block_sum<double>(dsum, s_d);
     const unsigned long long tc = block_sum<unsigned long long>(csum + (unsigned long long)chg, s_c);
     if (threadIdx.x == 0) {
-        *Dp = td;  // dangling mass of x_{t+1}
-        step->changed = tc;
+        fix_d[blockIdx.x] = td;
+        fix_c[blockIdx.x] = tc;
+        // release this workgroup's partials; acquire the others' if last
+        const uint32_t before = __hip_atomic_fetch_add(fix_done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = before == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    double d = 0.0;
+    unsigned long long c = 0;
+    for (uint32_t b = threadIdx.x; b < gridDim.x; b += PR_FIX_BLOCK) {
+        d += fix_d[b];
+        c += fix_c[b];
+    }
+    const double D = block_sum<double>(d, s_d);
+    const unsigned long long C = block_sum<unsigned long long>(c, s_c);
+    if (threadIdx.x == 0) {
+        *Dp = D;  // dangling mass of x_{t+1}
+        step->changed = C;
         step->frontier = 0;
         *next_step = DevStep{};
+        *fix_done = 0;  // for the next superstep (after this kernel ends)
     }
 }
 
@@ -959,6 +991,10 @@ static size_t state_layout(gx_graph *g, const gx_params *p, Carver &c, gx_state 
         s->dpart = c.take<double>(std::max<int64_t>(nt, grid_for<int64_t>(V, 256)));
         s->cpart = c.take<uint32_t>(std::max<int64_t>(nt, 1));
         s->Dval = c.take<double>(1);
+        s->pr_fix_grid = (int)std::min<int64_t>(PR_FIX_MAX_GRID, std::max<int64_t>(1, (nt + PR_FIX_BLOCK - 1) / PR_FIX_BLOCK));
+        s->fix_d = c.take<double>(s->pr_fix_grid);
+        s->fix_c = c.take<unsigned long long>(s->pr_fix_grid);
+        s->fix_done = c.take<uint32_t>(1);
     } else {
         int64_t Eimg = p->algo == GX_SSSP ? d.E : d.E_sym;
         s->val = c.take<uint32_t>(V);
@@ -1050,6 +1086,7 @@ extern "C" gx_status gx_state_init(gx_graph *g, const gx_params *p, void *dev_st
         hipLaunchKernelGGL(k_pr_init, dim3(nb), dim3(256), 0, hs, s->x[0], s->contrib[0], s->synced, d.outdeg, V, x0,
                            s->dpart, s->steps);
         hipLaunchKernelGGL(k_reduce_D, dim3(1), dim3(1024), 0, hs, s->dpart, (int)nb, s->Dval);
+        (void)hipMemsetAsync(s->fix_done, 0, sizeof(uint32_t), hs);
     } else {
         int64_t n = std::max<int64_t>(V, d.W);
         const int32_t *rp = p->algo == GX_CC ? d.sym_rp : d.out_rp;
@@ -1185,8 +1222,9 @@ static gx_status enqueue_superstep(gx_state *s, hipStream_t hs) {
                                d.E, s->contrib[cur], ap, s->Dval, inv_V, s->head, s->tailp, s->spill_row, s->dpart,
                                s->cpart);
             if (e1) (void)hipEventRecord(e1, hs);
-            hipLaunchKernelGGL(k_pr_fix, dim3(1), dim3(1024), 0, hs, d.in_rp, d.pr_ntiles, d.pr_tile, s->head,
-                               s->tailp, s->spill_row, s->dpart, s->cpart, ap, s->Dval, inv_V, step, next);
+            hipLaunchKernelGGL(k_pr_fix, dim3(s->pr_fix_grid), dim3(PR_FIX_BLOCK), 0, hs, d.in_rp, d.pr_ntiles,
+                               d.pr_tile, s->head, s->tailp, s->spill_row, s->dpart, s->cpart, ap, s->Dval, inv_V,
+                               step, next, s->fix_d, s->fix_c, s->fix_done);
         }
     } else {
         // superstep k: relax A_k (list built by the previous compaction), then

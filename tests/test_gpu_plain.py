@@ -331,6 +331,23 @@ def test_pagerank_edge_cases(gx, tile):
     check_pr(gx, g, 12, tile=tile)
 
 
+def test_pagerank_fix_over_many_workgroups(gx):
+    # 256-edge tiles: thousands of tiles, so the crossing rows are completed
+    # by many fix-up workgroups (256 tiles each); the hub's row starts in the
+    # first workgroup's range and ends in the second's, and a second hub
+    # crosses the next boundary; results stay bitwise reproducible
+    V = 200_000
+    rng = np.random.default_rng(11)
+    src = np.r_[rng.integers(0, V, 600_000), np.arange(2, 70_002), np.arange(3, 30_003)]
+    dst = np.r_[rng.integers(0, V, 600_000), np.full(70_000, 40), np.full(30_000, 150_000)]
+    g = gen.from_edges(V, src, dst)
+    st, x, ref = check_pr(gx, g, 12, tile=256)
+    st2, x2, _ = check_pr(gx, g, 12, tile=256)
+    assert np.array_equal(x.view(np.uint64), x2.view(np.uint64))
+    g = gen.rmat(16, seed=6)
+    check_pr(gx, g, 10, tile=256)
+
+
 @pytest.mark.parametrize("tile", [0, 2048])
 def test_pagerank_deterministic_and_checkpoint(gx, tile):
     g = gen.rmat(15, seed=4)
