@@ -284,13 +284,21 @@ class State:
             steps = [(ps[i].as_dict() if detail else ps[i].as_tuple()) for i in range(rs.supersteps)]
         return rs, steps
 
-    def sync_delta(self, cap: int | None = None, stream=None, on_device: bool = False):
+    def sync_delta(self, cap: int | None = None, stream=None, on_device: bool = False, out=None):
         """Returns (gids int32, value bits uint32, skippable) as numpy arrays, or
-        as device tensors (int32 bit patterns) with on_device=True."""
+        as device tensors (int32 bit patterns) with on_device=True.  `out`
+        optionally supplies the two int32 device buffers (at least `cap`
+        elements each) instead of allocating them per call."""
         import torch
         cap = self.graph.V if cap is None else int(cap)
-        gid = torch.empty(max(cap, 1), dtype=torch.int32, device=self.graph.device)
-        val = torch.empty(max(cap, 1), dtype=torch.int32, device=self.graph.device)
+        if out is not None:
+            gid, val = out
+            if (gid.dtype != torch.int32 or val.dtype != torch.int32 or gid.numel() < cap or val.numel() < cap
+                    or not gid.is_contiguous() or not val.is_contiguous()):
+                raise ValueError("out must be two contiguous int32 device tensors of at least cap elements")
+        else:
+            gid = torch.empty(max(cap, 1), dtype=torch.int32, device=self.graph.device)
+            val = torch.empty(max(cap, 1), dtype=torch.int32, device=self.graph.device)
         n = ctypes.c_uint32()
         sk = ctypes.c_int32()
         _check(lib.gx_sync_delta(self.handle, ctypes.c_void_p(gid.data_ptr()), ctypes.c_void_p(val.data_ptr()),
