@@ -229,6 +229,52 @@ def test_sssp_edge_cases(gx):
     assert st.values_numpy().tolist() == list(range(V))
 
 
+@pytest.mark.parametrize("mode", MODES)
+def test_sssp_wide_weights_push_only(gx, mode):
+    # weights beyond 8 bits: the banded pull records cannot hold them, so
+    # every superstep pushes whatever the switch point asks for; sums that
+    # overflow 32 bits saturate at INF (unreachable) on both sides
+    V, E = 5000, 30000
+    rng = np.random.default_rng(21)
+    src = np.r_[rng.integers(0, V, E), np.arange(100)]
+    dst = np.r_[rng.integers(0, V, E), np.arange(1, 101)]
+    w = np.r_[rng.integers(1, 1 << 31, E), np.full(100, 0x7FFFFFF0)]
+    g = gen.from_edges(V, src, dst, w)
+    st = check_sssp_stepwise(gx, g, 0, pull_fraction=mode)
+    ref = oracle.sssp(g, 0)
+    d = st.values_numpy()
+    assert np.array_equal(d, ref.state)
+    assert (d == gx.INF).sum() > 0 and d[d != gx.INF].max() > 1 << 31
+    st = gx.State(load(gx, g, gx.GX_NEED_OUT), gx.GX_SSSP, source=0, pull_fraction=mode)
+    rs, steps = st.run(10_000, per_step=True, detail=True)
+    assert rs.supersteps == ref.K and not any(x["pulled"] for x in steps)
+    assert np.array_equal(st.values_numpy(), ref.state)
+
+
+def test_vertex_ids_beyond_24_bits(gx):
+    # V > 2^24: SSSP cannot use the banded pull records (a source id and a
+    # weight share 32 bits there) and pushes every superstep; CC still pulls,
+    # with destination ids and bands above 2^24
+    V = (1 << 24) + 37
+    rng = np.random.default_rng(5)
+    hi = rng.integers(V - 3000, V, 20000)
+    src = np.r_[rng.integers(0, V, 150_000), hi, np.zeros(2000, int)]
+    dst = np.r_[rng.integers(0, V, 150_000), rng.permutation(hi), rng.integers(V - 3000, V, 2000)]
+    g = gen.from_edges(V, src, dst, rng.integers(1, 256, len(src)))
+    dg = load(gx, g, gx.GX_NEED_OUT | gx.GX_NEED_SYM)
+    ref = oracle.sssp(g, 0)
+    st = gx.State(dg, gx.GX_SSSP, source=0, pull_fraction=1e-9)
+    rs, steps = st.run(10_000, per_step=True, detail=True)
+    assert rs.supersteps == ref.K and not any(x["pulled"] for x in steps)
+    assert np.array_equal(st.values_numpy(), ref.state)
+    del st
+    ref = oracle.cc(g)
+    st = gx.State(dg, gx.GX_CC, pull_fraction=1e-9)
+    rs, steps = st.run(10_000, per_step=True, detail=True)
+    assert rs.supersteps == ref.K and any(x["pulled"] for x in steps)
+    assert np.array_equal(st.values_numpy(), ref.state)
+
+
 def test_sssp_deterministic_rerun(gx):
     g = gen.rmat(16, seed=9)
     dg = load(gx, g, gx.GX_NEED_OUT)
