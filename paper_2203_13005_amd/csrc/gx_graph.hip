@@ -194,9 +194,11 @@ static void build_tiles(const std::vector<int32_t> &rp, std::vector<int32_t> &ti
 // PULL_BIN_BYTES, and an XCD sweeps its S bins one after another.  Within a
 // bin the records are grouped by source band, keeping the (destination,
 // source) order of the CSR inside a group; every group is padded to whole
-// PULL_VT records with sentinels (destination PULL_SENTINEL, source the band
-// base) and cut into units of at most PULL_UNIT records.  `w` may be null
-// (records {dst, src}).
+// PULL_VT records with sentinels (destination PULL_SENTINEL) and cut into
+// units of at most PULL_UNIT records.  Weighted records are
+// {dst, (src mod PULL_BAND) << 8 | w}: the unit names the band, so a source
+// takes 12 bits and any vertex count fits; with `w` null they are {dst, src}
+// (sentinel source: the band base).
 static void build_pull(const std::vector<int32_t> &rp, const int32_t *src, const uint32_t *w,
                        std::vector<uint2> &out, std::vector<uint4> &units, PullSlices &sl) {
     const int64_t V = (int64_t)rp.size() - 1;
@@ -240,15 +242,16 @@ static void build_pull(const std::vector<int32_t> &rp, const int32_t *src, const
     std::vector<int64_t> pos((size_t)ng + 1, 0);
     for (int64_t g = 0; g < ng; g++) pos[g + 1] = pos[g] + (cnt[g] + PULL_VT - 1) / PULL_VT * PULL_VT;
     out.assign((size_t)pos[ng], make_uint2(PULL_SENTINEL, 0u));
-    for (int64_t g = 0; g < ng; g++) {  // sentinels carry their band's base as the source
+    for (int64_t g = 0; g < ng; g++) {  // sentinels: a source inside their band, weight 0
         const uint32_t bb = (uint32_t)((g % nb) << PULL_BAND_BITS);
-        for (int64_t i = pos[g] + cnt[g]; i < pos[g + 1]; i++) out[i].y = w ? (bb << 8) : bb;
+        for (int64_t i = pos[g] + cnt[g]; i < pos[g + 1]; i++) out[i].y = w ? 0u : bb;
     }
     std::vector<int64_t> fill(pos.begin(), pos.end() - 1);
     per_slice([&](int64_t v, int64_t g0) {
         for (int32_t e = rp[v]; e < rp[v + 1]; e++) {
             const uint32_t u = (uint32_t)src[e];
-            out[fill[g0 + (u >> PULL_BAND_BITS)]++] = make_uint2((uint32_t)v, w ? ((u << 8) | w[e]) : u);
+            out[fill[g0 + (u >> PULL_BAND_BITS)]++] =
+                make_uint2((uint32_t)v, w ? (((u & (PULL_BAND - 1)) << 8) | w[e]) : u);
         }
     });
     units.clear();
@@ -263,7 +266,6 @@ static void build_pull(const std::vector<int32_t> &rp, const int32_t *src, const
 }
 
 static bool banded_weights_fit(const gx_graph_desc *d) {
-    if (d->V >= (int64_t(1) << 24)) return false;
     std::atomic<bool> ok{true};
     parallel_for(d->E, [&](int64_t lo, int64_t hi) {
         for (int64_t e = lo; e < hi; e++)

@@ -106,9 +106,9 @@ struct DevGraph {
     int32_t pr_tile = PR_TILE_MAX;  // in-edges per PageRank tile
     int32_t pr_ntiles = 0;
     const int32_t *pr_tile_row = nullptr;  // [pr_ntiles + 1]
-    // sliced, banded in-edge records for the SSSP pull: {dst, (src << 8) | w}
-    // (padded to whole PULL_VT groups); null when V >= 2^24 or a weight
-    // exceeds 255 (the engine then only pushes)
+    // sliced, banded in-edge records for the SSSP pull:
+    // {dst, (src mod PULL_BAND) << 8 | w} (padded to whole PULL_VT groups);
+    // null when a weight exceeds 255 (the engine then only pushes)
     const uint2 *pull_w = nullptr;
     const uint4 *pull_w_units = nullptr;  // {first record, records, band base, 0}
     PullSlices pull_w_off{};

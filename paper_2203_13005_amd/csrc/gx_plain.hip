@@ -409,7 +409,7 @@ __device__ __forceinline__ void push_body(const uint4 *__restrict__ list, const 
 }
 
 // Pull form of the same superstep, for large frontiers.  The in-edges are
-// stored as records {dst, (src << 8) | w} (CC: {dst, src}) in work units of
+// stored as records {dst, (src mod PULL_BAND) << 8 | w} (CC: {dst, src}) in work units of
 // one destination slice and one band of PULL_BAND sources (layout built at
 // load).  Workgroup b takes the units of slice b mod PULL_SLICES in order;
 // since workgroups are dealt round-robin to the XCDs, each XCD's L2 holds
@@ -476,8 +476,7 @@ __device__ __forceinline__ void pull_body(const uint2 *__restrict__ rec, const u
             }
 #pragma unroll
             for (int i = 0; i < PULL_VT; i++) {
-                const uint32_t u = WEIGHTED ? (src[i] >> 8) : src[i];
-                const uint32_t sv = s_snap[(u - bb) & (PULL_BAND - 1)];
+                const uint32_t sv = s_snap[(WEIGHTED ? (src[i] >> 8) : (src[i] - bb)) & (PULL_BAND - 1)];
                 m[i] = WEIGHTED ? sat_add(sv, src[i] & 0xFFu) : sv;
                 if (dst[i] == PULL_SENTINEL || !live) m[i] = INF;
             }

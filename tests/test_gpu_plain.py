@@ -252,9 +252,9 @@ def test_sssp_wide_weights_push_only(gx, mode):
 
 
 def test_vertex_ids_beyond_24_bits(gx):
-    # V > 2^24: SSSP cannot use the banded pull records (a source id and a
-    # weight share 32 bits there) and pushes every superstep; CC still pulls,
-    # with destination ids and bands above 2^24
+    # V > 2^24: destination ids and source bands above 2^24 in the pull
+    # records of both SSSP (sources stored relative to their band next to an
+    # 8-bit weight) and CC, checked superstep by superstep for SSSP
     V = (1 << 24) + 37
     rng = np.random.default_rng(5)
     hi = rng.integers(V - 3000, V, 20000)
@@ -265,9 +265,10 @@ def test_vertex_ids_beyond_24_bits(gx):
     ref = oracle.sssp(g, 0)
     st = gx.State(dg, gx.GX_SSSP, source=0, pull_fraction=1e-9)
     rs, steps = st.run(10_000, per_step=True, detail=True)
-    assert rs.supersteps == ref.K and not any(x["pulled"] for x in steps)
+    assert rs.supersteps == ref.K and all(x["pulled"] for x in steps if x["edges"] > 0)
     assert np.array_equal(st.values_numpy(), ref.state)
     del st
+    check_sssp_stepwise(gx, g, 0, pull_fraction=1e-9)
     ref = oracle.cc(g)
     st = gx.State(dg, gx.GX_CC, pull_fraction=1e-9)
     rs, steps = st.run(10_000, per_step=True, detail=True)
