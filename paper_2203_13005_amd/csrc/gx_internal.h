@@ -74,7 +74,7 @@ constexpr int PR_TILE_MAX = PR_BLOCK * 8;
 constexpr int PULL_SLICES = 8;
 constexpr int PULL_SLICE_SHIFT = 6;
 constexpr int64_t PULL_BIN_BYTES = int64_t(2) << 20;  // destination values an XCD sweeps at a time
-constexpr int PULL_BAND_BITS = 12;
+constexpr int PULL_BAND_BITS = 13;  // 8192 sources: 32 KB of snapshots in LDS
 constexpr int PULL_BAND = 1 << PULL_BAND_BITS;
 constexpr int PULL_VT = 8;       // records per thread and group padding
 constexpr int PULL_UNIT = 8192;  // records per work unit at most (a multiple of PULL_VT)

@@ -409,20 +409,23 @@ __device__ __forceinline__ void push_body(const uint4 *__restrict__ list, const 
 }
 
 // Pull form of the same superstep, for large frontiers.  The in-edges are
-// stored as records {dst, (src mod PULL_BAND) << 8 | w} (CC: {dst, src}) in work units of
-// one destination slice and one band of PULL_BAND sources (layout built at
-// load).  Workgroup b takes the units of slice b mod PULL_SLICES in order;
-// since workgroups are dealt round-robin to the XCDs, each XCD's L2 holds
-// its slice's destination values.  A unit's band of snapshots is staged in
-// LDS, INF where the frontier map A_k says the source is inactive, so a
-// record's gather is an LDS read; the thread folds runs of equal
-// destination in its PULL_VT consecutive records to their minimum and
-// applies each with the filtered atomics of the push.  A record without a
-// candidate (inactive source, padding, or not the end of its run) reads
-// nothing: the destination reads are buffer loads whose offset for such
-// lanes lies past the buffer, which fetches nothing and returns 0.  Runs only
-// when the frontier's out-edges reach pull_edges (V * 4 must fit the 32-bit
-// buffer range; the host enables the pull only then).
+// stored as records {dst, (src mod PULL_BAND) << 8 | w} (CC: {dst, src}) in
+// work units of one destination slice and one band of PULL_BAND sources
+// (layout built at load).  Workgroup b takes the units of slice b mod
+// PULL_SLICES in order; since workgroups are dealt round-robin to the XCDs,
+// each XCD's L2 holds its slice's destination values.  A unit's band of
+// snapshots is staged in LDS, INF where the frontier map A_k says the source
+// is inactive, so a record's gather is an LDS read.  The 64 lanes of a wave
+// take 64 consecutive records (destinations in ascending order), so lanes
+// whose destinations share a cache line make one memory request between
+// them: the destination reads, one per record, are what bounds the pull,
+// and wider bands make consecutive records' destinations denser.  A record
+// without a candidate (inactive source or padding) reads nothing: the
+// destination reads are buffer loads whose offset for such lanes lies past
+// the buffer, which fetches nothing and returns 0.  Lanes holding the same
+// destination each apply their candidate; the fix-up pass leaves the
+// minimum.  Runs only when the frontier's out-edges reach pull_edges (V * 4
+// must fit the 32-bit buffer range; the host enables the pull only then).
 template <bool WEIGHTED>
 __device__ __forceinline__ void pull_body(const uint2 *__restrict__ rec, const uint4 *__restrict__ units,
                                           const PullSlices &sl, int64_t V, const uint32_t *__restrict__ snap,
@@ -459,37 +462,25 @@ __device__ __forceinline__ void pull_body(const uint2 *__restrict__ rec, const u
         }
         __syncthreads();
         // every lane runs every chunk (the hits' reservation is a wave-wide
-        // scan); lanes past the unit's end load its first group and offer nothing
+        // scan); lanes past the unit's end load its first record and offer nothing
         for (uint32_t c0 = start; c0 < start + cnt; c0 += 256 * PULL_VT) {
-            const uint32_t ex = c0 + (uint32_t)tid * PULL_VT;
-            const bool live = ex < start + cnt;
-            const uint32_t e0 = live ? ex : start;
             uint32_t dst[PULL_VT], src[PULL_VT], m[PULL_VT], cur[PULL_VT];
-            const uint4 *r4 = reinterpret_cast<const uint4 *>(rec + e0);  // units are whole groups of PULL_VT
 #pragma unroll
-            for (int i = 0; i < PULL_VT / 2; i++) {
-                const uint4 q = r4[i];
-                dst[2 * i] = q.x;
-                src[2 * i] = q.y;
-                dst[2 * i + 1] = q.z;
-                src[2 * i + 1] = q.w;
+            for (int i = 0; i < PULL_VT; i++) {  // record c0 + 256 i + tid; past the unit: no candidate
+                const uint32_t e = c0 + (uint32_t)i * 256 + (uint32_t)tid;
+                const bool in = e < start + cnt;
+                const uint2 q = rec[in ? e : start];
+                dst[i] = in ? q.x : PULL_SENTINEL;
+                src[i] = q.y;
             }
 #pragma unroll
             for (int i = 0; i < PULL_VT; i++) {
                 const uint32_t sv = s_snap[(WEIGHTED ? (src[i] >> 8) : (src[i] - bb)) & (PULL_BAND - 1)];
                 m[i] = WEIGHTED ? sat_add(sv, src[i] & 0xFFu) : sv;
-                if (dst[i] == PULL_SENTINEL || !live) m[i] = INF;
+                if (dst[i] == PULL_SENTINEL) m[i] = INF;
             }
-            // Minimum of each run of equal destination, kept at the run's
-            // last record; then one batched read of those destinations (only
-            // records with a candidate fetch), then the filtered atomics (no
-            // result awaited, as in the push).
-#pragma unroll
-            for (int i = 1; i < PULL_VT; i++)
-                if (dst[i] == dst[i - 1]) m[i] = min(m[i], m[i - 1]);
-#pragma unroll
-            for (int i = 0; i + 1 < PULL_VT; i++)
-                if (dst[i + 1] == dst[i]) m[i] = INF;
+            // one batched read of the destinations (only records with a
+            // candidate fetch), then the compares and the merge
 #pragma unroll
             for (int i = 0; i < PULL_VT; i++)
                 cur[i] = __builtin_amdgcn_raw_buffer_load_b32(vrs, m[i] != INF ? dst[i] * 4u : 0x80000000u, 0, 0);
