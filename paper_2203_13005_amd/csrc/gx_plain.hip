@@ -18,10 +18,11 @@
 //               compaction carries the marks into the dirty map).
 //   pull      : for large frontiers instead: one streaming sweep over all
 //               in-edge records, grouped by source band so the gathered
-//               snapshots stay cache resident, min per run of equal
-//               destination, the same filtered atomics.  The device picks
-//               push or pull from the frontier's out-edge count; no host
-//               round trip.
+//               snapshots are staged in LDS, 64 consecutive records per
+//               wave; improving candidates are stored plainly and recorded,
+//               and k_fixup re-applies the ones a racing store overwrote.
+//               The device picks push or pull from the frontier's out-edge
+//               count; no host round trip.
 //   k_compact : frontier byte map A_{k+1} -> active list of (edge offset,
 //               CSR base, snapshot) for active vertices with out-edges; one
 //               64-bit atomic per workgroup reserves list slots and edge
