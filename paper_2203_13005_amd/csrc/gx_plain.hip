@@ -164,7 +164,7 @@ __global__ __launch_bounds__(CBLOCK) void k_compact(const uint8_t *__restrict__ 
                                                  uint4 *__restrict__ list, uint32_t *__restrict__ tile_start,
                                                  DevStep *__restrict__ step, DevStep *__restrict__ next_step,
                                                  int snap_all, const DevStep *__restrict__ prev,
-                                                 uint8_t *__restrict__ dirty) {
+                                                 uint8_t *__restrict__ dirty, uint32_t pull_edges) {
     __shared__ unsigned long long s_scan[CBLOCK / 64];
     __shared__ unsigned long long s_base;
     __shared__ int s_nf[CBLOCK / 64];
@@ -258,6 +258,10 @@ __global__ __launch_bounds__(CBLOCK) void k_compact(const uint8_t *__restrict__ 
         for (int w = 0; w < CBLOCK / 64; w++) nfb += s_nf[w];
         atomicAdd(&step->frontier, (unsigned long long)nfb);
     }
+    // The out-edges counted up to this workgroup are a lower bound of the
+    // frontier's: once it reaches pull_edges the next superstep pulls and
+    // never reads the list, so the rest of the workgroups skip writing it.
+    if ((uint32_t)(s_base + total) >= pull_edges) return;
     unsigned long long pos = s_base + pre;
 #pragma unroll
     for (int i = 0; i < CVT; i++) {
@@ -1094,7 +1098,7 @@ extern "C" gx_status gx_state_init(gx_graph *g, const gx_params *p, void *dev_st
         if (V > 0)
             hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(V, CBLOCK * CVT)), dim3(CBLOCK), 0, hs, s->front8[0],
                                s->front8[1], rp, s->val, s->snap, V, s->list, s->tile_start, s->steps,
-                               s->steps + 1, (int)(s->pull_edges != 0xFFFFFFFFu), nullptr, nullptr);
+                               s->steps + 1, (int)(s->pull_edges != 0xFFFFFFFFu), nullptr, nullptr, s->pull_edges);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
@@ -1241,7 +1245,7 @@ static gx_status enqueue_superstep(gx_state *s, hipStream_t hs) {
             if (e1) (void)hipEventRecord(e1, hs);
             hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(d.V, CBLOCK * CVT)), dim3(CBLOCK), 0, hs,
                                s->front8[cur ^ 1], s->front8[cur], rp, s->val, s->snap, d.V, s->list, s->tile_start,
-                               next, next2, (int)(s->pull_edges != 0xFFFFFFFFu), step, s->dirty8);
+                               next, next2, (int)(s->pull_edges != 0xFFFFFFFFu), step, s->dirty8, s->pull_edges);
         }
     }
     hipError_t e = hipGetLastError();
@@ -1462,7 +1466,7 @@ extern "C" gx_status gx_apply_delta(gx_state *s, const int32_t *dev_gid, const u
         const int32_t *rp = s->p.algo == GX_CC ? d.sym_rp : d.out_rp;
         hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(d.V, CBLOCK * CVT)), dim3(CBLOCK), 0, hs, front,
                            s->front8[(s->k & 1) ^ 1], rp, s->val, s->snap, d.V, s->list, s->tile_start, slot, slot2,
-                           (int)(s->pull_edges != 0xFFFFFFFFu), nullptr, nullptr);
+                           (int)(s->pull_edges != 0xFFFFFFFFu), nullptr, nullptr, s->pull_edges);
         GX_CHECK_HIP(hipGetLastError(), s);
     }
     if (active_next) {
