@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cstring>
 #include <string>
@@ -137,6 +138,10 @@ struct gx_graph {
     bool dev_error = false;
     std::vector<int32_t> host_outdeg;  // out-degree (host copy, for sources and stats)
     std::vector<uint32_t> pull_w_recs, pull_sym_recs;  // records of each pull unit (sizes fix-up regions)
+    // supersteps of the last converged SSSP / CC run on this graph: the size
+    // of the next run's first speculative group (solves on one graph tend to
+    // need similar superstep counts)
+    std::atomic<uint32_t> last_supersteps[2] = {0u, 0u};
 };
 
 namespace gx {

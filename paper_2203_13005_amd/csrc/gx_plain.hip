@@ -1367,11 +1367,15 @@ extern "C" gx_status gx_run_until_converged(gx_state *s, uint32_t max_supersteps
         rs.supersteps = max_supersteps;
         rs.converged = 0;
     } else {
-        // Supersteps are enqueued in speculative groups (6, then 8 at a time)
-        // and the host synchronises once per group; supersteps enqueued after
-        // convergence find an empty frontier, change nothing and cost a few
-        // microseconds each, less than a host round trip.
-        uint32_t done = 0, spec = 6;
+        // Supersteps are enqueued in speculative groups and the host
+        // synchronises once per group; supersteps enqueued after convergence
+        // find an empty frontier, change nothing and cost a few microseconds
+        // each, less than a host round trip.  The first group covers the
+        // superstep count of the last converged run on this graph (at least
+        // 6, at most 16), the later ones 8 at a time.
+        const int hist = s->p.algo == GX_CC ? 1 : 0;
+        const uint32_t last = s->g->last_supersteps[hist].load(std::memory_order_relaxed);
+        uint32_t done = 0, spec = std::min<uint32_t>(16, std::max<uint32_t>(6, last + 1));
         bool conv = false;
         while (done < max_supersteps && !conv) {
             uint32_t g = std::min(spec, max_supersteps - done);
@@ -1398,6 +1402,7 @@ extern "C" gx_status gx_run_until_converged(gx_state *s, uint32_t max_supersteps
         }
         rs.supersteps = done;
         rs.converged = conv ? 1 : 0;
+        if (conv && k_begin == 0) s->g->last_supersteps[hist].store(done, std::memory_order_relaxed);
         if (!conv) {
             set_error("not converged after %u supersteps", max_supersteps);
             result = GX_ENOTCONVERGED;
