@@ -5,11 +5,14 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 (``paper_2203_13005_amd``) never imports it and shares no code with it; the
 two meet only in the seeded inputs from ``gen``.
 
-The arithmetic lives in ``oracle.c`` (plain C, single threaded, PageRank in
-float64).  The functions here drive it superstep by superstep and hold the
-independent pins that check it: a dense linear solve for the PageRank fixed
-point and a hop-bounded Bellman-Ford written as whole-array relaxation.
-Each function names the passage of the paper it follows.
+The arithmetic lives in ``oracle.c`` (plain C, PageRank in float64).  Its
+single-threaded functions are the reference; ``threads != 1`` selects the
+OpenMP timing mode, which runs the same supersteps on all host cores and is
+pinned bitwise to the reference by a CPU test.  The functions here drive it
+superstep by superstep and hold the independent pins that check it: a dense
+linear solve for the PageRank fixed point and a hop-bounded Bellman-Ford
+written as whole-array relaxation.  Each function names the passage of the
+paper it follows.
 """
 from __future__ import annotations
 
@@ -32,7 +35,7 @@ def build(force: bool = False) -> str:
     """Compile oracle.c into _oracle.so with gcc (no device code involved)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -55,6 +58,14 @@ def _load():
             "or_dijkstra": (ctypes.c_int, [I64, I64, P, P, P, I32, P, P]),
             "or_cc_hops": (I64, [I64, I64, P, P, P]),
             "or_union_find_min": (ctypes.c_int, [I64, I64, P, P, P, P]),
+            "or_sssp_omp": (I64, [I64, I64, P, P, P, I32, I64, P, P, P, P, ctypes.c_int]),
+            "or_cc_omp": (I64, [I64, I64, P, P, P, I64, P, P, P, P, ctypes.c_int]),
+            "or_in_edges": (None, [I64, I64, P, P, P, P]),
+            "or_pr_superstep_omp": (None, [I64, P, P, P, D, I32, P, P, ctypes.c_int]),
+            "or_sssp_many": (None, [I64, I64, P, P, P, P, I32, P, P, ctypes.c_int]),
+            "or_dijkstra_many": (None, [I64, I64, P, P, P, P, I32, P, ctypes.c_int]),
+            "or_ppr_many": (ctypes.c_int, [I64, I64, P, P, P, D, P, I32, I32, P, ctypes.c_int]),
+            "or_max_threads": (ctypes.c_int, []),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -89,39 +100,59 @@ def out_degree(g) -> np.ndarray:
 # iteration follows the template of Section "Algorithm Template").
 # --------------------------------------------------------------------------
 
-def pagerank(g, T: int, d: float = 0.85, x0: np.ndarray | None = None,
-             history: bool = False):
-    """x after T supersteps from x0 (default 1/V), float64.  With history=True
-    also returns the list of states x_0 .. x_T."""
+def max_threads() -> int:
+    """Host threads the OpenMP timing mode uses by default."""
+    return int(_load().or_max_threads())
+
+
+class _PrPull:
+    """Destination-major edge order for the OpenMP PageRank mode (each
+    destination keeps its messages in edge-list order)."""
+
+    def __init__(self, g):
+        src, dst, _ = _edges(g)
+        self.in_rp = np.empty(g.V + 1, np.int64)
+        self.in_src = np.empty(max(g.E, 1), np.int32)
+        _load().or_in_edges(g.V, g.E, _p(src), _p(dst), _p(self.in_rp), _p(self.in_src))
+
+
+def _pr_run(g, T, d, x, seed, history, threads):
     lib = _load()
-    src, dst, _ = _edges(g)
     deg = out_degree(g)
-    x = np.full(g.V, 1.0 / g.V) if x0 is None else np.array(x0, np.float64)
     hist = [x.copy()] if history else None
     nxt = np.empty_like(x)
+    if threads == 1:
+        src, dst, _ = _edges(g)
+    else:
+        pull = _PrPull(g)
     for _ in range(T):
-        lib.or_pr_superstep(g.V, g.E, _p(src), _p(dst), _p(deg), d, _p(x), _p(nxt))
+        if threads != 1:
+            lib.or_pr_superstep_omp(g.V, _p(pull.in_rp), _p(pull.in_src), _p(deg), d,
+                                    -1 if seed is None else int(seed), _p(x), _p(nxt), int(threads))
+        elif seed is None:
+            lib.or_pr_superstep(g.V, g.E, _p(src), _p(dst), _p(deg), d, _p(x), _p(nxt))
+        else:
+            lib.or_ppr_superstep(g.V, g.E, _p(src), _p(dst), _p(deg), d, int(seed), _p(x), _p(nxt))
         x, nxt = nxt, x
         if history:
             hist.append(x.copy())
     return (x, hist) if history else x
 
 
-def ppr(g, seed: int, T: int, d: float = 0.85, history: bool = False):
+def pagerank(g, T: int, d: float = 0.85, x0: np.ndarray | None = None,
+             history: bool = False, threads: int = 1):
+    """x after T supersteps from x0 (default 1/V), float64.  With history=True
+    also returns the list of states x_0 .. x_T.  threads != 1: OpenMP timing
+    mode (0 = all host threads), bitwise the same result."""
+    x = np.full(g.V, 1.0 / g.V) if x0 is None else np.array(x0, np.float64)
+    return _pr_run(g, T, d, x, None, history, threads)
+
+
+def ppr(g, seed: int, T: int, d: float = 0.85, history: bool = False, threads: int = 1):
     """Personalised PageRank from seed after T supersteps, x0 = e_seed."""
-    lib = _load()
-    src, dst, _ = _edges(g)
-    deg = out_degree(g)
     x = np.zeros(g.V)
     x[seed] = 1.0
-    hist = [x.copy()] if history else None
-    nxt = np.empty_like(x)
-    for _ in range(T):
-        lib.or_ppr_superstep(g.V, g.E, _p(src), _p(dst), _p(deg), d, int(seed), _p(x), _p(nxt))
-        x, nxt = nxt, x
-        if history:
-            hist.append(x.copy())
-    return (x, hist) if history else x
+    return _pr_run(g, T, d, x, seed, history, threads)
 
 
 # --------------------------------------------------------------------------
@@ -139,31 +170,77 @@ class MinRun:
     changed: np.ndarray        # |F_{k+1}| per superstep
 
 
-def sssp(g, source: int, max_steps: int = 1 << 30) -> MinRun:
+def sssp(g, source: int, max_steps: int = 1 << 30, threads: int = 1) -> MinRun:
+    """Bellman-Ford to convergence.  threads != 1: OpenMP timing mode (0 =
+    all host threads), bitwise the same result."""
     lib = _load()
     src, dst, w = _edges(g)
     cap = min(max_steps, g.V + 2)
     dist = np.empty(max(g.V, 1), np.uint32)
     fs, ef, ch = (np.zeros(cap, np.int64) for _ in range(3))
-    K = lib.or_sssp(g.V, g.E, _p(src), _p(dst), _p(w), int(source), cap, _p(dist), _p(fs), _p(ef), _p(ch))
+    if threads == 1:
+        K = lib.or_sssp(g.V, g.E, _p(src), _p(dst), _p(w), int(source), cap, _p(dist), _p(fs), _p(ef), _p(ch))
+    else:
+        K = lib.or_sssp_omp(g.V, g.E, _p(src), _p(dst), _p(w), int(source), cap, _p(dist), _p(fs), _p(ef),
+                            _p(ch), int(threads))
     if K == -2:
         raise MemoryError("oracle sssp")
     n = K if K > 0 else cap
     return MinRun(dist[: g.V], int(K), fs[:n], ef[:n], ch[:n])
 
 
-def cc(g, max_steps: int = 1 << 30) -> MinRun:
+def cc(g, max_steps: int = 1 << 30, threads: int = 1) -> MinRun:
     lib = _load()
     src, dst, _ = _edges(g)
     l2g = None if g.l2g is None else np.ascontiguousarray(g.l2g, np.int32)
     cap = min(max_steps, g.V + 2)
     lab = np.empty(max(g.V, 1), np.uint32)
     fs, ef, ch = (np.zeros(cap, np.int64) for _ in range(3))
-    K = lib.or_cc(g.V, g.E, _p(src), _p(dst), _p(l2g), cap, _p(lab), _p(fs), _p(ef), _p(ch))
+    if threads == 1:
+        K = lib.or_cc(g.V, g.E, _p(src), _p(dst), _p(l2g), cap, _p(lab), _p(fs), _p(ef), _p(ch))
+    else:
+        K = lib.or_cc_omp(g.V, g.E, _p(src), _p(dst), _p(l2g), cap, _p(lab), _p(fs), _p(ef), _p(ch),
+                          int(threads))
     if K == -2:
         raise MemoryError("oracle cc")
     n = K if K > 0 else cap
     return MinRun(lab[: g.V], int(K), fs[:n], ef[:n], ch[:n])
+
+
+def sssp_many(g, sources, threads: int = 0):
+    """Independent single-source runs of the reference Bellman-Ford, one per
+    host thread (the several sources of Section "Setup", first footnote):
+    returns (dist [B, V] uint32, K [B])."""
+    lib = _load()
+    src, dst, w = _edges(g)
+    s = np.ascontiguousarray(sources, np.int32)
+    dist = np.empty((len(s), max(g.V, 1)), np.uint32)
+    K = np.empty(len(s), np.int64)
+    lib.or_sssp_many(g.V, g.E, _p(src), _p(dst), _p(w), _p(s), len(s), _p(dist), _p(K), int(threads))
+    return dist[:, : g.V], K
+
+
+def ppr_many(g, seeds, T: int, d: float = 0.85, threads: int = 0) -> np.ndarray:
+    """Personalised PageRank of every seed (reference supersteps, one lane per
+    host thread): [B, V] float64, lane b bitwise ppr(g, seeds[b], T, d)."""
+    lib = _load()
+    src, dst, _ = _edges(g)
+    deg = out_degree(g)
+    s = np.ascontiguousarray(seeds, np.int32)
+    x = np.empty((len(s), max(g.V, 1)), np.float64)
+    if lib.or_ppr_many(g.V, g.E, _p(src), _p(dst), _p(deg), d, _p(s), len(s), int(T), _p(x), int(threads)):
+        raise MemoryError("oracle ppr_many")
+    return x[:, : g.V]
+
+
+def dijkstra_many(g, sources, threads: int = 0) -> np.ndarray:
+    """Dijkstra from every source, one run per host thread: [B, V] uint32."""
+    lib = _load()
+    src, dst, w = _edges(g)
+    s = np.ascontiguousarray(sources, np.int32)
+    dist = np.empty((len(s), max(g.V, 1)), np.uint32)
+    lib.or_dijkstra_many(g.V, g.E, _p(src), _p(dst), _p(w), _p(s), len(s), _p(dist), int(threads))
+    return dist[:, : g.V]
 
 
 def min_superstep(g, state: np.ndarray, front: np.ndarray, weighted: bool, both_dirs: bool):

@@ -28,12 +28,17 @@
  *             min; F_{k+1} = vertices whose distance strictly decreased.
  *   CC        label[v] = global id of v; F1 = vertices with an edge; labels
  *             travel along both directions of every edge; merge is min.
- * Everything runs in plain loops over the edge list, single threaded, with
- * PageRank in double precision.
+ * Everything runs in plain loops over the edge list, with PageRank in double
+ * precision.  The functions above the "OpenMP timing mode" line are the
+ * single-threaded reference.  The functions below it run the same
+ * supersteps on all host cores and exist only to time the CPU baseline;
+ * a CPU test pins them bitwise to the reference (integer minima are order
+ * free; PageRank sums each destination's messages in the same edge order).
  */
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 #define OR_INF 0xFFFFFFFFu
 
@@ -395,3 +400,202 @@ int or_union_find_min(int64_t V, int64_t E, const int32_t *src, const int32_t *d
     free(par); free(best);
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * OpenMP timing mode.  Same supersteps as the reference functions above,
+ * spread over `nthreads` host threads (0 = the OpenMP default).
+ * ------------------------------------------------------------------------ */
+
+static void set_threads(int nthreads)
+{
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+}
+
+/* Atomic minimum on a 32-bit word (compare-and-swap loop). */
+static inline void atomic_min_u32(uint32_t *p, uint32_t x)
+{
+    uint32_t cur = __atomic_load_n(p, __ATOMIC_RELAXED);
+    while (x < cur && !__atomic_compare_exchange_n(p, &cur, x, 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED)) {
+    }
+}
+
+/*
+ * The min superstep of or_min_superstep with the edge loop split over
+ * threads.  Each message is folded with an atomic minimum, so the merged
+ * value is the same whatever the order (min is exact and commutative).
+ */
+static int64_t min_superstep_omp(int64_t V, int64_t E, const int32_t *src, const int32_t *dst,
+                                 const uint32_t *w, int both_dirs, const uint32_t *state,
+                                 const uint8_t *front, uint32_t *state_next, uint8_t *front_next,
+                                 int64_t *edges_out)
+{
+    int64_t msgs = 0, changed = 0;
+    #pragma omp parallel for schedule(static)
+    for (int64_t v = 0; v < V; v++) state_next[v] = state[v];
+    #pragma omp parallel for schedule(static, 65536) reduction(+:msgs)
+    for (int64_t e = 0; e < E; e++) {
+        int32_t u = src[e], v = dst[e];
+        if (front[u]) {
+            atomic_min_u32(&state_next[v], w ? sat_add_u32(state[u], w[e]) : state[u]);
+            msgs++;
+        }
+        if (both_dirs && front[v]) {
+            atomic_min_u32(&state_next[u], state[v]);
+            msgs++;
+        }
+    }
+    #pragma omp parallel for schedule(static) reduction(+:changed)
+    for (int64_t v = 0; v < V; v++) {
+        front_next[v] = state_next[v] < state[v];
+        changed += front_next[v];
+    }
+    if (edges_out) *edges_out = msgs;
+    return changed;
+}
+
+/* or_sssp / or_cc on all threads: same arguments and return convention.
+ * Takes ownership of the frontier buffer f (frees it). */
+static int64_t min_run_omp(int64_t V, int64_t E, const int32_t *src, const int32_t *dst, const uint32_t *w,
+                           int both_dirs, int64_t max_steps, uint32_t *state, uint8_t *f,
+                           int64_t *front_size, int64_t *edges, int64_t *changed)
+{
+    uint32_t *ns = (uint32_t *)malloc((size_t)(V > 0 ? V : 1) * sizeof(uint32_t));
+    uint8_t *nf = (uint8_t *)calloc((size_t)(V > 0 ? V : 1), 1);
+    if (!ns || !nf) { free(ns); free(nf); return -2; }
+    int64_t fs = 0;
+    for (int64_t v = 0; v < V; v++) fs += f[v];
+    int64_t k = 0, K = -1;
+    while (k < max_steps) {
+        int64_t ef = 0;
+        int64_t c = min_superstep_omp(V, E, src, dst, w, both_dirs, state, f, ns, nf, &ef);
+        if (front_size) front_size[k] = fs;
+        if (edges) edges[k] = ef;
+        if (changed) changed[k] = c;
+        memcpy(state, ns, (size_t)V * sizeof(uint32_t));
+        uint8_t *t = f; f = nf; nf = t;
+        fs = c;
+        k++;
+        if (c == 0) { K = k; break; }
+    }
+    free(ns);
+    free(f);
+    free(nf);
+    return K;
+}
+
+int64_t or_sssp_omp(int64_t V, int64_t E, const int32_t *src, const int32_t *dst, const uint32_t *w,
+                    int32_t s, int64_t max_steps, uint32_t *dist,
+                    int64_t *front_size, int64_t *edges, int64_t *changed, int nthreads)
+{
+    set_threads(nthreads);
+    uint8_t *f = (uint8_t *)calloc((size_t)(V > 0 ? V : 1), 1);
+    if (!f) return -2;
+    for (int64_t v = 0; v < V; v++) dist[v] = OR_INF;
+    if (s >= 0 && s < V) { dist[s] = 0; f[s] = 1; }
+    return min_run_omp(V, E, src, dst, w, 0, max_steps, dist, f, front_size, edges, changed);
+}
+
+int64_t or_cc_omp(int64_t V, int64_t E, const int32_t *src, const int32_t *dst, const int32_t *l2g,
+                  int64_t max_steps, uint32_t *label,
+                  int64_t *front_size, int64_t *edges, int64_t *changed, int nthreads)
+{
+    set_threads(nthreads);
+    uint8_t *f = (uint8_t *)calloc((size_t)(V > 0 ? V : 1), 1);
+    if (!f) return -2;
+    for (int64_t v = 0; v < V; v++) label[v] = l2g ? (uint32_t)l2g[v] : (uint32_t)v;
+    for (int64_t e = 0; e < E; e++) { f[src[e]] = 1; f[dst[e]] = 1; }
+    return min_run_omp(V, E, src, dst, NULL, 1, max_steps, label, f, front_size, edges, changed);
+}
+
+/*
+ * Destination-major copy of the edge list for the PageRank timing mode: a
+ * stable counting sort by destination, so each destination lists its
+ * messages in edge-list order, the order in which or_pr_superstep adds them.
+ * in_rp[V+1] and in_src[E] are caller buffers.
+ */
+void or_in_edges(int64_t V, int64_t E, const int32_t *src, const int32_t *dst,
+                 int64_t *in_rp, int32_t *in_src)
+{
+    memset(in_rp, 0, (size_t)(V + 1) * sizeof(int64_t));
+    for (int64_t e = 0; e < E; e++) in_rp[dst[e] + 1]++;
+    for (int64_t v = 0; v < V; v++) in_rp[v + 1] += in_rp[v];
+    int64_t *pos = (int64_t *)malloc((size_t)(V > 0 ? V : 1) * sizeof(int64_t));
+    for (int64_t v = 0; v < V; v++) pos[v] = in_rp[v];
+    for (int64_t e = 0; e < E; e++) in_src[pos[dst[e]]++] = src[e];
+    free(pos);
+}
+
+/*
+ * or_pr_superstep (ppr_seed < 0) or or_ppr_superstep (ppr_seed = s) with
+ * the merge pulled per destination over the in-edges from or_in_edges and
+ * split over threads.  Each destination adds its messages in edge-list
+ * order starting from 0.0, exactly as the reference's edge loop does, and
+ * the dangling mass is summed over vertices in ascending order on one
+ * thread, so the result is bitwise the reference's.
+ */
+void or_pr_superstep_omp(int64_t V, const int64_t *in_rp, const int32_t *in_src, const int32_t *deg,
+                         double d, int32_t ppr_seed, const double *x, double *x_next, int nthreads)
+{
+    set_threads(nthreads);
+    double D = 0.0;
+    for (int64_t u = 0; u < V; u++)
+        if (deg[u] == 0) D += x[u];
+    double base = (1.0 - d) / (double)V;
+    #pragma omp parallel for schedule(dynamic, 4096)
+    for (int64_t v = 0; v < V; v++) {
+        double acc = 0.0;
+        for (int64_t i = in_rp[v]; i < in_rp[v + 1]; i++) {
+            int32_t u = in_src[i];
+            acc += x[u] / (double)deg[u];
+        }
+        x_next[v] = ppr_seed < 0 ? base + d * (acc + D / (double)V) : d * acc;
+    }
+    if (ppr_seed >= 0) x_next[ppr_seed] += (1.0 - d) + d * D;
+}
+
+/* B independent single-source SSSP runs (reference or_sssp, one per
+ * thread): dist is [B x V] (lane b at b*V), K[b] its superstep count. */
+void or_sssp_many(int64_t V, int64_t E, const int32_t *src, const int32_t *dst, const uint32_t *w,
+                  const int32_t *sources, int32_t B, uint32_t *dist, int64_t *K, int nthreads)
+{
+    set_threads(nthreads);
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t b = 0; b < B; b++)
+        K[b] = or_sssp(V, E, src, dst, w, sources[b], V + 2, dist + (size_t)b * (size_t)V, NULL, NULL, NULL);
+}
+
+/* B Dijkstra runs (or_dijkstra, one per thread); same layout. */
+void or_dijkstra_many(int64_t V, int64_t E, const int32_t *src, const int32_t *dst, const uint32_t *w,
+                      const int32_t *sources, int32_t B, uint32_t *dist, int nthreads)
+{
+    set_threads(nthreads);
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t b = 0; b < B; b++)
+        or_dijkstra(V, E, src, dst, w, sources[b], dist + (size_t)b * (size_t)V, NULL);
+}
+
+/* B independent personalised-PageRank runs of T reference supersteps
+ * (or_ppr_superstep, one lane per thread): x is [B x V] (lane b at b*V). */
+int or_ppr_many(int64_t V, int64_t E, const int32_t *src, const int32_t *dst, const int32_t *deg,
+                double d, const int32_t *seeds, int32_t B, int32_t T, double *x, int nthreads)
+{
+    set_threads(nthreads);
+    int bad = 0;
+    #pragma omp parallel for schedule(dynamic, 1) reduction(|:bad)
+    for (int32_t b = 0; b < B; b++) {
+        double *cur = x + (size_t)b * (size_t)V;
+        double *tmp = (double *)malloc((size_t)(V > 0 ? V : 1) * sizeof(double));
+        if (!tmp) { bad = 1; continue; }
+        for (int64_t v = 0; v < V; v++) cur[v] = 0.0;
+        cur[seeds[b]] = 1.0;
+        for (int32_t t = 0; t < T; t++) {
+            or_ppr_superstep(V, E, src, dst, deg, d, seeds[b], cur, tmp);
+            memcpy(cur, tmp, (size_t)V * sizeof(double));
+        }
+        free(tmp);
+    }
+    return bad ? -2 : 0;
+}
+
+/* Threads the OpenMP mode uses for nthreads = 0. */
+int or_max_threads(void) { return omp_get_max_threads(); }

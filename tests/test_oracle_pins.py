@@ -260,3 +260,40 @@ def test_delta_lazy_keeps_only_final_value():
     changed = (x5.view(np.uint32) != x0.view(np.uint32)) & (rem != 0)
     assert gids.tolist() == p.l2g[changed].tolist()
     assert vals.tolist() == x5.view(np.uint32)[changed].tolist()
+
+
+# ---------------------------------------------------------------- OpenMP timing mode
+
+@pytest.mark.parametrize("threads", [2, 0])
+@pytest.mark.parametrize("scale,seed", [(10, 1), (14, 3)])
+def test_openmp_mode_equals_reference_bitwise(scale, seed, threads):
+    """The timing mode on several threads gives the single-threaded
+    reference's results bit for bit: SSSP and CC values and every
+    superstep's counters, PageRank and PPR float64 values."""
+    g = gen.rmat(scale, seed=seed)
+    a, b = oracle.sssp(g, 0), oracle.sssp(g, 0, threads=threads)
+    assert a.K == b.K and np.array_equal(a.state, b.state)
+    for f in ("front", "msgs", "changed"):
+        assert np.array_equal(getattr(a, f), getattr(b, f)), f
+    p = gen.rmat_part(scale, seed=seed, part=1)
+    a, b = oracle.cc(p), oracle.cc(p, threads=threads)
+    assert a.K == b.K and np.array_equal(a.state, b.state) and np.array_equal(a.changed, b.changed)
+    x1, x2 = oracle.pagerank(g, 12), oracle.pagerank(g, 12, threads=threads)
+    assert np.array_equal(x1.view(np.uint64), x2.view(np.uint64))
+    s = int(np.argmax(np.diff(g.row_ptr)))
+    y1, y2 = oracle.ppr(g, s, 15), oracle.ppr(g, s, 15, threads=threads)
+    assert np.array_equal(y1.view(np.uint64), y2.view(np.uint64))
+
+
+def test_openmp_many_sources_equal_single_runs():
+    g = gen.rmat(11, seed=4)
+    srcs = gen.pick_sources(g, 24, seed=40)
+    D, K = oracle.sssp_many(g, srcs)
+    J = oracle.dijkstra_many(g, srcs, threads=3)
+    for b, s in enumerate(srcs):
+        r = oracle.sssp(g, int(s))
+        assert np.array_equal(D[b], r.state) and K[b] == r.K
+        assert np.array_equal(J[b], r.state)
+    X = oracle.ppr_many(g, srcs[:6], 20)
+    for b in range(6):
+        assert np.array_equal(X[b].view(np.uint64), oracle.ppr(g, int(srcs[b]), 20).view(np.uint64))
