@@ -78,33 +78,96 @@ def copy_ceiling_gbps(torch, nbytes=1 << 30, reps=5):
     return 2 * nbytes / (ms / 1e3) / 1e9
 
 
-def cpu_baseline(g, edges_per_solve, budget_s=20.0):
+def cpu_baseline(np, g, edges_per_solve, g4=None, src4=None, part=None, budget_s=20.0):
+    """The oracle timed on this host: the headline SSSP solve on one thread
+    (the reference mode) and on all threads (the OpenMP timing mode), with
+    Dijkstra on one thread for scale; the batched workload's 256 sources as
+    independent reference runs parallel over sources, and as 256 Dijkstra
+    runs; the partition's PageRank (two supersteps, scaled to 30) and CC on
+    all threads.  Results are checked against each other."""
     import oracle
-    times = []
-    t_all = time.perf_counter()
-    while True:
-        t0 = time.perf_counter()
-        r = oracle.sssp(g, 0)
-        times.append(time.perf_counter() - t0)
-        if time.perf_counter() - t_all > budget_s or len(times) >= 5:
-            break
-    times.sort()
-    med = times[len(times) // 2]
-    assert int(r.msgs.sum()) == edges_per_solve
+    nthr = oracle.max_threads()
+
+    def timed(f, min_runs=1, max_runs=5, budget=budget_s):
+        times, r = [], None
+        t_all = time.perf_counter()
+        while len(times) < max_runs:
+            t0 = time.perf_counter()
+            r = f()
+            times.append(time.perf_counter() - t0)
+            if len(times) >= min_runs and time.perf_counter() - t_all > budget:
+                break
+        times.sort()
+        return times[len(times) // 2], len(times), r
+
+    t1, n1, r1 = timed(lambda: oracle.sssp(g, 0), budget=budget_s / 2)
+    assert int(r1.msgs.sum()) == edges_per_solve
+    tn, nn, rn = timed(lambda: oracle.sssp(g, 0, threads=0), budget=budget_s / 2)
+    assert np.array_equal(rn.state, r1.state) and rn.K == r1.K
     t0 = time.perf_counter()
     dist = oracle.dijkstra(g, 0)  # the work-efficient sequential solve, for scale
     t_dij = time.perf_counter() - t0
-    assert (dist == r.state).all()
-    return {"value": edges_per_solve / med / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
-            "sample": f"full single-source solve from vertex 0 ({r.K} supersteps, {edges_per_solve} messages), "
-                      f"single-threaded C oracle, median of {len(times)} runs ({med:.2f} s each)",
-            "dijkstra_single_core_s": t_dij,
-            "host_cpu": platform.processor() or platform.machine(), "host_nproc": os.cpu_count()}
+    assert (dist == r1.state).all()
+    out = {"value": edges_per_solve / tn / 1e9, "unit": "GTEPS", "cores": nthr, "kind": "oracle",
+           "sample": f"full single-source solve from vertex 0 ({r1.K} supersteps, {edges_per_solve} messages): "
+                     f"OpenMP timing mode on {nthr} threads, median of {nn} runs ({tn:.3f} s each)",
+           "single_core": {"value": edges_per_solve / t1 / 1e9, "unit": "GTEPS", "cores": 1,
+                           "sample": f"reference mode, median of {n1} runs ({t1:.2f} s each)"},
+           "dijkstra_single_core_s": t_dij,
+           "host_cpu": platform.processor() or platform.machine(), "host_nproc": os.cpu_count()}
+    if g4 is not None:
+        t0 = time.perf_counter()
+        D, K = oracle.sssp_many(g4, src4)
+        t_bf = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        J = oracle.dijkstra_many(g4, src4)
+        t_dj = time.perf_counter() - t0
+        assert np.array_equal(D, J)
+        out["batched"] = {"workload": f"the batched workload's {len(src4)} sources on R-MAT scale 20",
+                          "cores": nthr,
+                          "bellman_ford_parallel_over_sources_s": t_bf, "queries_per_s": len(src4) / t_bf,
+                          "dijkstra_parallel_over_sources_s": t_dj, "dijkstra_queries_per_s": len(src4) / t_dj}
+    if part is not None:
+        t0 = time.perf_counter()
+        oracle.pagerank(part, 2, 0.85, threads=0)
+        t_pr2 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        rc = oracle.cc(part, threads=0)
+        t_cc = time.perf_counter() - t0
+        out["partition"] = {"workload": "the scale-25 partition (part 0 of 8)", "cores": nthr,
+                            "pagerank_30_s_estimated": t_pr2 * 15, "pagerank_sample": "2 supersteps, times 15",
+                            "pagerank_gteps": 2 * part.E / t_pr2 / 1e9,
+                            "cc_s": t_cc, "cc_supersteps": int(rc.K),
+                            "cc_gteps": float(rc.msgs.sum()) / t_cc / 1e9}
+    return out
+
+
+def batched_bytes_per_superstep(np, g, fronts, B):
+    """Algorithmic bytes of the batched SSSP kernel per superstep, from the
+    union F_k over lanes of the active vertices: lower bracket 8 E_F (edges
+    once) + 4 B |F| (snapshot lanes) + 8 B |N(F)| (destination lanes read
+    and written) + B/8 (|F| + |N(F)|) (lane masks); upper bracket 8 B per
+    lane message (a value gather and a min update per lane and edge)."""
+    deg = np.diff(g.row_ptr).astype(np.int64)
+    lo = up = 0
+    for f in fronts:
+        f = np.nonzero(f)[0]
+        f = f[deg[f] > 0]
+        ef = int(deg[f].sum())
+        if len(f):
+            starts = g.row_ptr[f].astype(np.int64)
+            idx = np.repeat(starts - np.cumsum(np.r_[0, deg[f][:-1]]), deg[f]) + np.arange(ef)
+            nf = int(np.unique(g.col[idx]).size)
+        else:
+            nf = 0
+        lo += 8 * ef + 4 * B * len(f) + 8 * B * nf + (B // 8) * (len(f) + nf)
+    return lo
 
 
 def bench_batched(gx, torch, np, gen, steps=3):
     """256 seeded sources on R-MAT scale 20 (seed 4): one persistent batched
-    launch (autotuned) against 256 sequential plain solves on the same GPU."""
+    launch (autotuned) against 256 sequential plain solves on the same GPU;
+    every lane is compared with its plain solve."""
     import paper_2203_13005_amd as m
     g = gen.rmat(20, seed=4)
     src = gen.pick_sources(g, 256, seed=40)
@@ -120,40 +183,59 @@ def bench_batched(gx, torch, np, gen, steps=3):
         _, rs = gx.batch_run(dg, gx.GX_SSSP, src, tune=best, out=out)
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / steps
-    D = out.cpu().numpy().view(np.uint32)
     # plain: 256 sequential solves, one state re-initialised per source
     st = m.State(dg, gx.GX_SSSP, source=int(src[0]))
     st.run(100_000)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plain_edges = 0
-    for b, s_ in enumerate(src):
+    for s_ in src:
         st.params.source = int(s_)
         st.reset()
         rsp, _ = st.run(100_000)
         plain_edges += rsp.edges
-        if b in (0, 17, 255):
-            torch.cuda.synchronize()
-            assert np.array_equal(st.values_numpy(), D[:, b]), f"lane {b} differs from its plain solve"
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
+    # untimed: every lane against its plain solve, superstep by superstep,
+    # collecting the union over lanes of each superstep's active set
+    union = [torch.zeros(g.V, dtype=torch.bool, device="cuda:0") for _ in range(rs.supersteps)]
+    for b, s_ in enumerate(src):
+        st.params.source = int(s_)
+        st.reset()
+        union[0][int(s_)] = True
+        k = 0
+        while True:
+            fr, ef, ch = st.superstep(stats=True)
+            if ch == 0:
+                break
+            k += 1
+            union[k] |= st.frontier_device() != 0
+        assert torch.equal(st.values(), out[:, b]), f"lane {b} differs from its plain solve"
+    fronts = [u.cpu().numpy() for u in union]
+    bytes_lo = batched_bytes_per_superstep(np, g, fronts, 256)
+    bytes_up = 8 * plain_edges
     log(f"batched: {t_batch * 1e3:.2f} ms for 256 lanes ({rs.supersteps} supersteps); "
-        f"256 plain solves {t_plain * 1e3:.1f} ms")
+        f"256 plain solves {t_plain * 1e3:.1f} ms; all 256 lanes equal their plain solves")
     return {"workload": "256 seeded sources (seed 40, out-degree > 0), Bellman-Ford SSSP, R-MAT scale 20 "
                         f"({g.V} vertices, {g.E} edges after dedup, seed 4), uint32 weights in [1,255]",
             "queries_per_s": 256 / t_batch, "ms_per_batch": t_batch * 1e3, "supersteps": int(rs.supersteps),
             "plain_queries_per_s": 256 / t_plain, "plain_ms_total": t_plain * 1e3,
             "speedup_vs_plain": t_plain / t_batch, "lane_messages_per_batch": int(plain_edges),
-            "lane_gteps": plain_edges / t_batch / 1e9,
-            # upper bracket: a 4 B value gather and a 4 B min update per lane message; VALU: an
-            # add and a min per lane message against 256 CUs x 64 lanes x 2.4 GHz int32 ops
-            "roofline": {"hbm_upper_GBps": 8 * plain_edges / t_batch / 1e9,
-                         "hbm_upper_frac": 8 * plain_edges / t_batch / 1e9 / HBM_PEAK_GBS,
+            "lane_gteps": plain_edges / t_batch / 1e9, "lanes_checked_against_plain": 256,
+            # lower bracket: compulsory bytes of the union frontiers; upper bracket: a 4 B value
+            # gather and a 4 B min update per lane message; VALU: an add and a min per lane
+            # message against 256 CUs x 64 lanes x 2.4 GHz int32 ops
+            "roofline": {"bound": "hbm",
+                         "algorithmic_bytes_lower": bytes_lo, "algorithmic_bytes_upper": bytes_up,
+                         "hbm_lower_GBps": bytes_lo / t_batch / 1e9,
+                         "hbm_lower_frac": bytes_lo / t_batch / 1e9 / HBM_PEAK_GBS,
+                         "hbm_upper_GBps": bytes_up / t_batch / 1e9,
+                         "hbm_upper_frac": bytes_up / t_batch / 1e9 / HBM_PEAK_GBS,
                          "valu_Tops": 2 * plain_edges / t_batch / 1e12,
                          "valu_frac": 2 * plain_edges / t_batch / VALU_INT32_PEAK_OPS,
                          "binds": "memory (random lane-row gathers); VALU far from its peak"},
             "tune": {"block": best.block, "tile": best.tile, "width": best.width},
-            "ppr": bench_batched_ppr(gx, torch, g, dg, src)}
+            "ppr": bench_batched_ppr(gx, torch, g, dg, src)}, g, src
 
 
 def bench_batched_ppr(gx, torch, g, dg, src, iters=50, reps=3):
@@ -176,12 +258,18 @@ def bench_batched_ppr(gx, torch, g, dg, src, iters=50, reps=3):
     return out
 
 
-def bench_serving(gx, torch, np, gen, n_queries=2000, qps_frac=0.7, budget_gib=64.0, lanes=64, max_pools=32):
+def bench_serving(gx, torch, np, gen, n_queries=10000, qps_frac=0.7, lanes=64, max_pools=32, budget_frac=0.5,
+                  sample=16):
     """16 resident R-MAT graphs (scales 16..22, seeds 100..115), 50% SSSP /
     50% PPR (50 iterations), Poisson arrivals (seed 5) at a fixed rate of
-    qps_frac x the measured closed-loop capacity.  The budget (64 GiB of the
-    288 GiB HBM) holds a pool for every (graph, algorithm) pair, so the
-    open-loop run measures batching and scheduling, not pool eviction."""
+    qps_frac x the measured closed-loop capacity.  The HBM budget holds
+    budget_frac of the lane pools of every (graph, algorithm) pair, so
+    admission binds: pools are created, evicted when idle and empty, and
+    queries wait for room.  After the timed run a seeded sample of the
+    completed queries is checked: SSSP against the plain engine's solve from
+    the same source, PPR against the same seed run alone in the batched
+    engine (bitwise)."""
+    import ctypes
     graphs, dgs = [], []
     t0 = time.perf_counter()
     for i in range(16):
@@ -191,6 +279,13 @@ def bench_serving(gx, torch, np, gen, n_queries=2000, qps_frac=0.7, budget_gib=6
         dgs.append(gx.DeviceGraph(g, gx.GX_NEED_OUT | gx.GX_NEED_IN))
     log(f"serving: 16 graphs ({sum(g.E for g in graphs)} edges) generated and loaded in "
         f"{time.perf_counter() - t0:.1f}s")
+    pools = 0
+    for dg in dgs:
+        for algo in (gx.GX_SSSP, gx.GX_PPR):
+            b = ctypes.c_size_t()
+            assert gx.binding.lib.gx_server_bytes_per_lane(dg.handle, algo, ctypes.byref(b)) == 0
+            pools += lanes * b.value
+    budget = int(budget_frac * pools)
     rng = np.random.default_rng(5)
     cands = [np.nonzero(np.diff(g.row_ptr) > 0)[0] for g in graphs]
 
@@ -201,37 +296,40 @@ def bench_serving(gx, torch, np, gen, n_queries=2000, qps_frac=0.7, budget_gib=6
             qs.append((gi, gx.GX_SSSP if rng.random() < 0.5 else gx.GX_PPR, int(rng.choice(cands[gi]))))
         return qs
 
-    budget = int(budget_gib * (1 << 30))
-
-    def run(qs, arrivals):
+    def run(qs, arrivals, keep=()):
         srv = gx.Server(budget, lanes_per_pool=lanes, max_pools=max_pools, epoch_supersteps=4, ppr_iters=50)
         ids = [srv.add_graph(d) for d in dgs]
-        done = []
+        done, qid_of, kept = [], {}, {}
         t_start = time.perf_counter()
         i = 0
         while len(done) < len(qs):
             now = time.perf_counter() - t_start
             while i < len(qs) and arrivals[i] <= now:
                 gi, algo, s_ = qs[i]
-                srv.submit(ids[gi], algo, s_)
+                qid_of[srv.submit(ids[gi], algo, s_)] = i
                 i += 1
             for c in srv.poll(wait_ms=0 if i < len(qs) else 20):
                 assert c.status == 0
                 done.append(c)
+                if qid_of[c.id] in keep:
+                    kept[qid_of[c.id]] = c.result
             if i < len(qs):
                 time.sleep(max(0.0, min(0.002, arrivals[i] - (time.perf_counter() - t_start))))
         wall = time.perf_counter() - t_start
         srv.close()
-        return done, wall
+        return done, wall, kept
 
-    cap_q = make(512)
-    done, wall = run(cap_q, np.zeros(len(cap_q)))
+    cap_q = make(1024)
+    done, wall, _ = run(cap_q, np.zeros(len(cap_q)))
     capacity = len(cap_q) / wall
-    log(f"serving: closed-loop capacity {capacity:.1f} queries/s")
+    log(f"serving: closed-loop capacity {capacity:.1f} queries/s (budget {budget / 2**30:.1f} GiB of "
+        f"{pools / 2**30:.1f} GiB for every pool)")
     qps = qps_frac * capacity
     qs = make(n_queries)
     arrivals = np.cumsum(np.random.default_rng(5).exponential(1.0 / qps, n_queries))
-    done, wall = run(qs, arrivals)
+    check_rng = np.random.default_rng(6)
+    keep = set(int(x) for x in check_rng.choice(n_queries, sample, replace=False))
+    done, wall, kept = run(qs, arrivals, keep)
     lat = np.array([c.done_s - c.submit_s for c in done])
     wait = np.array([c.start_s - c.submit_s for c in done])
     by_algo = {}
@@ -243,6 +341,19 @@ def bench_serving(gx, torch, np, gen, n_queries=2000, qps_frac=0.7, budget_gib=6
     log(f"serving: {len(done)} queries at {qps:.1f} q/s offered -> {len(done) / wall:.1f} q/s, "
         f"p50 {np.percentile(lat, 50) * 1e3:.1f} ms p99 {np.percentile(lat, 99) * 1e3:.1f} ms "
         f"(admission wait p50 {np.percentile(wait, 50) * 1e3:.1f} ms); {by_algo}")
+    # the seeded sample, checked outside the timed run
+    for i in sorted(kept):
+        gi, algo, s_ = qs[i]
+        if algo == gx.GX_SSSP:
+            st = gx.State(dgs[gi], gx.GX_SSSP, source=s_)
+            st.run(100_000)
+            assert np.array_equal(st.values_numpy(), kept[i]), f"served SSSP query {i} differs from the plain solve"
+            st.close()
+        else:
+            alone, _ = gx.batch_run(dgs[gi], gx.GX_PPR, np.array([s_], np.int32), iters=50)
+            assert np.array_equal(alone.cpu().numpy()[:, 0].view(np.uint32), kept[i].view(np.uint32)), \
+                f"served PPR query {i} differs from the same seed alone"
+    log(f"serving: {len(kept)} sampled queries equal their plain / alone results")
     return {"workload": "16 resident R-MAT graphs, scales 16..22 (scale 16 + floor(7i/16), seeds 100..115, "
                         "edge factor 16), queries 50% SSSP / 50% personalised PageRank (50 iterations), "
                         "Poisson arrivals (seed 5)",
@@ -250,7 +361,8 @@ def bench_serving(gx, torch, np, gen, n_queries=2000, qps_frac=0.7, budget_gib=6
             "queries_per_s": len(done) / wall, "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "admission_wait_p50_ms": float(np.percentile(wait, 50) * 1e3), "by_algorithm": by_algo,
-            "hbm_budget_gib": budget_gib, "lanes_per_pool": lanes, "max_pools": max_pools}
+            "hbm_budget_gib": budget / 2**30, "all_pools_gib": pools / 2**30, "lanes_per_pool": lanes,
+            "max_pools": max_pools, "sample_checked": len(kept)}
 
 
 def bench_pagerank_small(gx, torch, np, gen, reps=20):
@@ -379,7 +491,7 @@ def bench_partition(gx, torch, np, gen, reps=3):
             "cc_kernel_ms": sum(d["kernel_ms"] for d in steps),
             "sync_set_final": int(gids.numel()),
             "cc_per_superstep": [dict(edges=d["edges"], pulled=d["pulled"], us=round(d["kernel_ms"] * 1e3, 1))
-                                 for d in steps]}
+                                 for d in steps]}, p
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sssp_rmat22_relaxation_traffic.json")
@@ -445,41 +557,13 @@ def load_traffic():
     return t
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--scale", type=int, default=22)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--pull-fraction", type=float, default=0.0,
-                    help="SSSP switch point to the pull form (0 = library default, >= 1 = push only)")
-    ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--partition", action="store_true", help="also run the scale-25 partition (PR 30 + CC)")
-    ap.add_argument("--no-pagerank", action="store_true")
-    ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serving-queries", type=int, default=2000)
-    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
-                    help="write the traffic record from two rocprofv3 --pmc output folders and exit")
-    ap.add_argument("--pmc-solves", type=int, default=0,
-                    help="solves in the profiled run (1 validation + warmup + 1 detail + steps)")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain 1 GiB device copy (for HBM counter calibration)")
-    args = ap.parse_args()
-    if args.summarize_pmc:
-        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.pmc_solves)
-        return
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU exchange is not built.",
-              file=sys.stderr)
-        sys.exit(2)
+LEGS = ("sssp", "pagerank", "partition", "exchange", "batched", "serving")
 
-    import numpy as np
-    import torch
 
-    import gen
-    import paper_2203_13005_amd as gx
-
+def bench_sssp(args, gx, torch, np, gen):
+    """The headline: one SSSP solve per step on R-MAT scale 22 (seed 2),
+    source 0.  Returns (fields of the JSON line, host graph, messages per
+    solve)."""
     dev = torch.device("cuda:0")
     log(f"generating R-MAT scale {args.scale}")
     t0 = time.perf_counter()
@@ -546,15 +630,6 @@ def main():
     log(f"{dt * 1e3 / args.steps:.3f} ms/solve, relaxation kernel {kern_ms / args.steps:.3f} ms/solve "
         f"over {launches / args.steps:.1f} launches")
 
-    if args.copy_calibration:
-        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
-        b = torch.empty_like(a)
-        a.fill_(1)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        log("copy calibration: 1 GiB device-to-device copy done")
-
     achieved = bytes_per_solve * args.steps / (kern_ms / 1e3) / 1e9
     bytes_upper = sum(p["bytes_upper"] for p in per_step)
     achieved_upper = bytes_upper * args.steps / (kern_ms / 1e3) / 1e9
@@ -562,18 +637,8 @@ def main():
     log(f"device copy ceiling {copy_gbps:.0f} GB/s")
     traffic = load_traffic()
     out = {
-        "metric": "GTEPS per superstep and % HBM roofline; batched-vs-plain SSSP queries/s, p50/p99",
         "value": edges / dt / 1e9,
-        "unit": "GTEPS",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
         "ms_per_step": dt * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic",
         "config": {
             "workload": f"Bellman-Ford SSSP to convergence from vertex 0, R-MAT scale {args.scale} "
                         f"({g.V} vertices, {16 * g.V} raw edges, a=0.57 b=0.19 c=0.19 d=0.05, seed 2, "
@@ -606,18 +671,89 @@ def main():
                                    us=round(d["kernel_ms"] * 1e3, 1)) for p, d in zip(per_step, detail)],
         },
     }
-    if not args.no_pagerank:
+    return out, g, edges_per_solve
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--scale", type=int, default=22)
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="comma-separated legs to run (default: all of " + ",".join(LEGS) + ")")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pull-fraction", type=float, default=0.0,
+                    help="SSSP switch point to the pull form (0 = library default, >= 1 = push only)")
+    ap.add_argument("--serving-queries", type=int, default=10000)
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the traffic record from two rocprofv3 --pmc output folders and exit")
+    ap.add_argument("--pmc-solves", type=int, default=0,
+                    help="solves in the profiled run (1 validation + warmup + 1 detail + steps)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (for HBM counter calibration)")
+    args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.pmc_solves)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU exchange is not built.",
+              file=sys.stderr)
+        sys.exit(2)
+    legs = [x for x in args.legs.split(",") if x]
+    bad = [x for x in legs if x not in LEGS]
+    if bad:
+        ap.error(f"unknown legs {bad}; choose from {LEGS}")
+
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2203_13005_amd as gx
+
+    out = {
+        "metric": "GTEPS per superstep and % HBM roofline; batched-vs-plain SSSP queries/s, p50/p99",
+        "value": None,
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "none (headline leg not run)"},
+    }
+    g = edges_per_solve = None
+    if "sssp" in legs:
+        head, g, edges_per_solve = bench_sssp(args, gx, torch, np, gen)
+        out.update(head)
+    if "pagerank" in legs:
         out["pagerank_scale14"] = bench_pagerank_small(gx, torch, np, gen)
-    if args.partition:
-        out["partition_scale25"] = bench_partition(gx, torch, np, gen)
+    part = None
+    if "partition" in legs:
+        out["partition_scale25"], part = bench_partition(gx, torch, np, gen)
+    if "exchange" in legs:
         out["exchange_8parts_scale22"] = bench_exchange(gx, torch, np, gen)
-    if not args.no_batched:
-        out["batched"] = bench_batched(gx, torch, np, gen)
-    if not args.no_serving:
+    g4 = src4 = None
+    if "batched" in legs:
+        out["batched"], g4, src4 = bench_batched(gx, torch, np, gen)
+    if "serving" in legs:
         out["serving"] = bench_serving(gx, torch, np, gen, n_queries=args.serving_queries)
-    if not args.no_cpu_baseline:
+    if args.copy_calibration:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("copy calibration: 1 GiB device-to-device copy done")
+    if g is not None and not args.no_cpu_baseline:
         log("timing the CPU oracle")
-        out["cpu_baseline"] = cpu_baseline(g, edges_per_solve)
+        out["cpu_baseline"] = cpu_baseline(np, g, edges_per_solve, g4, src4, part)
     print(json.dumps(out), flush=True)
 
 

@@ -1,8 +1,10 @@
 """ctypes marshalling for libgx.so (see include/gx.h for the contract)."""
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -92,6 +94,7 @@ _SIGS = {
     "gx_state_values": (ctypes.c_int32, [_P, ctypes.POINTER(_P)]),
     "gx_state_frontier": (ctypes.c_int32, [_P, ctypes.POINTER(_P)]),
     "gx_state_superstep": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "gx_release_cached": (ctypes.c_int32, []),
     "gx_superstep": (ctypes.c_int32, [_P, _P, ctypes.POINTER(StepStats)]),
     "gx_run_until_converged": (ctypes.c_int32, [_P, ctypes.c_uint32, _P, ctypes.POINTER(RunStats),
                                                 ctypes.POINTER(StepStats)]),
@@ -136,6 +139,29 @@ def _load():
 
 
 lib = _load()
+
+
+# Handles still open at interpreter exit are closed before the HIP runtime
+# tears down (servers, then states, then graphs), and the library's cached
+# events and pinned buffers are freed after them.
+_live: "weakref.WeakSet" = weakref.WeakSet()
+
+
+def _close_all_at_exit():
+    for kind in ("Server", "State", "DeviceGraph"):
+        for obj in list(_live):
+            if type(obj).__name__ == kind:
+                try:
+                    obj.close()
+                except Exception:
+                    pass
+    try:
+        lib.gx_release_cached()
+    except Exception:
+        pass
+
+
+atexit.register(_close_all_at_exit)
 
 
 def exported_symbols() -> list[str]:
@@ -191,6 +217,7 @@ class DeviceGraph:
         self.handle = h
         self.V, self.E, self.needs = int(host.V), int(host.E), int(needs)
         self._keep = None
+        _live.add(self)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -223,6 +250,7 @@ class State:
             _check(lib.gx_state_init(graph.handle, ctypes.byref(self.params), ctypes.c_void_p(self.mem.data_ptr()),
                                      nbytes.value, _stream_handle(stream), ctypes.byref(h)))
         self.handle = h
+        _live.add(self)
 
     def reset(self, stream=None):
         """Re-initialises the state in the same device memory (no allocation)."""
@@ -252,13 +280,19 @@ class State:
         a = self.values().cpu().numpy()
         return a if self.algo == GX_PAGERANK else a.view(np.uint32)
 
+    def frontier_device(self):
+        """Device view (uint8 per vertex, nonzero = active in the next
+        superstep) of the current frontier byte map."""
+        p = ctypes.c_void_p()
+        _check(lib.gx_state_frontier(self.handle, ctypes.byref(p)))
+        return self._view(p.value, self.graph.V)
+
     def frontier_numpy(self) -> np.ndarray:
         """Boolean frontier (vertices active in the next superstep)."""
         import torch
-        p = ctypes.c_void_p()
-        _check(lib.gx_state_frontier(self.handle, ctypes.byref(p)))
+        v = self.frontier_device()
         torch.cuda.synchronize(self.graph.device)
-        return self._view(p.value, self.graph.V).cpu().numpy() != 0
+        return v.cpu().numpy() != 0
 
     @property
     def superstep_index(self) -> int:
@@ -402,6 +436,7 @@ class Server:
         h = ctypes.c_void_p()
         _check(lib.gx_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h
+        _live.add(self)
         self.graphs: list[DeviceGraph] = []
         self._buffers: dict[int, np.ndarray] = {}
 

@@ -127,15 +127,63 @@ def test_batched_ppr_lane_independent_of_batch(gx):
 
 @pytest.mark.slow
 def test_batched_sssp_full_scale20_b256(gx):
-    """The batched workload: R-MAT scale 20, 256 seeded sources, one launch;
-    16 sampled lanes against the oracle, and the superstep count."""
+    """The batched workload: R-MAT scale 20, 256 seeded sources, one launch
+    with the default shape and one with the autotuned shape (the bench's
+    launch); every lane against the oracle's single-source run from its
+    source, and the superstep count."""
     g = gen.rmat(20, seed=4)
     src = gen.pick_sources(g, 256, seed=40)
-    out, rs = gx.batch_run(load(gx, g), gx.GX_SSSP, src)
+    dg = load(gx, g)
+    ref, K = oracle.sssp_many(g, src)
+    out, rs = gx.batch_run(dg, gx.GX_SSSP, src)
     D = lanes_u32(out)
-    Ks = []
-    for b in range(0, 256, 16):
-        ref = oracle.sssp(g, int(src[b]))
-        assert np.array_equal(D[:, b], ref.state), b
-        Ks.append(ref.K)
-    assert rs.supersteps >= max(Ks)
+    for b in range(256):
+        assert np.array_equal(D[:, b], ref[b]), b
+    assert rs.supersteps == K.max()
+    best, _ = gx.batch_autotune(dg, gx.GX_SSSP, src)
+    out2, rs2 = gx.batch_run(dg, gx.GX_SSSP, src, tune=best)
+    assert np.array_equal(lanes_u32(out2), D), best
+    assert rs2.supersteps == K.max()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("B", [64, 256])
+def test_batched_ppr_scale16_every_lane(gx, B):
+    """PPR lanes, 50 iterations, R-MAT scale 16 (vertex 0's in-row spans
+    dozens of 256-edge pull tiles): every lane within 1e-6 of the float64
+    oracle, and every lane bitwise the same when run alone."""
+    g = gen.rmat(16, seed=6)
+    assert np.bincount(g.col, minlength=g.V).max() >= 10 * 256
+    src = gen.pick_sources(g, B, seed=45)
+    src[0] = 0  # the hub itself as a seed
+    dg = load(gx, g)
+    out, rs = gx.batch_run(dg, gx.GX_PPR, src, iters=50)
+    X = out.cpu().numpy().astype(np.float64)
+    ref = oracle.ppr_many(g, src, 50)
+    err = np.abs(X - ref.T).max(axis=0)
+    assert err.max() <= 1e-6, (int(err.argmax()), float(err.max()))
+    for b in (0, 1, B // 2, B - 1):
+        alone, _ = gx.batch_run(dg, gx.GX_PPR, src[b:b + 1], iters=50)
+        assert np.array_equal(alone.cpu().numpy()[:, 0].view(np.uint32), out.cpu().numpy()[:, b].view(np.uint32)), b
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("B", [64, 256])
+def test_batched_ppr_scale20_bench_shape(gx, B):
+    """The batched PPR workload the bench times: R-MAT scale 20 (seed 4),
+    B seeds, 50 iterations.  Every lane keeps its mass (float32 sums of a
+    float64-accumulated iteration) and holds at least the teleport share at
+    its seed; 16 lanes spread over the tile are checked against the
+    oracle."""
+    g = gen.rmat(20, seed=4)
+    src = gen.pick_sources(g, 256, seed=40)[:B]
+    out, _ = gx.batch_run(load(gx, g), gx.GX_PPR, src, iters=50)
+    X = out.cpu().numpy().astype(np.float64)
+    assert np.all(X >= 0)
+    assert np.abs(X.sum(axis=0) - 1.0).max() < 1e-4
+    assert np.all(X[src, np.arange(B)] >= 0.15 - 1e-6)
+    lanes = np.unique(np.r_[np.linspace(0, B - 1, 16).astype(int)])
+    ref = oracle.ppr_many(g, src[lanes], 50)
+    for i, b in enumerate(lanes):
+        err = np.abs(X[:, b] - ref[i]).max()
+        assert err <= 1e-6, (int(b), float(err))

@@ -26,14 +26,18 @@ def graphs():
     return [gen.rmat(10, seed=100), gen.rmat(11, seed=101), gen.rmat(12, seed=102)]
 
 
-def serve(gx, graphs, queries, budget=1 << 30, lanes=32, epoch=3, stagger_s=0.0):
-    dgs = [gx.DeviceGraph(g, gx.GX_NEED_OUT | gx.GX_NEED_IN) for g in graphs]
-    srv = gx.Server(budget, lanes_per_pool=lanes, max_pools=4, epoch_supersteps=epoch, ppr_iters=50)
+def serve(gx, graphs, queries, budget=1 << 30, lanes=32, epoch=3, stagger_s=0.0, max_pools=4, dgs=None,
+          gaps=None):
+    if dgs is None:
+        dgs = [gx.DeviceGraph(g, gx.GX_NEED_OUT | gx.GX_NEED_IN) for g in graphs]
+    srv = gx.Server(budget, lanes_per_pool=lanes, max_pools=max_pools, epoch_supersteps=epoch, ppr_iters=50)
     ids = [srv.add_graph(d) for d in dgs]
     qids = {}
     for i, (gi, algo, s) in enumerate(queries):
         qids[srv.submit(ids[gi], algo, s)] = i
-        if stagger_s:
+        if gaps is not None:
+            time.sleep(gaps[i])
+        elif stagger_s:
             time.sleep(stagger_s)
     done = {}
     t0 = time.time()
@@ -58,15 +62,15 @@ def mixed_queries(graphs, n, seed):
     return out
 
 
-def check(gx, graphs, q, c):
+def check(gx, graphs, q, c, threads=1):
     gi, algo, s = q
     g = graphs[gi]
     if algo == gx.GX_SSSP:
-        ref = oracle.sssp(g, s)
+        ref = oracle.sssp(g, s, threads=threads)
         assert np.array_equal(c.result, ref.state)
         assert c.supersteps == ref.K
     else:
-        ref = oracle.ppr(g, s, 50)
+        ref = oracle.ppr(g, s, 50, threads=threads)
         assert np.max(np.abs(c.result.astype(np.float64) - ref)) <= 1e-6
 
 
@@ -120,3 +124,45 @@ def test_serving_rejects_budget_below_one_pool(gx, graphs):
         srv.submit(gid, gx.GX_SSSP, 0)
     assert ei.value.status == 2  # GX_ENOMEM
     srv.close()
+
+
+@pytest.mark.slow
+def test_serving_bench_shape_scale16_to_22(gx):
+    """The served workload's shape: graphs of scales 16, 17, 18 and 22
+    (seeds as in the 16-graph mix), 64-lane pools, up to four pools running
+    at once, queries arriving on Poisson gaps while others run, a budget
+    that cannot hold every pool at once.  A seeded sample of 16 queries
+    (8 SSSP, 8 PPR, at least two of each on the scale-22 graph) is checked
+    against the oracle, and four of them against the same query alone."""
+    graphs = [gen.rmat(16, seed=100), gen.rmat(17, seed=103), gen.rmat(18, seed=105), gen.rmat(22, seed=114)]
+    dgs = [gx.DeviceGraph(g, gx.GX_NEED_OUT | gx.GX_NEED_IN) for g in graphs]
+    rng = np.random.default_rng(55)
+    queries = []
+    for i in range(64):
+        gi = 3 if i % 4 == 0 else int(rng.integers(0, 3))
+        cand = np.nonzero(np.diff(graphs[gi].row_ptr) > 0)[0]
+        queries.append((gi, 1 if i % 2 == 0 else 3, int(rng.choice(cand))))
+    gaps = rng.exponential(0.004, len(queries))
+    import ctypes
+    pool = {}
+    for gi, dg in enumerate(dgs):
+        for algo in (gx.GX_SSSP, gx.GX_PPR):
+            b = ctypes.c_size_t()
+            assert gx.binding.lib.gx_server_bytes_per_lane(dg.handle, algo, ctypes.byref(b)) == 0
+            pool[gi, algo] = 64 * b.value
+    # room for both scale-22 pools and two of the small ones: not for all eight
+    budget = pool[3, gx.GX_SSSP] + pool[3, gx.GX_PPR] + 2 * max(v for k, v in pool.items() if k[0] < 3)
+    assert sum(pool.values()) > budget
+    done = serve(gx, graphs, queries, budget=budget, lanes=64, epoch=4, max_pools=4, dgs=dgs, gaps=gaps)
+    spans = [(c.start_s, c.done_s) for c in done.values()]
+    assert any(a0 < b0 < a1 for a0, a1 in spans for b0, _ in spans)
+    big = [i for i, q in enumerate(queries) if q[0] == 3]
+    sample = [i for i in big if queries[i][1] == 1][:2] + [i for i in big if queries[i][1] == 3][:2]
+    rest = [i for i in rng.permutation(len(queries)) if i not in sample]
+    sample += [i for i in rest if queries[i][1] == 1][:6] + [i for i in rest if queries[i][1] == 3][:6]
+    assert len(sample) == 16
+    for i in sample:
+        check(gx, graphs, queries[i], done[i], threads=0)
+    for i in sample[:2] + sample[4:6]:
+        alone = serve(gx, graphs, [queries[i]], budget=budget, lanes=64, epoch=4, dgs=dgs)
+        assert np.array_equal(alone[0].result.view(np.uint32), done[i].result.view(np.uint32)), i
