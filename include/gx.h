@@ -79,7 +79,9 @@ typedef enum {
  * GX_NEED_OUT is asked; may be NULL otherwise).  l2g[V] maps local to global
  * ids (ascending; NULL = identity) and flags[V] holds GX_FLAG_* bits (NULL =
  * unpartitioned: no vertex is remote).  Self-loops are allowed in the input
- * and ignored by CC; duplicates are allowed.  E < 2^31, V < 2^31.
+ * and ignored by CC; duplicates are allowed.  E < 2^31, V < 2^31; with
+ * GX_NEED_SYM also 2E < 2^31 (the symmetric image holds up to two entries
+ * per edge), else GX_EINVAL.
  */
 typedef struct gx_graph_desc {
     int64_t V, E;
@@ -172,6 +174,16 @@ gx_status gx_state_values(gx_state *s, void **dev_values);
 gx_status gx_state_frontier(gx_state *s, void **dev_bytemap);
 /* Supersteps executed since init. */
 gx_status gx_state_superstep(gx_state *s, int64_t *k);
+
+/*
+ * Frees the process-wide caches the engine keeps between calls: timing
+ * events and the pinned host buffers superstep counters are read through.
+ * Resources held by live states are not touched (they return to the caches
+ * when the states are freed).  Call it before process exit, after freeing
+ * every state, so no HIP object outlives the caller's use of the runtime.
+ * Safe to call at any time; later calls recreate what they need.
+ */
+gx_status gx_release_cached(void);
 
 /*
  * requestGen() -> requestMerge() -> requestApply() in BSP order: one

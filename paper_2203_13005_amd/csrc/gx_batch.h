@@ -10,6 +10,7 @@ namespace gx {
 constexpr int BS_MIN_TILE = 1024;  // smallest SSSP work tile among the variants
 constexpr int BP_TILE = 256;       // in-edges per PPR pull tile (one wave)
 constexpr int BP_DCHUNK = 256;     // tiles per first-level dangling partial
+constexpr double BARRIER_LIMIT_S = 20.0;  // longest wait of a grid barrier before it reports an error
 
 struct BsCtl {
     GridBar bar;
@@ -34,6 +35,7 @@ struct BsArgs {
     uint32_t k0;          // global superstep index of the first superstep (mask parity)
     uint32_t *lane_cnt;   // optional [max_steps x B] activations per lane and superstep
     uint32_t stop_when_idle;
+    unsigned long long bar_ticks;  // wall-clock ticks a grid barrier waits before reporting an error
 };
 
 struct BsWork {
@@ -75,6 +77,7 @@ int coop_grid(const void *kernel, int block, int num_cus, int want, int max_per_
 void bs_layout(const DevGraph &d, uint32_t B, Carver &c, BsWork *w);
 void bp_layout(const DevGraph &d, uint32_t B, Carver &c, BpWork *w);
 hipError_t launch_coop(const void *kernel, int grid, int block, void *args, hipStream_t s);
+unsigned long long barrier_limit_ticks(int device);
 gx_tune default_tune(uint32_t B);
 
 hipError_t bs_launch_superstep(const BsArgs &a, uint32_t k, uint32_t it, int grid, hipStream_t s);

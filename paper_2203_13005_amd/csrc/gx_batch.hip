@@ -222,9 +222,9 @@ __global__ __launch_bounds__(BLOCK) void k_bsssp(BsArgs a) {
     uint32_t k = a.k0;
     for (uint32_t it = 0; it < a.max_steps; it++, k++) {
         bs_compact<BLOCK, VT>(a, k, sh);
-        if (!grid_sync(&a.ctl->bar, gridDim.x, &sh.flag)) return;
+        if (!grid_sync(&a.ctl->bar, gridDim.x, &sh.flag, a.bar_ticks)) return;
         bs_relax<BLOCK, VT>(a, k, it, sh);
-        if (!grid_sync(&a.ctl->bar, gridDim.x, &sh.flag)) return;
+        if (!grid_sync(&a.ctl->bar, gridDim.x, &sh.flag, a.bar_ticks)) return;
         const unsigned long long ch =
             __hip_atomic_load(&a.ctl->changed[k & 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->steps = it + 1;
@@ -637,6 +637,17 @@ void bp_layout(const DevGraph &d, uint32_t B, Carver &c, BpWork *w) {
     w->end = w->seed + B;
 }
 
+// Wall-clock ticks a grid barrier may wait: BARRIER_LIMIT_S seconds at the
+// device's constant wall-clock rate (a superstep phase of the batched
+// kernel takes milliseconds; only a grid that is not co-resident waits that
+// long).
+unsigned long long barrier_limit_ticks(int device) {
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || khz <= 0)
+        khz = 100000;  // 100 MHz, the gfx9 constant clock
+    return (unsigned long long)(BARRIER_LIMIT_S * 1e3 * (double)khz);
+}
+
 hipError_t launch_coop(const void *kernel, int grid, int block, void *args, hipStream_t s) {
     void *params[] = {args};
     return hipLaunchCooperativeKernel(kernel, dim3(grid), dim3(block), params, 0, s);
@@ -720,12 +731,14 @@ gx_status run_bsssp(gx_graph *g, const int32_t *dev_src, uint32_t B, BsWork &w, 
         a.k0 = 0;
         a.lane_cnt = nullptr;
         a.stop_when_idle = 1;
+        a.bar_ticks = barrier_limit_ticks(g->device);
         GX_CHECK_HIP(launch_coop(var->fn, grid, var->block, &a, s), g);
         BsCtl ctl;
         GX_CHECK_HIP(hipMemcpyAsync(&ctl, w.ctl, sizeof ctl, hipMemcpyDeviceToHost, s), g);
         GX_CHECK_HIP(hipStreamSynchronize(s), g);
         if (ctl.bar.error) {
-            set_error("grid barrier timed out in batched SSSP (pass at lane %u)", l0);
+            set_error("grid barrier waited over %.0f s in batched SSSP (pass at lane %u, grid %d x %u)",
+                      BARRIER_LIMIT_S, l0, grid, var->block);
             g->dev_error = true;
             return GX_EDEVICE;
         }

@@ -92,9 +92,11 @@ __device__ __forceinline__ void block_max_scan(int32_t *s, int n, int32_t *lds) 
 
 
 // Grid-wide barrier for a cooperative launch (all workgroups co-resident).
-// Sense is a generation counter; the wait is bounded: after `limit` polls
-// the barrier sets *error and returns false, so a grid can never spin
-// forever.  Returns true when every workgroup arrived.
+// Sense is a generation counter.  The wait is bounded in time: a workgroup
+// that has waited `limit_ticks` of the constant-rate wall clock
+// (wall_clock64) sets *error and leaves, and so does every workgroup that
+// finds *error set, so a grid can never spin forever; the host reports the
+// error.  Returns true when every workgroup arrived.
 struct GridBar {
     unsigned int count;
     unsigned int gen;
@@ -102,7 +104,8 @@ struct GridBar {
     unsigned int pad;
 };
 
-__device__ __forceinline__ bool grid_sync(GridBar *b, unsigned int nblocks, unsigned int *s_flag) {
+__device__ __forceinline__ bool grid_sync(GridBar *b, unsigned int nblocks, unsigned int *s_flag,
+                                          unsigned long long limit_ticks) {
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned int g = __hip_atomic_load(&b->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -112,10 +115,11 @@ __device__ __forceinline__ bool grid_sync(GridBar *b, unsigned int nblocks, unsi
             __hip_atomic_store(&b->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(&b->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            unsigned long long polls = 0;
+            const unsigned long long t0 = (unsigned long long)wall_clock64();
             while (__hip_atomic_load(&b->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
                 __builtin_amdgcn_s_sleep(2);
-                if (++polls > (1ull << 22)) {  // seconds: give up, report, let every block leave
+                if (__hip_atomic_load(&b->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+                if ((unsigned long long)wall_clock64() - t0 > limit_ticks) {
                     atomicOr(&b->error, 1u);
                     break;
                 }

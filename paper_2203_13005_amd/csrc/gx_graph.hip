@@ -86,6 +86,9 @@ static gx_status validate(const gx_graph_desc *d) {
                    d->pr_tile_edges == 1024 || d->pr_tile_edges == 2048,
                GX_EINVAL, "pr_tile_edges=%u not 0, 256, 512, 1024 or 2048", d->pr_tile_edges);
     GX_REQUIRE(d->needs != 0 && (d->needs & ~7u) == 0, GX_EINVAL, "needs=%u invalid", d->needs);
+    // the symmetric image holds up to two entries per directed edge, indexed by int32 row pointers
+    GX_REQUIRE(!(d->needs & GX_NEED_SYM) || 2 * d->E <= (int64_t)INT32_MAX - PULL_VT * 64, GX_EINVAL,
+               "E=%lld too large for the symmetric (CC) image: 2E must stay below 2^31", (long long)d->E);
     GX_REQUIRE(d->row_ptr || d->V == 0, GX_EINVAL, "row_ptr is NULL");
     GX_REQUIRE(d->col || d->E == 0, GX_EINVAL, "col is NULL");
     GX_REQUIRE(!(d->needs & GX_NEED_OUT) || d->w || d->E == 0, GX_EINVAL, "weights required for GX_NEED_OUT");
@@ -466,6 +469,9 @@ extern "C" gx_status gx_graph_load(const gx_graph_desc *desc, void *dev_arena, s
     } catch (const std::bad_alloc &) {
         set_error("host allocation failed while packaging the graph");
         return GX_ENOMEM;
+    } catch (const std::exception &ex) {
+        set_error("graph packaging failed: %s", ex.what());
+        return GX_EINVAL;
     }
 
     gx_graph *g = new (std::nothrow) gx_graph();

@@ -1193,6 +1193,24 @@ static void host_steps_return(DevStep *p) {
     g_hs_free.push_back(p);
 }
 
+extern "C" gx_status gx_release_cached(void) {
+    clear_error();
+    std::lock_guard<std::mutex> lk(g_ev_mu);
+    hipError_t first = hipSuccess;
+    for (hipEvent_t e : g_ev_free) {
+        hipError_t r = hipEventDestroy(e);
+        if (first == hipSuccess) first = r;
+    }
+    g_ev_free.clear();
+    for (DevStep *p : g_hs_free) {
+        hipError_t r = hipHostFree(p);
+        if (first == hipSuccess) first = r;
+    }
+    g_hs_free.clear();
+    GX_REQUIRE(first == hipSuccess, GX_EDEVICE, "releasing cached resources failed: %s", hipGetErrorString(first));
+    return GX_OK;
+}
+
 // Enqueues superstep s->k on `hs` and advances s->k.
 static gx_status enqueue_superstep(gx_state *s, hipStream_t hs) {
     const DevGraph &d = s->g->d;
@@ -1259,12 +1277,15 @@ static gx_status enqueue_superstep(gx_state *s, hipStream_t hs) {
     return GX_OK;
 }
 
-// After a stream synchronisation: fold the pending kernel timings; with
-// `per_step`, superstep k's time goes to per_step[k - k0] when in range.
-static void collect_timings(gx_state *s, gx_step_stats *per_step = nullptr, int64_t k0 = 0, int64_t n = 0) {
+// After a stream synchronisation: fold the pending kernel timings of
+// supersteps before k_end (later ones were enqueued speculatively after
+// convergence and do no work of the solve); with `per_step`, superstep k's
+// time goes to per_step[k - k0] when in range.
+static void collect_timings(gx_state *s, gx_step_stats *per_step = nullptr, int64_t k0 = 0, int64_t n = 0,
+                            int64_t k_end = INT64_MAX) {
     for (auto &pr : s->ev_pending) {
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, pr.a, pr.b) == hipSuccess) {
+        if (pr.k < k_end && hipEventElapsedTime(&ms, pr.a, pr.b) == hipSuccess) {
             s->kernel_ms += ms;
             s->kernel_launches++;
             if (per_step && pr.k >= k0 && pr.k < k0 + n) per_step[pr.k - k0].kernel_ms = ms;
@@ -1351,18 +1372,24 @@ extern "C" gx_status gx_run_until_converged(gx_state *s, uint32_t max_supersteps
     gx_status result = GX_OK;
     const int64_t k_begin = s->k;
     if (s->p.algo == GX_PAGERANK) {
-        int64_t kfirst = s->k;
-        for (uint32_t i = 0; i < max_supersteps; i++) {
-            gx_status st = enqueue_superstep(s, hs);
+        // In chunks that leave the counter ring room for the chunk's slots
+        // plus the following one, so no slot is reused before it is read.
+        for (uint32_t done = 0; done < max_supersteps;) {
+            const uint32_t g = std::min<uint32_t>(max_supersteps - done, STEP_RING - 2);
+            const int64_t kfirst = s->k;
+            for (uint32_t i = 0; i < g; i++) {
+                gx_status st = enqueue_superstep(s, hs);
+                if (st != GX_OK) return st;
+            }
+            gx_status st = read_steps(s, kfirst, g + 1, hs, host);
             if (st != GX_OK) return st;
-        }
-        gx_status st = read_steps(s, kfirst, max_supersteps + 1, hs, host);
-        if (st != GX_OK) return st;
-        for (uint32_t i = 0; i < max_supersteps; i++) {
-            gx_step_stats o;
-            to_stats(s, host[i], host[i + 1], &o);
-            if (per_step) per_step[i] = o;
-            rs.edges += o.edges;
+            for (uint32_t i = 0; i < g; i++) {
+                gx_step_stats o;
+                to_stats(s, host[i], host[i + 1], &o);
+                if (per_step) per_step[done + i] = o;
+                rs.edges += o.edges;
+            }
+            done += g;
         }
         rs.supersteps = max_supersteps;
         rs.converged = 0;
@@ -1371,11 +1398,13 @@ extern "C" gx_status gx_run_until_converged(gx_state *s, uint32_t max_supersteps
         // synchronises once per group; supersteps enqueued after convergence
         // find an empty frontier, change nothing and cost a few microseconds
         // each, less than a host round trip.  The first group covers the
-        // superstep count of the last converged run on this graph (at least
-        // 6, at most 16), the later ones 8 at a time.
+        // superstep count of the last converged run on this graph (which
+        // includes the superstep that changed nothing, so a repeat of that
+        // run converges inside the group; at least 6, at most 16), the later
+        // ones 8 at a time.
         const int hist = s->p.algo == GX_CC ? 1 : 0;
         const uint32_t last = s->g->last_supersteps[hist].load(std::memory_order_relaxed);
-        uint32_t done = 0, spec = std::min<uint32_t>(16, std::max<uint32_t>(6, last + 1));
+        uint32_t done = 0, spec = std::min<uint32_t>(16, std::max<uint32_t>(6, last));
         bool conv = false;
         while (done < max_supersteps && !conv) {
             uint32_t g = std::min(spec, max_supersteps - done);
@@ -1408,7 +1437,7 @@ extern "C" gx_status gx_run_until_converged(gx_state *s, uint32_t max_supersteps
             result = GX_ENOTCONVERGED;
         }
     }
-    collect_timings(s, per_step, k_begin, rs.supersteps);
+    collect_timings(s, per_step, k_begin, rs.supersteps, k_begin + rs.supersteps);
     rs.edge_kernel_ms = s->kernel_ms - ms0;
     rs.edge_kernel_launches = s->kernel_launches - l0;
     rs.wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

@@ -121,3 +121,17 @@ def test_batch_and_server_null_graph():
     n = ctypes.c_size_t()
     assert b.lib.gx_batch_bytes(None, b.GX_SSSP, 32, ctypes.byref(n)) == b.GX_EINVAL
     assert b.lib.gx_server_bytes_per_lane(None, b.GX_SSSP, ctypes.byref(n)) == b.GX_EINVAL
+
+
+def test_symmetric_image_size_limit_is_einval():
+    """CC's symmetric image holds up to 2E entries behind int32 row pointers:
+    a description with 2E beyond that range is refused on the host before
+    any array is read (the arrays here are far shorter than E)."""
+    from paper_2203_13005_amd import binding as b
+    rp = np.zeros(3, np.int32)
+    col = np.zeros(1, np.int32)
+    E = (1 << 30) + 1
+    d = b._GraphDesc(2, E, b._np_ptr(rp), b._np_ptr(col), None, None, None, b.GX_NEED_SYM)
+    n = ctypes.c_size_t()
+    assert b.lib.gx_graph_bytes(ctypes.byref(d), ctypes.byref(n)) == b.GX_EINVAL
+    assert b"symmetric" in b.lib.gx_last_error()
