@@ -141,7 +141,8 @@ def test_serving_bench_shape_scale16_to_22(gx):
     for i in range(64):
         gi = 3 if i % 4 == 0 else int(rng.integers(0, 3))
         cand = np.nonzero(np.diff(graphs[gi].row_ptr) > 0)[0]
-        queries.append((gi, 1 if i % 2 == 0 else 3, int(rng.choice(cand))))
+        # SSSP and PPR alternate in pairs, so the scale-22 queries (every fourth) hold both kinds
+        queries.append((gi, 1 if i % 8 < 4 else 3, int(rng.choice(cand))))
     gaps = rng.exponential(0.004, len(queries))
     import ctypes
     pool = {}
