@@ -222,6 +222,26 @@ gx_status gx_sync_delta(gx_state *s, int32_t *dev_gid, uint32_t *dev_val, uint32
                         uint32_t *count, int32_t *skippable, void *stream);
 
 /*
+ * For callers that cannot allocate device memory or synchronise -- code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc: gx_sync_delta with the same pairs, order and commit rule, made
+ * asynchronous.  The per-workgroup counts go to a fixed static device array
+ * of 256 KiB (one per GPU, held until the process ends) instead of the
+ * state's workspace, and the pair count is written to the device word
+ * *dev_count instead of being returned, so the call allocates nothing,
+ * copies nothing to the host and does not synchronise `stream`.  The pairs
+ * are committed (dirty map cleared, synced copy updated) only when the count
+ * is at most `cap`; a caller seeing *dev_count > cap has a full count and an
+ * unchanged sync record, as with GX_ENOMEM of gx_sync_delta.  Limit: graphs
+ * of at most 2^29 vertices (GX_EINVAL beyond).  Calls that overlap in time
+ * on one GPU share the array and race: issue them on one stream, or order
+ * them.  Errors: GX_EINVAL, GX_EDEVICE (also if the array's address cannot
+ * be looked up).
+ */
+gx_status gx_sync_delta_noalloc(gx_state *s, int32_t *dev_gid, uint32_t *dev_val, uint32_t cap,
+                                uint32_t *dev_count, void *stream);
+
+/*
  * The receiving side of update(): merges the (global id, value) pairs that
  * other parts emitted with gx_sync_delta into this part's replicas, for
  * SSSP and CC (integer min; Section "Operation Interfaces", Section

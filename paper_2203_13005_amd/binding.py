@@ -100,6 +100,7 @@ _SIGS = {
                                                 ctypes.POINTER(StepStats)]),
     "gx_sync_delta": (ctypes.c_int32, [_P, _P, _P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
                                        ctypes.POINTER(ctypes.c_int32), _P]),
+    "gx_sync_delta_noalloc": (ctypes.c_int32, [_P, _P, _P, ctypes.c_uint32, _P, _P]),
     "gx_apply_delta": (ctypes.c_int32, [_P, _P, _P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int64), _P]),
     "gx_batch_bytes": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_size_t)]),
     "gx_batch_run": (ctypes.c_int32, [_P, ctypes.c_int32, _P, ctypes.c_uint32, ctypes.c_float, ctypes.c_uint32,
@@ -341,6 +342,19 @@ class State:
         if on_device:
             return gid[:c], val[:c], bool(sk.value)
         return gid[:c].cpu().numpy(), val[:c].cpu().numpy().view(np.uint32), bool(sk.value)
+
+    def sync_delta_noalloc(self, gid, val, count, stream=None):
+        """gx_sync_delta_noalloc: writes up to gid.numel() pairs into the given
+        int32 device tensors and the pair count into the one-element int32
+        device tensor `count`; asynchronous, allocates nothing."""
+        import torch
+        for t in (gid, val, count):
+            if t.dtype != torch.int32 or not t.is_contiguous() or t.device.type != "cuda":
+                raise ValueError("gid, val and count must be contiguous int32 device tensors")
+        cap = min(gid.numel(), val.numel())
+        _check(lib.gx_sync_delta_noalloc(self.handle, ctypes.c_void_p(gid.data_ptr()),
+                                         ctypes.c_void_p(val.data_ptr()), cap, ctypes.c_void_p(count.data_ptr()),
+                                         _stream_handle(stream)))
 
     def apply_delta(self, gids, vals, stream=None) -> int:
         """Merges (global id, value) pairs that other parts emitted (device int32

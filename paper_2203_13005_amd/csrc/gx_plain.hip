@@ -926,6 +926,7 @@ __global__ __launch_bounds__(256) void k_apply_delta(const int32_t *__restrict__
 }
 
 __global__ void k_zero_step(DevStep *step) { *step = DevStep{}; }
+__global__ void k_set_u32(uint32_t *p, uint32_t v) { *p = v; }
 
 template <class T>
 inline unsigned grid_for(T n, unsigned block) {
@@ -1476,6 +1477,75 @@ extern "C" gx_status gx_sync_delta(gx_state *s, int32_t *dev_gid, uint32_t *dev_
         set_error("sync set has %u entries, capacity %u", total, cap);
         return GX_ENOMEM;
     }
+    return GX_OK;
+}
+
+// ------------------------------------------------------------ sync set, no allocation
+// The per-workgroup counts of gx_sync_delta_noalloc live in this array: one
+// copy per GPU, held until the process ends, shared by every call on that
+// GPU.  Host code never passes its name to a kernel (on the host it is only a
+// stand-in symbol): the device address of each GPU's copy is looked up once
+// with hipGetSymbolAddress, with that GPU current, and kept in g_scratch_ptr.
+// Every count a launch reads is written earlier in the same call, so nothing
+// in the array has to start at zero.
+constexpr int NOALLOC_SCRATCH_WORDS = 65536;  // 256 KiB: sync sets of up to 2^29 vertices
+static __device__ __align__(256) uint32_t scratch[NOALLOC_SCRATCH_WORDS];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static uint32_t *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+static gx_status scratch_for_device(int device, uint32_t **out) {
+    GX_REQUIRE(device >= 0 && device < NOALLOC_MAX_DEVICES, GX_EINVAL, "device ordinal %d out of range", device);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != device) e = hipSetDevice(device);
+        void *ptr = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !ptr) {
+            set_error("hipGetSymbolAddress(scratch) on device %d failed: %s", device,
+                      hipGetErrorString(e == hipSuccess ? hipErrorInvalidSymbol : e));
+            return GX_EDEVICE;
+        }
+        g_scratch_ptr[device] = static_cast<uint32_t *>(ptr);
+    }
+    *out = g_scratch_ptr[device];
+    return GX_OK;
+}
+
+extern "C" gx_status gx_sync_delta_noalloc(gx_state *s, int32_t *dev_gid, uint32_t *dev_val, uint32_t cap,
+                                           uint32_t *dev_count, void *stream) {
+    clear_error();
+    GX_REQUIRE(s && dev_count, GX_EINVAL, "NULL argument");
+    GX_REQUIRE(cap == 0 || (dev_gid && dev_val), GX_EINVAL, "output buffers are NULL");
+    GX_REQUIRE(!s->dev_error && !s->g->dev_error, GX_EDEVICE, "sticky device error");
+    GX_REQUIRE(s->delta_blocks <= NOALLOC_SCRATCH_WORDS, GX_EINVAL,
+               "gx_sync_delta_noalloc handles at most %lld vertices (graph has %lld)",
+               (long long)NOALLOC_SCRATCH_WORDS * 256 * 32, (long long)s->g->d.V);
+    uint32_t *cnt = nullptr;
+    gx_status st = scratch_for_device(s->g->device, &cnt);
+    if (st != GX_OK) return st;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const DevGraph &d = s->g->d;
+    if (d.W == 0) {  // no vertices: the count is zero (a one-thread kernel, not a memset node)
+        hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, hs, dev_count, 0u);
+        GX_CHECK_HIP(hipGetLastError(), s);
+        return GX_OK;
+    }
+    bool all = s->p.delta_mode == GX_DELTA_ALL;
+    const uint32_t *remote = s->p.algo == GX_CC ? d.remote_any : d.remote_out;
+    bool pr = s->p.algo == GX_PAGERANK;
+    const uint32_t *vals = pr ? reinterpret_cast<const uint32_t *>(s->x[s->k & 1]) : s->val;
+    uint8_t *dirty = pr ? nullptr : s->dirty8;
+    uint32_t *synced = pr ? s->synced : nullptr;
+    hipLaunchKernelGGL(k_delta_count, dim3(s->delta_blocks), dim3(256), 0, hs, d.W, d.V, remote, (int)all, dirty,
+                       vals, synced, cnt);
+    hipLaunchKernelGGL(k_delta_emit, dim3(s->delta_blocks), dim3(256), 0, hs, d.W, d.V, remote, (int)all, dirty,
+                       vals, synced, d.l2g, cnt, s->delta_blocks, cap, dev_gid, dev_val, dev_count);
+    GX_CHECK_HIP(hipGetLastError(), s);
     return GX_OK;
 }
 

@@ -94,6 +94,7 @@ def test_null_handles_are_einval():
     assert b.lib.gx_superstep(None, None, None) == b.GX_EINVAL
     n = ctypes.c_uint32()
     assert b.lib.gx_sync_delta(None, None, None, 0, ctypes.byref(n), None, None) == b.GX_EINVAL
+    assert b.lib.gx_sync_delta_noalloc(None, None, None, 0, None, None) == b.GX_EINVAL
     act = ctypes.c_int64()
     assert b.lib.gx_apply_delta(None, None, None, 0, ctypes.byref(act), None) == b.GX_EINVAL
     assert b.lib.gx_version().startswith(b"gx")
