@@ -66,6 +66,9 @@ def _load():
             "or_dijkstra_many": (None, [I64, I64, P, P, P, P, I32, P, ctypes.c_int]),
             "or_ppr_many": (ctypes.c_int, [I64, I64, P, P, P, D, P, I32, I32, P, ctypes.c_int]),
             "or_max_threads": (ctypes.c_int, []),
+            "or_sym_adjacency": (I64, [I64, I64, P, P, P, P]),
+            "or_lp_superstep": (I64, [I64, P, P, P, P]),
+            "or_lp": (I64, [I64, I64, P, P, P, I64, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -205,6 +208,50 @@ def cc(g, max_steps: int = 1 << 30, threads: int = 1) -> MinRun:
         raise MemoryError("oracle cc")
     n = K if K > 0 else cap
     return MinRun(lab[: g.V], int(K), fs[:n], ef[:n], ch[:n])
+
+
+class LpRun:
+    def __init__(self, state, K, changed):
+        self.state, self.K, self.changed = state, K, changed
+
+
+def lp(g, max_steps: int = 15) -> LpRun:
+    """Label propagation (most frequent neighbour label, smallest on a tie),
+    at most max_steps iterations.  K = iterations run when the last one
+    changed nothing, -1 when the cap was reached with labels still moving."""
+    lib = _load()
+    src, dst, _ = _edges(g)
+    l2g = None if g.l2g is None else np.ascontiguousarray(g.l2g, np.int32)
+    lab = np.empty(max(g.V, 1), np.uint32)
+    ch = np.zeros(max(max_steps, 1), np.int64)
+    K = lib.or_lp(g.V, g.E, _p(src), _p(dst), _p(l2g), int(max_steps), _p(lab), _p(ch))
+    if K == -2:
+        raise MemoryError("oracle lp")
+    n = K if K > 0 else max_steps
+    return LpRun(lab[: g.V], int(K), ch[:n])
+
+
+def lp_steps(g, max_steps: int = 15):
+    """Labels after every LP iteration: list label_0 .. label_n (n = the
+    iterations run, stopping after the first that changes nothing)."""
+    lib = _load()
+    src, dst, _ = _edges(g)
+    rp = np.empty(g.V + 1, np.int64)
+    nb = np.empty(max(2 * g.E, 1), np.int32)
+    if lib.or_sym_adjacency(g.V, g.E, _p(src), _p(dst), _p(rp), _p(nb)) < 0:
+        raise MemoryError("oracle lp")
+    lab = (np.arange(g.V) if g.l2g is None else np.asarray(g.l2g)).astype(np.uint32)
+    out = [lab.copy()]
+    for _ in range(max_steps):
+        nxt = np.empty(max(g.V, 1), np.uint32)
+        c = lib.or_lp_superstep(g.V, _p(rp), _p(nb), _p(lab), _p(nxt))
+        if c < 0:
+            raise MemoryError("oracle lp")
+        lab = nxt[: g.V].copy()
+        out.append(lab.copy())
+        if c == 0:
+            break
+    return out
 
 
 def sssp_many(g, sources, threads: int = 0):

@@ -28,6 +28,10 @@
  *             min; F_{k+1} = vertices whose distance strictly decreased.
  *   CC        label[v] = global id of v; F1 = vertices with an edge; labels
  *             travel along both directions of every edge; merge is min.
+ *   LP        (second reading of "label propagation", with the evaluation's
+ *             15-iteration cap) labels start at the global id; every vertex
+ *             takes the most frequent label among its distinct neighbours,
+ *             the smallest on a tie (or_lp).
  * Everything runs in plain loops over the edge list, with PageRank in double
  * precision.  The functions above the "OpenMP timing mode" line are the
  * single-threaded reference.  The functions below it run the same
@@ -231,6 +235,127 @@ int64_t or_delta(int64_t V, const uint8_t *remote, const int32_t *l2g, const uin
         n++;
     }
     return n;
+}
+
+/*
+ * Label propagation in its community-detection form (the "LP" of Section
+ * "Setup", which the evaluation caps at 15 iterations; NEXT-3 reading):
+ *   labels start at the global id (l2g[v], or v);
+ *   Gen:   every edge carries the label of each endpoint to the other
+ *          (edges are undirected; self-loops carry nothing; a neighbour
+ *          joined to v by several edges counts once);
+ *   Merge: the multiset of labels arriving at v;
+ *   Apply: v takes the label that arrives most often, the smallest of the
+ *          most frequent ones on a tie; a vertex without neighbours keeps
+ *          its label.  Messages read the labels of the start of the
+ *          iteration (Jacobi), like every other superstep here.
+ * or_sym_adjacency builds the deduplicated neighbour lists once (rows in
+ * ascending vertex order, each row ascending); or_lp_superstep runs one
+ * iteration on them and returns the number of vertices whose label changed.
+ */
+static int cmp_u64(const void *a, const void *b)
+{
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return x < y ? -1 : x > y;
+}
+
+static int cmp_u32(const void *a, const void *b)
+{
+    uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
+    return x < y ? -1 : x > y;
+}
+
+/* Returns the number of neighbour entries (nb_out needs room for 2E); -2 on
+ * allocation failure.  rp_out has V+1 entries. */
+int64_t or_sym_adjacency(int64_t V, int64_t E, const int32_t *src, const int32_t *dst,
+                         int64_t *rp_out, int32_t *nb_out)
+{
+    uint64_t *pairs = (uint64_t *)malloc((size_t)(2 * E > 0 ? 2 * E : 1) * sizeof(uint64_t));
+    if (!pairs) return -2;
+    int64_t n = 0;
+    for (int64_t e = 0; e < E; e++) {
+        uint64_t u = (uint32_t)src[e], v = (uint32_t)dst[e];
+        if (u == v) continue;
+        pairs[n++] = (u << 32) | v;
+        pairs[n++] = (v << 32) | u;
+    }
+    qsort(pairs, (size_t)n, sizeof(uint64_t), cmp_u64);
+    for (int64_t v = 0; v <= V; v++) rp_out[v] = 0;
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; i++) {
+        if (i > 0 && pairs[i] == pairs[i - 1]) continue;
+        int64_t u = (int64_t)(pairs[i] >> 32);
+        nb_out[m++] = (int32_t)(pairs[i] & 0xFFFFFFFFu);
+        rp_out[u + 1]++;
+    }
+    for (int64_t v = 0; v < V; v++) rp_out[v + 1] += rp_out[v];
+    free(pairs);
+    return m;
+}
+
+int64_t or_lp_superstep(int64_t V, const int64_t *rp, const int32_t *nb, const uint32_t *label,
+                        uint32_t *label_next)
+{
+    int64_t maxd = 0;
+    for (int64_t v = 0; v < V; v++)
+        if (rp[v + 1] - rp[v] > maxd) maxd = rp[v + 1] - rp[v];
+    uint32_t *tmp = (uint32_t *)malloc((size_t)(maxd > 0 ? maxd : 1) * sizeof(uint32_t));
+    if (!tmp) return -2;
+    int64_t changed = 0;
+    for (int64_t v = 0; v < V; v++) {
+        int64_t d = rp[v + 1] - rp[v];
+        if (d == 0) {
+            label_next[v] = label[v];
+            continue;
+        }
+        for (int64_t i = 0; i < d; i++) tmp[i] = label[nb[rp[v] + i]];
+        qsort(tmp, (size_t)d, sizeof(uint32_t), cmp_u32);
+        /* runs of equal labels in ascending order: the first longest run
+         * holds the smallest of the most frequent labels */
+        uint32_t best = tmp[0];
+        int64_t best_n = 0, run = 0;
+        for (int64_t i = 0; i < d; i++) {
+            run = (i > 0 && tmp[i] == tmp[i - 1]) ? run + 1 : 1;
+            if (run > best_n) {
+                best_n = run;
+                best = tmp[i];
+            }
+        }
+        label_next[v] = best;
+        changed += best != label[v];
+    }
+    free(tmp);
+    return changed;
+}
+
+/*
+ * LP for at most max_steps iterations, stopping after the first iteration
+ * that changes nothing (counted).  label: V outputs; changed[k] (optional)
+ * receives iteration k's changed count.  Returns the iterations run when the
+ * last one changed nothing, -1 when max_steps ran and labels still moved
+ * (label then holds the state after max_steps), -2 on allocation failure.
+ */
+int64_t or_lp(int64_t V, int64_t E, const int32_t *src, const int32_t *dst, const int32_t *l2g,
+              int64_t max_steps, uint32_t *label, int64_t *changed)
+{
+    int64_t *rp = (int64_t *)malloc((size_t)(V + 1) * sizeof(int64_t));
+    int32_t *nb = (int32_t *)malloc((size_t)(2 * E > 0 ? 2 * E : 1) * sizeof(int32_t));
+    uint32_t *nl = (uint32_t *)malloc((size_t)(V > 0 ? V : 1) * sizeof(uint32_t));
+    if (!rp || !nb || !nl || or_sym_adjacency(V, E, src, dst, rp, nb) < 0) {
+        free(rp); free(nb); free(nl);
+        return -2;
+    }
+    for (int64_t v = 0; v < V; v++) label[v] = l2g ? (uint32_t)l2g[v] : (uint32_t)v;
+    int64_t K = -1;
+    for (int64_t k = 0; k < max_steps; k++) {
+        int64_t c = or_lp_superstep(V, rp, nb, label, nl);
+        if (c < 0) { K = -2; break; }
+        if (changed) changed[k] = c;
+        memcpy(label, nl, (size_t)V * sizeof(uint32_t));
+        if (c == 0) { K = k + 1; break; }
+    }
+    free(rp); free(nb); free(nl);
+    return K;
 }
 
 /* ------------------------------------------------------------------------

@@ -297,3 +297,105 @@ def test_openmp_many_sources_equal_single_runs():
     X = oracle.ppr_many(g, srcs[:6], 20)
     for b in range(6):
         assert np.array_equal(X[b].view(np.uint64), oracle.ppr(g, int(srcs[b]), 20).view(np.uint64))
+
+
+# ---------------------------------------------------------------- label propagation
+
+def _undirected(V, pairs):
+    e = np.array(pairs, dtype=np.int64).reshape(-1, 2)
+    return gen.from_edges(V, e[:, 0], e[:, 1], np.ones(len(e), np.int64))
+
+
+def test_hand_example_lp():
+    with open(os.path.join(GOLDEN, "hand_lp_8v.json")) as f:
+        h = json.load(f)
+    g = _undirected(h["V"], h["edges"])
+    steps = oracle.lp_steps(g)
+    assert [s.tolist() for s in steps[1:]] == h["labels_after_iteration"]
+    run = oracle.lp(g, 15)
+    assert run.K == h["K"] and run.changed.tolist() == h["changed"]
+    assert run.state.tolist() == h["labels_after_iteration"][-1]
+
+
+@pytest.mark.parametrize("n", [3, 4, 7])
+def test_lp_complete_graph(n):
+    # iteration 1: vertex 0 sees ids 1..n-1 once each -> 1; every other
+    # vertex sees 0 among its distinct ids -> 0.  Iteration 2: 0 is the
+    # majority (or the smaller of a 1-1 tie at n = 3) everywhere.
+    g = _undirected(n, [(i, j) for i in range(n) for j in range(i + 1, n)])
+    steps = oracle.lp_steps(g)
+    assert steps[1].tolist() == [1] + [0] * (n - 1)
+    assert steps[2].tolist() == [0] * n
+    run = oracle.lp(g)
+    assert run.K == 3 and run.changed.tolist() == [n, 1, 0]
+
+
+@pytest.mark.parametrize("m", [2, 5])
+def test_lp_star_oscillates_to_the_cap(m):
+    # the hub takes the smallest leaf id, the leaves the hub's label, and the
+    # two sides swap every iteration: after an odd count, hub 1 and leaves 0
+    g = _undirected(m + 1, [(0, j) for j in range(1, m + 1)])
+    run = oracle.lp(g, 15)
+    assert run.K == -1
+    assert run.state.tolist() == [1] + [0] * m
+    assert run.changed.tolist() == [m + 1] * 15
+    assert oracle.lp(g, 4).state.tolist() == [0] + [1] * m
+
+
+def test_lp_path_first_iteration():
+    n = 9
+    g = _undirected(n, [(i, i + 1) for i in range(n - 1)])
+    assert oracle.lp_steps(g, 1)[1].tolist() == [1] + list(range(0, n - 2)) + [n - 2]
+
+
+def test_lp_degenerate_cases():
+    # no edges: every label stays, one iteration that changes nothing
+    g = gen.from_edges(5, np.array([], np.int64), np.array([], np.int64), np.array([], np.int64))
+    run = oracle.lp(g)
+    assert run.K == 1 and run.state.tolist() == list(range(5))
+    # self-loops carry nothing, duplicates count once: the same as the clean graph
+    clean = _undirected(4, [(0, 1), (1, 2), (2, 3)])
+    dirty = _undirected(4, [(0, 1), (1, 0), (0, 1), (1, 2), (2, 3), (3, 3), (2, 2), (3, 2)])
+    for a, b in zip(oracle.lp_steps(clean), oracle.lp_steps(dirty)):
+        assert np.array_equal(a, b)
+    # two disjoint cliques settle on their smallest ids
+    pairs = [(i, j) for i in range(4) for j in range(i + 1, 4)] + \
+            [(i, j) for i in range(4, 9) for j in range(i + 1, 9)]
+    assert oracle.lp(_undirected(9, pairs)).state.tolist() == [0] * 4 + [4] * 5
+
+
+def test_lp_partition_starts_from_global_ids():
+    p = gen.rmat_part(10, seed=3, part=2)
+    steps = oracle.lp_steps(p, 1)
+    assert np.array_equal(steps[0], p.l2g.astype(np.uint32))
+    # every new label is a global id of a neighbour (or the vertex's own, when isolated)
+    assert np.isin(steps[1], p.l2g).all()
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_lp_certificate_random(seed):
+    """Every label after an iteration occurs among the neighbours' labels of
+    the iteration before at least as often as any other, and no smaller
+    label occurs as often (counted with Python dictionaries over a
+    numpy-built neighbour set)."""
+    rng = np.random.default_rng(seed)
+    V = 60
+    src, dst = rng.integers(0, V, 200), rng.integers(0, V, 200)
+    g = gen.from_edges(V, src, dst, np.ones(200, np.int64))
+    nbrs = [set() for _ in range(V)]
+    for u, v in zip(src, dst):
+        if u != v:
+            nbrs[u].add(int(v))
+            nbrs[v].add(int(u))
+    steps = oracle.lp_steps(g, 15)
+    for old, new in zip(steps[:-1], steps[1:]):
+        for v in range(V):
+            if not nbrs[v]:
+                assert new[v] == old[v]
+                continue
+            cnt = {}
+            for u in nbrs[v]:
+                cnt[int(old[u])] = cnt.get(int(old[u]), 0) + 1
+            top = max(cnt.values())
+            assert cnt.get(int(new[v]), 0) == top
+            assert all(lab >= new[v] for lab, c in cnt.items() if c == top)
