@@ -443,6 +443,46 @@ def bench_exchange(gx, torch, np, gen, scale=22, nparts=8, reps=3):
             "whole_graph_messages_per_solve": int(rs.edges), "gteps": rs.edges / dt / 1e9}
 
 
+def bench_lp(gx, torch, np, gen, g=None, scale=22, cap=15, reps=3):
+    """Label propagation (most frequent neighbour label, smallest on a tie)
+    on the symmetrised R-MAT scale-22 graph (seed 2), at most 15 iterations;
+    the first iteration is checked against the oracle's iteration."""
+    import oracle
+    if g is None:
+        g = gen.rmat(scale, seed=2)
+    dg = gx.DeviceGraph(g, gx.GX_NEED_SYM)
+    st = gx.State(dg, gx.GX_LP, timing=True)
+    st.superstep()
+    adj = oracle.SymAdjacency(g)
+    t0 = time.perf_counter()
+    want = adj.lp_step(np.arange(g.V, dtype=np.uint32))
+    cpu_iter_s = time.perf_counter() - t0
+    assert np.array_equal(st.values_numpy(), want), "LP iteration 1 differs from the oracle"
+    times, kern = [], []
+    for _ in range(reps + 1):
+        st.reset()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rs, steps = st.run(cap, per_step=True, allow_cap=True)
+        times.append(time.perf_counter() - t)
+        kern.append(rs.edge_kernel_ms)
+    times, kern = times[1:], kern[1:]
+    i = int(np.argsort(times)[len(times) // 2])
+    dt, it = times[i], int(rs.supersteps)
+    E_sym = int(steps[0][1])
+    log(f"LP: {it} iterations ({'converged' if rs.converged else 'cap'}), {dt * 1e3:.2f} ms per run, "
+        f"{dt * 1e3 / it:.3f} ms per iteration; one oracle iteration on one core {cpu_iter_s:.2f} s")
+    alg = 4 * E_sym + 16 * g.V  # neighbour ids + labels read once per vertex + new labels written (lower bracket)
+    return {"workload": f"label propagation on R-MAT scale {scale} (seed 2, symmetrised: {g.V} vertices, "
+                        f"{E_sym} neighbour entries), at most {cap} iterations",
+            "iterations": it, "converged": bool(rs.converged), "changed_per_iteration": [s[2] for s in steps],
+            "ms_per_run": dt * 1e3, "ms_per_iteration": dt * 1e3 / it,
+            "kernel_ms_per_iteration": kern[i] / it, "gteps": E_sym * it / dt / 1e9,
+            "algorithmic_bytes_per_iteration": alg,
+            "frac_of_hbm_peak": alg / (kern[i] / it / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "oracle_one_iteration_one_core_s": cpu_iter_s}
+
+
 def bench_partition(gx, torch, np, gen, reps=3):
     """One part (1 of 8) of a hash vertex-cut of R-MAT scale 25 (seed 3):
     30 PageRank supersteps and min-label CC to convergence."""
@@ -557,7 +597,7 @@ def load_traffic():
     return t
 
 
-LEGS = ("sssp", "pagerank", "partition", "exchange", "batched", "serving")
+LEGS = ("sssp", "pagerank", "partition", "lp", "exchange", "batched", "serving")
 
 
 def bench_sssp(args, gx, torch, np, gen):
@@ -735,6 +775,8 @@ def main():
     part = None
     if "partition" in legs:
         out["partition_scale25"], part = bench_partition(gx, torch, np, gen)
+    if "lp" in legs:
+        out["lp_scale22"] = bench_lp(gx, torch, np, gen, g)
     if "exchange" in legs:
         out["exchange_8parts_scale22"] = bench_exchange(gx, torch, np, gen)
     g4 = src4 = None

@@ -59,7 +59,10 @@ typedef enum {
     GX_PAGERANK = 0,  /* float32 ranks; fixed number of supersteps */
     GX_SSSP     = 1,  /* uint32 distances, INF = 0xFFFFFFFF; to convergence */
     GX_CC       = 2,  /* uint32 labels (global ids); to convergence */
-    GX_PPR      = 3   /* float32 personalised PageRank (batched / serving only) */
+    GX_PPR      = 3,  /* float32 personalised PageRank (batched / serving only) */
+    GX_LP       = 4   /* uint32 labels (global ids), label propagation: the most frequent label among
+                         a vertex's distinct neighbours, the smallest on a tie; runs until nothing
+                         changes or max_supersteps (the evaluation caps it at 15); needs GX_NEED_SYM */
 } gx_algo;
 
 /* Which device images gx_graph_load builds (bitmask). */

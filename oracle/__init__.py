@@ -254,6 +254,27 @@ def lp_steps(g, max_steps: int = 15):
     return out
 
 
+class SymAdjacency:
+    """Deduplicated symmetric neighbour lists of a graph (the oracle's own)."""
+
+    def __init__(self, g):
+        lib = _load()
+        src, dst, _ = _edges(g)
+        self.rp = np.empty(g.V + 1, np.int64)
+        self.nb = np.empty(max(2 * g.E, 1), np.int32)
+        if lib.or_sym_adjacency(g.V, g.E, _p(src), _p(dst), _p(self.rp), _p(self.nb)) < 0:
+            raise MemoryError("oracle lp")
+        self.V = g.V
+
+    def lp_step(self, labels: np.ndarray) -> np.ndarray:
+        """One LP iteration from the given labels."""
+        lab = np.ascontiguousarray(labels, np.uint32)
+        nxt = np.empty(max(self.V, 1), np.uint32)
+        if _load().or_lp_superstep(self.V, _p(self.rp), _p(self.nb), _p(lab), _p(nxt)) < 0:
+            raise MemoryError("oracle lp")
+        return nxt[: self.V]
+
+
 def sssp_many(g, sources, threads: int = 0):
     """Independent single-source runs of the reference Bellman-Ford, one per
     host thread (the several sources of Section "Setup", first footnote):

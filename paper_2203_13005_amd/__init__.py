@@ -9,8 +9,10 @@ no CPU fallback.
 """
 from .binding import (  # noqa: F401
     GX_CC,
+    GX_OK,
     GX_DELTA_ALL,
     GX_DELTA_REMOTE,
+    GX_LP,
     GX_NEED_IN,
     GX_NEED_OUT,
     GX_NEED_SYM,

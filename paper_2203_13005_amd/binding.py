@@ -13,7 +13,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_PKG, "libgx.so")
 
 GX_OK, GX_EINVAL, GX_ENOMEM, GX_EDEVICE, GX_ENOTCONVERGED, GX_EBUSY, GX_ENOTFOUND = range(7)
-GX_PAGERANK, GX_SSSP, GX_CC, GX_PPR = 0, 1, 2, 3
+GX_PAGERANK, GX_SSSP, GX_CC, GX_PPR, GX_LP = 0, 1, 2, 3, 4
 GX_NEED_OUT, GX_NEED_IN, GX_NEED_SYM = 1, 2, 4
 GX_DELTA_REMOTE, GX_DELTA_ALL = 0, 1
 INF = 0xFFFFFFFF

@@ -489,6 +489,10 @@ extern "C" gx_status gx_graph_load(const gx_graph_desc *desc, void *dev_arena, s
     g->num_cus = device_cus(g->device);
     g->host_outdeg.resize(desc->V);
     for (int64_t v = 0; v < desc->V; v++) g->host_outdeg[v] = desc->row_ptr[v + 1] - desc->row_ptr[v];
+    if (!h.sym_rp.empty()) {
+        g->host_symdeg.resize(desc->V);
+        for (int64_t v = 0; v < desc->V; v++) g->host_symdeg[v] = h.sym_rp[v + 1] - h.sym_rp[v];
+    }
 
     hipStream_t s = static_cast<hipStream_t>(stream);
     Uploader up;

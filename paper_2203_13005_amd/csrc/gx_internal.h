@@ -93,6 +93,17 @@ inline int64_t pull_groups(int64_t V) { return pull_bins(V) * ((V >> PULL_BAND_B
 inline int64_t pull_rec_cap(int64_t V, int64_t E) { return E + (PULL_VT - 1) * pull_groups(V) + PULL_VT; }
 inline int64_t pull_unit_cap(int64_t V, int64_t E) { return pull_rec_cap(V, E) / PULL_UNIT + pull_groups(V) + 1; }
 
+// Label propagation: vertices are grouped by the number of distinct
+// neighbours d.  Classes 0..4 take d <= 4, 8, 16, 32, 64 and run as lane
+// groups of that width; class 5 (d <= LP_MID_MAX) runs one workgroup per
+// vertex with a hash table of labels in LDS; class 6 (hubs) counts in hash
+// tables in device memory, cut into chunks of LP_HUB_CHUNK neighbours.
+constexpr int LP_CLASSES = 7;
+constexpr int LP_MID_MAX = 2048;
+constexpr int LP_MID_SLOTS = 4096;   // LDS table of the mid class (load at most 1/2)
+constexpr int LP_HUB_CHUNK = 8192;
+constexpr uint32_t LP_NONE = 0xFFFFFFFFu;
+
 struct DevGraph {
     int64_t V = 0, E = 0, E_sym = 0;
     int32_t W = 0;                 // bitmap words: ceil(V / 32)
@@ -137,6 +148,7 @@ struct gx_graph {
     int num_cus = 0;
     bool dev_error = false;
     std::vector<int32_t> host_outdeg;  // out-degree (host copy, for sources and stats)
+    std::vector<int32_t> host_symdeg;  // distinct neighbours (with GX_NEED_SYM; label propagation classes)
     std::vector<uint32_t> pull_w_recs, pull_sym_recs;  // records of each pull unit (sizes fix-up regions)
     // supersteps of the last converged SSSP / CC run on this graph: the size
     // of the next run's first speculative group (solves on one graph tend to
@@ -175,4 +187,71 @@ int device_cus(int device);
 // the current device; cached, because the query is slow.
 int occupancy_per_cu(const void *kernel, int block);
 
+}  // namespace gx
+
+// Engine state of one algorithm run on a graph (gx_plain.hip, gx_lp.hip).
+struct gx_state {
+    gx_graph *g = nullptr;
+    gx_params p{};
+    int64_t k = 0;
+    bool dev_error = false;
+    int relax_grid = 0;   // persistent grid of the relaxation kernel
+    uint2 *fix = nullptr;         // fix-up regions, fix_cap entries per relaxation workgroup
+    uint32_t *fixn = nullptr;     // entries recorded per workgroup
+    uint32_t fix_cap = 0;
+    // SSSP / CC
+    uint32_t *val = nullptr;
+    uint8_t *front8[2] = {nullptr, nullptr};  // frontier byte maps: A_k lives in front8[k & 1]
+    uint8_t *dirty8 = nullptr;                // changed since the last sync (byte per vertex)
+    uint4 *list = nullptr;
+    uint32_t *tile_start = nullptr;
+    uint32_t *snap = nullptr;      // start-of-superstep values of active vertices (pull)
+    uint32_t pull_edges = 0xFFFFFFFFu;
+    // PageRank
+    float *x[2] = {nullptr, nullptr};
+    float *contrib[2] = {nullptr, nullptr};
+    uint32_t *synced = nullptr;
+    double *head = nullptr, *tailp = nullptr;
+    int32_t *spill_row = nullptr;
+    double *dpart = nullptr;
+    uint32_t *cpart = nullptr;   // per-tile changed counts (PageRank)
+    double *Dval = nullptr;
+    int pr_fix_grid = 1;              // workgroups of k_pr_fix
+    double *fix_d = nullptr;          // their dangling-mass partials
+    unsigned long long *fix_c = nullptr;  // and changed counts
+    uint32_t *fix_done = nullptr;     // workgroups finished (the last resets it)
+    // label propagation: lab[k & 1] holds the labels at the start of superstep k
+    uint32_t *lab[2] = {nullptr, nullptr};
+    uint32_t *lp_list = nullptr;              // vertices with neighbours, grouped by degree class
+    int64_t lp_off[gx::LP_CLASSES + 1] = {};  // class c owns lp_list[lp_off[c] .. lp_off[c + 1])
+    uint4 *lp_chunks = nullptr;               // hub edge chunks {hub index, first entry, end entry, 0}
+    int64_t lp_nchunks = 0;
+    uint2 *lp_hub = nullptr;                  // per hub {first table slot, slots (a power of two)}
+    uint2 *lp_tab = nullptr;                  // hub tables {label, count}; label LP_NONE = free
+    int64_t lp_tab_slots = 0;
+    // shared
+    gx::DevStep *steps = nullptr;
+    uint32_t *blk_cnt = nullptr;
+    uint32_t *delta_total = nullptr;
+    int delta_blocks = 0;
+    // edge-kernel timing
+    std::vector<hipEvent_t> ev_pool;
+    struct Pending {
+        int64_t k;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> ev_pending;
+    double kernel_ms = 0;
+    int64_t kernel_launches = 0;
+    gx::DevStep *host_steps = nullptr;  // pinned, HOST_STEPS entries (from a process-wide pool)
+    ~gx_state();
+};
+
+namespace gx {
+// Label propagation (gx_lp.hip): state layout (also sizes the arena with a
+// measuring Carver), initialisation (synchronises `hs`), one superstep.
+size_t lp_layout(gx_graph *g, Carver &c, gx_state *s);
+gx_status lp_init(gx_state *s, hipStream_t hs);
+void lp_enqueue(gx_state *s, hipStream_t hs, DevStep *step, DevStep *next);
+int64_t lp_active(const gx_state *s);
 }  // namespace gx

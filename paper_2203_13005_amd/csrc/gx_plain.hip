@@ -54,53 +54,6 @@
 
 using namespace gx;
 
-struct gx_state {
-    gx_graph *g = nullptr;
-    gx_params p{};
-    int64_t k = 0;
-    bool dev_error = false;
-    int relax_grid = 0;   // persistent grid of the relaxation kernel
-    uint2 *fix = nullptr;         // fix-up regions, fix_cap entries per relaxation workgroup
-    uint32_t *fixn = nullptr;     // entries recorded per workgroup
-    uint32_t fix_cap = 0;
-    // SSSP / CC
-    uint32_t *val = nullptr;
-    uint8_t *front8[2] = {nullptr, nullptr};  // frontier byte maps: A_k lives in front8[k & 1]
-    uint8_t *dirty8 = nullptr;                // changed since the last sync (byte per vertex)
-    uint4 *list = nullptr;
-    uint32_t *tile_start = nullptr;
-    uint32_t *snap = nullptr;      // start-of-superstep values of active vertices (pull)
-    uint32_t pull_edges = 0xFFFFFFFFu;
-    // PageRank
-    float *x[2] = {nullptr, nullptr};
-    float *contrib[2] = {nullptr, nullptr};
-    uint32_t *synced = nullptr;
-    double *head = nullptr, *tailp = nullptr;
-    int32_t *spill_row = nullptr;
-    double *dpart = nullptr;
-    uint32_t *cpart = nullptr;   // per-tile changed counts (PageRank)
-    double *Dval = nullptr;
-    int pr_fix_grid = 1;              // workgroups of k_pr_fix
-    double *fix_d = nullptr;          // their dangling-mass partials
-    unsigned long long *fix_c = nullptr;  // and changed counts
-    uint32_t *fix_done = nullptr;     // workgroups finished (the last resets it)
-    // shared
-    DevStep *steps = nullptr;
-    uint32_t *blk_cnt = nullptr;
-    uint32_t *delta_total = nullptr;
-    int delta_blocks = 0;
-    // edge-kernel timing
-    std::vector<hipEvent_t> ev_pool;
-    struct Pending {
-        int64_t k;
-        hipEvent_t a, b;
-    };
-    std::vector<Pending> ev_pending;
-    double kernel_ms = 0;
-    int64_t kernel_launches = 0;
-    DevStep *host_steps = nullptr;  // pinned, HOST_STEPS entries (from a process-wide pool)
-    ~gx_state();
-};
 
 static void pool_return(hipEvent_t e);
 static void host_steps_return(gx::DevStep *p);
@@ -974,7 +927,9 @@ static size_t state_layout(gx_graph *g, const gx_params *p, Carver &c, gx_state 
     const DevGraph &d = g->d;
     int64_t V = d.V;
     int32_t W = d.W;
-    if (p->algo == GX_PAGERANK) {
+    if (p->algo == GX_LP) {
+        lp_layout(g, c, s);
+    } else if (p->algo == GX_PAGERANK) {
         int32_t nt = d.pr_ntiles;
         s->x[0] = c.take<float>(V);
         s->x[1] = c.take<float>(V);
@@ -1017,7 +972,7 @@ static gx_status check_params(const gx_graph *g, const gx_params *p) {
     GX_REQUIRE(g, GX_EINVAL, "graph is NULL");
     GX_REQUIRE(p, GX_EINVAL, "params is NULL");
     GX_REQUIRE(!g->dev_error, GX_EDEVICE, "graph handle has a sticky device error");
-    GX_REQUIRE(p->algo == GX_PAGERANK || p->algo == GX_SSSP || p->algo == GX_CC, GX_EINVAL,
+    GX_REQUIRE(p->algo == GX_PAGERANK || p->algo == GX_SSSP || p->algo == GX_CC || p->algo == GX_LP, GX_EINVAL,
                "algo %d not supported by the plain engine", p->algo);
     GX_REQUIRE(p->delta_mode <= GX_DELTA_ALL, GX_EINVAL, "delta_mode %u invalid", p->delta_mode);
     if (p->algo == GX_PAGERANK) {
@@ -1029,6 +984,13 @@ static gx_status check_params(const gx_graph *g, const gx_params *p) {
         GX_REQUIRE(p->source >= -1 && p->source < g->d.V, GX_EINVAL, "source %d out of [-1,V)", p->source);
     }
     if (p->algo == GX_CC) GX_REQUIRE(g->needs & GX_NEED_SYM, GX_EINVAL, "CC needs GX_NEED_SYM");
+    if (p->algo == GX_LP) {
+        GX_REQUIRE(g->needs & GX_NEED_SYM, GX_EINVAL, "LP needs GX_NEED_SYM");
+        int64_t slots = 0;
+        for (int32_t d : g->host_symdeg)
+            if (d > LP_MID_MAX) slots += 3 * (int64_t)d + 256;
+        GX_REQUIRE(slots < (int64_t(1) << 32), GX_EINVAL, "LP hub tables would exceed 2^32 slots");
+    }
     return GX_OK;
 }
 
@@ -1064,7 +1026,7 @@ extern "C" gx_status gx_state_init(gx_graph *g, const gx_params *p, void *dev_st
     s->p = *p;
     Carver c(dev_state, bytes);
     state_layout(g, p, c, s);
-    if (p->algo != GX_PAGERANK) {
+    if (p->algo == GX_SSSP || p->algo == GX_CC) {
         const DevGraph &dg = g->d;
         // (the pull addresses values through a 32-bit buffer range)
         bool can_pull = dg.V < (int64_t(1) << 30) &&
@@ -1076,7 +1038,13 @@ extern "C" gx_status gx_state_init(gx_graph *g, const gx_params *p, void *dev_st
     hipStream_t hs = static_cast<hipStream_t>(stream);
     const DevGraph &d = g->d;
     int64_t V = d.V;
-    if (p->algo == GX_PAGERANK) {
+    if (p->algo == GX_LP) {
+        gx_status ls = lp_init(s, hs);
+        if (ls != GX_OK) {
+            delete s;
+            return ls;
+        }
+    } else if (p->algo == GX_PAGERANK) {
         float x0 = V > 0 ? (float)(1.0 / (double)V) : 0.f;
         unsigned nb = grid_for<int64_t>(V, 256);
         hipLaunchKernelGGL(k_pr_init, dim3(nb), dim3(256), 0, hs, s->x[0], s->contrib[0], s->synced, d.outdeg, V, x0,
@@ -1120,14 +1088,16 @@ extern "C" gx_status gx_state_free(gx_state *s) {
 extern "C" gx_status gx_state_values(gx_state *s, void **dev_values) {
     clear_error();
     GX_REQUIRE(s && dev_values, GX_EINVAL, "NULL argument");
-    *dev_values = s->p.algo == GX_PAGERANK ? (void *)s->x[s->k & 1] : (void *)s->val;
+    *dev_values = s->p.algo == GX_PAGERANK ? (void *)s->x[s->k & 1]
+                : s->p.algo == GX_LP       ? (void *)s->lab[s->k & 1]
+                                           : (void *)s->val;
     return GX_OK;
 }
 
 extern "C" gx_status gx_state_frontier(gx_state *s, void **dev_bitmap) {
     clear_error();
     GX_REQUIRE(s && dev_bitmap, GX_EINVAL, "NULL argument");
-    GX_REQUIRE(s->p.algo != GX_PAGERANK, GX_EINVAL, "PageRank has no frontier");
+    GX_REQUIRE(s->p.algo == GX_SSSP || s->p.algo == GX_CC, GX_EINVAL, "only SSSP and CC keep a frontier");
     *dev_bitmap = s->front8[s->k & 1];
     return GX_OK;
 }
@@ -1223,7 +1193,11 @@ static gx_status enqueue_superstep(gx_state *s, hipStream_t hs) {
         e0 = pool_event(s);
         e1 = pool_event(s);
     }
-    if (p.algo == GX_PAGERANK) {
+    if (p.algo == GX_LP) {
+        if (e0) (void)hipEventRecord(e0, hs);
+        lp_enqueue(s, hs, step, next);
+        if (e1) (void)hipEventRecord(e1, hs);
+    } else if (p.algo == GX_PAGERANK) {
         int cur = (int)(s->k & 1);
         double dd = p.damping;
         PrApply ap{(1.0 - dd) / (double)d.V, dd, 0.0, d.outdeg, s->x[cur], s->x[cur ^ 1], s->contrib[cur ^ 1]};
@@ -1303,6 +1277,11 @@ static void to_stats(const gx_state *s, const DevStep &ds, const DevStep &next, 
     if (s->p.algo == GX_PAGERANK) {
         o->frontier = s->g->d.V;
         o->edges = s->g->d.E;
+        o->pulled = 1;
+        o->changed = (int64_t)ds.changed;
+    } else if (s->p.algo == GX_LP) {
+        o->frontier = lp_active(s);
+        o->edges = s->g->d.E_sym;
         o->pulled = 1;
         o->changed = (int64_t)ds.changed;
     } else {
@@ -1403,8 +1382,11 @@ extern "C" gx_status gx_run_until_converged(gx_state *s, uint32_t max_supersteps
         // includes the superstep that changed nothing, so a repeat of that
         // run converges inside the group; at least 6, at most 16), the later
         // ones 8 at a time.
+        // (label propagation keeps no history: its first group covers 16, the
+        // evaluation's cap of 15 plus one)
         const int hist = s->p.algo == GX_CC ? 1 : 0;
-        const uint32_t last = s->g->last_supersteps[hist].load(std::memory_order_relaxed);
+        const bool lp = s->p.algo == GX_LP;
+        const uint32_t last = lp ? 16u : s->g->last_supersteps[hist].load(std::memory_order_relaxed);
         uint32_t done = 0, spec = std::min<uint32_t>(16, std::max<uint32_t>(6, last));
         bool conv = false;
         while (done < max_supersteps && !conv) {
@@ -1432,7 +1414,7 @@ extern "C" gx_status gx_run_until_converged(gx_state *s, uint32_t max_supersteps
         }
         rs.supersteps = done;
         rs.converged = conv ? 1 : 0;
-        if (conv && k_begin == 0) s->g->last_supersteps[hist].store(done, std::memory_order_relaxed);
+        if (conv && k_begin == 0 && !lp) s->g->last_supersteps[hist].store(done, std::memory_order_relaxed);
         if (!conv) {
             set_error("not converged after %u supersteps", max_supersteps);
             result = GX_ENOTCONVERGED;
@@ -1458,11 +1440,15 @@ extern "C" gx_status gx_sync_delta(gx_state *s, int32_t *dev_gid, uint32_t *dev_
     if (skippable) *skippable = 1;
     if (d.W == 0) return GX_OK;
     bool all = s->p.delta_mode == GX_DELTA_ALL;
-    const uint32_t *remote = s->p.algo == GX_CC ? d.remote_any : d.remote_out;
-    bool pr = s->p.algo == GX_PAGERANK;
-    const uint32_t *vals = pr ? reinterpret_cast<const uint32_t *>(s->x[s->k & 1]) : s->val;
-    uint8_t *dirty = pr ? nullptr : s->dirty8;
-    uint32_t *synced = pr ? s->synced : nullptr;
+    const uint32_t *remote = (s->p.algo == GX_CC || s->p.algo == GX_LP) ? d.remote_any : d.remote_out;
+    // PageRank and LP compare with the synced copy (LP labels can return to an
+    // earlier value); SSSP / CC values only fall, so the dirty map decides
+    const bool by_copy = s->p.algo == GX_PAGERANK || s->p.algo == GX_LP;
+    const uint32_t *vals = s->p.algo == GX_PAGERANK ? reinterpret_cast<const uint32_t *>(s->x[s->k & 1])
+                         : s->p.algo == GX_LP       ? s->lab[s->k & 1]
+                                                    : s->val;
+    uint8_t *dirty = by_copy ? nullptr : s->dirty8;
+    uint32_t *synced = by_copy ? s->synced : nullptr;
     hipLaunchKernelGGL(k_delta_count, dim3(s->delta_blocks), dim3(256), 0, hs, d.W, d.V, remote, (int)all, dirty,
                        vals, synced, s->blk_cnt);
     hipLaunchKernelGGL(k_delta_emit, dim3(s->delta_blocks), dim3(256), 0, hs, d.W, d.V, remote, (int)all, dirty,
@@ -1536,11 +1522,15 @@ extern "C" gx_status gx_sync_delta_noalloc(gx_state *s, int32_t *dev_gid, uint32
         return GX_OK;
     }
     bool all = s->p.delta_mode == GX_DELTA_ALL;
-    const uint32_t *remote = s->p.algo == GX_CC ? d.remote_any : d.remote_out;
-    bool pr = s->p.algo == GX_PAGERANK;
-    const uint32_t *vals = pr ? reinterpret_cast<const uint32_t *>(s->x[s->k & 1]) : s->val;
-    uint8_t *dirty = pr ? nullptr : s->dirty8;
-    uint32_t *synced = pr ? s->synced : nullptr;
+    const uint32_t *remote = (s->p.algo == GX_CC || s->p.algo == GX_LP) ? d.remote_any : d.remote_out;
+    // PageRank and LP compare with the synced copy (LP labels can return to an
+    // earlier value); SSSP / CC values only fall, so the dirty map decides
+    const bool by_copy = s->p.algo == GX_PAGERANK || s->p.algo == GX_LP;
+    const uint32_t *vals = s->p.algo == GX_PAGERANK ? reinterpret_cast<const uint32_t *>(s->x[s->k & 1])
+                         : s->p.algo == GX_LP       ? s->lab[s->k & 1]
+                                                    : s->val;
+    uint8_t *dirty = by_copy ? nullptr : s->dirty8;
+    uint32_t *synced = by_copy ? s->synced : nullptr;
     hipLaunchKernelGGL(k_delta_count, dim3(s->delta_blocks), dim3(256), 0, hs, d.W, d.V, remote, (int)all, dirty,
                        vals, synced, cnt);
     hipLaunchKernelGGL(k_delta_emit, dim3(s->delta_blocks), dim3(256), 0, hs, d.W, d.V, remote, (int)all, dirty,
