@@ -483,6 +483,65 @@ def bench_lp(gx, torch, np, gen, g=None, scale=22, cap=15, reps=3):
             "oracle_one_iteration_one_core_s": cpu_iter_s}
 
 
+def bench_phases(gx, torch, np, gen, g=None, reps=5):
+    """SSSP from vertex 0 on R-MAT scale 22 (seed 2) driven by the template's
+    three calls made separately, in BSP order (Gen, Merge, Apply) and in GAS
+    order (Merge, Apply, Gen), against the fused superstep; the same number
+    of supersteps, the same distances."""
+    if g is None:
+        g = gen.rmat(22, seed=2)
+    dg = gx.DeviceGraph(g, gx.GX_NEED_OUT)
+    fused = gx.State(dg, gx.GX_SSSP, source=0)
+    rs, _ = fused.run(100_000)
+    K = int(rs.supersteps)
+    want = fused.values_numpy().copy()
+
+    def timed(fn):
+        ts = []
+        for _ in range(reps + 1):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        assert np.array_equal(st.values_numpy(), want)
+        ts = sorted(ts[1:])
+        return ts[len(ts) // 2] * 1e3
+
+    def run_fused():
+        fused.reset()
+        fused.run(100_000)
+        return fused
+
+    split = gx.State(dg, gx.GX_SSSP, source=0, phases=True)
+
+    def run_bsp():
+        split.reset()
+        for _ in range(K):
+            split.msg_gen()
+            split.msg_merge()
+            split.msg_apply(stats=False)
+        return split
+
+    def run_gas():
+        split.reset()
+        split.msg_merge()
+        split.msg_apply(stats=False)
+        split.msg_gen()
+        for _ in range(K):
+            split.msg_merge()
+            split.msg_apply(stats=False)
+            split.msg_gen()
+        return split
+
+    out = {"workload": f"SSSP from vertex 0 on R-MAT scale 22 (seed 2), {K} supersteps",
+           "fused_ms_per_solve": timed(run_fused), "bsp_separate_calls_ms_per_solve": timed(run_bsp),
+           "gas_separate_calls_ms_per_solve": timed(run_gas)}
+    log(f"template calls: fused {out['fused_ms_per_solve']:.2f} ms, BSP order "
+        f"{out['bsp_separate_calls_ms_per_solve']:.2f} ms, GAS order {out['gas_separate_calls_ms_per_solve']:.2f} ms")
+    return out
+
+
 def bench_partition(gx, torch, np, gen, reps=3):
     """One part (1 of 8) of a hash vertex-cut of R-MAT scale 25 (seed 3):
     30 PageRank supersteps and min-label CC to convergence."""
@@ -597,7 +656,7 @@ def load_traffic():
     return t
 
 
-LEGS = ("sssp", "pagerank", "partition", "lp", "exchange", "batched", "serving")
+LEGS = ("sssp", "pagerank", "partition", "lp", "phases", "exchange", "batched", "serving")
 
 
 def bench_sssp(args, gx, torch, np, gen):
@@ -775,6 +834,8 @@ def main():
     part = None
     if "partition" in legs:
         out["partition_scale25"], part = bench_partition(gx, torch, np, gen)
+    if "phases" in legs:
+        out["template_calls_sssp_scale22"] = bench_phases(gx, torch, np, gen, g)
     if "lp" in legs:
         out["lp_scale22"] = bench_lp(gx, torch, np, gen, g)
     if "exchange" in legs:

@@ -113,6 +113,10 @@ typedef struct gx_params {
     float    pull_fraction;   /* SSSP/CC: a superstep whose active out-edges exceed this fraction of
                                  all edges pulls (one sweep over every in-edge record) instead of
                                  pushing; 0 = default (0.3), >= 1 = always push */
+    uint32_t phases;          /* nonzero (PageRank, SSSP, CC): the state is driven by the separate
+                                 template calls gx_msg_gen / gx_msg_merge / gx_msg_apply in any
+                                 order an upper system uses (BSP or GAS); gx_superstep and
+                                 gx_run_until_converged refuse it */
 } gx_params;
 
 /* Statistics of one superstep (counts are exact). */
@@ -210,6 +214,39 @@ gx_status gx_superstep(gx_state *s, void *stream, gx_step_stats *stats);
  */
 gx_status gx_run_until_converged(gx_state *s, uint32_t max_supersteps, void *stream,
                                  gx_run_stats *out, gx_step_stats *per_step);
+
+/*
+ * The algorithm template's three calls as separate requests (Section
+ * "Algorithm Template": MSGGen, MSGMerge, MSGApply; Section "Operation
+ * Interfaces": requestX() for each; Section "PowerGraph": BSP calls them in
+ * the order Gen -> Merge -> Apply, GAS in the order Merge -> Apply -> Gen).
+ * For a state initialised with gx_params.phases != 0:
+ *   gx_msg_gen    MSGGen: the vertices changed since their messages were
+ *                 last generated (at first: the SSSP source, every CC vertex
+ *                 with an edge, every PageRank vertex) emit their messages:
+ *                 SSSP/CC the active list with the values they send (each
+ *                 out-edge then carries sat_add(value, w) or the value),
+ *                 PageRank x[u]/outdeg(u) per vertex and the dangling mass.
+ *                 GX_EINVAL if messages are already pending.
+ *   gx_msg_merge  MSGMerge: the pending messages combined per destination
+ *                 (integer min; PageRank the fp64 sum over in-edges in
+ *                 source order) into an accumulator; no-op when nothing is
+ *                 pending.
+ *   gx_msg_apply  MSGApply: the merged messages applied to the vertices
+ *                 (SSSP/CC new = min(old, merged), a vertex that falls is
+ *                 marked for the next Gen and the sync set; PageRank
+ *                 x' = (1-d)/V + d*(merged + D/V)); no-op when nothing was
+ *                 merged.  Each apply that ran counts as one superstep.
+ * One BSP superstep (Gen, Merge, Apply) equals gx_superstep's result.  In
+ * GAS order the first Merge and Apply find nothing and do nothing, so after
+ * n GAS iterations the values are those of n - 1 supersteps (the last Gen's
+ * messages pending).  Asynchronous, except gx_msg_apply with stats != NULL,
+ * which synchronises `stream` and reports the superstep's active vertices,
+ * messages and changed vertices (all zero when the apply did nothing).
+ */
+gx_status gx_msg_gen(gx_state *s, void *stream);
+gx_status gx_msg_merge(gx_state *s, void *stream);
+gx_status gx_msg_apply(gx_state *s, void *stream, gx_step_stats *stats);
 
 /*
  * update() with lazy uploading and synchronisation skipping: emits the

@@ -37,7 +37,7 @@ class _GraphDesc(ctypes.Structure):
 class _Params(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("damping", ctypes.c_float), ("source", ctypes.c_int32),
                 ("max_supersteps", ctypes.c_uint32), ("delta_mode", ctypes.c_uint32),
-                ("timing", ctypes.c_uint32), ("pull_fraction", ctypes.c_float)]
+                ("timing", ctypes.c_uint32), ("pull_fraction", ctypes.c_float), ("phases", ctypes.c_uint32)]
 
 
 class StepStats(ctypes.Structure):
@@ -101,6 +101,9 @@ _SIGS = {
     "gx_sync_delta": (ctypes.c_int32, [_P, _P, _P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
                                        ctypes.POINTER(ctypes.c_int32), _P]),
     "gx_sync_delta_noalloc": (ctypes.c_int32, [_P, _P, _P, ctypes.c_uint32, _P, _P]),
+    "gx_msg_gen": (ctypes.c_int32, [_P, _P]),
+    "gx_msg_merge": (ctypes.c_int32, [_P, _P]),
+    "gx_msg_apply": (ctypes.c_int32, [_P, _P, ctypes.POINTER(StepStats)]),
     "gx_apply_delta": (ctypes.c_int32, [_P, _P, _P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int64), _P]),
     "gx_batch_bytes": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_size_t)]),
     "gx_batch_run": (ctypes.c_int32, [_P, ctypes.c_int32, _P, ctypes.c_uint32, ctypes.c_float, ctypes.c_uint32,
@@ -237,12 +240,12 @@ class State:
 
     def __init__(self, graph: DeviceGraph, algo: int, source: int = 0, damping: float = 0.85,
                  max_supersteps: int = 1 << 20, delta_mode: int = GX_DELTA_REMOTE, timing: bool = False,
-                 pull_fraction: float = 0.0, stream=None):
+                 pull_fraction: float = 0.0, stream=None, phases: bool = False):
         import torch
         self.graph = graph
         self.algo = algo
         self.params = _Params(int(algo), float(damping), int(source), int(max_supersteps), int(delta_mode),
-                              int(bool(timing)), float(pull_fraction))
+                              int(bool(timing)), float(pull_fraction), int(bool(phases)))
         nbytes = ctypes.c_size_t(0)
         _check(lib.gx_state_bytes(graph.handle, ctypes.byref(self.params), ctypes.byref(nbytes)))
         with torch.cuda.device(graph.device):
@@ -342,6 +345,21 @@ class State:
         if on_device:
             return gid[:c], val[:c], bool(sk.value)
         return gid[:c].cpu().numpy(), val[:c].cpu().numpy().view(np.uint32), bool(sk.value)
+
+    def msg_gen(self, stream=None):
+        """MSGGen (separate template calls; state created with phases=True)."""
+        _check(lib.gx_msg_gen(self.handle, _stream_handle(stream)))
+
+    def msg_merge(self, stream=None):
+        """MSGMerge: combines the pending messages per destination."""
+        _check(lib.gx_msg_merge(self.handle, _stream_handle(stream)))
+
+    def msg_apply(self, stats: bool = True, stream=None):
+        """MSGApply; with stats, returns (active, messages, changed) of the
+        superstep it completed (zeros when nothing was merged)."""
+        st = StepStats()
+        _check(lib.gx_msg_apply(self.handle, _stream_handle(stream), ctypes.byref(st) if stats else None))
+        return st.as_tuple() if stats else None
 
     def sync_delta_noalloc(self, gid, val, count, stream=None):
         """gx_sync_delta_noalloc: writes up to gid.numel() pairs into the given

@@ -229,6 +229,15 @@ struct gx_state {
     uint2 *lp_hub = nullptr;                  // per hub {first table slot, slots (a power of two)}
     uint2 *lp_tab = nullptr;                  // hub tables {label, count}; label LP_NONE = free
     int64_t lp_tab_slots = 0;
+    // separate template calls (gx_params.phases): merged messages per vertex,
+    // the index of the pending map in front8, and what is waiting
+    uint32_t *acc = nullptr;         // SSSP / CC: min of the merged messages (INF = none)
+    double *acc_d = nullptr;         // PageRank: sum of the merged messages
+    uint8_t *junk8 = nullptr;        // marks the relaxation makes against the accumulator (never read)
+    double *Dscratch = nullptr;      // dangling-mass slot the merge's fix-up writes (never read)
+    gx::DevStep *ph_steps = nullptr; // counter slots the merge's fix-up writes (never read)
+    int ph_p = 0;                    // front8[ph_p] collects the vertices the next MSGGen sends from
+    bool ph_msgs = false, ph_merged = false;
     // shared
     gx::DevStep *steps = nullptr;
     uint32_t *blk_cnt = nullptr;

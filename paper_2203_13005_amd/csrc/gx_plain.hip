@@ -541,11 +541,19 @@ struct PrApply {
     }
 };
 
-template <int VT>
+// The merge alone (separate template calls): the combined messages of a row
+// are stored; what is applied happens later.
+struct PrStore {
+    double d, dD;  // (unused)
+    double *acc;
+    __device__ __forceinline__ void operator()(int32_t r, double total, double &, int &) const { acc[r] = total; }
+};
+
+template <int VT, class AP>
 __global__ __launch_bounds__(PR_BLOCK) void k_pr_pull(const int32_t *__restrict__ in_rp,
                                                       const int32_t *__restrict__ in_col,
                                                       const int32_t *__restrict__ tile_row, int64_t E,
-                                                      const float *__restrict__ c_in, PrApply ap,
+                                                      const float *__restrict__ c_in, AP ap,
                                                       const double *__restrict__ Dp, double inv_V,
                                                       double *__restrict__ head, double *__restrict__ tailp,
                                                       int32_t *__restrict__ spill_row, double *__restrict__ dpart,
@@ -699,12 +707,13 @@ __global__ __launch_bounds__(PR_BLOCK) void k_pr_pull(const int32_t *__restrict_
 constexpr int PR_FIX_BLOCK = 256;
 constexpr int PR_FIX_MAX_GRID = 1024;
 
+template <class AP>
 __global__ __launch_bounds__(PR_FIX_BLOCK) void k_pr_fix(const int32_t *__restrict__ in_rp, int32_t ntiles,
                                                          int32_t tile, const double *__restrict__ head,
                                                          const double *__restrict__ tailp,
                                                          const int32_t *__restrict__ spill_row,
                                                          const double *__restrict__ dpart,
-                                                         const uint32_t *__restrict__ cpart, PrApply ap, double *Dp,
+                                                         const uint32_t *__restrict__ cpart, AP ap, double *Dp,
                                                          double inv_V, DevStep *__restrict__ step,
                                                          DevStep *__restrict__ next_step, double *fix_d,
                                                          unsigned long long *fix_c, uint32_t *fix_done) {
@@ -881,6 +890,75 @@ __global__ __launch_bounds__(256) void k_apply_delta(const int32_t *__restrict__
 __global__ void k_zero_step(DevStep *step) { *step = DevStep{}; }
 __global__ void k_set_u32(uint32_t *p, uint32_t v) { *p = v; }
 
+// ------------------------------------------------------------ separate template calls
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// MSGApply of SSSP / CC: a vertex whose merged message is below its value
+// takes it, and is marked for the next MSGGen and for the sync set; the
+// accumulator is reset for the next merge.
+__global__ __launch_bounds__(256) void k_ph_apply(uint32_t *__restrict__ acc, uint32_t *__restrict__ val,
+                                                  uint8_t *__restrict__ pend, uint8_t *__restrict__ dirty, int64_t V,
+                                                  DevStep *step) {
+    __shared__ unsigned long long s_c[4];
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    unsigned c = 0;
+    if (v < V) {
+        const uint32_t a = acc[v];
+        if (a != INF) {
+            acc[v] = INF;
+            if (a < val[v]) {
+                val[v] = a;
+                pend[v] = 1;
+                dirty[v] = 1;
+                c = 1;
+            }
+        }
+    }
+    const unsigned long long t = block_sum<unsigned long long>((unsigned long long)c, s_c);
+    if (threadIdx.x == 0 && t) atomicAdd(&step->changed, t);
+}
+
+// MSGGen of PageRank: every vertex's message x[u]/outdeg(u) and the
+// dangling mass (per-workgroup partials, summed in order by k_reduce_D).
+__global__ __launch_bounds__(256) void k_ph_pr_gen(const float *__restrict__ x, const int32_t *__restrict__ outdeg,
+                                                   float *__restrict__ contrib, int64_t V, double *dpart) {
+    __shared__ double s_d[4];
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double dl = 0.0;
+    if (v < V) {
+        const float xv = x[v];
+        const int od = outdeg[v];
+        contrib[v] = od > 0 ? xv / (float)od : 0.0f;
+        if (od == 0) dl = (double)xv;
+    }
+    const double t = block_sum<double>(dl, s_d);
+    if (threadIdx.x == 0) dpart[blockIdx.x] = t;
+}
+
+// MSGApply of PageRank: x' = (1-d)/V + d * (merged + D/V), in place.
+__global__ __launch_bounds__(256) void k_ph_pr_apply(const double *__restrict__ acc, float *__restrict__ x, int64_t V,
+                                                     double base, double d, const double *__restrict__ Dp,
+                                                     double inv_V, DevStep *step, DevStep *next) {
+    __shared__ unsigned long long s_c[4];
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const double dD = d * (*Dp) * inv_V;
+    unsigned c = 0;
+    if (v < V) {
+        const float xn = (float)(base + d * acc[v] + dD);
+        c = __float_as_uint(xn) != __float_as_uint(x[v]);
+        x[v] = xn;
+    }
+    const unsigned long long t = block_sum<unsigned long long>((unsigned long long)c, s_c);
+    if (threadIdx.x == 0) {
+        if (t) atomicAdd(&step->changed, t);
+        if (blockIdx.x == 0) *next = DevStep{};
+    }
+}
+
 template <class T>
 inline unsigned grid_for(T n, unsigned block) {
     return (unsigned)std::max<T>(1, (n + block - 1) / block);
@@ -961,6 +1039,16 @@ static size_t state_layout(gx_graph *g, const gx_params *p, Carver &c, gx_state 
         s->fix = c.take<uint2>((size_t)s->relax_grid * s->fix_cap);
         s->fixn = c.take<uint32_t>(s->relax_grid);
     }
+    if (p->phases) {
+        if (p->algo == GX_PAGERANK) {
+            s->acc_d = c.take<double>(V);
+            s->Dscratch = c.take<double>(1);
+            s->ph_steps = c.take<DevStep>(2);
+        } else {
+            s->acc = c.take<uint32_t>(V);
+            s->junk8 = c.take<uint8_t>((size_t)W * 32);
+        }
+    }
     s->steps = c.take<DevStep>(STEP_RING);
     s->delta_blocks = (int)grid_for<int64_t>(W, 256);
     s->blk_cnt = c.take<uint32_t>(s->delta_blocks);
@@ -975,6 +1063,7 @@ static gx_status check_params(const gx_graph *g, const gx_params *p) {
     GX_REQUIRE(p->algo == GX_PAGERANK || p->algo == GX_SSSP || p->algo == GX_CC || p->algo == GX_LP, GX_EINVAL,
                "algo %d not supported by the plain engine", p->algo);
     GX_REQUIRE(p->delta_mode <= GX_DELTA_ALL, GX_EINVAL, "delta_mode %u invalid", p->delta_mode);
+    GX_REQUIRE(!p->phases || p->algo != GX_LP, GX_EINVAL, "the separate template calls serve PageRank, SSSP and CC");
     if (p->algo == GX_PAGERANK) {
         GX_REQUIRE(g->needs & GX_NEED_IN, GX_EINVAL, "PageRank needs GX_NEED_IN");
         GX_REQUIRE(p->damping >= 0.f && p->damping < 1.f, GX_EINVAL, "damping %f out of [0,1)", p->damping);
@@ -1063,8 +1152,11 @@ extern "C" gx_status gx_state_init(gx_graph *g, const gx_params *p, void *dev_st
             (void)hipMemsetAsync(s->front8[1] + V, 0, pad, hs);
             (void)hipMemsetAsync(s->dirty8 + V, 0, pad, hs);
         }
-        // compaction of superstep 0 (each superstep then relaxes and compacts the next)
-        if (V > 0)
+        if (p->phases && V > 0)
+            hipLaunchKernelGGL(k_fill_u32, dim3(grid_for<int64_t>(V, 256)), dim3(256), 0, hs, s->acc, V, INF);
+        // compaction of superstep 0 (each superstep then relaxes and compacts the
+        // next); with separate template calls the first MSGGen does it
+        if (V > 0 && !p->phases)
             hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(V, CBLOCK * CVT)), dim3(CBLOCK), 0, hs, s->front8[0],
                                s->front8[1], rp, s->val, s->snap, V, s->list, s->tile_start, s->steps,
                                s->steps + 1, (int)(s->pull_edges != 0xFFFFFFFFu), nullptr, nullptr, s->pull_edges);
@@ -1085,12 +1177,19 @@ extern "C" gx_status gx_state_free(gx_state *s) {
     return GX_OK;
 }
 
+// The current vertex values (PageRank ranks move between two buffers per
+// superstep, except under separate template calls, which update in place).
+static uint32_t *cur_values(const gx_state *s) {
+    if (s->p.algo == GX_PAGERANK)
+        return reinterpret_cast<uint32_t *>(s->x[s->p.phases ? 0 : (s->k & 1)]);
+    if (s->p.algo == GX_LP) return s->lab[s->k & 1];
+    return s->val;
+}
+
 extern "C" gx_status gx_state_values(gx_state *s, void **dev_values) {
     clear_error();
     GX_REQUIRE(s && dev_values, GX_EINVAL, "NULL argument");
-    *dev_values = s->p.algo == GX_PAGERANK ? (void *)s->x[s->k & 1]
-                : s->p.algo == GX_LP       ? (void *)s->lab[s->k & 1]
-                                           : (void *)s->val;
+    *dev_values = cur_values(s);
     return GX_OK;
 }
 
@@ -1098,7 +1197,8 @@ extern "C" gx_status gx_state_frontier(gx_state *s, void **dev_bitmap) {
     clear_error();
     GX_REQUIRE(s && dev_bitmap, GX_EINVAL, "NULL argument");
     GX_REQUIRE(s->p.algo == GX_SSSP || s->p.algo == GX_CC, GX_EINVAL, "only SSSP and CC keep a frontier");
-    *dev_bitmap = s->front8[s->k & 1];
+    // (separate template calls: the vertices the next MSGGen sends from)
+    *dev_bitmap = s->front8[s->p.phases ? s->ph_p : (s->k & 1)];
     return GX_OK;
 }
 
@@ -1204,13 +1304,13 @@ static gx_status enqueue_superstep(gx_state *s, hipStream_t hs) {
         double inv_V = d.V > 0 ? 1.0 / (double)d.V : 0.0;
         if (d.V > 0) {
             if (e0) (void)hipEventRecord(e0, hs);
-            auto pull = d.pr_tile == 256 ? k_pr_pull<1> : d.pr_tile == 512 ? k_pr_pull<2>
-                      : d.pr_tile == 1024 ? k_pr_pull<4> : k_pr_pull<8>;
+            auto pull = d.pr_tile == 256 ? k_pr_pull<1, PrApply> : d.pr_tile == 512 ? k_pr_pull<2, PrApply>
+                      : d.pr_tile == 1024 ? k_pr_pull<4, PrApply> : k_pr_pull<8, PrApply>;
             hipLaunchKernelGGL(pull, dim3(d.pr_ntiles), dim3(PR_BLOCK), 0, hs, d.in_rp, d.in_col, d.pr_tile_row,
                                d.E, s->contrib[cur], ap, s->Dval, inv_V, s->head, s->tailp, s->spill_row, s->dpart,
                                s->cpart);
             if (e1) (void)hipEventRecord(e1, hs);
-            hipLaunchKernelGGL(k_pr_fix, dim3(s->pr_fix_grid), dim3(PR_FIX_BLOCK), 0, hs, d.in_rp, d.pr_ntiles,
+            hipLaunchKernelGGL(k_pr_fix<PrApply>, dim3(s->pr_fix_grid), dim3(PR_FIX_BLOCK), 0, hs, d.in_rp, d.pr_ntiles,
                                d.pr_tile, s->head, s->tailp, s->spill_row, s->dpart, s->cpart, ap, s->Dval, inv_V,
                                step, next, s->fix_d, s->fix_c, s->fix_done);
         }
@@ -1298,6 +1398,7 @@ static gx_status read_steps(gx_state *s, int64_t kfirst, uint32_t n, hipStream_t
 extern "C" gx_status gx_superstep(gx_state *s, void *stream, gx_step_stats *stats) {
     clear_error();
     GX_REQUIRE(s, GX_EINVAL, "state is NULL");
+    GX_REQUIRE(!s->p.phases, GX_EINVAL, "this state is driven by gx_msg_gen / gx_msg_merge / gx_msg_apply");
     GX_REQUIRE(!s->dev_error && !s->g->dev_error, GX_EDEVICE, "sticky device error");
     hipStream_t hs = static_cast<hipStream_t>(stream);
     int64_t k = s->k;
@@ -1342,6 +1443,7 @@ extern "C" gx_status gx_run_until_converged(gx_state *s, uint32_t max_supersteps
                                             gx_step_stats *per_step) {
     clear_error();
     GX_REQUIRE(s, GX_EINVAL, "state is NULL");
+    GX_REQUIRE(!s->p.phases, GX_EINVAL, "this state is driven by gx_msg_gen / gx_msg_merge / gx_msg_apply");
     GX_REQUIRE(!s->dev_error && !s->g->dev_error, GX_EDEVICE, "sticky device error");
     hipStream_t hs = static_cast<hipStream_t>(stream);
     auto t0 = std::chrono::steady_clock::now();
@@ -1444,9 +1546,7 @@ extern "C" gx_status gx_sync_delta(gx_state *s, int32_t *dev_gid, uint32_t *dev_
     // PageRank and LP compare with the synced copy (LP labels can return to an
     // earlier value); SSSP / CC values only fall, so the dirty map decides
     const bool by_copy = s->p.algo == GX_PAGERANK || s->p.algo == GX_LP;
-    const uint32_t *vals = s->p.algo == GX_PAGERANK ? reinterpret_cast<const uint32_t *>(s->x[s->k & 1])
-                         : s->p.algo == GX_LP       ? s->lab[s->k & 1]
-                                                    : s->val;
+    const uint32_t *vals = cur_values(s);
     uint8_t *dirty = by_copy ? nullptr : s->dirty8;
     uint32_t *synced = by_copy ? s->synced : nullptr;
     hipLaunchKernelGGL(k_delta_count, dim3(s->delta_blocks), dim3(256), 0, hs, d.W, d.V, remote, (int)all, dirty,
@@ -1526,9 +1626,7 @@ extern "C" gx_status gx_sync_delta_noalloc(gx_state *s, int32_t *dev_gid, uint32
     // PageRank and LP compare with the synced copy (LP labels can return to an
     // earlier value); SSSP / CC values only fall, so the dirty map decides
     const bool by_copy = s->p.algo == GX_PAGERANK || s->p.algo == GX_LP;
-    const uint32_t *vals = s->p.algo == GX_PAGERANK ? reinterpret_cast<const uint32_t *>(s->x[s->k & 1])
-                         : s->p.algo == GX_LP       ? s->lab[s->k & 1]
-                                                    : s->val;
+    const uint32_t *vals = cur_values(s);
     uint8_t *dirty = by_copy ? nullptr : s->dirty8;
     uint32_t *synced = by_copy ? s->synced : nullptr;
     hipLaunchKernelGGL(k_delta_count, dim3(s->delta_blocks), dim3(256), 0, hs, d.W, d.V, remote, (int)all, dirty,
@@ -1545,6 +1643,7 @@ extern "C" gx_status gx_apply_delta(gx_state *s, const int32_t *dev_gid, const u
     GX_REQUIRE(s, GX_EINVAL, "state is NULL");
     GX_REQUIRE(n == 0 || (dev_gid && dev_val), GX_EINVAL, "input buffers are NULL");
     GX_REQUIRE(s->p.algo == GX_SSSP || s->p.algo == GX_CC, GX_EINVAL, "gx_apply_delta merges SSSP / CC values only");
+    GX_REQUIRE(!s->p.phases, GX_EINVAL, "gx_apply_delta serves states driven by gx_superstep");
     GX_REQUIRE(!s->dev_error && !s->g->dev_error, GX_EDEVICE, "sticky device error");
     hipStream_t hs = static_cast<hipStream_t>(stream);
     const DevGraph &d = s->g->d;
@@ -1571,6 +1670,125 @@ extern "C" gx_status gx_apply_delta(gx_state *s, const int32_t *dev_gid, const u
             GX_CHECK_HIP(hipStreamSynchronize(hs), s);
             *active_next = (int64_t)ds.frontier;
         }
+    }
+    return GX_OK;
+}
+
+// ------------------------------------------------------------ separate template calls
+
+static gx_status ph_check(gx_state *s) {
+    GX_REQUIRE(s, GX_EINVAL, "state is NULL");
+    GX_REQUIRE(s->p.phases, GX_EINVAL, "state was not initialised with gx_params.phases");
+    GX_REQUIRE(!s->dev_error && !s->g->dev_error, GX_EDEVICE, "sticky device error");
+    return GX_OK;
+}
+
+extern "C" gx_status gx_msg_gen(gx_state *s, void *stream) {
+    clear_error();
+    gx_status st = ph_check(s);
+    if (st != GX_OK) return st;
+    GX_REQUIRE(!s->ph_msgs, GX_EINVAL, "MSGGen: the previous messages have not been merged");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const DevGraph &d = s->g->d;
+    if (d.V > 0) {
+        if (s->p.algo == GX_PAGERANK) {
+            const unsigned nb = grid_for<int64_t>(d.V, 256);
+            hipLaunchKernelGGL(k_ph_pr_gen, dim3(nb), dim3(256), 0, hs, s->x[0], d.outdeg, s->contrib[0], d.V,
+                               s->dpart);
+            hipLaunchKernelGGL(k_reduce_D, dim3(1), dim3(1024), 0, hs, s->dpart, (int)nb, s->Dval);
+        } else {
+            // the pending map's vertices become the active list (with the values
+            // they send); the other map is cleared to collect the next changes
+            const int32_t *rp = s->p.algo == GX_CC ? d.sym_rp : d.out_rp;
+            DevStep *step = s->steps + (s->k % STEP_RING), *next = s->steps + ((s->k + 1) % STEP_RING);
+            hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(d.V, CBLOCK * CVT)), dim3(CBLOCK), 0, hs,
+                               s->front8[s->ph_p], s->front8[s->ph_p ^ 1], rp, s->val, s->snap, d.V, s->list,
+                               s->tile_start, step, next, (int)(s->pull_edges != 0xFFFFFFFFu), nullptr, nullptr,
+                               s->pull_edges);
+        }
+        GX_CHECK_HIP(hipGetLastError(), s);
+    }
+    s->ph_p ^= 1;
+    s->ph_msgs = true;
+    return GX_OK;
+}
+
+extern "C" gx_status gx_msg_merge(gx_state *s, void *stream) {
+    clear_error();
+    gx_status st = ph_check(s);
+    if (st != GX_OK) return st;
+    if (!s->ph_msgs) return GX_OK;  // nothing generated since the last merge
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const DevGraph &d = s->g->d;
+    if (d.V > 0) {
+        if (s->p.algo == GX_PAGERANK) {
+            const PrStore ap{(double)s->p.damping, 0.0, s->acc_d};
+            const double inv_V = 1.0 / (double)d.V;
+            auto pull = d.pr_tile == 256 ? k_pr_pull<1, PrStore> : d.pr_tile == 512 ? k_pr_pull<2, PrStore>
+                      : d.pr_tile == 1024 ? k_pr_pull<4, PrStore> : k_pr_pull<8, PrStore>;
+            hipLaunchKernelGGL(pull, dim3(d.pr_ntiles), dim3(PR_BLOCK), 0, hs, d.in_rp, d.in_col, d.pr_tile_row, d.E,
+                               s->contrib[0], ap, s->Dscratch, inv_V, s->head, s->tailp, s->spill_row, s->dpart,
+                               s->cpart);
+            hipLaunchKernelGGL(k_pr_fix<PrStore>, dim3(s->pr_fix_grid), dim3(PR_FIX_BLOCK), 0, hs, d.in_rp,
+                               d.pr_ntiles, d.pr_tile, s->head, s->tailp, s->spill_row, s->dpart, s->cpart, ap,
+                               s->Dscratch, inv_V, s->ph_steps, s->ph_steps + 1, s->fix_d, s->fix_c, s->fix_done);
+        } else {
+            // the relaxation of the fused superstep, against the accumulator:
+            // it combines the messages by minimum and changes no vertex value
+            DevStep *step = s->steps + (s->k % STEP_RING);
+            const uint8_t *cur = s->front8[s->ph_p ^ 1];
+            if (s->p.algo == GX_SSSP) {
+                const PullArgs pa{d.pull_w, d.pull_w_units, d.pull_w_off};
+                hipLaunchKernelGGL(k_relax<true>, dim3(s->relax_grid), dim3(256), 0, hs, s->list, s->tile_start,
+                                   (const void *)d.out_adj, pa, d.V, s->snap, s->acc, cur, s->junk8, step,
+                                   s->pull_edges, s->fix, s->fixn, s->fix_cap);
+            } else {
+                const PullArgs pa{d.pull_sym, d.pull_sym_units, d.pull_sym_off};
+                hipLaunchKernelGGL(k_relax<false>, dim3(s->relax_grid), dim3(256), 0, hs, s->list, s->tile_start,
+                                   (const void *)d.sym_col, pa, d.V, s->snap, s->acc, cur, s->junk8, step,
+                                   s->pull_edges, s->fix, s->fixn, s->fix_cap);
+            }
+            hipLaunchKernelGGL(k_fixup, dim3(s->relax_grid), dim3(256), 0, hs, s->fix, s->fixn, s->fix_cap, s->acc);
+        }
+        GX_CHECK_HIP(hipGetLastError(), s);
+    }
+    s->ph_msgs = false;
+    s->ph_merged = true;
+    return GX_OK;
+}
+
+extern "C" gx_status gx_msg_apply(gx_state *s, void *stream, gx_step_stats *stats) {
+    clear_error();
+    gx_status st = ph_check(s);
+    if (st != GX_OK) return st;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    if (stats) *stats = gx_step_stats{};
+    if (!s->ph_merged) return GX_OK;  // nothing merged since the last apply
+    const DevGraph &d = s->g->d;
+    const int64_t k = s->k;
+    DevStep *step = s->steps + (k % STEP_RING), *next = s->steps + ((k + 1) % STEP_RING);
+    if (d.V > 0) {
+        if (s->p.algo == GX_PAGERANK) {
+            hipLaunchKernelGGL(k_ph_pr_apply, dim3(grid_for<int64_t>(d.V, 256)), dim3(256), 0, hs, s->acc_d, s->x[0],
+                               d.V, (1.0 - (double)s->p.damping) / (double)d.V, (double)s->p.damping, s->Dval,
+                               1.0 / (double)d.V, step, next);
+        } else {
+            hipLaunchKernelGGL(k_ph_apply, dim3(grid_for<int64_t>(d.V, 256)), dim3(256), 0, hs, s->acc, s->val,
+                               s->front8[s->ph_p], s->dirty8, d.V, step);
+        }
+        GX_CHECK_HIP(hipGetLastError(), s);
+    }
+    s->ph_merged = false;
+    s->k++;
+    if (stats && d.V > 0) {
+        std::vector<DevStep> ds;
+        st = read_steps(s, k, 1, hs, ds);
+        if (st != GX_OK) return st;
+        const bool pr = s->p.algo == GX_PAGERANK;
+        stats->frontier = pr ? d.V : (int64_t)ds[0].frontier;
+        stats->edges = pr ? d.E : (int64_t)(uint32_t)ds[0].list;
+        stats->changed = (int64_t)ds[0].changed;
+        stats->pulled = pr ? 1 : (ds[0].pad ? 1 : 0);
     }
     return GX_OK;
 }

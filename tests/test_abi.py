@@ -95,6 +95,9 @@ def test_null_handles_are_einval():
     n = ctypes.c_uint32()
     assert b.lib.gx_sync_delta(None, None, None, 0, ctypes.byref(n), None, None) == b.GX_EINVAL
     assert b.lib.gx_sync_delta_noalloc(None, None, None, 0, None, None) == b.GX_EINVAL
+    assert b.lib.gx_msg_gen(None, None) == b.GX_EINVAL
+    assert b.lib.gx_msg_merge(None, None) == b.GX_EINVAL
+    assert b.lib.gx_msg_apply(None, None, None) == b.GX_EINVAL
     act = ctypes.c_int64()
     assert b.lib.gx_apply_delta(None, None, None, 0, ctypes.byref(act), None) == b.GX_EINVAL
     assert b.lib.gx_version().startswith(b"gx")
