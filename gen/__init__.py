@@ -136,6 +136,30 @@ def rmat_part(scale: int, edge_factor: int = 16, seed: int = 3, nparts: int = 8,
                  meta=dict(scale=scale, E_raw=E_raw, seed=seed, nparts=nparts, part=part))
 
 
+def cover_isolated(parts: list, V_global: int) -> list:
+    """The parts of a vertex-cut with every global vertex that no part holds
+    (no edge at all) added to part 0 as a master without edges, so that each
+    global vertex lives in exactly one master part.  Local ids stay sorted by
+    global id; part 0's rows are re-indexed accordingly."""
+    covered = np.zeros(V_global, bool)
+    for p in parts:
+        covered[p.l2g] = True
+    iso = np.nonzero(~covered)[0].astype(np.int32)
+    if len(iso) == 0:
+        return list(parts)
+    p0 = parts[0]
+    l2g = np.union1d(p0.l2g, iso).astype(np.int32)
+    pos = np.searchsorted(l2g, p0.l2g)
+    deg = np.zeros(len(l2g), np.int64)
+    deg[pos] = np.diff(p0.row_ptr)
+    row_ptr = np.r_[0, np.cumsum(deg)].astype(np.int32)
+    flags = np.full(len(l2g), 1, np.uint8)  # master, no remote edge
+    flags[pos] = p0.flags
+    q = Graph(len(l2g), p0.E, row_ptr, pos[p0.col].astype(np.int32), p0.w.copy(), l2g, flags,
+              name=p0.name + "_covered", meta=dict(p0.meta, isolated_added=int(len(iso))))
+    return [q] + list(parts[1:])
+
+
 def quadrant_counts(scale: int, n: int, seed: int, a: float = RMAT_A, b: float = RMAT_B,
                     c: float = RMAT_C) -> np.ndarray:
     lib = _load()

@@ -97,11 +97,18 @@ typedef struct gx_graph_desc {
     uint32_t pr_tile_edges;  /* in-edges per PageRank workgroup tile: 0 = automatic (the largest of
                                 2048, 1024, 512 that still gives 2048 tiles, else 256), or one of
                                 256, 512, 1024, 2048 */
+    /* One part of a vertex-cut whose PageRank is exchanged between the parts
+     * (gx_params.phases == GX_PHASES_MASTERS): the whole graph's vertex count
+     * and, per local vertex, its out-degree in the whole graph (host array,
+     * copied).  V_global = 0 and outdeg_global = NULL otherwise. */
+    int64_t V_global;
+    const int32_t *outdeg_global;
 } gx_graph_desc;
 
 /* Sync-set selection (gx_params.delta_mode). */
-#define GX_DELTA_REMOTE 0u  /* only vertices another part needs (lazy uploading) */
-#define GX_DELTA_ALL    1u  /* every changed vertex */
+#define GX_DELTA_REMOTE  0u  /* only vertices another part needs (lazy uploading) */
+#define GX_DELTA_ALL     1u  /* every changed vertex */
+#define GX_DELTA_MASTERS 2u  /* masters that another part holds a replica of */
 
 typedef struct gx_params {
     int32_t  algo;            /* gx_algo: GX_PAGERANK, GX_SSSP or GX_CC */
@@ -113,11 +120,16 @@ typedef struct gx_params {
     float    pull_fraction;   /* SSSP/CC: a superstep whose active out-edges exceed this fraction of
                                  all edges pulls (one sweep over every in-edge record) instead of
                                  pushing; 0 = default (0.3), >= 1 = always push */
-    uint32_t phases;          /* nonzero (PageRank, SSSP, CC): the state is driven by the separate
-                                 template calls gx_msg_gen / gx_msg_merge / gx_msg_apply in any
-                                 order an upper system uses (BSP or GAS); gx_superstep and
-                                 gx_run_until_converged refuse it */
+    uint32_t phases;          /* GX_PHASES_LOCAL or GX_PHASES_MASTERS (PageRank, SSSP, CC): the state
+                                 is driven by the separate template calls gx_msg_gen / gx_msg_merge /
+                                 gx_msg_apply in any order an upper system uses (BSP or GAS);
+                                 gx_superstep and gx_run_until_converged refuse it.  0 = fused */
 } gx_params;
+
+#define GX_PHASES_LOCAL   1u  /* the part is the whole graph */
+#define GX_PHASES_MASTERS 2u  /* PageRank on one part of a vertex-cut, exchanged with the other parts:
+                                 messages use the whole graph's out-degrees, MSGApply updates the
+                                 masters only (x0 and teleport use V_global); see gx_partial_emit */
 
 /* Statistics of one superstep (counts are exact). */
 typedef struct gx_step_stats {
@@ -249,6 +261,38 @@ gx_status gx_msg_merge(gx_state *s, void *stream);
 gx_status gx_msg_apply(gx_state *s, void *stream, gx_step_stats *stats);
 
 /*
+ * PageRank across the parts of a vertex-cut, one state per part created with
+ * GX_PHASES_MASTERS (Section "Synchronization Caching": mirrors and masters
+ * exchange only what changed; the combined value is the master's).  One
+ * superstep, over all parts p (the caller moves the buffers between them):
+ *   gx_msg_gen(p); gx_msg_merge(p)       every part sums its own in-edges'
+ *                                        messages, x[u] / outdeg_global(u);
+ *   gx_dangling_get(p) summed over the parts in part order, then
+ *   gx_dangling_set(p, total)            the whole graph's dangling mass;
+ *   gx_partial_emit(p)                   (gid, sum) of every replica whose
+ *                                        master is elsewhere and that has an
+ *                                        in-edge here, ascending gid;
+ *   gx_partial_add(q, pairs of p)        for every other part p, in part
+ *                                        order: masters add the sums (the
+ *                                        master's own sum comes first, so the
+ *                                        order of the additions is fixed);
+ *   gx_msg_apply(p)                      masters: x' = (1-d)/V_global +
+ *                                        d*(sum + D/V_global);
+ *   gx_sync_delta(p) (GX_DELTA_MASTERS)  then gx_apply_delta(q, pairs) on
+ *                                        every other part: replicas take
+ *                                        their masters' new ranks.
+ * gx_dangling_get synchronises `stream`; gx_dangling_set and gx_partial_add
+ * are asynchronous; gx_partial_emit synchronises and returns GX_ENOMEM when
+ * count > cap (nothing beyond cap written).  gx_partial_emit and
+ * gx_partial_add need merged, not yet applied, messages (GX_EINVAL).
+ */
+gx_status gx_dangling_get(gx_state *s, double *mass, void *stream);
+gx_status gx_dangling_set(gx_state *s, double mass, void *stream);
+gx_status gx_partial_emit(gx_state *s, int32_t *dev_gid, double *dev_val, uint32_t cap, uint32_t *count,
+                          void *stream);
+gx_status gx_partial_add(gx_state *s, const int32_t *dev_gid, const double *dev_val, uint32_t n, void *stream);
+
+/*
  * update() with lazy uploading and synchronisation skipping: emits the
  * (global id, value bits) pairs of vertices that (GX_DELTA_REMOTE) another
  * part needs -- remote_out for PageRank/SSSP, remote_any for CC -- and whose
@@ -293,7 +337,9 @@ gx_status gx_sync_delta_noalloc(gx_state *s, int32_t *dev_gid, uint32_t *dev_val
  * between gx_superstep calls: it rebuilds the active list of the next
  * superstep.  *active_next (optional) receives the next superstep's active
  * vertex count and then the call synchronises `stream`; otherwise it is
- * asynchronous.  GX_EINVAL for PageRank or NULL buffers with n > 0.
+ * asynchronous.  For a PageRank state under GX_PHASES_MASTERS the values are
+ * rank bits and every replica held here that is not the master takes them.
+ * GX_EINVAL for other PageRank states or NULL buffers with n > 0.
  */
 gx_status gx_apply_delta(gx_state *s, const int32_t *dev_gid, const uint32_t *dev_val, uint32_t n,
                          int64_t *active_next, void *stream);

@@ -11,12 +11,15 @@ from .binding import (  # noqa: F401
     GX_CC,
     GX_OK,
     GX_DELTA_ALL,
+    GX_DELTA_MASTERS,
     GX_DELTA_REMOTE,
     GX_LP,
     GX_NEED_IN,
     GX_NEED_OUT,
     GX_NEED_SYM,
     GX_PAGERANK,
+    GX_PHASES_LOCAL,
+    GX_PHASES_MASTERS,
     GX_PPR,
     GX_SSSP,
     INF,

@@ -15,7 +15,8 @@ _LIB_PATH = os.path.join(_PKG, "libgx.so")
 GX_OK, GX_EINVAL, GX_ENOMEM, GX_EDEVICE, GX_ENOTCONVERGED, GX_EBUSY, GX_ENOTFOUND = range(7)
 GX_PAGERANK, GX_SSSP, GX_CC, GX_PPR, GX_LP = 0, 1, 2, 3, 4
 GX_NEED_OUT, GX_NEED_IN, GX_NEED_SYM = 1, 2, 4
-GX_DELTA_REMOTE, GX_DELTA_ALL = 0, 1
+GX_DELTA_REMOTE, GX_DELTA_ALL, GX_DELTA_MASTERS = 0, 1, 2
+GX_PHASES_LOCAL, GX_PHASES_MASTERS = 1, 2
 INF = 0xFFFFFFFF
 
 _STATUS = {0: "GX_OK", 1: "GX_EINVAL", 2: "GX_ENOMEM", 3: "GX_EDEVICE", 4: "GX_ENOTCONVERGED",
@@ -31,7 +32,8 @@ class GxError(RuntimeError):
 class _GraphDesc(ctypes.Structure):
     _fields_ = [("V", ctypes.c_int64), ("E", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
                 ("col", ctypes.c_void_p), ("w", ctypes.c_void_p), ("l2g", ctypes.c_void_p),
-                ("flags", ctypes.c_void_p), ("needs", ctypes.c_uint32), ("pr_tile_edges", ctypes.c_uint32)]
+                ("flags", ctypes.c_void_p), ("needs", ctypes.c_uint32), ("pr_tile_edges", ctypes.c_uint32),
+                ("V_global", ctypes.c_int64), ("outdeg_global", ctypes.c_void_p)]
 
 
 class _Params(ctypes.Structure):
@@ -101,6 +103,10 @@ _SIGS = {
     "gx_sync_delta": (ctypes.c_int32, [_P, _P, _P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
                                        ctypes.POINTER(ctypes.c_int32), _P]),
     "gx_sync_delta_noalloc": (ctypes.c_int32, [_P, _P, _P, ctypes.c_uint32, _P, _P]),
+    "gx_dangling_get": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_double), _P]),
+    "gx_dangling_set": (ctypes.c_int32, [_P, ctypes.c_double, _P]),
+    "gx_partial_emit": (ctypes.c_int32, [_P, _P, _P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32), _P]),
+    "gx_partial_add": (ctypes.c_int32, [_P, _P, _P, ctypes.c_uint32, _P]),
     "gx_msg_gen": (ctypes.c_int32, [_P, _P]),
     "gx_msg_merge": (ctypes.c_int32, [_P, _P]),
     "gx_msg_apply": (ctypes.c_int32, [_P, _P, ctypes.POINTER(StepStats)]),
@@ -200,16 +206,18 @@ class DeviceGraph:
     """A worker's graph resident in HBM.  ``host`` is any object with V, E,
     row_ptr, col, w and optional l2g / flags numpy arrays (out-CSR)."""
 
-    def __init__(self, host, needs: int, device="cuda:0", stream=None, pr_tile_edges: int = 0):
+    def __init__(self, host, needs: int, device="cuda:0", stream=None, pr_tile_edges: int = 0,
+                 V_global: int = 0, outdeg_global=None):
         import torch
         self.device = torch.device(device)
         self._keep = [np.ascontiguousarray(host.row_ptr, np.int32), np.ascontiguousarray(host.col, np.int32),
                       None if host.w is None else np.ascontiguousarray(host.w, np.uint32),
                       None if getattr(host, "l2g", None) is None else np.ascontiguousarray(host.l2g, np.int32),
-                      None if getattr(host, "flags", None) is None else np.ascontiguousarray(host.flags, np.uint8)]
-        rp, col, w, l2g, flags = self._keep
+                      None if getattr(host, "flags", None) is None else np.ascontiguousarray(host.flags, np.uint8),
+                      None if outdeg_global is None else np.ascontiguousarray(outdeg_global, np.int32)]
+        rp, col, w, l2g, flags, odg = self._keep
         self.desc = _GraphDesc(int(host.V), int(host.E), _np_ptr(rp), _np_ptr(col), _np_ptr(w), _np_ptr(l2g),
-                               _np_ptr(flags), int(needs), int(pr_tile_edges))
+                               _np_ptr(flags), int(needs), int(pr_tile_edges), int(V_global), _np_ptr(odg))
         nbytes = ctypes.c_size_t(0)
         _check(lib.gx_graph_bytes(ctypes.byref(self.desc), ctypes.byref(nbytes)))
         self.arena_bytes = nbytes.value
@@ -240,12 +248,12 @@ class State:
 
     def __init__(self, graph: DeviceGraph, algo: int, source: int = 0, damping: float = 0.85,
                  max_supersteps: int = 1 << 20, delta_mode: int = GX_DELTA_REMOTE, timing: bool = False,
-                 pull_fraction: float = 0.0, stream=None, phases: bool = False):
+                 pull_fraction: float = 0.0, stream=None, phases: int = 0):
         import torch
         self.graph = graph
         self.algo = algo
         self.params = _Params(int(algo), float(damping), int(source), int(max_supersteps), int(delta_mode),
-                              int(bool(timing)), float(pull_fraction), int(bool(phases)))
+                              int(bool(timing)), float(pull_fraction), int(phases))
         nbytes = ctypes.c_size_t(0)
         _check(lib.gx_state_bytes(graph.handle, ctypes.byref(self.params), ctypes.byref(nbytes)))
         with torch.cuda.device(graph.device):
@@ -360,6 +368,32 @@ class State:
         st = StepStats()
         _check(lib.gx_msg_apply(self.handle, _stream_handle(stream), ctypes.byref(st) if stats else None))
         return st.as_tuple() if stats else None
+
+    def dangling_get(self, stream=None) -> float:
+        """This part's masters' dangling mass from the last MSGGen (GX_PHASES_MASTERS)."""
+        m = ctypes.c_double()
+        _check(lib.gx_dangling_get(self.handle, ctypes.byref(m), _stream_handle(stream)))
+        return m.value
+
+    def dangling_set(self, mass: float, stream=None):
+        _check(lib.gx_dangling_set(self.handle, float(mass), _stream_handle(stream)))
+
+    def partial_emit(self, cap: int | None = None, stream=None):
+        """(gid int32, sum float64) device tensors of the merged sums this part
+        sends to the replicas' masters."""
+        import torch
+        cap = self.graph.V if cap is None else int(cap)
+        gid = torch.empty(max(cap, 1), dtype=torch.int32, device=self.graph.device)
+        val = torch.empty(max(cap, 1), dtype=torch.float64, device=self.graph.device)
+        n = ctypes.c_uint32()
+        _check(lib.gx_partial_emit(self.handle, ctypes.c_void_p(gid.data_ptr()), ctypes.c_void_p(val.data_ptr()),
+                                   cap, ctypes.byref(n), _stream_handle(stream)))
+        return gid[:n.value], val[:n.value]
+
+    def partial_add(self, gid, val, stream=None):
+        n = int(gid.numel())
+        _check(lib.gx_partial_add(self.handle, ctypes.c_void_p(gid.data_ptr()) if n else None,
+                                  ctypes.c_void_p(val.data_ptr()) if n else None, n, _stream_handle(stream)))
 
     def sync_delta_noalloc(self, gid, val, count, stream=None):
         """gx_sync_delta_noalloc: writes up to gid.numel() pairs into the given

@@ -74,7 +74,7 @@ struct HostImages {
     std::vector<uint2> pull_w, pull_sym;
     std::vector<uint4> pull_w_units, pull_sym_units;
     PullSlices pull_w_off{}, pull_sym_off{};
-    std::vector<uint32_t> rem_out, rem_any;
+    std::vector<uint32_t> rem_out, rem_any, master, master_rep;
 };
 
 static gx_status validate(const gx_graph_desc *d) {
@@ -109,6 +109,15 @@ static gx_status validate(const gx_graph_desc *d) {
             break;
         }
     GX_REQUIRE(!bad, GX_EINVAL, "col[%lld]=%d out of [0,V)", (long long)badpos, bad ? d->col[badpos] : 0);
+    GX_REQUIRE((d->V_global == 0) == (d->outdeg_global == nullptr), GX_EINVAL,
+               "V_global and outdeg_global come together");
+    if (d->outdeg_global) {
+        GX_REQUIRE(d->V_global >= d->V && d->V_global < (int64_t(1) << 31), GX_EINVAL, "V_global=%lld out of range",
+                   (long long)d->V_global);
+        for (int64_t v = 0; v < d->V; v++)
+            GX_REQUIRE(d->outdeg_global[v] >= d->row_ptr[v + 1] - d->row_ptr[v], GX_EINVAL,
+                       "outdeg_global[%lld] below the local out-degree", (long long)v);
+    }
     if (d->l2g) {
         GX_REQUIRE(d->l2g[0] >= 0, GX_EINVAL, "l2g[0] negative");
         for (int64_t v = 1; v < d->V; v++)
@@ -313,11 +322,16 @@ static void build_sym(const gx_graph_desc *d, HostImages &h) {
 static void build_flags(const gx_graph_desc *d, int32_t W, HostImages &h) {
     h.rem_out.assign(W, 0);
     h.rem_any.assign(W, 0);
+    h.master.assign(W, 0);
+    h.master_rep.assign(W, 0);
     if (!d->flags) return;
     for (int64_t v = 0; v < d->V; v++) {
         uint32_t bit = 1u << (v & 31);
-        if (d->flags[v] & GX_FLAG_REMOTE_OUT) h.rem_out[v >> 5] |= bit;
-        if (d->flags[v] & GX_FLAG_REMOTE_ANY) h.rem_any[v >> 5] |= bit;
+        const uint8_t f = d->flags[v];
+        if (f & GX_FLAG_REMOTE_OUT) h.rem_out[v >> 5] |= bit;
+        if (f & GX_FLAG_REMOTE_ANY) h.rem_any[v >> 5] |= bit;
+        if (f & GX_FLAG_MASTER) h.master[v >> 5] |= bit;
+        if ((f & GX_FLAG_MASTER) && (f & GX_FLAG_REMOTE_ANY)) h.master_rep[v >> 5] |= bit;
     }
 }
 
@@ -354,9 +368,15 @@ static void layout(const gx_graph_desc *desc, int64_t E_sym, Carver &c, DevGraph
         d->pull_sym_units = c.take<uint4>(pull_unit_cap(V, E_sym));
     }
     if (desc->l2g) d->l2g = c.take<int32_t>(V);
+    if (desc->outdeg_global) {
+        d->outdeg_g = c.take<int32_t>(V);
+        d->V_global = desc->V_global;
+    }
     if (desc->flags) {
         d->remote_out = c.take<uint32_t>(d->W);
         d->remote_any = c.take<uint32_t>(d->W);
+        d->master = c.take<uint32_t>(d->W);
+        d->master_rep = c.take<uint32_t>(d->W);
     }
 }
 
@@ -535,9 +555,12 @@ extern "C" gx_status gx_graph_load(const gx_graph_desc *desc, void *dev_arena, s
                              h.pull_sym_units.size() * sizeof(uint4));
     }
     if (e == hipSuccess && d.l2g) e = up.put_array((void *)d.l2g, desc->l2g, V * 4);
+    if (e == hipSuccess && d.outdeg_g) e = up.put_array((void *)d.outdeg_g, desc->outdeg_global, V * 4);
     if (e == hipSuccess && d.remote_out) {
         e = up.put_array((void *)d.remote_out, h.rem_out.data(), (size_t)W * 4);
         if (e == hipSuccess) e = up.put_array((void *)d.remote_any, h.rem_any.data(), (size_t)W * 4);
+        if (e == hipSuccess) e = up.put_array((void *)d.master, h.master.data(), (size_t)W * 4);
+        if (e == hipSuccess) e = up.put_array((void *)d.master_rep, h.master_rep.data(), (size_t)W * 4);
     }
     if (e == hipSuccess) e = up.finish(s);
     if (e != hipSuccess) {

@@ -135,6 +135,11 @@ struct DevGraph {
     const int32_t *l2g = nullptr;          // nullptr = identity
     const uint32_t *remote_out = nullptr;  // bitmaps of W words (nullptr = none remote)
     const uint32_t *remote_any = nullptr;
+    const uint32_t *master = nullptr;      // this part holds the master copy
+    const uint32_t *master_rep = nullptr;  // ... of a vertex another part holds a replica of
+    // PageRank exchanged between the parts: out-degrees in the whole graph
+    const int32_t *outdeg_g = nullptr;
+    int64_t V_global = 0;
 };
 
 }  // namespace gx
@@ -237,6 +242,7 @@ struct gx_state {
     double *Dscratch = nullptr;      // dangling-mass slot the merge's fix-up writes (never read)
     gx::DevStep *ph_steps = nullptr; // counter slots the merge's fix-up writes (never read)
     int ph_p = 0;                    // front8[ph_p] collects the vertices the next MSGGen sends from
+    double D_host = 0.0;             // staging of gx_dangling_set (lives as long as the state)
     bool ph_msgs = false, ph_merged = false;
     // shared
     gx::DevStep *steps = nullptr;

@@ -764,6 +764,112 @@ __global__ __launch_bounds__(PR_FIX_BLOCK) void k_pr_fix(const int32_t *__restri
     }
 }
 
+// ------------------------------------------------------------ PageRank across the parts of a vertex-cut
+
+__device__ __forceinline__ bool bit_of(const uint32_t *bm, int64_t v) { return (bm[v >> 5] >> (v & 31)) & 1u; }
+
+// Replicas this part sends its merged messages for: held elsewhere too, the
+// master elsewhere, and with at least one in-edge here (else the sum is 0).
+__device__ __forceinline__ uint32_t partial_word(int32_t w, int64_t V, const uint32_t *remote_any,
+                                                 const uint32_t *master, const int32_t *in_rp) {
+    const uint32_t valid = (int64_t)(w + 1) * 32 <= V ? 0xFFFFFFFFu : ((1u << (V - (int64_t)w * 32)) - 1u);
+    const uint32_t cand = remote_any[w] & ~master[w] & valid;
+    uint32_t out = 0;
+    for (uint32_t m = cand; m; m &= m - 1) {
+        const int b = __ffs(m) - 1;
+        const int64_t v = (int64_t)w * 32 + b;
+        if (in_rp[v + 1] > in_rp[v]) out |= 1u << b;
+    }
+    return out;
+}
+
+__global__ __launch_bounds__(256) void k_part_count(int32_t W, int64_t V, const uint32_t *remote_any,
+                                                    const uint32_t *master, const int32_t *in_rp, uint32_t *blk_cnt) {
+    __shared__ unsigned long long s[4];
+    const int32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t c = w < W ? __popc(partial_word(w, V, remote_any, master, in_rp)) : 0u;
+    const unsigned long long t = block_sum<unsigned long long>(c, s);
+    if (threadIdx.x == 0) blk_cnt[blockIdx.x] = (uint32_t)t;
+}
+
+// (gid, merged sum) of the selected replicas in ascending gid; positions from
+// the block counts as in the sync set.
+__global__ __launch_bounds__(256) void k_part_emit(int32_t W, int64_t V, const uint32_t *remote_any,
+                                                   const uint32_t *master, const int32_t *in_rp,
+                                                   const int32_t *l2g, const double *__restrict__ acc,
+                                                   const uint32_t *__restrict__ blk_cnt, int nblk, uint32_t cap,
+                                                   int32_t *gid_out, double *val_out, uint32_t *total_out) {
+    __shared__ unsigned long long s_scan[4];
+    __shared__ unsigned long long s_pre[4], s_all[4];
+    const int tid = threadIdx.x;
+    unsigned long long pre = 0, all_ = 0;
+    for (int b = tid; b < nblk; b += blockDim.x) {
+        const unsigned long long c = blk_cnt[b];
+        all_ += c;
+        if (b < (int)blockIdx.x) pre += c;
+    }
+    {
+        const int lane = tid & 63, wid = tid >> 6;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            pre += __shfl_down(pre, o, 64);
+            all_ += __shfl_down(all_, o, 64);
+        }
+        if (lane == 0) {
+            s_pre[wid] = pre;
+            s_all[wid] = all_;
+        }
+        __syncthreads();
+        pre = s_pre[0] + s_pre[1] + s_pre[2] + s_pre[3];
+        all_ = s_all[0] + s_all[1] + s_all[2] + s_all[3];
+        __syncthreads();
+    }
+    if (blockIdx.x == 0 && tid == 0) *total_out = (uint32_t)all_;
+    const int32_t w = blockIdx.x * blockDim.x + tid;
+    const uint32_t bits = w < W ? partial_word(w, V, remote_any, master, in_rp) : 0u;
+    unsigned long long tot;
+    unsigned long long pos = pre + block_excl_scan_u64(__popc(bits), &tot, s_scan);
+    for (uint32_t m = bits; m; m &= m - 1) {
+        const int64_t v = (int64_t)w * 32 + __ffs(m) - 1;
+        if (pos < cap) {
+            gid_out[pos] = l2g[v];
+            val_out[pos] = acc[v];
+        }
+        pos++;
+    }
+}
+
+__device__ __forceinline__ int64_t local_of(const int32_t *__restrict__ l2g, int64_t V, int32_t g) {
+    int64_t lo = 0, hi = V;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if (l2g[mid] < g) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < V && l2g[lo] == g) ? lo : -1;
+}
+
+// A master adds another part's merged sum for it (one pair per vertex per
+// call; the caller orders the calls, so the sum's order is fixed).
+__global__ __launch_bounds__(256) void k_part_add(const int32_t *__restrict__ gid, const double *__restrict__ vals,
+                                                  uint32_t n, const int32_t *__restrict__ l2g, int64_t V,
+                                                  const uint32_t *__restrict__ master, double *__restrict__ acc) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t x = local_of(l2g, V, gid[i]);
+    if (x >= 0 && bit_of(master, x)) acc[x] += vals[i];
+}
+
+// A replica takes its master's new rank.
+__global__ __launch_bounds__(256) void k_replica_set(const int32_t *__restrict__ gid, const uint32_t *__restrict__ vals,
+                                                     uint32_t n, const int32_t *__restrict__ l2g, int64_t V,
+                                                     const uint32_t *__restrict__ master, uint32_t *__restrict__ x) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t v = local_of(l2g, V, gid[i]);
+    if (v >= 0 && !bit_of(master, v)) x[v] = vals[i];
+}
+
 // ------------------------------------------------------------ sync set
 
 __device__ __forceinline__ uint32_t delta_word(int32_t w, int64_t V, const uint32_t *remote, bool all,
@@ -924,8 +1030,11 @@ __global__ __launch_bounds__(256) void k_ph_apply(uint32_t *__restrict__ acc, ui
 
 // MSGGen of PageRank: every vertex's message x[u]/outdeg(u) and the
 // dangling mass (per-workgroup partials, summed in order by k_reduce_D).
+// (master != NULL: a part of a vertex-cut; only its masters' dangling mass
+// counts, every other part counts its own masters)
 __global__ __launch_bounds__(256) void k_ph_pr_gen(const float *__restrict__ x, const int32_t *__restrict__ outdeg,
-                                                   float *__restrict__ contrib, int64_t V, double *dpart) {
+                                                   float *__restrict__ contrib, int64_t V, double *dpart,
+                                                   const uint32_t *__restrict__ master) {
     __shared__ double s_d[4];
     const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
     double dl = 0.0;
@@ -933,7 +1042,7 @@ __global__ __launch_bounds__(256) void k_ph_pr_gen(const float *__restrict__ x, 
         const float xv = x[v];
         const int od = outdeg[v];
         contrib[v] = od > 0 ? xv / (float)od : 0.0f;
-        if (od == 0) dl = (double)xv;
+        if (od == 0 && (!master || bit_of(master, v))) dl = (double)xv;
     }
     const double t = block_sum<double>(dl, s_d);
     if (threadIdx.x == 0) dpart[blockIdx.x] = t;
@@ -942,12 +1051,13 @@ __global__ __launch_bounds__(256) void k_ph_pr_gen(const float *__restrict__ x, 
 // MSGApply of PageRank: x' = (1-d)/V + d * (merged + D/V), in place.
 __global__ __launch_bounds__(256) void k_ph_pr_apply(const double *__restrict__ acc, float *__restrict__ x, int64_t V,
                                                      double base, double d, const double *__restrict__ Dp,
-                                                     double inv_V, DevStep *step, DevStep *next) {
+                                                     double inv_V, DevStep *step, DevStep *next,
+                                                     const uint32_t *__restrict__ master) {
     __shared__ unsigned long long s_c[4];
     const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const double dD = d * (*Dp) * inv_V;
     unsigned c = 0;
-    if (v < V) {
+    if (v < V && (!master || bit_of(master, v))) {  // a part of a vertex-cut applies at its masters
         const float xn = (float)(base + d * acc[v] + dD);
         c = __float_as_uint(xn) != __float_as_uint(x[v]);
         x[v] = xn;
@@ -1062,8 +1172,13 @@ static gx_status check_params(const gx_graph *g, const gx_params *p) {
     GX_REQUIRE(!g->dev_error, GX_EDEVICE, "graph handle has a sticky device error");
     GX_REQUIRE(p->algo == GX_PAGERANK || p->algo == GX_SSSP || p->algo == GX_CC || p->algo == GX_LP, GX_EINVAL,
                "algo %d not supported by the plain engine", p->algo);
-    GX_REQUIRE(p->delta_mode <= GX_DELTA_ALL, GX_EINVAL, "delta_mode %u invalid", p->delta_mode);
+    GX_REQUIRE(p->delta_mode <= GX_DELTA_MASTERS, GX_EINVAL, "delta_mode %u invalid", p->delta_mode);
+    GX_REQUIRE(p->delta_mode != GX_DELTA_MASTERS || g->d.master_rep, GX_EINVAL,
+               "GX_DELTA_MASTERS needs a partitioned graph (flags)");
+    GX_REQUIRE(p->phases <= GX_PHASES_MASTERS, GX_EINVAL, "phases %u invalid", p->phases);
     GX_REQUIRE(!p->phases || p->algo != GX_LP, GX_EINVAL, "the separate template calls serve PageRank, SSSP and CC");
+    GX_REQUIRE(p->phases != GX_PHASES_MASTERS || (p->algo == GX_PAGERANK && g->d.outdeg_g && g->d.master), GX_EINVAL,
+               "GX_PHASES_MASTERS is PageRank on a part loaded with flags, V_global and outdeg_global");
     if (p->algo == GX_PAGERANK) {
         GX_REQUIRE(g->needs & GX_NEED_IN, GX_EINVAL, "PageRank needs GX_NEED_IN");
         GX_REQUIRE(p->damping >= 0.f && p->damping < 1.f, GX_EINVAL, "damping %f out of [0,1)", p->damping);
@@ -1134,7 +1249,8 @@ extern "C" gx_status gx_state_init(gx_graph *g, const gx_params *p, void *dev_st
             return ls;
         }
     } else if (p->algo == GX_PAGERANK) {
-        float x0 = V > 0 ? (float)(1.0 / (double)V) : 0.f;
+        const int64_t Vn = p->phases == GX_PHASES_MASTERS ? d.V_global : V;
+        float x0 = V > 0 ? (float)(1.0 / (double)Vn) : 0.f;
         unsigned nb = grid_for<int64_t>(V, 256);
         hipLaunchKernelGGL(k_pr_init, dim3(nb), dim3(256), 0, hs, s->x[0], s->contrib[0], s->synced, d.outdeg, V, x0,
                            s->dpart, s->steps);
@@ -1542,7 +1658,9 @@ extern "C" gx_status gx_sync_delta(gx_state *s, int32_t *dev_gid, uint32_t *dev_
     if (skippable) *skippable = 1;
     if (d.W == 0) return GX_OK;
     bool all = s->p.delta_mode == GX_DELTA_ALL;
-    const uint32_t *remote = (s->p.algo == GX_CC || s->p.algo == GX_LP) ? d.remote_any : d.remote_out;
+    const uint32_t *remote = s->p.delta_mode == GX_DELTA_MASTERS              ? d.master_rep
+                           : (s->p.algo == GX_CC || s->p.algo == GX_LP) ? d.remote_any
+                                                                        : d.remote_out;
     // PageRank and LP compare with the synced copy (LP labels can return to an
     // earlier value); SSSP / CC values only fall, so the dirty map decides
     const bool by_copy = s->p.algo == GX_PAGERANK || s->p.algo == GX_LP;
@@ -1622,7 +1740,9 @@ extern "C" gx_status gx_sync_delta_noalloc(gx_state *s, int32_t *dev_gid, uint32
         return GX_OK;
     }
     bool all = s->p.delta_mode == GX_DELTA_ALL;
-    const uint32_t *remote = (s->p.algo == GX_CC || s->p.algo == GX_LP) ? d.remote_any : d.remote_out;
+    const uint32_t *remote = s->p.delta_mode == GX_DELTA_MASTERS              ? d.master_rep
+                           : (s->p.algo == GX_CC || s->p.algo == GX_LP) ? d.remote_any
+                                                                        : d.remote_out;
     // PageRank and LP compare with the synced copy (LP labels can return to an
     // earlier value); SSSP / CC values only fall, so the dirty map decides
     const bool by_copy = s->p.algo == GX_PAGERANK || s->p.algo == GX_LP;
@@ -1642,11 +1762,20 @@ extern "C" gx_status gx_apply_delta(gx_state *s, const int32_t *dev_gid, const u
     clear_error();
     GX_REQUIRE(s, GX_EINVAL, "state is NULL");
     GX_REQUIRE(n == 0 || (dev_gid && dev_val), GX_EINVAL, "input buffers are NULL");
-    GX_REQUIRE(s->p.algo == GX_SSSP || s->p.algo == GX_CC, GX_EINVAL, "gx_apply_delta merges SSSP / CC values only");
-    GX_REQUIRE(!s->p.phases, GX_EINVAL, "gx_apply_delta serves states driven by gx_superstep");
     GX_REQUIRE(!s->dev_error && !s->g->dev_error, GX_EDEVICE, "sticky device error");
     hipStream_t hs = static_cast<hipStream_t>(stream);
     const DevGraph &d = s->g->d;
+    if (s->p.phases == GX_PHASES_MASTERS) {  // PageRank replicas take their masters' new ranks
+        if (n > 0 && d.V > 0)
+            hipLaunchKernelGGL(k_replica_set, dim3(grid_for<uint32_t>(n, 256)), dim3(256), 0, hs, dev_gid, dev_val, n,
+                               d.l2g, d.V, d.master, reinterpret_cast<uint32_t *>(s->x[0]));
+        GX_CHECK_HIP(hipGetLastError(), s);
+        if (active_next) *active_next = 0;
+        return GX_OK;
+    }
+    GX_REQUIRE(s->p.algo == GX_SSSP || s->p.algo == GX_CC, GX_EINVAL,
+               "gx_apply_delta merges SSSP / CC values (and PageRank ranks under GX_PHASES_MASTERS)");
+    GX_REQUIRE(!s->p.phases, GX_EINVAL, "gx_apply_delta serves SSSP / CC states driven by gx_superstep");
     if (d.V > 0) {
         // A_{k+1} (the frontier of the superstep about to run) and its counter slot
         uint8_t *front = s->front8[s->k & 1];
@@ -1693,8 +1822,9 @@ extern "C" gx_status gx_msg_gen(gx_state *s, void *stream) {
     if (d.V > 0) {
         if (s->p.algo == GX_PAGERANK) {
             const unsigned nb = grid_for<int64_t>(d.V, 256);
-            hipLaunchKernelGGL(k_ph_pr_gen, dim3(nb), dim3(256), 0, hs, s->x[0], d.outdeg, s->contrib[0], d.V,
-                               s->dpart);
+            const bool parts = s->p.phases == GX_PHASES_MASTERS;
+            hipLaunchKernelGGL(k_ph_pr_gen, dim3(nb), dim3(256), 0, hs, s->x[0], parts ? d.outdeg_g : d.outdeg,
+                               s->contrib[0], d.V, s->dpart, parts ? d.master : nullptr);
             hipLaunchKernelGGL(k_reduce_D, dim3(1), dim3(1024), 0, hs, s->dpart, (int)nb, s->Dval);
         } else {
             // the pending map's vertices become the active list (with the values
@@ -1769,9 +1899,11 @@ extern "C" gx_status gx_msg_apply(gx_state *s, void *stream, gx_step_stats *stat
     DevStep *step = s->steps + (k % STEP_RING), *next = s->steps + ((k + 1) % STEP_RING);
     if (d.V > 0) {
         if (s->p.algo == GX_PAGERANK) {
+            const bool parts = s->p.phases == GX_PHASES_MASTERS;
+            const double Vn = (double)(parts ? d.V_global : d.V);
             hipLaunchKernelGGL(k_ph_pr_apply, dim3(grid_for<int64_t>(d.V, 256)), dim3(256), 0, hs, s->acc_d, s->x[0],
-                               d.V, (1.0 - (double)s->p.damping) / (double)d.V, (double)s->p.damping, s->Dval,
-                               1.0 / (double)d.V, step, next);
+                               d.V, (1.0 - (double)s->p.damping) / Vn, (double)s->p.damping, s->Dval, 1.0 / Vn, step,
+                               next, parts ? d.master : nullptr);
         } else {
             hipLaunchKernelGGL(k_ph_apply, dim3(grid_for<int64_t>(d.V, 256)), dim3(256), 0, hs, s->acc, s->val,
                                s->front8[s->ph_p], s->dirty8, d.V, step);
@@ -1790,5 +1922,79 @@ extern "C" gx_status gx_msg_apply(gx_state *s, void *stream, gx_step_stats *stat
         stats->changed = (int64_t)ds[0].changed;
         stats->pulled = pr ? 1 : (ds[0].pad ? 1 : 0);
     }
+    return GX_OK;
+}
+
+// ------------------------------------------------------------ PageRank across the parts of a vertex-cut
+
+static gx_status parts_check(gx_state *s) {
+    GX_REQUIRE(s, GX_EINVAL, "state is NULL");
+    GX_REQUIRE(s->p.phases == GX_PHASES_MASTERS, GX_EINVAL, "state was not initialised with GX_PHASES_MASTERS");
+    GX_REQUIRE(!s->dev_error && !s->g->dev_error, GX_EDEVICE, "sticky device error");
+    return GX_OK;
+}
+
+extern "C" gx_status gx_dangling_get(gx_state *s, double *mass, void *stream) {
+    clear_error();
+    gx_status st = parts_check(s);
+    if (st != GX_OK) return st;
+    GX_REQUIRE(mass, GX_EINVAL, "mass is NULL");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    GX_CHECK_HIP(hipMemcpyAsync(mass, s->Dval, sizeof(double), hipMemcpyDeviceToHost, hs), s);
+    GX_CHECK_HIP(hipStreamSynchronize(hs), s);
+    return GX_OK;
+}
+
+extern "C" gx_status gx_dangling_set(gx_state *s, double mass, void *stream) {
+    clear_error();
+    gx_status st = parts_check(s);
+    if (st != GX_OK) return st;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    s->D_host = mass;
+    GX_CHECK_HIP(hipMemcpyAsync(s->Dval, &s->D_host, sizeof(double), hipMemcpyHostToDevice, hs), s);
+    return GX_OK;
+}
+
+extern "C" gx_status gx_partial_emit(gx_state *s, int32_t *dev_gid, double *dev_val, uint32_t cap, uint32_t *count,
+                                     void *stream) {
+    clear_error();
+    gx_status st = parts_check(s);
+    if (st != GX_OK) return st;
+    GX_REQUIRE(count, GX_EINVAL, "count is NULL");
+    GX_REQUIRE(cap == 0 || (dev_gid && dev_val), GX_EINVAL, "output buffers are NULL");
+    GX_REQUIRE(s->ph_merged, GX_EINVAL, "no merged messages to send");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const DevGraph &d = s->g->d;
+    *count = 0;
+    if (d.W == 0) return GX_OK;
+    hipLaunchKernelGGL(k_part_count, dim3(s->delta_blocks), dim3(256), 0, hs, d.W, d.V, d.remote_any, d.master,
+                       d.in_rp, s->blk_cnt);
+    hipLaunchKernelGGL(k_part_emit, dim3(s->delta_blocks), dim3(256), 0, hs, d.W, d.V, d.remote_any, d.master,
+                       d.in_rp, d.l2g, s->acc_d, s->blk_cnt, s->delta_blocks, cap, dev_gid, dev_val, s->delta_total);
+    GX_CHECK_HIP(hipGetLastError(), s);
+    uint32_t total = 0;
+    GX_CHECK_HIP(hipMemcpyAsync(&total, s->delta_total, 4, hipMemcpyDeviceToHost, hs), s);
+    GX_CHECK_HIP(hipStreamSynchronize(hs), s);
+    *count = total;
+    if (total > cap) {
+        set_error("%u merged sums to send, capacity %u", total, cap);
+        return GX_ENOMEM;
+    }
+    return GX_OK;
+}
+
+extern "C" gx_status gx_partial_add(gx_state *s, const int32_t *dev_gid, const double *dev_val, uint32_t n,
+                                    void *stream) {
+    clear_error();
+    gx_status st = parts_check(s);
+    if (st != GX_OK) return st;
+    GX_REQUIRE(n == 0 || (dev_gid && dev_val), GX_EINVAL, "input buffers are NULL");
+    GX_REQUIRE(s->ph_merged, GX_EINVAL, "merge this part's messages before adding other parts' sums");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const DevGraph &d = s->g->d;
+    if (n > 0 && d.V > 0)
+        hipLaunchKernelGGL(k_part_add, dim3(grid_for<uint32_t>(n, 256)), dim3(256), 0, hs, dev_gid, dev_val, n, d.l2g,
+                           d.V, d.master, s->acc_d);
+    GX_CHECK_HIP(hipGetLastError(), s);
     return GX_OK;
 }

@@ -81,3 +81,18 @@ def test_pick_sources_distinct_with_out_edges():
     assert len(np.unique(s)) == 64
     assert np.all(np.diff(g.row_ptr)[s] > 0)
     assert np.array_equal(s, gen.pick_sources(g, 64, seed=40))
+
+
+def test_cover_isolated_gives_every_vertex_one_master():
+    g = gen.rmat(10, seed=3)
+    parts = [gen.rmat_part(10, seed=3, part=p) for p in range(8)]
+    cov = gen.cover_isolated(parts, g.V)
+    masters = np.zeros(g.V, int)
+    for p in cov:
+        masters[p.l2g[(p.flags & 1) != 0]] += 1
+    assert (masters == 1).all()
+    for a, b in zip(parts, cov):
+        ea = set(zip(a.l2g[a.src].tolist(), a.l2g[a.col].tolist()))
+        eb = set(zip(b.l2g[b.src].tolist(), b.l2g[b.col].tolist()))
+        assert ea == eb and np.all(np.diff(b.l2g) > 0)
+    assert cov[0].V == parts[0].V + cov[0].meta["isolated_added"]
