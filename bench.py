@@ -435,12 +435,69 @@ def bench_exchange(gx, torch, np, gen, scale=22, nparts=8, reps=3):
     assert K == rs.supersteps
     dt = sorted(times)[len(times) // 2]
     log(f"exchange: {nparts} parts, K={K}, {pairs} pairs exchanged, {dt * 1e3:.1f} ms per solve")
-    return {"workload": f"all {nparts} parts of a hash vertex-cut of R-MAT scale {scale} (seed 2) resident, "
-                        "SSSP from vertex 0 with the sync sets exchanged every superstep (gx_sync_delta / "
-                        "gx_apply_delta), equal to the whole-graph solve",
-            "parts": nparts, "replicas": int(sum(p.V for p in parts)), "edges": int(sum(p.E for p in parts)),
-            "supersteps": K, "pairs_exchanged_per_solve": pairs, "ms_per_solve": dt * 1e3,
-            "whole_graph_messages_per_solve": int(rs.edges), "gteps": rs.edges / dt / 1e9}
+    out = {"workload": f"all {nparts} parts of a hash vertex-cut of R-MAT scale {scale} (seed 2) resident, "
+                       "SSSP from vertex 0 with the sync sets exchanged every superstep (gx_sync_delta / "
+                       "gx_apply_delta), equal to the whole-graph solve",
+           "parts": nparts, "replicas": int(sum(p.V for p in parts)), "edges": int(sum(p.E for p in parts)),
+           "supersteps": K, "pairs_exchanged_per_solve": pairs, "ms_per_solve": dt * 1e3,
+           "whole_graph_messages_per_solve": int(rs.edges), "gteps": rs.edges / dt / 1e9}
+    del states, dgs, ref
+    out["pagerank"] = bench_exchange_pagerank(gx, torch, np, gen, g, parts)
+    return out
+
+
+def bench_exchange_pagerank(gx, torch, np, gen, g, parts, T=30):
+    """PageRank, 30 supersteps, across all parts of the vertex-cut: merged
+    sums of replicas to their masters in part order, masters apply with the
+    whole graph's dangling mass, replicas take the masters' ranks; within
+    1e-6 of the whole-graph PageRank."""
+    parts = gen.cover_isolated(parts, g.V)
+    deg = np.diff(g.row_ptr).astype(np.int32)
+    states = []
+    for p in parts:
+        dg = gx.DeviceGraph(p, gx.GX_NEED_IN, V_global=g.V, outdeg_global=deg[p.l2g])
+        states.append(gx.State(dg, gx.GX_PAGERANK, damping=0.85, phases=gx.GX_PHASES_MASTERS,
+                               delta_mode=gx.GX_DELTA_MASTERS))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sums = bcast = 0
+    for _ in range(T):
+        for st in states:
+            st.msg_gen()
+            st.msg_merge()
+        D = 0.0
+        for st in states:
+            D += st.dangling_get()
+        for st in states:
+            st.dangling_set(D)
+        sent = [st.partial_emit() for st in states]
+        sums += sum(int(x[0].numel()) for x in sent)
+        for q, st in enumerate(states):
+            for p in range(len(states)):
+                if p != q and sent[p][0].numel():
+                    st.partial_add(*sent[p])
+        for st in states:
+            st.msg_apply(stats=False)
+        bc = [st.sync_delta(on_device=True) for st in states]
+        bcast += sum(int(x[0].numel()) for x in bc)
+        for q, st in enumerate(states):
+            others = [b for p, b in enumerate(bc) if p != q and b[0].numel()]
+            if others:
+                st.apply_delta(torch.cat([o[0] for o in others]), torch.cat([o[1] for o in others]))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    whole = gx.State(gx.DeviceGraph(g, gx.GX_NEED_IN), gx.GX_PAGERANK, damping=0.85)
+    whole.run(T)
+    xw = whole.values_numpy()
+    err = max(float(np.max(np.abs(st.values_numpy() - xw[p.l2g]))) for p, st in zip(parts, states))
+    assert err <= 1e-6, f"PageRank exchange differs from the whole-graph PageRank by {err}"
+    log(f"exchange PageRank: {T} supersteps in {dt * 1e3:.1f} ms ({dt * 1e3 / T:.2f} ms per superstep), "
+        f"{sums} merged sums and {bcast} ranks exchanged, max |diff| vs whole graph {err:.2e}")
+    return {"workload": f"PageRank {T} supersteps across the {len(parts)} parts (isolated vertices mastered by "
+                        "part 0), merged sums to masters in part order, masters' ranks back to replicas",
+            "ms": dt * 1e3, "ms_per_superstep": dt * 1e3 / T, "merged_sums_exchanged": sums,
+            "ranks_exchanged": bcast, "max_abs_diff_vs_whole_graph": err,
+            "gteps": T * g.E / dt / 1e9}
 
 
 def bench_lp(gx, torch, np, gen, g=None, scale=22, cap=15, reps=3):

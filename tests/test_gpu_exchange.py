@@ -100,7 +100,7 @@ def test_apply_delta_merges_min_and_ignores_foreign_ids(gx):
 
 # ------------------------------------------------------------------ PageRank across the parts
 
-def pagerank_exchange(gx, g, parts, T, needs=None):
+def pagerank_exchange(gx, g, parts, T, needs=None, record=None):
     """All parts resident, GX_PHASES_MASTERS states, T supersteps of the
     exchange (merged sums to masters in part order, masters apply, replicas
     take the masters' ranks); returns the per-part ranks after every
@@ -134,7 +134,10 @@ def pagerank_exchange(gx, g, parts, T, needs=None):
             others = [b for p, b in enumerate(bc) if p != q and b[0].numel()]
             if others:
                 st.apply_delta(torch.cat([o[0] for o in others]), torch.cat([o[1] for o in others]))
-        hist.append([st.values_numpy().copy() for st in states])
+        if record is None or len(hist) + 1 in record:
+            hist.append([st.values_numpy().copy() for st in states])
+        else:
+            hist.append(None)
     return hist, states
 
 
@@ -163,3 +166,45 @@ def test_exchange_pagerank_is_reproducible(gx):
     b, _ = pagerank_exchange(gx, g, parts, 6)
     for xa, xb in zip(a[-1], b[-1]):
         assert np.array_equal(xa.view(np.uint32), xb.view(np.uint32))
+
+
+# ------------------------------------------------------------------ the partition workload's shape
+
+@pytest.fixture(scope="module")
+def c3_shape():
+    """All eight parts of the hash vertex-cut of R-MAT scale 25 (seed 3)."""
+    g = gen.rmat(25, seed=3)
+    parts = [gen.rmat_part(25, seed=3, part=p) for p in range(NPARTS)]
+    return g, parts
+
+
+@pytest.mark.slow
+def test_exchange_scale25_sssp_and_cc(gx, c3_shape):
+    g, parts = c3_shape
+    ref = oracle.sssp(g, 0, threads=0)
+    K, vals = run_exchange(gx, parts, gx.GX_SSSP, 0)
+    assert K == ref.K
+    for p, v in zip(parts, vals):
+        assert np.array_equal(v, ref.state[p.l2g])
+    del vals
+    ref = oracle.cc(g, threads=0)
+    K, vals = run_exchange(gx, parts, gx.GX_CC)
+    assert K == ref.K
+    for p, v in zip(parts, vals):
+        assert np.array_equal(v, ref.state[p.l2g])
+
+
+@pytest.mark.slow
+def test_exchange_scale25_pagerank30(gx, c3_shape):
+    g, parts = c3_shape
+    parts = gen.cover_isolated(parts, g.V)
+    ref = oracle.pagerank(g, 30, 0.85, threads=0)
+    hist, _ = pagerank_exchange(gx, g, parts, 30, record={30})
+    seen = 0
+    for p, x in zip(parts, hist[-1]):
+        want = ref[p.l2g]
+        err = np.abs(x.astype(np.float64) - want)
+        assert err.max() <= 1e-6
+        assert (err / want).max() < 1e-4
+        seen += int(np.count_nonzero(p.flags & 1))
+    assert seen == g.V
