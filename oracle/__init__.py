@@ -446,3 +446,28 @@ def hop_bounded_distances(g, source: int, k: int) -> np.ndarray:
         d = nd
     out = np.where(d >= np.iinfo(np.int64).max // 4, INF, d)
     return np.minimum(out, INF).astype(np.uint32)
+
+
+# --------------------------------------------------------------------------
+# Pipeline block size (Section "Block Size Selection", Eq.
+# "PipelineTimeSimplied2", Lemma "bSizeSelection"): the oracle minimises the
+# equation by brute force over the block count.
+# --------------------------------------------------------------------------
+
+def pipeline_time(k1: float, k2: float, k3: float, a: float, d: float, s) -> np.ndarray:
+    """Eq. "PipelineTimeSimplied2": d entities in s equal blocks of b = d / s;
+    download k1 b, computation a + k2 b, upload k3 b per block; the first
+    block's download and the last block's upload are not overlapped."""
+    s = np.asarray(s, np.float64)
+    b = d / s
+    tn, tc, tu = k1 * b, a + k2 * b, k3 * b
+    return tn + np.maximum(tn, tc) + (s - 2) * np.maximum(np.maximum(tn, tc), tu) + np.maximum(tc, tu) + tu
+
+
+def pipeline_brute_force(k1: float, k2: float, k3: float, a: float, d: int):
+    """(s, T): the block count in [2, d] with the smallest modelled time (the
+    smallest such s on a tie)."""
+    s = np.arange(2, int(d) + 1, dtype=np.float64)
+    t = pipeline_time(k1, k2, k3, a, float(d), s)
+    i = int(np.argmin(t))
+    return int(s[i]), float(t[i])

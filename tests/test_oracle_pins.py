@@ -399,3 +399,37 @@ def test_lp_certificate_random(seed):
             top = max(cnt.values())
             assert cnt.get(int(new[v]), 0) == top
             assert all(lab >= new[v] for lab, c in cnt.items() if c == top)
+
+
+# ---------------------------------------------------------------- pipeline block size
+
+def test_pipeline_hand_example():
+    # d = 12, k1 = k3 = 1, k2 = 2, a = 4, worked by hand from the equation:
+    # s=2 (b=6): 6+16+0+16+6 = 44; s=3 (b=4): 4+12+12+12+4 = 44;
+    # s=4 (b=3): 3+10+20+10+3 = 46; s=5 (b=2.4): 48.8; s=6 (b=2): 52
+    t = oracle.pipeline_time(1, 2, 1, 4, 12, [2, 3, 4, 5, 6])
+    assert np.allclose(t, [44, 44, 46, 48.8, 52])
+    assert oracle.pipeline_brute_force(1, 2, 1, 4, 12) == (2, 44.0)
+
+
+def test_pipeline_lemma_closed_forms():
+    # computation dominant (k2 largest): b = Q = sqrt(a d / (k1 + k3)),
+    # T = k2 d + 2 sqrt((k1 + k3) a d): k = (1, 3, 1), a = 2, d = 100 -> Q = 10
+    assert oracle.pipeline_brute_force(1, 3, 1, 2, 100) == (10, 340.0)
+    # download dominant with a / (k1 - k2) < Q: b = a / (k1 - k2) = 5,
+    # T = k1 d + (k1 + k3) a / (k1 - k2) = 400 + 25
+    s, t = oracle.pipeline_brute_force(4, 2, 1, 10, 100)
+    assert (s, round(t, 9)) == (20, 425.0)
+    # upload dominant: the same with k1 and k3 swapped, T = k3 d + (k1 + k3) a / (k3 - k2)
+    # (the Lemma's case (iii) prints k1 d; the equation gives k3 d = 400 here)
+    s, t = oracle.pipeline_brute_force(1, 2, 4, 10, 100)
+    assert (s, round(t, 9)) == (20, 425.0)
+
+
+def test_pipeline_degenerate_forms():
+    # no per-call cost: more blocks always hide more, T = k1 d + (k2 + k3) d / s
+    s, t = oracle.pipeline_brute_force(3, 2, 1, 0.0, 50)
+    assert s == 50 and abs(t - (3 * 50 + 3 * 50 / 50)) < 1e-9
+    # no transfers: T = s a + k2 d, fewest blocks
+    s, t = oracle.pipeline_brute_force(0.0, 2, 0.0, 5, 40)
+    assert s == 2 and abs(t - (2 * 5 + 2 * 40)) < 1e-9
