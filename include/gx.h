@@ -345,6 +345,78 @@ gx_status gx_apply_delta(gx_state *s, const int32_t *dev_gid, const uint32_t *de
                          int64_t *active_next, void *stream);
 
 /* ---------------------------------------------------------------------
+ * Streamed supersteps (Section "Intra-Iteration Optimization: Pipeline
+ * Shuffling", Algorithms "Pipeline Shuffle - Daemon Side" and "Agent Side",
+ * Lemma "bSizeSelection").  The edge triplets stay in pinned host memory
+ * (copied at creation; SSSP: the out-edges (u, v, w) in CSR order; CC: both
+ * directions of every distinct undirected edge, self-loops dropped) and every
+ * superstep streams them through the device in blocks of `block_edges`
+ * triplets.  Vertex state stays resident.  Block i runs in device buffer
+ * i mod 3: downloaded on a copy stream (n-block), computed (c-block: each
+ * triplet whose source is active carries sat_add(value, w) or the value, is
+ * merged into the destination by integer min, and its message is written
+ * into the triplet's result slot, INF when the source is inactive), and its
+ * results uploaded to pinned host memory on a third stream (u-block); the
+ * three stages of consecutive blocks overlap and the buffers rotate roles.
+ * GX_STREAM_SERIAL runs the same stages one after the other on one stream
+ * and times each (download_ms, compute_ms, upload_ms: sums over the blocks).
+ * Superstep semantics are those of gx_superstep (Jacobi: messages read the
+ * values of the superstep's start; the next frontier is the set of vertices
+ * whose value fell).
+ * --------------------------------------------------------------------- */
+
+typedef struct gx_stream gx_stream;
+#define GX_STREAM_PIPELINED 0u
+#define GX_STREAM_SERIAL    1u
+
+typedef struct gx_stream_stats {
+    int64_t blocks;       /* s */
+    int64_t triplets;     /* d: triplets streamed */
+    int64_t messages;     /* triplets whose source was active */
+    int64_t changed;      /* vertices in the next frontier (0: converged) */
+    double  wall_ms;      /* host wall time of the superstep */
+    double  download_ms, compute_ms, upload_ms;  /* GX_STREAM_SERIAL only */
+} gx_stream_stats;
+
+/* Per-entity costs of the three stages and the per-call constant of the
+ * computation (Eq. "PipelineTimeSimplied2": k1, k2, k3 and a). */
+typedef struct gx_pipeline_coef {
+    double k1, k2, k3, a;
+} gx_pipeline_coef;
+
+/* Device arena bytes of a stream handle for this graph and largest block. */
+gx_status gx_stream_bytes(const gx_graph_desc *desc, int32_t algo, uint64_t block_edges_max, size_t *bytes);
+/* Copies the triplets into pinned host memory the handle owns, carves the
+ * vertex state and three block buffers of block_edges_max triplets from
+ * `dev_arena`, and initialises the state (SSSP from `source`, -1 = none;
+ * CC labels = global ids).  Synchronous.  GX_EINVAL, GX_ENOMEM, GX_EDEVICE. */
+gx_status gx_stream_create(const gx_graph_desc *desc, int32_t algo, int32_t source, void *dev_arena,
+                           size_t arena_bytes, uint64_t block_edges_max, gx_stream **out);
+/* Re-initialises the vertex state (superstep 0).  Synchronous. */
+gx_status gx_stream_reset(gx_stream *s);
+/* One streamed superstep; synchronous (returns after the last upload). */
+gx_status gx_stream_superstep(gx_stream *s, uint64_t block_edges, uint32_t mode, gx_stream_stats *stats);
+/* Device pointers to the values (uint32 per vertex) and to the byte map of
+ * the next superstep's active vertices. */
+gx_status gx_stream_values(gx_stream *s, void **dev_values, void **dev_frontier);
+/* The results the last superstep uploaded: one message per triplet, in
+ * triplet order, in pinned host memory the handle owns (valid until the
+ * next superstep or gx_stream_free). */
+gx_status gx_stream_results(gx_stream *s, const uint32_t **host_results, int64_t *n);
+gx_status gx_stream_free(gx_stream *s);
+
+/* Eq. "PipelineTimeSimplied2": the time of d entities in s equal blocks
+ * (2 <= s <= d).  GX_EINVAL otherwise. */
+gx_status gx_pipeline_time(const gx_pipeline_coef *k, double d, double s, double *T);
+/* Lemma "bSizeSelection": the optimal block size b for d entities (a/(k1-k2)
+ * or a/(k3-k2) when downloads or uploads cost most per entity and that block
+ * is below Q = sqrt(a d / (k1 + k3)), else Q), then of the floor and the
+ * ceiling of d / b (clamped to [2, d]) the block count with the smaller
+ * modelled time.  *blocks, *block_size = d / *blocks, *T = the model's time.
+ * GX_EINVAL for d < 2 or negative coefficients. */
+gx_status gx_pipeline_plan(const gx_pipeline_coef *k, int64_t d, int64_t *blocks, double *block_size, double *T);
+
+/* ---------------------------------------------------------------------
  * Batched lanes: B independent single-source SSSP (or personalised
  * PageRank) solves over one resident graph, run as one persistent kernel
  * over a [V x B] state tile (B contiguous per vertex).  Generalises the

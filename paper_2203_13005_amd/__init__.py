@@ -27,6 +27,8 @@ from .binding import (  # noqa: F401
     GxError,
     Server,
     State,
+    Stream,
+    pipeline_plan,
     Tune,
     batch_autotune,
     batch_run,

@@ -68,6 +68,19 @@ class Tune(ctypes.Structure):
         return f"Tune(block={self.block}, tile={self.tile}, width={self.width}, grid={self.grid})"
 
 
+class StreamStats(ctypes.Structure):
+    _fields_ = [("blocks", ctypes.c_int64), ("triplets", ctypes.c_int64), ("messages", ctypes.c_int64),
+                ("changed", ctypes.c_int64), ("wall_ms", ctypes.c_double), ("download_ms", ctypes.c_double),
+                ("compute_ms", ctypes.c_double), ("upload_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class PipelineCoef(ctypes.Structure):
+    _fields_ = [("k1", ctypes.c_double), ("k2", ctypes.c_double), ("k3", ctypes.c_double), ("a", ctypes.c_double)]
+
+
 class _ServerConfig(ctypes.Structure):
     _fields_ = [("dev_arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t),
                 ("lanes_per_pool", ctypes.c_uint32), ("max_pools", ctypes.c_uint32),
@@ -107,6 +120,19 @@ _SIGS = {
     "gx_dangling_set": (ctypes.c_int32, [_P, ctypes.c_double, _P]),
     "gx_partial_emit": (ctypes.c_int32, [_P, _P, _P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32), _P]),
     "gx_partial_add": (ctypes.c_int32, [_P, _P, _P, ctypes.c_uint32, _P]),
+    "gx_stream_bytes": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(ctypes.c_size_t)]),
+    "gx_stream_create": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_size_t, ctypes.c_uint64,
+                                          ctypes.POINTER(_P)]),
+    "gx_stream_reset": (ctypes.c_int32, [_P]),
+    "gx_stream_superstep": (ctypes.c_int32, [_P, ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(StreamStats)]),
+    "gx_stream_values": (ctypes.c_int32, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P)]),
+    "gx_stream_results": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.POINTER(ctypes.c_uint32)),
+                                           ctypes.POINTER(ctypes.c_int64)]),
+    "gx_stream_free": (ctypes.c_int32, [_P]),
+    "gx_pipeline_time": (ctypes.c_int32, [ctypes.POINTER(PipelineCoef), ctypes.c_double, ctypes.c_double,
+                                          ctypes.POINTER(ctypes.c_double)]),
+    "gx_pipeline_plan": (ctypes.c_int32, [ctypes.POINTER(PipelineCoef), ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "gx_msg_gen": (ctypes.c_int32, [_P, _P]),
     "gx_msg_merge": (ctypes.c_int32, [_P, _P]),
     "gx_msg_apply": (ctypes.c_int32, [_P, _P, ctypes.POINTER(StepStats)]),
@@ -158,7 +184,7 @@ _live: "weakref.WeakSet" = weakref.WeakSet()
 
 
 def _close_all_at_exit():
-    for kind in ("Server", "State", "DeviceGraph"):
+    for kind in ("Server", "Stream", "State", "DeviceGraph"):
         for obj in list(_live):
             if type(obj).__name__ == kind:
                 try:
@@ -540,6 +566,87 @@ class Server:
     def close(self):
         if getattr(self, "handle", None):
             lib.gx_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+GX_STREAM_PIPELINED, GX_STREAM_SERIAL = 0, 1
+
+
+def pipeline_plan(k1: float, k2: float, k3: float, a: float, d: int):
+    """Lemma "bSizeSelection" with the floor/ceiling rule: (blocks, block size, modelled time)."""
+    s, b, t = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    _check(lib.gx_pipeline_plan(ctypes.byref(PipelineCoef(k1, k2, k3, a)), int(d), ctypes.byref(s), ctypes.byref(b),
+                                ctypes.byref(t)))
+    return s.value, b.value, t.value
+
+
+class Stream:
+    """Streamed supersteps: the triplets in pinned host memory, blocks of them
+    through three rotating device buffers per superstep."""
+
+    def __init__(self, host, algo: int, source: int = 0, block_edges_max: int = 1 << 20, device="cuda:0"):
+        import torch
+        self.device = torch.device(device)
+        keep = [np.ascontiguousarray(host.row_ptr, np.int32), np.ascontiguousarray(host.col, np.int32),
+                None if host.w is None else np.ascontiguousarray(host.w, np.uint32),
+                None if getattr(host, "l2g", None) is None else np.ascontiguousarray(host.l2g, np.int32)]
+        rp, col, w, l2g = keep
+        desc = _GraphDesc(int(host.V), int(host.E), _np_ptr(rp), _np_ptr(col), _np_ptr(w), _np_ptr(l2g), None,
+                          GX_NEED_OUT, 0, 0, None)
+        nbytes = ctypes.c_size_t()
+        _check(lib.gx_stream_bytes(ctypes.byref(desc), int(algo), int(block_edges_max), ctypes.byref(nbytes)))
+        with torch.cuda.device(self.device):
+            self.mem = _arena(nbytes.value, self.device)
+            h = ctypes.c_void_p()
+            _check(lib.gx_stream_create(ctypes.byref(desc), int(algo), int(source), ctypes.c_void_p(self.mem.data_ptr()),
+                                        nbytes.value, int(block_edges_max), ctypes.byref(h)))
+        self.handle = h
+        self.V, self.algo = int(host.V), int(algo)
+        _live.add(self)
+
+    def reset(self):
+        _check(lib.gx_stream_reset(self.handle))
+
+    def superstep(self, block_edges: int, serial: bool = False) -> dict:
+        st = StreamStats()
+        _check(lib.gx_stream_superstep(self.handle, int(block_edges), GX_STREAM_SERIAL if serial else GX_STREAM_PIPELINED,
+                                       ctypes.byref(st)))
+        return st.as_dict()
+
+    def _dev(self, which: int, dtype_bytes: int):
+        import torch
+        v, f = ctypes.c_void_p(), ctypes.c_void_p()
+        _check(lib.gx_stream_values(self.handle, ctypes.byref(v), ctypes.byref(f)))
+        p = (v, f)[which].value
+        off = p - self.mem.data_ptr()
+        return self.mem[off: off + dtype_bytes * self.V]
+
+    def values_numpy(self) -> np.ndarray:
+        import torch
+        torch.cuda.synchronize(self.device)
+        return self._dev(0, 4).cpu().numpy().view(np.uint32)
+
+    def frontier_numpy(self) -> np.ndarray:
+        import torch
+        torch.cuda.synchronize(self.device)
+        return self._dev(1, 1).cpu().numpy() != 0
+
+    def results_numpy(self) -> np.ndarray:
+        """Messages the last superstep uploaded, one per triplet (a copy)."""
+        p = ctypes.POINTER(ctypes.c_uint32)()
+        n = ctypes.c_int64()
+        _check(lib.gx_stream_results(self.handle, ctypes.byref(p), ctypes.byref(n)))
+        return np.ctypeslib.as_array(p, shape=(max(n.value, 1),))[: n.value].copy()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.gx_stream_free(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -139,3 +139,35 @@ def test_symmetric_image_size_limit_is_einval():
     n = ctypes.c_size_t()
     assert b.lib.gx_graph_bytes(ctypes.byref(d), ctypes.byref(n)) == b.GX_EINVAL
     assert b"symmetric" in b.lib.gx_last_error()
+
+
+def test_pipeline_plan_matches_brute_force():
+    """The Lemma's block size with the floor/ceiling rule reaches the brute
+    force minimum of the time model in every case (download, computation or
+    upload dominant; optimum inside or at the ends of [2, d])."""
+    import numpy as np
+    import oracle
+    from paper_2203_13005_amd import binding as b
+    rng = np.random.default_rng(7)
+    cases = [(1, 2, 1, 4, 12), (4, 2, 1, 10, 100), (1, 2, 4, 10, 100), (1, 3, 1, 2, 100),
+             (0.24e-9, 0.03e-9, 0.08e-9, 10e-6, 65_000_000 // 1000), (5, 1, 1, 1e-6, 1000), (1, 1, 1, 1e6, 50)]
+    for _ in range(300):
+        k = rng.exponential(1.0, 3) * rng.choice([0.01, 1, 100], 3)
+        cases.append((k[0], k[1], k[2], float(rng.exponential(1.0) * rng.choice([0.01, 1, 100])),
+                      int(rng.integers(2, 3000))))
+    for k1, k2, k3, a, d in cases:
+        s, bs, t = b.pipeline_plan(k1, k2, k3, a, d)
+        s_bf, t_bf = oracle.pipeline_brute_force(k1, k2, k3, a, d)
+        assert 2 <= s <= d and abs(bs - d / s) < 1e-9 * d
+        assert t <= t_bf * (1 + 1e-9), (k1, k2, k3, a, d, s, t, s_bf, t_bf)
+
+
+def test_pipeline_plan_validation():
+    import pytest
+    from paper_2203_13005_amd import binding as b
+    with pytest.raises(b.GxError):
+        b.pipeline_plan(1, 1, 1, 1, 1)  # fewer than 2 entities
+    with pytest.raises(b.GxError):
+        b.pipeline_plan(-1, 1, 1, 1, 100)
+    assert b.lib.gx_stream_superstep(None, 1, 0, None) == b.GX_EINVAL
+    assert b.lib.gx_stream_free(None) == b.GX_OK
