@@ -599,6 +599,107 @@ def bench_phases(gx, torch, np, gen, g=None, reps=5):
     return out
 
 
+def host_link_gbps(torch, nbytes=1 << 30, reps=3):
+    """Pinned host -> device copy rate (the host link the load and the
+    streamed supersteps cross)."""
+    h = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+    h.fill_(1)
+    d = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    d.copy_(h, non_blocking=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        d.copy_(h, non_blocking=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    del h, d
+    return nbytes / dt / 1e9
+
+
+def bench_stream(gx, torch, np, gen, g=None):
+    """Streamed supersteps (Section "Pipeline Shuffling") of SSSP from vertex 0
+    on R-MAT scale 22 (seed 2), triplets in pinned host memory.  The stage
+    costs are measured in the serial form at the superstep with the most
+    messages (the paper calibrates at the SSSP iteration with the largest
+    workload): k1 and k3 per triplet from the downloads and uploads of a
+    large-block run, k2 from the computation at two block sizes, and a, the
+    constant cost of one block, from the serial wall time at two block
+    counts.  The Lemma's block size (Pipeline*) is then timed against a fixed
+    block of 2^20 triplets and against no pipeline (one block, the stages in
+    turn), with the paper's three rotating buffers and with eight, and a
+    sweep of block sizes gives the measured best."""
+    if g is None:
+        g = gen.rmat(22, seed=2)
+    res = gx.State(gx.DeviceGraph(g, gx.GX_NEED_OUT), gx.GX_SSSP, source=0)
+    _, steps = res.run(100_000, per_step=True)
+    want = res.values_numpy().copy()
+    del res
+    kmax = int(np.argmax([x[1] for x in steps]))  # superstep with the most messages
+    E = g.E
+    handles = {3: gx.Stream(g, gx.GX_SSSP, source=0, block_edges_max=E, ring=3),
+               8: gx.Stream(g, gx.GX_SSSP, source=0, block_edges_max=1 << 22, ring=8)}
+
+    def at(k, block, serial, ring=3):
+        st = handles[ring]
+        st.reset()
+        for _ in range(k):
+            st.superstep(1 << 22)
+        return st.superstep(block, serial=serial)
+
+    def timed(block, serial, ring=3):
+        ts = sorted(at(kmax, block, serial, ring)["wall_ms"] for _ in range(3))
+        return ts[1]
+
+    b1, b2 = 1 << 16, 1 << 22
+    r1, r2 = at(kmax, b1, True), at(kmax, b2, True)
+    k1 = r2["download_ms"] * 1e-3 / E
+    k3 = r2["upload_ms"] * 1e-3 / E
+    tc1, tc2 = r1["compute_ms"] * 1e-3 / r1["blocks"], r2["compute_ms"] * 1e-3 / r2["blocks"]
+    k2 = max((tc2 - tc1) / (b2 - b1), 0.0)
+    w1, w2 = timed(b1, True), timed(b2, True)
+    a = max((w1 - w2) * 1e-3 / (r1["blocks"] - r2["blocks"]), 0.0)
+    blocks, bsize, t_model = gx.pipeline_plan(k1, k2, k3, a, E)
+    bopt = int(np.ceil(E / blocks))
+    forms = {"no_pipeline": {"block_triplets": E, "ring": 1, "wall_ms": timed(E, True)},
+             "fixed_block_2^20": {"block_triplets": 1 << 20, "ring": 3, "wall_ms": timed(1 << 20, False)},
+             "pipeline_star": {"block_triplets": bopt, "ring": 3, "wall_ms": timed(bopt, False)}}
+    if bopt <= 1 << 22:
+        forms["pipeline_star_ring8"] = {"block_triplets": bopt, "ring": 8, "wall_ms": timed(bopt, False, 8)}
+    sweep = {f"2^{e}_ring{r}": timed(1 << e, False, r) for e in (16, 18, 20, 22) for r in (3, 8)}
+    best = min(sweep, key=sweep.get)
+    for f in forms.values():
+        f["model_ms"] = (gx.pipeline_plan(k1, k2, k3, a, E)[2] if f is forms["pipeline_star"] else None)
+    # the whole solve, streamed at the Lemma's block size
+    st = handles[3]
+    st.reset()
+    t0 = time.perf_counter()
+    K = msgs = 0
+    while True:
+        r = st.superstep(bopt)
+        K += 1
+        msgs += r["messages"]
+        if r["changed"] == 0:
+            break
+    solve_s = time.perf_counter() - t0
+    assert np.array_equal(st.values_numpy(), want), "streamed solve differs from the resident one"
+    link = host_link_gbps(torch)
+    log(f"stream: k1={k1 * 1e9:.3f} k2={k2 * 1e9:.3f} k3={k3 * 1e9:.3f} ns/triplet, a={a * 1e6:.1f} us per block; "
+        f"Lemma: {blocks} blocks of {bsize:.0f} (model {t_model * 1e3:.2f} ms); superstep {kmax}: "
+        + ", ".join(f"{n} {f['wall_ms']:.2f} ms" for n, f in forms.items())
+        + f"; best of sweep {best} {sweep[best]:.2f} ms; solve {solve_s * 1e3:.1f} ms; host link {link:.1f} GB/s")
+    return {"workload": f"SSSP from vertex 0 on R-MAT scale 22 (seed 2), {E} triplets (12 B down, 4 B up each) "
+                        f"streamed from pinned host memory every superstep",
+            "calibration_superstep": kmax, "messages_at_calibration": int(steps[kmax][1]),
+            "coef": {"k1_ns": k1 * 1e9, "k2_ns": k2 * 1e9, "k3_ns": k3 * 1e9, "a_us": a * 1e6},
+            "lemma_blocks": blocks, "lemma_block_triplets": bsize, "model_ms": t_model * 1e3,
+            "forms": forms, "sweep_pipelined_ms": sweep, "sweep_best": best,
+            "pipeline_star_speedup_vs_none": forms["no_pipeline"]["wall_ms"] / forms["pipeline_star"]["wall_ms"],
+            "pipeline_star_speedup_vs_fixed": forms["fixed_block_2^20"]["wall_ms"] / forms["pipeline_star"]["wall_ms"],
+            "solve": {"supersteps": K, "ms": solve_s * 1e3, "messages": int(msgs),
+                      "host_bytes_per_superstep": 16 * E, "GBps_over_host_link": 16 * E * K / solve_s / 1e9},
+            "host_link_h2d_GBps": link}
+
+
 def bench_partition(gx, torch, np, gen, reps=3):
     """One part (1 of 8) of a hash vertex-cut of R-MAT scale 25 (seed 3):
     30 PageRank supersteps and min-label CC to convergence."""
@@ -713,7 +814,7 @@ def load_traffic():
     return t
 
 
-LEGS = ("sssp", "pagerank", "partition", "lp", "phases", "exchange", "batched", "serving")
+LEGS = ("sssp", "pagerank", "partition", "lp", "phases", "stream", "exchange", "batched", "serving")
 
 
 def bench_sssp(args, gx, torch, np, gen):
@@ -891,6 +992,8 @@ def main():
     part = None
     if "partition" in legs:
         out["partition_scale25"], part = bench_partition(gx, torch, np, gen)
+    if "stream" in legs:
+        out["stream_sssp_scale22"] = bench_stream(gx, torch, np, gen, g)
     if "phases" in legs:
         out["template_calls_sssp_scale22"] = bench_phases(gx, torch, np, gen, g)
     if "lp" in legs:

@@ -351,8 +351,10 @@ gx_status gx_apply_delta(gx_state *s, const int32_t *dev_gid, const uint32_t *de
  * (copied at creation; SSSP: the out-edges (u, v, w) in CSR order; CC: both
  * directions of every distinct undirected edge, self-loops dropped) and every
  * superstep streams them through the device in blocks of `block_edges`
- * triplets.  Vertex state stays resident.  Block i runs in device buffer
- * i mod 3: downloaded on a copy stream (n-block), computed (c-block: each
+ * triplets, packed (u, v, w) (CC: (u, v)) so one copy downloads a block.
+ * Vertex state stays resident.  Block i runs in device buffer i mod R (R =
+ * `ring`, 3 to GX_STREAM_RING_MAX): downloaded on a copy stream (n-block),
+ * computed (c-block: each
  * triplet whose source is active carries sat_add(value, w) or the value, is
  * merged into the destination by integer min, and its message is written
  * into the triplet's result slot, INF when the source is inactive), and its
@@ -368,6 +370,7 @@ gx_status gx_apply_delta(gx_state *s, const int32_t *dev_gid, const uint32_t *de
 typedef struct gx_stream gx_stream;
 #define GX_STREAM_PIPELINED 0u
 #define GX_STREAM_SERIAL    1u
+#define GX_STREAM_RING_MAX  8   /* device block buffers at most (3 = the n, c, u rotation itself) */
 
 typedef struct gx_stream_stats {
     int64_t blocks;       /* s */
@@ -385,13 +388,14 @@ typedef struct gx_pipeline_coef {
 } gx_pipeline_coef;
 
 /* Device arena bytes of a stream handle for this graph and largest block. */
-gx_status gx_stream_bytes(const gx_graph_desc *desc, int32_t algo, uint64_t block_edges_max, size_t *bytes);
+gx_status gx_stream_bytes(const gx_graph_desc *desc, int32_t algo, uint64_t block_edges_max, int32_t ring,
+                          size_t *bytes);
 /* Copies the triplets into pinned host memory the handle owns, carves the
- * vertex state and three block buffers of block_edges_max triplets from
+ * vertex state and `ring` block buffers of block_edges_max triplets from
  * `dev_arena`, and initialises the state (SSSP from `source`, -1 = none;
  * CC labels = global ids).  Synchronous.  GX_EINVAL, GX_ENOMEM, GX_EDEVICE. */
 gx_status gx_stream_create(const gx_graph_desc *desc, int32_t algo, int32_t source, void *dev_arena,
-                           size_t arena_bytes, uint64_t block_edges_max, gx_stream **out);
+                           size_t arena_bytes, uint64_t block_edges_max, int32_t ring, gx_stream **out);
 /* Re-initialises the vertex state (superstep 0).  Synchronous. */
 gx_status gx_stream_reset(gx_stream *s);
 /* One streamed superstep; synchronous (returns after the last upload). */

@@ -120,9 +120,10 @@ _SIGS = {
     "gx_dangling_set": (ctypes.c_int32, [_P, ctypes.c_double, _P]),
     "gx_partial_emit": (ctypes.c_int32, [_P, _P, _P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32), _P]),
     "gx_partial_add": (ctypes.c_int32, [_P, _P, _P, ctypes.c_uint32, _P]),
-    "gx_stream_bytes": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(ctypes.c_size_t)]),
+    "gx_stream_bytes": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_size_t)]),
     "gx_stream_create": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_size_t, ctypes.c_uint64,
-                                          ctypes.POINTER(_P)]),
+                                          ctypes.c_int32, ctypes.POINTER(_P)]),
     "gx_stream_reset": (ctypes.c_int32, [_P]),
     "gx_stream_superstep": (ctypes.c_int32, [_P, ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(StreamStats)]),
     "gx_stream_values": (ctypes.c_int32, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P)]),
@@ -590,7 +591,8 @@ class Stream:
     """Streamed supersteps: the triplets in pinned host memory, blocks of them
     through three rotating device buffers per superstep."""
 
-    def __init__(self, host, algo: int, source: int = 0, block_edges_max: int = 1 << 20, device="cuda:0"):
+    def __init__(self, host, algo: int, source: int = 0, block_edges_max: int = 1 << 20, ring: int = 3,
+                 device="cuda:0"):
         import torch
         self.device = torch.device(device)
         keep = [np.ascontiguousarray(host.row_ptr, np.int32), np.ascontiguousarray(host.col, np.int32),
@@ -600,12 +602,13 @@ class Stream:
         desc = _GraphDesc(int(host.V), int(host.E), _np_ptr(rp), _np_ptr(col), _np_ptr(w), _np_ptr(l2g), None,
                           GX_NEED_OUT, 0, 0, None)
         nbytes = ctypes.c_size_t()
-        _check(lib.gx_stream_bytes(ctypes.byref(desc), int(algo), int(block_edges_max), ctypes.byref(nbytes)))
+        _check(lib.gx_stream_bytes(ctypes.byref(desc), int(algo), int(block_edges_max), int(ring),
+                                   ctypes.byref(nbytes)))
         with torch.cuda.device(self.device):
             self.mem = _arena(nbytes.value, self.device)
             h = ctypes.c_void_p()
             _check(lib.gx_stream_create(ctypes.byref(desc), int(algo), int(source), ctypes.c_void_p(self.mem.data_ptr()),
-                                        nbytes.value, int(block_edges_max), ctypes.byref(h)))
+                                        nbytes.value, int(block_edges_max), int(ring), ctypes.byref(h)))
         self.handle = h
         self.V, self.algo = int(host.V), int(algo)
         _live.add(self)

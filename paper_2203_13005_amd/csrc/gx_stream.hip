@@ -2,13 +2,15 @@
 // memory and every superstep streams them through the device in blocks,
 // following Section "Intra-Iteration Optimization: Pipeline Shuffling".
 //
-// Three device block buffers play the n-, c- and u-blocks of the paper's
-// pipeline (Algorithms "Pipeline Shuffle - Daemon Side" / "Agent Side"):
-// block i is downloaded into buffer i mod 3 on a copy stream, computed there
-// on the compute stream, and its results uploaded from the same buffer on a
-// third stream, so the download of block i+1, the computation of block i and
-// the upload of block i-1 overlap, and the three roles rotate over the
-// buffers without copying data between them.  Events order the stages: a
+// Device block buffers play the n-, c- and u-blocks of the paper's pipeline
+// (Algorithms "Pipeline Shuffle - Daemon Side" / "Agent Side"): block i is
+// downloaded into buffer i mod R on a copy stream, computed there on the
+// compute stream, and its results uploaded from the same buffer on a third
+// stream, so the download of block i+1, the computation of block i and the
+// upload of block i-1 overlap, and the roles rotate over the buffers without
+// copying data between them.  R = 3 is the paper's rotation; a deeper ring
+// (up to GX_STREAM_RING_MAX) lets a download start before the upload three
+// blocks back has finished, which hides the latency between the streams.  Events order the stages: a
 // download waits for the upload that last used its buffer, a computation
 // for its download, an upload for its computation.
 //
@@ -70,8 +72,9 @@ __global__ __launch_bounds__(ST_BLOCK) void k_st_begin(const uint32_t *__restric
     next[v] = 0;
 }
 
-__global__ __launch_bounds__(ST_BLOCK) void k_st_relax(const uint32_t *__restrict__ src, const uint32_t *__restrict__ dst,
-                                                       const uint32_t *__restrict__ w, uint32_t n,
+// A block holds its triplets packed: (u, v, w) (SSSP, tw = 3) or (u, v)
+// (CC, tw = 2), so one copy downloads it.
+__global__ __launch_bounds__(ST_BLOCK) void k_st_relax(const uint32_t *__restrict__ trip, int tw, uint32_t n,
                                                        const uint32_t *__restrict__ snap,
                                                        const uint8_t *__restrict__ front, uint32_t *__restrict__ val,
                                                        uint8_t *__restrict__ next, uint32_t *__restrict__ msg,
@@ -80,11 +83,12 @@ __global__ __launch_bounds__(ST_BLOCK) void k_st_relax(const uint32_t *__restric
     const uint32_t i = blockIdx.x * ST_BLOCK + threadIdx.x;
     unsigned act = 0;
     if (i < n) {
-        const uint32_t u = src[i], v = dst[i];
+        const uint32_t *t = trip + (size_t)i * tw;
+        const uint32_t u = t[0], v = t[1];
         uint32_t m = INF;
         if (front[u]) {
             act = 1;
-            m = w ? sat_add(snap[u], w[i]) : snap[u];
+            m = tw == 3 ? sat_add(snap[u], t[2]) : snap[u];
             if (m < val[v]) {
                 atomicMin(&val[v], m);
                 next[v] = 1;
@@ -125,8 +129,10 @@ struct gx_stream {
     uint64_t bmax = 0;
     int device = 0;
     bool dev_error = false;
-    // pinned host memory: the triplets and the uploaded results
-    uint32_t *h_src = nullptr, *h_dst = nullptr, *h_w = nullptr, *h_msg = nullptr;
+    int ring = 3;   // device block buffers (the n-, c- and u-blocks rotate over them)
+    int tw = 3;     // words per triplet
+    // pinned host memory: the packed triplets and the uploaded results
+    uint32_t *h_trip = nullptr, *h_msg = nullptr;
     std::vector<int32_t> l2g;
     std::vector<uint8_t> has_edge;
     // device
@@ -135,27 +141,28 @@ struct gx_stream {
     int32_t *d_l2g = nullptr;
     uint8_t *d_has_edge = nullptr;
     StCounters *cnt = nullptr;
-    uint32_t *b_src[3] = {}, *b_dst[3] = {}, *b_w[3] = {}, *b_msg[3] = {};
+    uint32_t *b_trip[GX_STREAM_RING_MAX] = {}, *b_msg[GX_STREAM_RING_MAX] = {};
     int64_t k = 0;
     hipStream_t s_copy = nullptr, s_comp = nullptr, s_up = nullptr;
-    hipEvent_t ev_n[3] = {}, ev_c[3] = {}, ev_u[3] = {};
+    hipEvent_t ev_n[GX_STREAM_RING_MAX] = {}, ev_c[GX_STREAM_RING_MAX] = {}, ev_u[GX_STREAM_RING_MAX] = {};
     std::vector<hipEvent_t> tev;  // timing events of the serial form
     StCounters *h_cnt = nullptr;  // pinned
     ~gx_stream() {
         for (hipStream_t s : {s_copy, s_comp, s_up})
             if (s) (void)hipStreamSynchronize(s);
-        for (int i = 0; i < 3; i++)
+        for (int i = 0; i < GX_STREAM_RING_MAX; i++)
             for (hipEvent_t e : {ev_n[i], ev_c[i], ev_u[i]})
                 if (e) (void)hipEventDestroy(e);
         for (hipEvent_t e : tev) (void)hipEventDestroy(e);
         for (hipStream_t s : {s_copy, s_comp, s_up})
             if (s) (void)hipStreamDestroy(s);
-        for (void *p : {(void *)h_src, (void *)h_dst, (void *)h_w, (void *)h_msg, (void *)h_cnt})
+        for (void *p : {(void *)h_trip, (void *)h_msg, (void *)h_cnt})
             if (p) (void)hipHostFree(p);
     }
 };
 
-static size_t stream_layout(int64_t V, uint64_t bmax, bool weighted, bool partitioned, Carver &c, gx_stream *s) {
+static size_t stream_layout(int64_t V, uint64_t bmax, int ring, bool weighted, bool partitioned, Carver &c,
+                            gx_stream *s) {
     s->val = c.take<uint32_t>(V);
     s->snap = c.take<uint32_t>(V);
     s->front[0] = c.take<uint8_t>(V);
@@ -163,10 +170,8 @@ static size_t stream_layout(int64_t V, uint64_t bmax, bool weighted, bool partit
     s->d_has_edge = c.take<uint8_t>(V);
     s->d_l2g = partitioned ? c.take<int32_t>(V) : nullptr;
     s->cnt = c.take<StCounters>(1);
-    for (int i = 0; i < 3; i++) {
-        s->b_src[i] = c.take<uint32_t>(bmax);
-        s->b_dst[i] = c.take<uint32_t>(bmax);
-        s->b_w[i] = weighted ? c.take<uint32_t>(bmax) : nullptr;
+    for (int i = 0; i < ring; i++) {
+        s->b_trip[i] = c.take<uint32_t>(bmax * (weighted ? 3 : 2));
         s->b_msg[i] = c.take<uint32_t>(bmax);
     }
     return c.used;
@@ -217,7 +222,9 @@ static int64_t triplet_count(const gx_graph_desc *d, int32_t algo) {
     return (int64_t)s.size();
 }
 
-static gx_status check_desc(const gx_graph_desc *d, int32_t algo, uint64_t bmax) {
+static gx_status check_desc(const gx_graph_desc *d, int32_t algo, uint64_t bmax, int ring) {
+    GX_REQUIRE(ring >= 3 && ring <= GX_STREAM_RING_MAX, GX_EINVAL, "ring %d out of [3, %d]", ring,
+               GX_STREAM_RING_MAX);
     GX_REQUIRE(d, GX_EINVAL, "desc is NULL");
     GX_REQUIRE(algo == GX_SSSP || algo == GX_CC, GX_EINVAL, "streamed supersteps serve SSSP and CC");
     GX_REQUIRE(d->V >= 0 && d->V < (int64_t(1) << 31) && d->E >= 0 && d->E < (int64_t(1) << 31), GX_EINVAL,
@@ -245,24 +252,24 @@ static gx_status check_desc(const gx_graph_desc *d, int32_t algo, uint64_t bmax)
         }                                                                                                \
     } while (0)
 
-extern "C" gx_status gx_stream_bytes(const gx_graph_desc *desc, int32_t algo, uint64_t block_edges_max,
+extern "C" gx_status gx_stream_bytes(const gx_graph_desc *desc, int32_t algo, uint64_t block_edges_max, int32_t ring,
                                      size_t *bytes) {
     clear_error();
     GX_REQUIRE(bytes, GX_EINVAL, "bytes is NULL");
-    gx_status st = check_desc(desc, algo, block_edges_max);
+    gx_status st = check_desc(desc, algo, block_edges_max, ring);
     if (st != GX_OK) return st;
     Carver c(nullptr, 0);
     gx_stream tmp;
-    *bytes = stream_layout(desc->V, block_edges_max, algo == GX_SSSP, desc->l2g != nullptr, c, &tmp);
+    *bytes = stream_layout(desc->V, block_edges_max, ring, algo == GX_SSSP, desc->l2g != nullptr, c, &tmp);
     return GX_OK;
 }
 
 extern "C" gx_status gx_stream_create(const gx_graph_desc *desc, int32_t algo, int32_t source, void *dev_arena,
-                                      size_t arena_bytes, uint64_t block_edges_max, gx_stream **out) {
+                                      size_t arena_bytes, uint64_t block_edges_max, int32_t ring, gx_stream **out) {
     clear_error();
     GX_REQUIRE(out, GX_EINVAL, "out is NULL");
     *out = nullptr;
-    gx_status st = check_desc(desc, algo, block_edges_max);
+    gx_status st = check_desc(desc, algo, block_edges_max, ring);
     if (st != GX_OK) return st;
     GX_REQUIRE(algo != GX_SSSP || (source >= -1 && source < desc->V), GX_EINVAL, "source out of [-1, V)");
     GX_REQUIRE(dev_arena && reinterpret_cast<uintptr_t>(dev_arena) % ALIGN == 0, GX_EINVAL,
@@ -270,7 +277,7 @@ extern "C" gx_status gx_stream_create(const gx_graph_desc *desc, int32_t algo, i
     {
         Carver m(nullptr, 0);
         gx_stream tmp;
-        size_t need = stream_layout(desc->V, block_edges_max, algo == GX_SSSP, desc->l2g != nullptr, m, &tmp);
+        size_t need = stream_layout(desc->V, block_edges_max, ring, algo == GX_SSSP, desc->l2g != nullptr, m, &tmp);
         GX_REQUIRE(need <= arena_bytes, GX_ENOMEM, "arena too small: need %zu bytes, have %zu", need, arena_bytes);
     }
     std::vector<uint32_t> src, dst, w;
@@ -287,26 +294,27 @@ extern "C" gx_status gx_stream_create(const gx_graph_desc *desc, int32_t algo, i
     s->E = (int64_t)src.size();
     s->source = source;
     s->bmax = block_edges_max;
+    s->ring = ring;
+    s->tw = algo == GX_SSSP ? 3 : 2;
     if (hipGetDevice(&s->device) != hipSuccess) s->device = 0;
     Carver c(dev_arena, arena_bytes);
-    stream_layout(desc->V, block_edges_max, algo == GX_SSSP, desc->l2g != nullptr, c, s);
+    stream_layout(desc->V, block_edges_max, ring, algo == GX_SSSP, desc->l2g != nullptr, c, s);
     auto fail = [&](gx_status code) {
         delete s;
         return code;
     };
     const size_t nb = (size_t)std::max<int64_t>(1, s->E) * 4;
-    if (hipHostMalloc((void **)&s->h_src, nb, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&s->h_dst, nb, hipHostMallocDefault) != hipSuccess ||
-        (algo == GX_SSSP && hipHostMalloc((void **)&s->h_w, nb, hipHostMallocDefault) != hipSuccess) ||
+    if (hipHostMalloc((void **)&s->h_trip, nb * s->tw, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&s->h_msg, nb, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&s->h_cnt, sizeof(StCounters), hipHostMallocDefault) != hipSuccess) {
-        set_error("pinned host allocation of %zu bytes failed", 4 * nb);
+        set_error("pinned host allocation of %zu bytes failed", nb * (s->tw + 1));
         return fail(GX_ENOMEM);
     }
-    if (s->E > 0) {
-        std::memcpy(s->h_src, src.data(), (size_t)s->E * 4);
-        std::memcpy(s->h_dst, dst.data(), (size_t)s->E * 4);
-        if (s->h_w) std::memcpy(s->h_w, w.data(), (size_t)s->E * 4);
+    for (int64_t i = 0; i < s->E; i++) {
+        uint32_t *t = s->h_trip + (size_t)i * s->tw;
+        t[0] = src[(size_t)i];
+        t[1] = dst[(size_t)i];
+        if (s->tw == 3) t[2] = w[(size_t)i];
     }
     s->has_edge.assign((size_t)std::max<int64_t>(1, s->V), 0);
     for (int64_t i = 0; i < s->E; i++) s->has_edge[src[(size_t)i]] = 1;
@@ -316,7 +324,7 @@ extern "C" gx_status gx_stream_create(const gx_graph_desc *desc, int32_t algo, i
             set_error("stream creation failed");
             return fail(GX_EDEVICE);
         }
-    for (int i = 0; i < 3; i++)
+    for (int i = 0; i < s->ring; i++)
         for (hipEvent_t *e : {&s->ev_n[i], &s->ev_c[i], &s->ev_u[i]})
             if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) {
                 set_error("event creation failed");
@@ -382,19 +390,18 @@ extern "C" gx_status gx_stream_superstep(gx_stream *s, uint64_t block_edges, uin
     for (int64_t i = 0; i < nblocks; i++) {
         const int64_t e0 = i * (int64_t)block_edges;
         const uint32_t n = (uint32_t)std::min<int64_t>((int64_t)block_edges, s->E - e0);
-        const int b = serial ? 0 : (int)(i % 3);
+        const int b = serial ? 0 : (int)(i % s->ring);
         hipStream_t sn = serial ? s->s_comp : s->s_copy, sc = s->s_comp, su = serial ? s->s_comp : s->s_up;
         // n-block: download block i (the upload that last used this buffer is done)
-        if (!serial && i >= 3) ST_CHECK(hipStreamWaitEvent(sn, s->ev_u[b], 0));
-        ST_CHECK(hipMemcpyAsync(s->b_src[b], s->h_src + e0, (size_t)n * 4, hipMemcpyHostToDevice, sn));
-        ST_CHECK(hipMemcpyAsync(s->b_dst[b], s->h_dst + e0, (size_t)n * 4, hipMemcpyHostToDevice, sn));
-        if (s->h_w) ST_CHECK(hipMemcpyAsync(s->b_w[b], s->h_w + e0, (size_t)n * 4, hipMemcpyHostToDevice, sn));
+        if (!serial && i >= s->ring) ST_CHECK(hipStreamWaitEvent(sn, s->ev_u[b], 0));
+        ST_CHECK(hipMemcpyAsync(s->b_trip[b], s->h_trip + (size_t)e0 * s->tw, (size_t)n * 4 * s->tw,
+                                hipMemcpyHostToDevice, sn));
         if (serial) ST_CHECK(hipEventRecord(s->tev[3 * i + 1], sn));
         else ST_CHECK(hipEventRecord(s->ev_n[b], sn));
         // c-block: compute it
         if (!serial) ST_CHECK(hipStreamWaitEvent(sc, s->ev_n[b], 0));
-        hipLaunchKernelGGL(k_st_relax, dim3(blocks_of<uint32_t>(n)), dim3(ST_BLOCK), 0, sc, s->b_src[b], s->b_dst[b],
-                           s->h_w ? s->b_w[b] : nullptr, n, s->snap, front, s->val, next, s->b_msg[b], s->cnt);
+        hipLaunchKernelGGL(k_st_relax, dim3(blocks_of<uint32_t>(n)), dim3(ST_BLOCK), 0, sc, s->b_trip[b], s->tw, n,
+                           s->snap, front, s->val, next, s->b_msg[b], s->cnt);
         ST_CHECK(hipGetLastError());
         if (serial) ST_CHECK(hipEventRecord(s->tev[3 * i + 2], sc));
         else ST_CHECK(hipEventRecord(s->ev_c[b], sc));
