@@ -471,3 +471,30 @@ def pipeline_brute_force(k1: float, k2: float, k3: float, a: float, d: int):
     t = pipeline_time(k1, k2, k3, a, float(d), s)
     i = int(np.argmin(t))
     return int(s[i]), float(t[i])
+
+
+# --------------------------------------------------------------------------
+# Workload balancing (Section "Beyond-Iteration Optimization: Workload
+# Balancing", objective min max_j c_j d_j, Lemma "minmaxcidi"): the oracle
+# minimises the objective over integer splits by exhaustive search.
+# --------------------------------------------------------------------------
+
+def balance_brute_force(c, D: int):
+    """(split, value): the integer split d_1 + ... + d_m = D (d_j >= 0) with the
+    smallest max_j c_j d_j, searched exhaustively (m <= 3, small D)."""
+    c = [float(x) for x in c]
+    m = len(c)
+    best, arg = float("inf"), None
+
+    def rec(j, left, cur, acc):
+        nonlocal best, arg
+        if j == m - 1:
+            v = max(acc, c[j] * left)
+            if v < best:
+                best, arg = v, cur + [left]
+            return
+        for dj in range(left + 1):
+            rec(j + 1, left - dj, cur + [dj], max(acc, c[j] * dj))
+
+    rec(0, int(D), [], 0.0)
+    return arg, best

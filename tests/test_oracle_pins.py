@@ -433,3 +433,25 @@ def test_pipeline_degenerate_forms():
     # no transfers: T = s a + k2 d, fewest blocks
     s, t = oracle.pipeline_brute_force(0.0, 2, 0.0, 5, 40)
     assert s == 2 and abs(t - (2 * 5 + 2 * 40)) < 1e-9
+
+
+# ---------------------------------------------------------------- workload balancing
+
+def test_balance_brute_force_pins():
+    # equal costs: the even split, value c D / m
+    split, v = oracle.balance_brute_force([2.0, 2.0], 10)
+    assert sorted(split) == [5, 5] and v == 10.0
+    # costs 1 and 3 over D = 8: d = (6, 2), both nodes at 6 (the Lemma's D / (1 + 1/3) = 6)
+    split, v = oracle.balance_brute_force([1.0, 3.0], 8)
+    assert split == [6, 2] and v == 6.0
+    # three nodes 1, 2, 4 over D = 7: (4, 2, 1), every node at 4 = D / (1 + 1/2 + 1/4)
+    split, v = oracle.balance_brute_force([1.0, 2.0, 4.0], 7)
+    assert split == [4, 2, 1] and v == 4.0
+    # no split does better than the Lemma's value, and integers cost at most one entity's time
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        c = rng.uniform(0.5, 5.0, int(rng.integers(2, 4)))
+        D = int(rng.integers(1, 25))
+        _, v = oracle.balance_brute_force(c, D)
+        lemma = D / np.sum(1.0 / c)
+        assert lemma - 1e-12 <= v <= lemma + c.max() + 1e-12
