@@ -699,6 +699,86 @@ def bench_stream(gx, torch, np, gen, g=None):
             "host_link_h2d_GBps": link}
 
 
+def bench_split(gx, torch, np, gen, g=None):
+    """The graph split between the GPU and the CPU daemon (Section "Workload
+    Balancing", Lemma "minmaxcidi"): SSSP from vertex 0 on R-MAT scale 22
+    (seed 2).  c_j = a whole solve's time per edge on each worker alone; the
+    Lemma's share d_cpu = D (1/c_cpu) / (1/c_cpu + 1/c_gpu) is timed against
+    an even split and the GPU alone, each superstep running both parts at
+    once and exchanging their sync sets."""
+    if g is None:
+        g = gen.rmat(22, seed=2)
+    E = g.E
+    whole = gx.State(gx.DeviceGraph(g, gx.GX_NEED_OUT), gx.GX_SSSP, source=0)
+    whole.run(100_000)
+    ts = []
+    for _ in range(5):
+        whole.reset()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rs, _ = whole.run(100_000)
+        ts.append(time.perf_counter() - t)
+    t_gpu = sorted(ts)[2]
+    want = whole.values_numpy().copy()
+    del whole
+    cw = gx.CpuPart(g, gx.GX_SSSP, source=0)
+    t = time.perf_counter()
+    while cw.superstep()[2]:
+        pass
+    t_cpu = time.perf_counter() - t
+    assert np.array_equal(cw.values_numpy(), want)
+    del cw
+    c = np.array([t_gpu / E, t_cpu / E])
+    d = gx.balance_split(c, E)
+    share = float(d[1] / E)
+
+    def run(share):
+        parts = gen.split_by_share(g, share)
+
+        def local(p):
+            loc = int(np.searchsorted(p.l2g, 0))
+            return loc if loc < p.V and p.l2g[loc] == 0 else -1
+
+        gpu = gx.State(gx.DeviceGraph(parts[0], gx.GX_NEED_OUT), gx.GX_SSSP, source=local(parts[0]))
+        cpu = gx.CpuPart(parts[1], gx.GX_SSSP, source=local(parts[1]))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        K = tc = 0
+        while True:
+            K += 1
+            gpu.superstep(stats=False)
+            t1 = time.perf_counter()
+            cpu.superstep()
+            tc += time.perf_counter() - t1
+            gg, gv, _ = gpu.sync_delta()
+            cg, cv = cpu.sync_delta()
+            act = cpu.apply_delta(gg, gv)
+            act += gpu.apply_delta(torch.tensor(cg, device="cuda:0"), torch.tensor(cv.view(np.int32), device="cuda:0"))
+            if act == 0:
+                break
+        dt = time.perf_counter() - t0
+        best = np.full(g.V, 0xFFFFFFFF, np.uint32)
+        np.minimum.at(best, parts[0].l2g, gpu.values_numpy())
+        np.minimum.at(best, parts[1].l2g, cpu.values_numpy())
+        held = np.zeros(g.V, bool)
+        held[parts[0].l2g] = True
+        held[parts[1].l2g] = True
+        assert np.array_equal(best[held], want[held]), f"split at share {share} differs from the whole-graph solve"
+        return {"cpu_share": share, "cpu_edges": int(parts[1].E), "gpu_edges": int(parts[0].E), "supersteps": K,
+                "ms_per_solve": dt * 1e3, "cpu_superstep_ms_total": tc * 1e3}
+
+    out = {"workload": f"SSSP from vertex 0 on R-MAT scale 22 (seed 2) split by edge hash between the GPU and the "
+                       f"CPU daemon ({os.cpu_count()} host threads), sync sets exchanged every superstep",
+           "c_gpu_ns_per_edge": c[0] * 1e9, "c_cpu_ns_per_edge": c[1] * 1e9, "gpu_alone_ms": t_gpu * 1e3,
+           "cpu_alone_ms": t_cpu * 1e3, "lemma_cpu_share": share,
+           "lemma_predicted_ms": E / np.sum(1.0 / c) * 1e3,
+           "lemma_split": run(share), "even_split": run(0.5)}
+    log(f"split: c_gpu {c[0] * 1e9:.4f} c_cpu {c[1] * 1e9:.3f} ns/edge; Lemma share {share:.5f} -> "
+        f"{out['lemma_split']['ms_per_solve']:.2f} ms (model {out['lemma_predicted_ms']:.2f} ms), even split "
+        f"{out['even_split']['ms_per_solve']:.1f} ms, GPU alone {t_gpu * 1e3:.2f} ms, CPU alone {t_cpu * 1e3:.0f} ms")
+    return out
+
+
 def bench_partition(gx, torch, np, gen, reps=3):
     """One part (1 of 8) of a hash vertex-cut of R-MAT scale 25 (seed 3):
     30 PageRank supersteps and min-label CC to convergence."""
@@ -813,7 +893,7 @@ def load_traffic():
     return t
 
 
-LEGS = ("sssp", "pagerank", "partition", "lp", "phases", "stream", "exchange", "batched", "serving")
+LEGS = ("sssp", "pagerank", "partition", "lp", "phases", "stream", "split", "exchange", "batched", "serving")
 
 
 def bench_sssp(args, gx, torch, np, gen):
@@ -993,6 +1073,8 @@ def main():
         out["partition_scale25"], part = bench_partition(gx, torch, np, gen)
     if "stream" in legs:
         out["stream_sssp_scale22"] = bench_stream(gx, torch, np, gen, g)
+    if "split" in legs:
+        out["split_sssp_scale22"] = bench_split(gx, torch, np, gen, g)
     if "phases" in legs:
         out["template_calls_sssp_scale22"] = bench_phases(gx, torch, np, gen, g)
     if "lp" in legs:

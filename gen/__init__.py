@@ -160,6 +160,53 @@ def cover_isolated(parts: list, V_global: int) -> list:
     return [q] + list(parts[1:])
 
 
+def _splitmix64(x: np.ndarray) -> np.ndarray:
+    """SplitMix64 finaliser (Steele, Lea and Flood 2014), vectorised."""
+    z = (x + np.uint64(0x9E3779B97F4A7C15)).astype(np.uint64)
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def _subgraph(src, dst, w, name, other_out=None, other_any=None, master=None):
+    l2g = np.unique(np.r_[src, dst]).astype(np.int32)
+    u = np.searchsorted(l2g, src)
+    v = np.searchsorted(l2g, dst)
+    order = np.lexsort((v, u))
+    u, v, w = u[order], v[order], w[order]
+    row_ptr = np.r_[0, np.cumsum(np.bincount(u, minlength=len(l2g)))].astype(np.int32)
+    flags = np.zeros(len(l2g), np.uint8)
+    if master is not None:
+        flags |= master[l2g].astype(np.uint8)
+        flags |= (other_out[l2g].astype(np.uint8) << 1) | (other_any[l2g].astype(np.uint8) << 2)
+    return Graph(len(l2g), len(u), row_ptr, v.astype(np.int32), w.astype(np.uint32), l2g, flags, name=name)
+
+
+def split_by_share(g: Graph, share: float, seed: int = 11) -> list:
+    """Two parts of a vertex-cut by edge hash: an edge goes to part 1 when the
+    SplitMix64 hash of (seed, u, v), scaled to [0, 1), is below `share`,
+    else to part 0.  Local ids are sorted global ids; flags mark masters and
+    the vertices the other part also holds."""
+    src = g.src.astype(np.int64)
+    dst = g.col.astype(np.int64)
+    key = ((src.astype(np.uint64) << np.uint64(32)) | dst.astype(np.uint64)) ^ np.uint64(seed)
+    h = (_splitmix64(key) >> np.uint64(11)).astype(np.float64) / float(1 << 53)
+    one = h < share
+    out_in, any_in = [], []
+    for sel in (~one, one):
+        o = np.zeros(g.V, bool)
+        o[src[sel]] = True
+        a = o.copy()
+        a[dst[sel]] = True
+        out_in.append(o)
+        any_in.append(a)
+    # flags: bit 0 master (part 0 when it holds the vertex), bit 1 an out-edge
+    # in the other part, bit 2 any edge in the other part
+    m0 = any_in[0]
+    return [_subgraph(src[~one], dst[~one], g.w[~one], g.name + "_p0", out_in[1], any_in[1], m0),
+            _subgraph(src[one], dst[one], g.w[one], g.name + "_p1", out_in[0], any_in[0], ~m0)]
+
+
 def quadrant_counts(scale: int, n: int, seed: int, a: float = RMAT_A, b: float = RMAT_B,
                     c: float = RMAT_C) -> np.ndarray:
     lib = _load()

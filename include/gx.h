@@ -421,6 +421,35 @@ gx_status gx_pipeline_time(const gx_pipeline_coef *k, double d, double s, double
 gx_status gx_pipeline_plan(const gx_pipeline_coef *k, int64_t d, int64_t *blocks, double *block_size, double *T);
 
 /* ---------------------------------------------------------------------
+ * The CPU daemon and workload balancing (Section "Beyond-Iteration
+ * Optimization: Workload Balancing", Eq. "CostModelOneIteration", Lemma
+ * "minmaxcidi").  A part of a vertex-cut can run on host threads with the
+ * device engine's superstep semantics (Jacobi min superstep, SSSP on the
+ * out-CSR, CC on the symmetric adjacency) and exchange sync sets with parts
+ * on the GPU; host arrays throughout.  `threads` = 0: all hardware threads.
+ * --------------------------------------------------------------------- */
+
+typedef struct gx_cpu gx_cpu;
+/* Copies the description's CSR (E < 2^30).  GX_EINVAL, GX_ENOMEM. */
+gx_status gx_cpu_create(const gx_graph_desc *desc, int32_t algo, int32_t source, int32_t threads, gx_cpu **out);
+/* One superstep; fills *stats (frontier, messages, changed). */
+gx_status gx_cpu_superstep(gx_cpu *c, gx_step_stats *stats);
+/* Every vertex changed since the last call that another part needs (flags
+ * given: remote_out for SSSP, remote_any for CC; no flags: every changed
+ * vertex), (global id, value) in ascending id; GX_ENOMEM with *count set
+ * when count > cap (nothing written, nothing committed). */
+gx_status gx_cpu_sync_delta(gx_cpu *c, int32_t *gid, uint32_t *val, uint32_t cap, uint32_t *count);
+/* Other parts' pairs merged by integer min; lowered replicas become active. */
+gx_status gx_cpu_apply_delta(gx_cpu *c, const int32_t *gid, const uint32_t *val, uint32_t n, int64_t *active_next);
+/* The current values (V entries, valid until the next call on the handle). */
+gx_status gx_cpu_values(gx_cpu *c, const uint32_t **values);
+gx_status gx_cpu_free(gx_cpu *c);
+/* Lemma "minmaxcidi": the split d_j = D (1/c_j) / sum_i (1/c_i) of D entities
+ * over m workers of cost c_j per entity, which minimises max_j c_j d_j.
+ * GX_EINVAL for non-positive costs. */
+gx_status gx_balance_split(const double *c, int32_t m, double D, double *d_out);
+
+/* ---------------------------------------------------------------------
  * Batched lanes: B independent single-source SSSP (or personalised
  * PageRank) solves over one resident graph, run as one persistent kernel
  * over a [V x B] state tile (B contiguous per vertex).  Generalises the

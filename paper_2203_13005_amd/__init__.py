@@ -26,7 +26,9 @@ from .binding import (  # noqa: F401
     DeviceGraph,
     GxError,
     Server,
+    CpuPart,
     State,
+    balance_split,
     Stream,
     pipeline_plan,
     Tune,

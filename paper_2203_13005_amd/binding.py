@@ -134,6 +134,13 @@ _SIGS = {
                                           ctypes.POINTER(ctypes.c_double)]),
     "gx_pipeline_plan": (ctypes.c_int32, [ctypes.POINTER(PipelineCoef), ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "gx_cpu_create": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)]),
+    "gx_cpu_superstep": (ctypes.c_int32, [_P, ctypes.POINTER(StepStats)]),
+    "gx_cpu_sync_delta": (ctypes.c_int32, [_P, _P, _P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]),
+    "gx_cpu_apply_delta": (ctypes.c_int32, [_P, _P, _P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int64)]),
+    "gx_cpu_values": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.POINTER(ctypes.c_uint32))]),
+    "gx_cpu_free": (ctypes.c_int32, [_P]),
+    "gx_balance_split": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_double, _P]),
     "gx_msg_gen": (ctypes.c_int32, [_P, _P]),
     "gx_msg_merge": (ctypes.c_int32, [_P, _P]),
     "gx_msg_apply": (ctypes.c_int32, [_P, _P, ctypes.POINTER(StepStats)]),
@@ -185,7 +192,7 @@ _live: "weakref.WeakSet" = weakref.WeakSet()
 
 
 def _close_all_at_exit():
-    for kind in ("Server", "Stream", "State", "DeviceGraph"):
+    for kind in ("Server", "Stream", "CpuPart", "State", "DeviceGraph"):
         for obj in list(_live):
             if type(obj).__name__ == kind:
                 try:
@@ -650,6 +657,69 @@ class Stream:
     def close(self):
         if getattr(self, "handle", None):
             lib.gx_stream_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def balance_split(c, D: float) -> np.ndarray:
+    """Lemma "minmaxcidi": entities per worker, d_j proportional to 1 / c_j."""
+    cc = np.ascontiguousarray(c, np.float64)
+    out = np.empty(len(cc), np.float64)
+    _check(lib.gx_balance_split(_np_ptr(cc), len(cc), float(D), _np_ptr(out)))
+    return out
+
+
+class CpuPart:
+    """A part run by the CPU daemon (host threads), exchanging sync sets like
+    a State with GX_DELTA_ALL."""
+
+    def __init__(self, host, algo: int, source: int = 0, threads: int = 0):
+        self._keep = [np.ascontiguousarray(host.row_ptr, np.int32), np.ascontiguousarray(host.col, np.int32),
+                      None if host.w is None else np.ascontiguousarray(host.w, np.uint32),
+                      None if getattr(host, "l2g", None) is None else np.ascontiguousarray(host.l2g, np.int32),
+                      None if getattr(host, "flags", None) is None else np.ascontiguousarray(host.flags, np.uint8)]
+        rp, col, w, l2g, flags = self._keep
+        desc = _GraphDesc(int(host.V), int(host.E), _np_ptr(rp), _np_ptr(col), _np_ptr(w), _np_ptr(l2g),
+                          _np_ptr(flags), GX_NEED_OUT, 0, 0, None)
+        h = ctypes.c_void_p()
+        _check(lib.gx_cpu_create(ctypes.byref(desc), int(algo), int(source), int(threads), ctypes.byref(h)))
+        self.handle, self.V = h, int(host.V)
+        self._keep = None
+        _live.add(self)
+
+    def superstep(self):
+        st = StepStats()
+        _check(lib.gx_cpu_superstep(self.handle, ctypes.byref(st)))
+        return st.as_tuple()
+
+    def sync_delta(self):
+        gid = np.empty(max(self.V, 1), np.int32)
+        val = np.empty(max(self.V, 1), np.uint32)
+        n = ctypes.c_uint32()
+        _check(lib.gx_cpu_sync_delta(self.handle, _np_ptr(gid), _np_ptr(val), self.V, ctypes.byref(n)))
+        return gid[:n.value], val[:n.value]
+
+    def apply_delta(self, gid, val) -> int:
+        g = np.ascontiguousarray(gid, np.int32)
+        v = np.ascontiguousarray(val, np.uint32)
+        act = ctypes.c_int64()
+        _check(lib.gx_cpu_apply_delta(self.handle, _np_ptr(g) if len(g) else None, _np_ptr(v) if len(v) else None,
+                                      len(g), ctypes.byref(act)))
+        return act.value
+
+    def values_numpy(self) -> np.ndarray:
+        p = ctypes.POINTER(ctypes.c_uint32)()
+        _check(lib.gx_cpu_values(self.handle, ctypes.byref(p)))
+        return np.ctypeslib.as_array(p, shape=(max(self.V, 1),))[: self.V].copy()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.gx_cpu_free(self.handle)
             self.handle = None
 
     def __del__(self):
