@@ -68,7 +68,7 @@ static void parallel_for(int64_t n, F f) {
 
 // Host images built from the description before upload.
 struct HostImages {
-    std::vector<int32_t> in_rp, in_col, outdeg, tile_row;
+    std::vector<int32_t> in_rp, in_col, outdeg, tile_row, pr_slot, pr_src;
     std::vector<uint32_t> in_w;
     std::vector<int32_t> sym_rp, sym_col;
     std::vector<uint2> pull_w, pull_sym;
@@ -171,6 +171,28 @@ static void build_in_csr(const gx_graph_desc *d, HostImages &h) {
                 }
         });
     for (auto &x : th) x.join();
+}
+
+// PageRank contribution slots: the PR_HOT vertices with the most out-edges
+// (ties by id) take slots 0.. in that order, the others follow in id order,
+// so the gathers of hub contributions fall on a few cache lines.
+static void build_pr_slots(const gx_graph_desc *d, HostImages &h) {
+    const int64_t V = d->V, E = d->E;
+    const int64_t K = std::min<int64_t>(V, PR_HOT);
+    std::vector<int32_t> ids(V);
+    for (int64_t v = 0; v < V; v++) ids[v] = (int32_t)v;
+    auto deg = [d](int32_t v) { return d->row_ptr[v + 1] - d->row_ptr[v]; };
+    auto hotter = [&](int32_t a, int32_t b) { return deg(a) != deg(b) ? deg(a) > deg(b) : a < b; };
+    std::partial_sort(ids.begin(), ids.begin() + K, ids.end(), hotter);
+    h.pr_slot.assign(V, -1);
+    for (int64_t i = 0; i < K; i++) h.pr_slot[ids[i]] = (int32_t)i;
+    int64_t next = K;
+    for (int64_t v = 0; v < V; v++)
+        if (h.pr_slot[v] < 0) h.pr_slot[v] = (int32_t)next++;
+    h.pr_src.resize(E);
+    parallel_for(E, [&](int64_t lo, int64_t hi) {
+        for (int64_t e = lo; e < hi; e++) h.pr_src[e] = h.pr_slot[h.in_col[e]];
+    });
 }
 
 // Pull tiles: tile t covers edges [t*T, (t+1)*T) of a CSR and owns the rows
@@ -356,6 +378,8 @@ static void layout(const gx_graph_desc *desc, int64_t E_sym, Carver &c, DevGraph
     if (desc->needs & GX_NEED_IN) {
         d->in_col = c.take<int32_t>(E);
         d->outdeg = c.take<int32_t>(V);
+        d->pr_src = c.take<int32_t>(E);
+        d->pr_slot = c.take<int32_t>(V);
     }
     if ((desc->needs & GX_NEED_OUT) && (desc->E == 0 || banded_weights_fit(desc))) {
         d->pull_w = c.take<uint2>(pull_rec_cap(V, E));
@@ -479,6 +503,7 @@ extern "C" gx_status gx_graph_load(const gx_graph_desc *desc, void *dev_arena, s
     try {
         build_in_csr(desc, h);
         build_tiles(h.in_rp, h.tile_row, pr_tile_for(desc));
+        if (desc->needs & GX_NEED_IN) build_pr_slots(desc, h);
         if ((desc->needs & GX_NEED_OUT) && (desc->E == 0 || banded_weights_fit(desc)))
             build_pull(h.in_rp, h.in_col.data(), h.in_w.data(), h.pull_w, h.pull_w_units, h.pull_w_off);
         if (desc->needs & GX_NEED_SYM) {
@@ -539,6 +564,8 @@ extern "C" gx_status gx_graph_load(const gx_graph_desc *desc, void *dev_arena, s
     if (e == hipSuccess && d.in_col) {
         e = up.put_array((void *)d.in_col, h.in_col.data(), E * 4);
         if (e == hipSuccess) e = up.put_array((void *)d.outdeg, g->host_outdeg.data(), V * 4);
+        if (e == hipSuccess) e = up.put_array((void *)d.pr_src, h.pr_src.data(), E * 4);
+        if (e == hipSuccess) e = up.put_array((void *)d.pr_slot, h.pr_slot.data(), V * 4);
     }
     if (e == hipSuccess && d.pull_w) {
         e = up.put_array((void *)d.pull_w, h.pull_w.data(), h.pull_w.size() * sizeof(uint2));

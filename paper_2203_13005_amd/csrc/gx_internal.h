@@ -61,6 +61,10 @@ struct Carver {
 // Edge tile of the PageRank pull (in-edges per workgroup tile): PR_BLOCK
 // threads times 1, 2, 4 or 8 edges, chosen per graph at load.
 constexpr int PR_BLOCK = 256;
+// Contribution slots of the hottest sources, contiguous at the front: 2 MiB
+// of fp32, which a workgroup's L2 keeps while the in-edges stream past (on
+// R-MAT graphs they are the sources of about 70% of the in-edges).
+constexpr int64_t PR_HOT = int64_t(1) << 19;
 constexpr int PR_TILE_MAX = PR_BLOCK * 8;
 // Records of the SSSP / CC pull.  Destinations are dealt to PULL_SLICES
 // slices in blocks of 2^PULL_SLICE_SHIFT vertices, balanced by in-edge
@@ -115,6 +119,12 @@ struct DevGraph {
     const int32_t *in_rp = nullptr;
     const int32_t *in_col = nullptr;
     const int32_t *outdeg = nullptr;
+    // PageRank contributions live in slots: the PR_HOT sources with the most
+    // out-edges first (by out-degree, then id), every other vertex after them
+    // in id order.  pr_src = the slot of each in-edge's source, pr_slot = the
+    // slot of each vertex.
+    const int32_t *pr_src = nullptr;
+    const int32_t *pr_slot = nullptr;
     int32_t pr_tile = PR_TILE_MAX;  // in-edges per PageRank tile
     int32_t pr_ntiles = 0;
     const int32_t *pr_tile_row = nullptr;  // [pr_ntiles + 1]

@@ -500,8 +500,8 @@ __global__ __launch_bounds__(256) void k_fixup(const uint2 *__restrict__ fix, co
 // ------------------------------------------------------------ PageRank
 
 __global__ __launch_bounds__(256) void k_pr_init(float *x, float *contrib, uint32_t *synced,
-                                                 const int32_t *__restrict__ outdeg, int64_t V, float x0,
-                                                 double *dpart, DevStep *step0) {
+                                                 const int32_t *__restrict__ outdeg, const int32_t *__restrict__ slot,
+                                                 int64_t V, float x0, double *dpart, DevStep *step0) {
     __shared__ double s_d[4];
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v == 0) *step0 = DevStep{};
@@ -510,7 +510,7 @@ __global__ __launch_bounds__(256) void k_pr_init(float *x, float *contrib, uint3
         int od = outdeg[v];
         x[v] = x0;
         synced[v] = __float_as_uint(x0);
-        contrib[v] = od > 0 ? x0 / (float)od : 0.0f;
+        contrib[slot[v]] = od > 0 ? x0 / (float)od : 0.0f;
         if (od == 0) dl = (double)x0;
     }
     double t = block_sum<double>(dl, s_d);
@@ -531,13 +531,23 @@ struct PrApply {
     const int32_t *outdeg;
     const float *x_in;
     float *x_out, *c_out;
-    __device__ __forceinline__ void operator()(int32_t r, double acc, double &dsum, int &chg) const {
+    const int32_t *slot;  // contribution slot of each vertex (hottest sources first)
+    static constexpr bool kRows = true;  // the pull stages outdeg, slot and x_in of its rows in LDS
+    __device__ __forceinline__ void load_row(int32_t r, int32_t &od, int32_t &sl, float &xi) const {
+        od = outdeg[r];
+        sl = slot[r];
+        xi = x_in[r];
+    }
+    __device__ __forceinline__ void row(int32_t r, double acc, int32_t od, int32_t sl, float xi, double &dsum,
+                                        int &chg) const {
         float xn = (float)(base + d * acc + dD);
         x_out[r] = xn;
-        int od = outdeg[r];
-        c_out[r] = od > 0 ? xn / (float)od : 0.0f;
+        c_out[sl] = od > 0 ? xn / (float)od : 0.0f;
         if (od == 0) dsum += (double)xn;
-        chg += __float_as_uint(xn) != __float_as_uint(x_in[r]);
+        chg += __float_as_uint(xn) != __float_as_uint(xi);
+    }
+    __device__ __forceinline__ void operator()(int32_t r, double acc, double &dsum, int &chg) const {
+        row(r, acc, outdeg[r], slot[r], x_in[r], dsum, chg);
     }
 };
 
@@ -546,6 +556,11 @@ struct PrApply {
 struct PrStore {
     double d, dD;  // (unused)
     double *acc;
+    static constexpr bool kRows = false;
+    __device__ __forceinline__ void load_row(int32_t, int32_t &, int32_t &, float &) const {}
+    __device__ __forceinline__ void row(int32_t r, double total, int32_t, int32_t, float, double &, int &) const {
+        acc[r] = total;
+    }
     __device__ __forceinline__ void operator()(int32_t r, double total, double &, int &) const { acc[r] = total; }
 };
 
@@ -559,6 +574,8 @@ __global__ __launch_bounds__(PR_BLOCK) void k_pr_pull(const int32_t *__restrict_
                                                       int32_t *__restrict__ spill_row, double *__restrict__ dpart,
                                                       uint32_t *__restrict__ cpart) {
     constexpr int TILE = PR_BLOCK * VT;
+    constexpr int RPT = 2;                    // rows per thread whose data is staged in LDS
+    constexpr int ROWS = RPT * PR_BLOCK;
     __shared__ float s_val[TILE];
     __shared__ int32_t s_own[TILE];
     __shared__ double s_last[PR_BLOCK];
@@ -567,6 +584,9 @@ __global__ __launch_bounds__(PR_BLOCK) void k_pr_pull(const int32_t *__restrict_
     __shared__ int32_t s_red[4];
     __shared__ double s_d[4];
     __shared__ unsigned long long s_c[4];
+    __shared__ int32_t s_re[ROWS];            // end of row r_lo + i (in_rp[r + 1])
+    __shared__ int32_t s_od[AP::kRows ? ROWS : 1], s_sl[AP::kRows ? ROWS : 1];
+    __shared__ float s_xi[AP::kRows ? ROWS : 1];
     const int tid = threadIdx.x;
     const int32_t t = blockIdx.x;
     const int64_t e0 = (int64_t)t * TILE;
@@ -574,30 +594,72 @@ __global__ __launch_bounds__(PR_BLOCK) void k_pr_pull(const int32_t *__restrict_
     const int32_t r_lo = tile_row[t], r_hi = tile_row[t + 1];
     ap.dD = ap.d * (*Dp) * inv_V;
     if (tid == 0) spill_row[t] = -1;
-    if (n > 0) {  // contributions into LDS: all source ids, then all gathers
-        // (unconditional loads: slots past the tile's end repeat its last edge)
-        int32_t u[VT];
-        float cv[VT];
+    // Every load that depends only on the tile is issued at once: the edges'
+    // sources, the row pointers of the tile's first ROWS rows and what the
+    // apply reads of them; then the gathers of the contributions.
+    int32_t u[VT];
+    float cv[VT];
+    int32_t ra[RPT], rb[RPT], od[RPT], sl[RPT];
+    float xi[RPT];
 #pragma unroll
-        for (int i = 0; i < VT; i++) u[i] = in_col[e0 + min(tid + i * PR_BLOCK, n - 1)];
+    for (int i = 0; i < VT; i++)  // (the in-edges stream by once: kept out of the caches' way)
+        u[i] = n > 0 ? __builtin_nontemporal_load(&in_col[e0 + min(tid + i * PR_BLOCK, n - 1)]) : 0;
 #pragma unroll
-        for (int i = 0; i < VT; i++) cv[i] = c_in[u[i]];
+    for (int k = 0; k < RPT; k++) {
+        const int32_t r = r_lo + tid + k * PR_BLOCK;
+        ra[k] = rb[k] = 0;
+        od[k] = sl[k] = 0;
+        xi[k] = 0.f;
+        if (r < r_hi) {
+            ra[k] = in_rp[r];
+            rb[k] = in_rp[r + 1];
+            ap.load_row(r, od[k], sl[k], xi[k]);
+        }
+    }
 #pragma unroll
-        for (int i = 0; i < VT; i++) {
-            const int p = tid + i * PR_BLOCK;
-            if (p < n) {
-                s_val[p] = cv[i];
-                s_own[p] = 0;
+    for (int i = 0; i < VT; i++) cv[i] = n > 0 ? c_in[u[i]] : 0.f;
+#pragma unroll
+    for (int i = 0; i < VT; i++) {
+        const int p = tid + i * PR_BLOCK;
+        if (p < n) {
+            s_val[p] = cv[i];
+            s_own[p] = 0;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < RPT; k++) {
+        const int i = tid + k * PR_BLOCK;
+        if (r_lo + i < r_hi) {
+            s_re[i] = rb[k];
+            if (AP::kRows) {
+                s_od[i] = od[k];
+                s_sl[i] = sl[k];
+                s_xi[i] = xi[k];
             }
         }
     }
     __syncthreads();
-    for (int32_t r = r_lo + tid; r < r_hi; r += PR_BLOCK) {
+#pragma unroll
+    for (int k = 0; k < RPT; k++) {
+        const int32_t r = r_lo + tid + k * PR_BLOCK;
+        if (r < r_hi && rb[k] > ra[k]) s_own[ra[k] - e0] = r - r_lo + 1;
+    }
+    for (int32_t r = r_lo + ROWS + tid; r < r_hi; r += PR_BLOCK) {  // rows past the staged ones
         int32_t a = in_rp[r], b = in_rp[r + 1];
         if (b > a) s_own[a - e0] = r - r_lo + 1;
     }
     __syncthreads();
     block_max_scan<VT>(s_own, n, s_red);
+
+    // a row's apply, from its staged data when it has some
+    auto apply_row = [&](int32_t r, double total, double &dsum, int &chg) {
+        const int i = r - r_lo;
+        if (i < ROWS)
+            ap.row(r, total, s_od[AP::kRows ? i : 0], s_sl[AP::kRows ? i : 0], s_xi[AP::kRows ? i : 0], dsum, chg);
+        else
+            ap(r, total, dsum, chg);
+    };
+    auto row_end = [&](int32_t r) { return r - r_lo < ROWS ? s_re[r - r_lo] : in_rp[r + 1]; };
 
     // Per-thread contiguous chunk: sequential sums per destination row.
     double dsum = 0.0;
@@ -614,12 +676,12 @@ __global__ __launch_bounds__(PR_BLOCK) void k_pr_pull(const int32_t *__restrict_
             return;
         }
         int32_t r = r_lo + o - 1;
-        if (ends_tile && in_rp[r + 1] > e0 + n) {
+        if (ends_tile && row_end(r) > e0 + n) {
             tailp[t] = total;  // row continues into later tiles
             spill_row[t] = r;
             return;
         }
-        ap(r, total, dsum, chg);
+        apply_row(r, total, dsum, chg);
     };
     for (int p = c0; p < c1; p++) {
         int o = s_own[p];
@@ -687,7 +749,12 @@ __global__ __launch_bounds__(PR_BLOCK) void k_pr_pull(const int32_t *__restrict_
     __syncthreads();
     if (defer_first) finish(first_own, tid > 0 ? first_sum + s_last[tid - 1] : first_sum, defer_ends_tile);
     // Rows of this tile without in-edges.
-    for (int32_t r = r_lo + tid; r < r_hi; r += PR_BLOCK)
+#pragma unroll
+    for (int k = 0; k < RPT; k++) {
+        const int32_t r = r_lo + tid + k * PR_BLOCK;
+        if (r < r_hi && rb[k] == ra[k]) apply_row(r, 0.0, dsum, chg);
+    }
+    for (int32_t r = r_lo + ROWS + tid; r < r_hi; r += PR_BLOCK)
         if (in_rp[r + 1] == in_rp[r]) ap(r, 0.0, dsum, chg);
     double td = block_sum<double>(dsum, s_d);
     unsigned long long tc = block_sum<unsigned long long>((unsigned long long)chg, s_c);
@@ -1033,15 +1100,15 @@ __global__ __launch_bounds__(256) void k_ph_apply(uint32_t *__restrict__ acc, ui
 // (master != NULL: a part of a vertex-cut; only its masters' dangling mass
 // counts, every other part counts its own masters)
 __global__ __launch_bounds__(256) void k_ph_pr_gen(const float *__restrict__ x, const int32_t *__restrict__ outdeg,
-                                                   float *__restrict__ contrib, int64_t V, double *dpart,
-                                                   const uint32_t *__restrict__ master) {
+                                                   const int32_t *__restrict__ slot, float *__restrict__ contrib,
+                                                   int64_t V, double *dpart, const uint32_t *__restrict__ master) {
     __shared__ double s_d[4];
     const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
     double dl = 0.0;
     if (v < V) {
         const float xv = x[v];
         const int od = outdeg[v];
-        contrib[v] = od > 0 ? xv / (float)od : 0.0f;
+        contrib[slot[v]] = od > 0 ? xv / (float)od : 0.0f;
         if (od == 0 && (!master || bit_of(master, v))) dl = (double)xv;
     }
     const double t = block_sum<double>(dl, s_d);
@@ -1252,8 +1319,8 @@ extern "C" gx_status gx_state_init(gx_graph *g, const gx_params *p, void *dev_st
         const int64_t Vn = p->phases == GX_PHASES_MASTERS ? d.V_global : V;
         float x0 = V > 0 ? (float)(1.0 / (double)Vn) : 0.f;
         unsigned nb = grid_for<int64_t>(V, 256);
-        hipLaunchKernelGGL(k_pr_init, dim3(nb), dim3(256), 0, hs, s->x[0], s->contrib[0], s->synced, d.outdeg, V, x0,
-                           s->dpart, s->steps);
+        hipLaunchKernelGGL(k_pr_init, dim3(nb), dim3(256), 0, hs, s->x[0], s->contrib[0], s->synced, d.outdeg,
+                           d.pr_slot, V, x0, s->dpart, s->steps);
         hipLaunchKernelGGL(k_reduce_D, dim3(1), dim3(1024), 0, hs, s->dpart, (int)nb, s->Dval);
         (void)hipMemsetAsync(s->fix_done, 0, sizeof(uint32_t), hs);
     } else {
@@ -1416,13 +1483,14 @@ static gx_status enqueue_superstep(gx_state *s, hipStream_t hs) {
     } else if (p.algo == GX_PAGERANK) {
         int cur = (int)(s->k & 1);
         double dd = p.damping;
-        PrApply ap{(1.0 - dd) / (double)d.V, dd, 0.0, d.outdeg, s->x[cur], s->x[cur ^ 1], s->contrib[cur ^ 1]};
+        PrApply ap{(1.0 - dd) / (double)d.V, dd, 0.0, d.outdeg, s->x[cur], s->x[cur ^ 1], s->contrib[cur ^ 1],
+                   d.pr_slot};
         double inv_V = d.V > 0 ? 1.0 / (double)d.V : 0.0;
         if (d.V > 0) {
             if (e0) (void)hipEventRecord(e0, hs);
             auto pull = d.pr_tile == 256 ? k_pr_pull<1, PrApply> : d.pr_tile == 512 ? k_pr_pull<2, PrApply>
                       : d.pr_tile == 1024 ? k_pr_pull<4, PrApply> : k_pr_pull<8, PrApply>;
-            hipLaunchKernelGGL(pull, dim3(d.pr_ntiles), dim3(PR_BLOCK), 0, hs, d.in_rp, d.in_col, d.pr_tile_row,
+            hipLaunchKernelGGL(pull, dim3(d.pr_ntiles), dim3(PR_BLOCK), 0, hs, d.in_rp, d.pr_src, d.pr_tile_row,
                                d.E, s->contrib[cur], ap, s->Dval, inv_V, s->head, s->tailp, s->spill_row, s->dpart,
                                s->cpart);
             if (e1) (void)hipEventRecord(e1, hs);
@@ -1824,7 +1892,7 @@ extern "C" gx_status gx_msg_gen(gx_state *s, void *stream) {
             const unsigned nb = grid_for<int64_t>(d.V, 256);
             const bool parts = s->p.phases == GX_PHASES_MASTERS;
             hipLaunchKernelGGL(k_ph_pr_gen, dim3(nb), dim3(256), 0, hs, s->x[0], parts ? d.outdeg_g : d.outdeg,
-                               s->contrib[0], d.V, s->dpart, parts ? d.master : nullptr);
+                               d.pr_slot, s->contrib[0], d.V, s->dpart, parts ? d.master : nullptr);
             hipLaunchKernelGGL(k_reduce_D, dim3(1), dim3(1024), 0, hs, s->dpart, (int)nb, s->Dval);
         } else {
             // the pending map's vertices become the active list (with the values
@@ -1856,7 +1924,7 @@ extern "C" gx_status gx_msg_merge(gx_state *s, void *stream) {
             const double inv_V = 1.0 / (double)d.V;
             auto pull = d.pr_tile == 256 ? k_pr_pull<1, PrStore> : d.pr_tile == 512 ? k_pr_pull<2, PrStore>
                       : d.pr_tile == 1024 ? k_pr_pull<4, PrStore> : k_pr_pull<8, PrStore>;
-            hipLaunchKernelGGL(pull, dim3(d.pr_ntiles), dim3(PR_BLOCK), 0, hs, d.in_rp, d.in_col, d.pr_tile_row, d.E,
+            hipLaunchKernelGGL(pull, dim3(d.pr_ntiles), dim3(PR_BLOCK), 0, hs, d.in_rp, d.pr_src, d.pr_tile_row, d.E,
                                s->contrib[0], ap, s->Dscratch, inv_V, s->head, s->tailp, s->spill_row, s->dpart,
                                s->cpart);
             hipLaunchKernelGGL(k_pr_fix<PrStore>, dim3(s->pr_fix_grid), dim3(PR_FIX_BLOCK), 0, hs, d.in_rp,
