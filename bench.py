@@ -259,10 +259,11 @@ def bench_batched_ppr(gx, torch, g, dg, src, iters=50, reps=3):
 
 
 def bench_serving(gx, torch, np, gen, n_queries=10000, qps_frac=0.7, lanes=64, max_pools=32, budget_frac=0.5,
-                  sample=16):
+                  sample=16, outstanding=512, records=None):
     """16 resident R-MAT graphs (scales 16..22, seeds 100..115), 50% SSSP /
     50% PPR (50 iterations), Poisson arrivals (seed 5) at a fixed rate of
-    qps_frac x the measured closed-loop capacity.  The HBM budget holds
+    qps_frac x the capacity measured closed-loop with `outstanding` queries
+    in flight.  The HBM budget holds
     budget_frac of the lane pools of every (graph, algorithm) pair, so
     admission binds: pools are created, evicted when idle and empty, and
     queries wait for room.  After the timed run a seeded sample of the
@@ -319,17 +320,36 @@ def bench_serving(gx, torch, np, gen, n_queries=10000, qps_frac=0.7, lanes=64, m
         srv.close()
         return done, wall, kept
 
-    cap_q = make(1024)
-    done, wall, _ = run(cap_q, np.zeros(len(cap_q)))
-    capacity = len(cap_q) / wall
-    log(f"serving: closed-loop capacity {capacity:.1f} queries/s (budget {budget / 2**30:.1f} GiB of "
-        f"{pools / 2**30:.1f} GiB for every pool)")
+    def run_closed(qs, outstanding):
+        # a fixed number of queries in flight: each completion submits the next
+        srv = gx.Server(budget, lanes_per_pool=lanes, max_pools=max_pools, epoch_supersteps=4, ppr_iters=50)
+        ids = [srv.add_graph(d) for d in dgs]
+        t_start = time.perf_counter()
+        i = n_done = 0
+        while n_done < len(qs):
+            while i < len(qs) and i - n_done < outstanding:
+                gi, algo, s_ = qs[i]
+                srv.submit(ids[gi], algo, s_)
+                i += 1
+            for c in srv.poll(wait_ms=20):
+                assert c.status == 0
+                n_done += 1
+        wall = time.perf_counter() - t_start
+        srv.close()
+        return wall
+
+    cap_q = make(2048)
+    capacity = len(cap_q) / run_closed(cap_q, outstanding)
+    log(f"serving: closed-loop capacity {capacity:.1f} queries/s with {outstanding} in flight (budget "
+        f"{budget / 2**30:.1f} GiB of {pools / 2**30:.1f} GiB for every pool)")
     qps = qps_frac * capacity
     qs = make(n_queries)
     arrivals = np.cumsum(np.random.default_rng(5).exponential(1.0 / qps, n_queries))
     check_rng = np.random.default_rng(6)
     keep = set(int(x) for x in check_rng.choice(n_queries, sample, replace=False))
     done, wall, kept = run(qs, arrivals, keep)
+    if records is not None:  # per-query (graph, algorithm, submit, start, done, supersteps)
+        records.extend((c.graph, c.algo, c.submit_s, c.start_s, c.done_s, c.supersteps) for c in done)
     lat = np.array([c.done_s - c.submit_s for c in done])
     wait = np.array([c.start_s - c.submit_s for c in done])
     by_algo = {}
@@ -358,6 +378,7 @@ def bench_serving(gx, torch, np, gen, n_queries=10000, qps_frac=0.7, lanes=64, m
                         "edge factor 16), queries 50% SSSP / 50% personalised PageRank (50 iterations), "
                         "Poisson arrivals (seed 5)",
             "queries": len(done), "offered_qps": qps, "closed_loop_capacity_qps": capacity,
+            "closed_loop_outstanding": outstanding,
             "queries_per_s": len(done) / wall, "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "admission_wait_p50_ms": float(np.percentile(wait, 50) * 1e3), "by_algorithm": by_algo,

@@ -502,11 +502,16 @@ typedef struct gx_server gx_server;
 typedef struct gx_server_config {
     void    *dev_arena;       /* device memory for lane pools */
     size_t   arena_bytes;     /* budget: lane pools are admitted only while they fit */
-    uint32_t lanes_per_pool;  /* lanes per pool (multiple of 32, <= 256); 0 = 64 */
+    uint32_t lanes_per_pool;  /* most lanes in one pool (multiple of 32, <= 256); 0 = 64.  A new
+                               * pool takes the queries of its pair waiting at that moment,
+                               * rounded up to a multiple of 32 lanes, at most this many */
     uint32_t max_pools;       /* concurrently running pools (one stream each); 0 = 4 */
-    uint32_t epoch_supersteps;/* supersteps per pool launch before admitting/retiring; 0 = 4 */
+    uint32_t epoch_supersteps;/* PPR supersteps per pool launch before admitting/retiring; 0 = 4 */
     float    damping;         /* PPR damping; 0 = 0.85 */
     uint32_t ppr_iters;       /* PPR supersteps per query; 0 = 50 */
+    uint32_t sssp_epoch_supersteps; /* SSSP supersteps per pool launch; 0 = 16.  Converged lanes
+                               * cost next to nothing, and epochs that run a query to its end
+                               * save the round trips behind other pools' work */
 } gx_server_config;
 
 typedef struct gx_query_result {
@@ -534,7 +539,7 @@ gx_status gx_server_submit(gx_server *s, int32_t graph_id, int32_t algo, int32_t
  * With wait_ms > 0 blocks until at least one completes or the time passes. */
 gx_status gx_server_poll(gx_server *s, gx_query_result *out, uint32_t cap, uint32_t *n,
                          int32_t wait_ms);
-/* Queries queued or running. */
+/* Queries queued, running, or finished with their result still being copied out. */
 gx_status gx_server_pending(gx_server *s, int64_t *n);
 gx_status gx_server_destroy(gx_server *s);
 

@@ -85,7 +85,7 @@ class _ServerConfig(ctypes.Structure):
     _fields_ = [("dev_arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t),
                 ("lanes_per_pool", ctypes.c_uint32), ("max_pools", ctypes.c_uint32),
                 ("epoch_supersteps", ctypes.c_uint32), ("damping", ctypes.c_float),
-                ("ppr_iters", ctypes.c_uint32)]
+                ("ppr_iters", ctypes.c_uint32), ("sssp_epoch_supersteps", ctypes.c_uint32)]
 
 
 class QueryResult(ctypes.Structure):
@@ -526,13 +526,14 @@ class Server:
     """Continuous-batching query server over resident graphs."""
 
     def __init__(self, arena_bytes: int, lanes_per_pool: int = 64, max_pools: int = 4, epoch_supersteps: int = 4,
-                 damping: float = 0.85, ppr_iters: int = 50, device="cuda:0"):
+                 damping: float = 0.85, ppr_iters: int = 50, sssp_epoch_supersteps: int = 16, device="cuda:0"):
         import torch
         self.device = torch.device(device)
         with torch.cuda.device(self.device):
             self.arena = _arena(arena_bytes, self.device)
         cfg = _ServerConfig(ctypes.c_void_p(self.arena.data_ptr()), int(arena_bytes), int(lanes_per_pool),
-                            int(max_pools), int(epoch_supersteps), float(damping), int(ppr_iters))
+                            int(max_pools), int(epoch_supersteps), float(damping), int(ppr_iters),
+                            int(sssp_epoch_supersteps))
         h = ctypes.c_void_p()
         _check(lib.gx_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h

@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstring>
 #include <deque>
 #include <map>
 #include <memory>
@@ -94,18 +95,28 @@ struct Pool {
     hipEvent_t done = nullptr;
     void *mem = nullptr;
     size_t bytes = 0;
+    double t_ready = 0;     // when it last became idle (created, or its epoch ended)
+    bool draining = false;  // takes no new queries, so that it empties and its memory can go to a waiting pair
     // SSSP
     uint32_t *D = nullptr;
     BsWork bw{};
     uint32_t *lane_cnt = nullptr;
     // PPR
     BpWork pw{};
-    // result staging
-    uint32_t *stage = nullptr;
-    uint32_t *host_stage = nullptr;  // pinned, V words
-    uint32_t *host_cnt = nullptr;    // pinned: SSSP epoch x B activation counts; PPR seeds and ends
+    // result staging: a finished lane is copied into a free slot (device, then
+    // pinned host memory) on the pool's stream, and the completion thread
+    // hands it to the caller once the copy's event has fired, so no copy is
+    // waited for while the scheduler holds the lock
+    static constexpr int SLOTS = 4;
+    uint32_t *stage[SLOTS] = {};
+    uint32_t *host_stage[SLOTS] = {};  // pinned, V words each
+    hipEvent_t stage_ev[SLOTS] = {};
+    bool stage_busy[SLOTS] = {};
+    int pending = 0;                   // copies handed to the completion thread, not yet delivered
+    uint32_t *host_cnt = nullptr;      // pinned: SSSP epoch x B activation counts; PPR seeds and ends
     std::vector<int64_t> lane_q;     // query id per lane, -1 = free
     std::vector<int64_t> lane_age;   // supersteps since the lane joined
+    std::vector<int64_t> lane_done;  // finished, waiting for a staging slot: supersteps it took (-1 = running)
     std::vector<int32_t> seeds;      // PPR seed per lane (-1 = free)
     std::vector<uint32_t> ends;      // PPR: first superstep the lane no longer runs (mod 2^32)
     uint32_t k = 0;                  // supersteps run (buffer parity)
@@ -130,9 +141,17 @@ size_t pool_bytes(const gx_graph *g, int32_t algo, uint32_t B, uint32_t epoch_ma
         BpWork w;
         bp_layout(d, B, c, &w);
     }
-    c.take<uint32_t>(d.V);
+    for (int i = 0; i < Pool::SLOTS; i++) c.take<uint32_t>(d.V);
     return c.used;
 }
+
+struct Delivery {  // a result on its way to the caller
+    Pool *pool;
+    int slot;
+    gx_query_result r;
+    void *result;
+    int64_t V;
+};
 
 }  // namespace
 
@@ -145,12 +164,17 @@ struct gx_server {
     std::map<int64_t, SQuery> running;
     std::vector<gx_query_result> completed;
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
-    std::thread worker;
-    bool stop = false;
+    std::condition_variable cv_work, cv_done, cv_deliver;
+    std::thread worker, deliverer;
+    std::deque<Delivery> deliveries;
+    bool stop = false, stop_delivery = false;
     int64_t next_id = 1;
     std::string fatal;
     int grid = 0;
+    // the one pair that may carve a new pool while the arena has no room
+    // for it; pools chosen to make room for it drain meanwhile
+    bool reserved = false;
+    int32_t res_graph = -1, res_algo = -1;
 
     ~gx_server() {
         {
@@ -159,34 +183,68 @@ struct gx_server {
         }
         cv_work.notify_all();
         if (worker.joinable()) worker.join();
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            stop_delivery = true;
+        }
+        cv_deliver.notify_all();
+        if (deliverer.joinable()) deliverer.join();
         for (auto &p : pools) destroy_pool(*p, false);
+    }
+
+    // Completion thread: waits for each staged copy, copies it into the
+    // caller's buffer and publishes the result.
+    void deliver() {
+        (void)hipSetDevice(device);
+        std::unique_lock<std::mutex> lk(mu);
+        while (true) {
+            cv_deliver.wait(lk, [this] { return stop_delivery || !deliveries.empty(); });
+            if (deliveries.empty()) break;
+            Delivery dv = deliveries.front();
+            deliveries.pop_front();
+            lk.unlock();
+            hipError_t e = hipEventSynchronize(dv.pool->stage_ev[dv.slot]);
+            if (e == hipSuccess) std::memcpy(dv.result, dv.pool->host_stage[dv.slot], (size_t)dv.V * 4);
+            dv.r.done_s = now_s();
+            if (e != hipSuccess) dv.r.status = GX_EDEVICE;
+            lk.lock();
+            dv.pool->stage_busy[dv.slot] = false;
+            dv.pool->pending--;
+            completed.push_back(dv.r);
+            cv_done.notify_all();
+            cv_work.notify_all();
+        }
     }
 
     void destroy_pool(Pool &p, bool give_back) {
         if (p.stream) (void)hipStreamSynchronize(p.stream);
         if (p.done) (void)hipEventDestroy(p.done);
+        for (int i = 0; i < Pool::SLOTS; i++) {
+            if (p.stage_ev[i]) (void)hipEventDestroy(p.stage_ev[i]);
+            if (p.host_stage[i]) (void)hipHostFree(p.host_stage[i]);
+            p.stage_ev[i] = nullptr;
+            p.host_stage[i] = nullptr;
+        }
         if (p.stream) (void)hipStreamDestroy(p.stream);
-        if (p.host_stage) (void)hipHostFree(p.host_stage);
         if (p.host_cnt) (void)hipHostFree(p.host_cnt);
         if (give_back && p.mem) arena.release(p.mem, p.bytes);
         p.stream = nullptr;
         p.done = nullptr;
-        p.host_stage = p.host_cnt = nullptr;
+        p.host_cnt = nullptr;
         p.mem = nullptr;
     }
 
-    uint32_t epoch_max() const { return cfg.epoch_supersteps; }
+    uint32_t epoch_max(int32_t algo) const { return algo == GX_SSSP ? cfg.sssp_epoch_supersteps : cfg.epoch_supersteps; }
 
     // Creates a pool for (graph, algo) inside the budget; nullptr if it does not fit.
-    Pool *create_pool(int32_t graph, int32_t algo) {
+    Pool *create_pool(int32_t graph, int32_t algo, uint32_t B) {
         gx_graph *g = graphs[graph];
-        const uint32_t B = cfg.lanes_per_pool;
-        size_t bytes = pool_bytes(g, algo, B, epoch_max());
+        size_t bytes = pool_bytes(g, algo, B, epoch_max(algo));
         void *mem = arena.alloc(bytes);
         if (!mem) {  // evict idle empty pools, then retry
             for (size_t i = 0; i < pools.size();) {
                 Pool &p = *pools[i];
-                if (!p.in_flight && p.occupied() == 0) {
+                if (!p.in_flight && p.occupied() == 0 && p.pending == 0) {
                     destroy_pool(p, true);
                     pools.erase(pools.begin() + i);
                 } else {
@@ -203,26 +261,30 @@ struct gx_server {
         p->B = B;
         p->mem = mem;
         p->bytes = bytes;
+        p->t_ready = now_s();
         p->lane_q.assign(B, -1);
         p->lane_age.assign(B, 0);
+        p->lane_done.assign(B, -1);
         p->seeds.assign(B, -1);
         p->ends.assign(B, 0u);
         const DevGraph &d = g->d;
         Carver c(mem, bytes);
         bool ok = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) == hipSuccess &&
                   hipEventCreateWithFlags(&p->done, hipEventDisableTiming) == hipSuccess &&
-                  hipHostMalloc((void **)&p->host_stage, std::max<size_t>(4, d.V * 4), hipHostMallocDefault) ==
-                      hipSuccess &&
-                  hipHostMalloc((void **)&p->host_cnt, std::max<size_t>((size_t)epoch_max(), 2) * B * 4,
+                  hipHostMalloc((void **)&p->host_cnt, std::max<size_t>((size_t)epoch_max(algo), 2) * B * 4,
                                 hipHostMallocDefault) == hipSuccess;
+        for (int i = 0; i < Pool::SLOTS && ok; i++)
+            ok = hipEventCreateWithFlags(&p->stage_ev[i], hipEventDisableTiming) == hipSuccess &&
+                 hipHostMalloc((void **)&p->host_stage[i], std::max<size_t>(4, d.V * 4), hipHostMallocDefault) ==
+                     hipSuccess;
         if (algo == GX_SSSP) {
             p->D = c.take<uint32_t>((size_t)d.V * B);
             bs_layout(d, B, c, &p->bw);
-            p->lane_cnt = c.take<uint32_t>((size_t)epoch_max() * B);
+            p->lane_cnt = c.take<uint32_t>((size_t)epoch_max(algo) * B);
         } else {
             bp_layout(d, B, c, &p->pw);
         }
-        p->stage = c.take<uint32_t>(d.V);
+        for (int i = 0; i < Pool::SLOTS; i++) p->stage[i] = c.take<uint32_t>(d.V);
         if (ok) {
             hipStream_t s = p->stream;
             if (algo == GX_SSSP) {
@@ -326,35 +388,70 @@ struct gx_server {
         return true;
     }
 
-    void retire(Pool &p, uint32_t lane, int64_t steps) {
+    // A finished lane's column goes to a free staging slot on the pool's
+    // stream (later work on the stream is ordered after the copy, so the lane
+    // is free at once); without a free slot the lane waits, finished, for the
+    // next pass of the scheduler (it changes no more: an SSSP lane that
+    // activated nothing stays idle, a PPR lane past its end is frozen).
+    bool retire(Pool &p, uint32_t lane, int64_t steps) {
         const DevGraph &d = p.g->d;
         auto it = running.find(p.lane_q[lane]);
-        if (it == running.end()) return;
+        if (it == running.end()) return true;
+        int slot = -1;
+        for (int i = 0; i < Pool::SLOTS; i++)
+            if (!p.stage_busy[i]) {
+                slot = i;
+                break;
+            }
+        if (slot < 0) {
+            p.lane_done[lane] = steps;
+            return false;
+        }
         SQuery &q = it->second;
         // a PPR lane froze after its last superstep: its values are in x[end & 1]
         const uint32_t *tile =
             p.algo == GX_SSSP ? p.D : reinterpret_cast<const uint32_t *>(p.pw.x[p.ends[lane] & 1]);
-        hipError_t e = lane_extract(tile, d.V, p.B, lane, p.stage, p.stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(p.host_stage, p.stage, d.V * 4, hipMemcpyDeviceToHost, p.stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
-        if (e == hipSuccess) std::memcpy(q.result, p.host_stage, d.V * 4);
+        hipError_t e = lane_extract(tile, d.V, p.B, lane, p.stage[slot], p.stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(p.host_stage[slot], p.stage[slot], d.V * 4, hipMemcpyDeviceToHost, p.stream);
+        if (e == hipSuccess) e = hipEventRecord(p.stage_ev[slot], p.stream);
         q.status = e == hipSuccess ? GX_OK : GX_EDEVICE;
         q.steps = steps;
-        q.t_done = now_s();
-        gx_query_result r{q.id, q.graph, q.algo, q.source, q.status, q.t_submit, q.t_start, q.t_done, q.steps};
-        completed.push_back(r);
+        Delivery dv{&p, slot, {q.id, q.graph, q.algo, q.source, q.status, q.t_submit, q.t_start, 0.0, q.steps},
+                    q.result, d.V};
+        if (e != hipSuccess) {  // nothing in flight for this slot: publish the failure now
+            dv.r.done_s = now_s();
+            completed.push_back(dv.r);
+            cv_done.notify_all();
+        } else {
+            p.stage_busy[slot] = true;
+            p.pending++;
+            deliveries.push_back(dv);
+            cv_deliver.notify_all();
+        }
         running.erase(it);
         p.lane_q[lane] = -1;
         p.seeds[lane] = -1;
-        cv_done.notify_all();
+        p.lane_done[lane] = -1;
+        return true;
+    }
+
+    void retire_waiting() {
+        for (auto &pp : pools) {
+            Pool &p = *pp;
+            if (p.in_flight) continue;
+            for (uint32_t b = 0; b < p.B; b++)
+                if (p.lane_q[b] >= 0 && p.lane_done[b] >= 0 && !retire(p, b, p.lane_done[b])) break;
+        }
     }
 
     void finish_epoch(Pool &p) {
         p.in_flight = false;
+        p.t_ready = now_s();
         const uint32_t B = p.B;
         if (p.algo == GX_SSSP) {
             for (uint32_t b = 0; b < B; b++) {
-                if (p.lane_q[b] < 0) continue;
+                if (p.lane_q[b] < 0 || p.lane_done[b] >= 0) continue;
                 int64_t conv = -1;
                 for (uint32_t it = 0; it < p.epoch_len; it++)
                     if (p.host_cnt[(size_t)it * B + b] == 0) {
@@ -369,7 +466,7 @@ struct gx_server {
             }
         } else {
             for (uint32_t b = 0; b < B; b++) {
-                if (p.lane_q[b] < 0) continue;
+                if (p.lane_q[b] < 0 || p.lane_done[b] >= 0) continue;
                 p.lane_age[b] += p.epoch_len;
                 if ((int32_t)(p.ends[b] - p.k) <= 0) retire(p, b, (int64_t)cfg.ppr_iters);
             }
@@ -378,7 +475,7 @@ struct gx_server {
 
     bool launch_epoch(Pool &p) {
         if (p.algo == GX_SSSP) {
-            p.epoch_len = epoch_max();
+            p.epoch_len = epoch_max(GX_SSSP);
             if (hipMemsetAsync(p.lane_cnt, 0, (size_t)p.epoch_len * p.B * 4, p.stream) != hipSuccess) return false;
             BsArgs a = bs_args(p);
             for (uint32_t it = 0; it < p.epoch_len; it++)
@@ -392,7 +489,7 @@ struct gx_server {
             int64_t left = 1;
             for (uint32_t b = 0; b < p.B; b++)
                 if (p.lane_q[b] >= 0) left = std::max<int64_t>(left, (int32_t)(p.ends[b] - p.k));
-            p.epoch_len = (uint32_t)std::min<int64_t>(left, epoch_max());
+            p.epoch_len = (uint32_t)std::min<int64_t>(left, epoch_max(GX_PPR));
             int32_t *lt = reinterpret_cast<int32_t *>(p.host_cnt);  // idle pool: the last epoch's copies are done
             for (uint32_t b = 0; b < p.B; b++) {
                 lt[b] = p.lane_q[b] >= 0 ? p.seeds[b] : -1;
@@ -415,19 +512,89 @@ struct gx_server {
         return true;
     }
 
-    // Admission in arrival order: a query takes a free lane of an idle pool of
-    // its (graph, algorithm); it waits while such a pool is mid-epoch and has
-    // a free lane (lanes join at superstep boundaries); otherwise a new pool
-    // is created if the budget allows, else it waits.
+    // Lanes for a new pool of a pair: enough for the pair's waiting queries,
+    // in multiples of 32, at most lanes_per_pool (a pair with steady demand
+    // adds pools; one with little demand holds little memory).
+    uint32_t pool_lanes(int32_t graph, int32_t algo) const {
+        uint32_t n = 0;
+        for (auto &q : queue) n += q.graph == graph && q.algo == algo;
+        return std::min<uint32_t>(cfg.lanes_per_pool, std::max<uint32_t>(32, (n + 31) / 32 * 32));
+    }
+
+    // Picks the contiguous stretch of the arena, made of free ranges and
+    // pools, that can hold `need` bytes at the least cost (lanes running
+    // plus queries waiting for the pools it covers) and drains its pools.
+    void plan_room(size_t need) {
+        struct Seg {
+            size_t off, len;
+            int64_t cost;
+            Pool *pool;
+        };
+        std::vector<Seg> seg;
+        for (auto &f : arena.free_) seg.push_back({f.first, f.second, 0, nullptr});
+        for (auto &pp : pools) {
+            Pool &p = *pp;
+            int64_t cost = 0;
+            if (!p.draining) {
+                cost = p.occupied();
+                for (auto &q : queue) cost += q.graph == p.graph && q.algo == p.algo;
+            }
+            seg.push_back({(size_t)(static_cast<char *>(p.mem) - arena.base), align_up(p.bytes), cost, &p});
+        }
+        std::sort(seg.begin(), seg.end(), [](const Seg &x, const Seg &y) { return x.off < y.off; });
+        size_t best_i = 0, best_j = 0;
+        int64_t best_cost = -1;
+        for (size_t i = 0; i < seg.size(); i++) {
+            size_t len = 0;
+            int64_t cost = 0;
+            for (size_t j = i; j < seg.size(); j++) {
+                if (j > i && seg[j].off != seg[j - 1].off + seg[j - 1].len) break;  // not contiguous
+                len += seg[j].len;
+                cost += seg[j].cost;
+                if (len >= need) {
+                    if (best_cost < 0 || cost < best_cost) {
+                        best_cost = cost;
+                        best_i = i;
+                        best_j = j;
+                    }
+                    break;
+                }
+            }
+        }
+        if (best_cost < 0) return;
+        for (size_t j = best_i; j <= best_j; j++)
+            if (seg[j].pool) seg[j].pool->draining = true;
+    }
+
+    // Admission in arrival order.  A query joins a pool of its (graph,
+    // algorithm) that has a free lane, at an epoch boundary (it waits while
+    // that pool is mid-epoch).  A pair with no pool gets a new one carved from
+    // the arena after evicting pools that are idle and empty.  When even that
+    // leaves no room, the pair takes the reservation: the cheapest stretch of
+    // the arena that would hold its pool is drained (its pools admit nothing
+    // more, finish what they run and are then evicted) and no other pair may
+    // carve a pool until the reserving pair has its own, so that steady
+    // traffic to the resident pairs or small pools filling the holes cannot
+    // starve a pair.
     void admit_queued() {
+        for (size_t i = 0; i < pools.size();) {  // drained pools leave at once
+            Pool &p = *pools[i];
+            if (p.draining && !p.in_flight && p.occupied() == 0 && p.pending == 0) {
+                destroy_pool(p, true);
+                pools.erase(pools.begin() + i);
+            } else {
+                i++;
+            }
+        }
         for (size_t i = 0; i < queue.size();) {
             SQuery &q = queue[i];
             Pool *target = nullptr;
             uint32_t lane = 0;
-            bool wait_boundary = false;
+            bool live_pool = false, wait_boundary = false;
             for (auto &pp : pools) {
                 Pool &p = *pp;
-                if (p.graph != q.graph || p.algo != q.algo) continue;
+                if (p.graph != q.graph || p.algo != q.algo || p.draining) continue;
+                live_pool = true;
                 int free_lane = -1;
                 for (uint32_t b = 0; b < p.B; b++)
                     if (p.lane_q[b] < 0) {
@@ -443,7 +610,23 @@ struct gx_server {
                 lane = (uint32_t)free_lane;
                 break;
             }
-            if (!target && !wait_boundary) target = create_pool(q.graph, q.algo);
+            bool draining_pool = false;
+            for (auto &pp : pools) draining_pool |= pp->graph == q.graph && pp->algo == q.algo && pp->draining;
+            const bool mine = reserved && res_graph == q.graph && res_algo == q.algo;
+            // a pair whose pools all drain waits for their eviction; while another
+            // pair holds the reservation only pools that already exist take queries
+            if (!target && !wait_boundary && (live_pool || !draining_pool || mine) && (!reserved || mine)) {
+                const uint32_t B = pool_lanes(q.graph, q.algo);
+                target = create_pool(q.graph, q.algo, B);
+                if (!target && B > 32) target = create_pool(q.graph, q.algo, 32);
+                if (target && mine) reserved = false;
+                if (!target && !live_pool && !reserved) {
+                    reserved = true;
+                    res_graph = q.graph;
+                    res_algo = q.algo;
+                    plan_room(align_up(pool_bytes(graphs[q.graph], q.algo, 32, epoch_max(q.algo))));
+                }
+            }
             if (target && admit(*target, q, lane)) {
                 queue.erase(queue.begin() + i);
                 continue;
@@ -463,15 +646,21 @@ struct gx_server {
                 Pool &p = *pp;
                 if (p.in_flight && hipEventQuery(p.done) == hipSuccess) finish_epoch(p);
             }
+            retire_waiting();
             admit_queued();
+            // idle pools launch in the order they became idle, so that with
+            // more pools than running slots none waits behind the others twice
             int flying = 0;
-            for (auto &pp : pools) flying += pp->in_flight;
+            std::vector<Pool *> ready;
             for (auto &pp : pools) {
-                Pool &p = *pp;
-                if (!p.in_flight && p.occupied() > 0 && flying < (int)cfg.max_pools) {
-                    if (launch_epoch(p)) flying++;
-                    else fatal = "epoch launch failed";
-                }
+                flying += pp->in_flight;
+                if (!pp->in_flight && pp->occupied() > 0) ready.push_back(pp.get());
+            }
+            std::sort(ready.begin(), ready.end(), [](const Pool *x, const Pool *y) { return x->t_ready < y->t_ready; });
+            for (Pool *p : ready) {
+                if (flying >= (int)cfg.max_pools) break;
+                if (launch_epoch(*p)) flying++;
+                else fatal = "epoch launch failed";
             }
             for (auto &pp : pools) any_flight |= pp->in_flight;
             if (stop && !any_flight) break;
@@ -502,11 +691,13 @@ extern "C" gx_status gx_server_create(const gx_server_config *cfg, gx_server **o
     if (c.lanes_per_pool == 0) c.lanes_per_pool = 64;
     if (c.max_pools == 0) c.max_pools = 4;
     if (c.epoch_supersteps == 0) c.epoch_supersteps = 4;
+    if (c.sssp_epoch_supersteps == 0) c.sssp_epoch_supersteps = 16;
     if (c.damping == 0.f) c.damping = 0.85f;
     if (c.ppr_iters == 0) c.ppr_iters = 50;
     GX_REQUIRE(c.lanes_per_pool % 32 == 0 && c.lanes_per_pool <= 256, GX_EINVAL,
                "lanes_per_pool must be a multiple of 32 up to 256");
-    GX_REQUIRE(c.epoch_supersteps <= 64, GX_EINVAL, "epoch_supersteps must be <= 64");
+    GX_REQUIRE(c.epoch_supersteps <= 64 && c.sssp_epoch_supersteps <= 64, GX_EINVAL,
+               "epoch_supersteps and sssp_epoch_supersteps must be <= 64");
     GX_REQUIRE(c.damping > 0.f && c.damping < 1.f, GX_EINVAL, "damping out of (0,1)");
     gx_server *s = new (std::nothrow) gx_server();
     GX_REQUIRE(s, GX_ENOMEM, "host allocation failed");
@@ -517,6 +708,7 @@ extern "C" gx_status gx_server_create(const gx_server_config *cfg, gx_server **o
     s->device = dev;
     s->grid = device_cus(dev) * 2;
     s->worker = std::thread([s] { s->run(); });
+    s->deliverer = std::thread([s] { s->deliver(); });
     *out = s;
     return GX_OK;
 }
@@ -541,8 +733,9 @@ extern "C" gx_status gx_server_submit(gx_server *s, int32_t graph_id, int32_t al
     GX_REQUIRE(graph_id >= 0 && graph_id < (int32_t)s->graphs.size(), GX_ENOTFOUND, "unknown graph %d", graph_id);
     gx_graph *g = s->graphs[graph_id];
     GX_REQUIRE(source >= 0 && source < g->d.V, GX_EINVAL, "source %d out of [0,V)", source);
-    const size_t need = pool_bytes(g, algo, s->cfg.lanes_per_pool, s->cfg.epoch_supersteps);
-    GX_REQUIRE(need <= s->arena.cap, GX_ENOMEM, "one lane pool needs %zu bytes, the budget is %zu", need,
+    const size_t need = align_up(pool_bytes(g, algo, 32, algo == GX_SSSP ? s->cfg.sssp_epoch_supersteps
+                                                                        : s->cfg.epoch_supersteps));
+    GX_REQUIRE(need <= s->arena.cap, GX_ENOMEM, "a 32-lane pool needs %zu bytes, the budget is %zu", need,
                s->arena.cap);
     GX_REQUIRE(s->fatal.empty(), GX_EDEVICE, "server failed: %s", s->fatal.c_str());
     SQuery q;
@@ -576,7 +769,7 @@ extern "C" gx_status gx_server_pending(gx_server *s, int64_t *n) {
     clear_error();
     GX_REQUIRE(s && n, GX_EINVAL, "NULL argument");
     std::lock_guard<std::mutex> lk(s->mu);
-    *n = (int64_t)(s->queue.size() + s->running.size());
+    *n = (int64_t)(s->queue.size() + s->running.size() + s->deliveries.size());
     return GX_OK;
 }
 

@@ -116,6 +116,31 @@ def test_serving_small_budget_queues(gx, graphs):
         check(gx, [g], q, done[i])
 
 
+def test_serving_tight_budget_serves_every_pair(gx, graphs):
+    """Six (graph, algorithm) pairs under a budget of about two 32-lane pools
+    of the largest kind, with steady traffic to one pair: every other pair
+    still gets a pool in turn (resident pools are drained to make room), and
+    every result matches the oracle."""
+    import ctypes
+    dgs = [gx.DeviceGraph(g, gx.GX_NEED_OUT | gx.GX_NEED_IN) for g in graphs]
+    per_lane = 0
+    for d in dgs:
+        for algo in (gx.GX_SSSP, gx.GX_PPR):
+            b = ctypes.c_size_t()
+            gx.binding.lib.gx_server_bytes_per_lane(d.handle, algo, ctypes.byref(b))
+            per_lane = max(per_lane, b.value)
+    rng = np.random.default_rng(21)
+    queries = []
+    for i in range(72):
+        gi, algo = (2, gx.GX_PPR) if i % 2 == 0 else (int(rng.integers(0, 3)), (gx.GX_SSSP, gx.GX_PPR)[i % 4 // 2])
+        cand = np.nonzero(np.diff(graphs[gi].row_ptr) > 0)[0]
+        queries.append((gi, algo, int(rng.choice(cand))))
+    done = serve(gx, graphs, queries, budget=int(per_lane * 64 * 1.1), lanes=64, epoch=2, stagger_s=0.001,
+                 dgs=dgs)
+    for i, q in enumerate(queries):
+        check(gx, graphs, q, done[i])
+
+
 def test_serving_rejects_budget_below_one_pool(gx, graphs):
     dg = gx.DeviceGraph(graphs[2], gx.GX_NEED_OUT | gx.GX_NEED_IN)
     srv = gx.Server(1 << 16, lanes_per_pool=32)
