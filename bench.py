@@ -258,7 +258,7 @@ def bench_batched_ppr(gx, torch, g, dg, src, iters=50, reps=3):
     return out
 
 
-def bench_serving(gx, torch, np, gen, n_queries=10000, qps_frac=0.7, lanes=64, max_pools=32, budget_frac=0.5,
+def bench_serving(gx, torch, np, gen, n_queries=10000, qps_frac=0.7, lanes=64, max_pools=4, budget_frac=0.5,
                   sample=16, outstanding=512, records=None):
     """16 resident R-MAT graphs (scales 16..22, seeds 100..115), 50% SSSP /
     50% PPR (50 iterations), Poisson arrivals (seed 5) at a fixed rate of

@@ -648,15 +648,22 @@ struct gx_server {
             }
             retire_waiting();
             admit_queued();
-            // idle pools launch in the order they became idle, so that with
-            // more pools than running slots none waits behind the others twice
+            // Idle pools launch SSSP first, then in the order they became idle.
+            // An SSSP epoch is a few cheap supersteps, a PPR epoch whole-graph
+            // pulls, and epochs that share a hardware queue run in order: with
+            // few running slots (max_pools near the hardware queue count) the
+            // order chosen here is the order the GPU runs them in, so short
+            // queries pass long ones instead of queueing behind them.
             int flying = 0;
             std::vector<Pool *> ready;
             for (auto &pp : pools) {
                 flying += pp->in_flight;
                 if (!pp->in_flight && pp->occupied() > 0) ready.push_back(pp.get());
             }
-            std::sort(ready.begin(), ready.end(), [](const Pool *x, const Pool *y) { return x->t_ready < y->t_ready; });
+            std::sort(ready.begin(), ready.end(), [](const Pool *x, const Pool *y) {
+                if ((x->algo == GX_SSSP) != (y->algo == GX_SSSP)) return x->algo == GX_SSSP;
+                return x->t_ready < y->t_ready;
+            });
             for (Pool *p : ready) {
                 if (flying >= (int)cfg.max_pools) break;
                 if (launch_epoch(*p)) flying++;
