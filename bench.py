@@ -855,15 +855,20 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sssp_rmat22_relaxation_traffic.js
 KERNEL_SOURCES = os.path.join(ROOT, "paper_2203_13005_amd", "csrc")
 
 
+# The sources the relaxation kernels, their launches and the graph layout
+# they read come from (the batched, serving, label-propagation, streaming
+# and CPU-daemon files hold none of them).
+RELAXATION_SOURCES = ("gx_device.h", "gx_graph.hip", "gx_internal.h", "gx_plain.hip")
+
+
 def kernel_source_hash():
-    """Hash of the device library's sources (kernels, layouts, launch code):
-    a traffic record taken on other sources is not reported."""
-    import glob
+    """Hash of the sources behind the relaxation kernels (kernels, layouts,
+    launch code): a traffic record taken on other sources is not reported."""
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(KERNEL_SOURCES, "*.hip")) + glob.glob(os.path.join(KERNEL_SOURCES, "*.h"))):
-        h.update(os.path.basename(f).encode())
-        h.update(open(f, "rb").read())
+    for name in RELAXATION_SOURCES:
+        h.update(name.encode())
+        h.update(open(os.path.join(KERNEL_SOURCES, name), "rb").read())
     return h.hexdigest()[:16]
 
 
