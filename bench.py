@@ -839,6 +839,26 @@ def bench_partition(gx, torch, np, gen, reps=3):
     t_cc = (time.perf_counter() - t0) / reps
     log(f"partition CC: solve {t_solve / reps * 1e3:.2f} ms (kernels {sum(d['kernel_ms'] for d in steps):.2f} ms), "
         f"sync set {t_sync / reps * 1e3:.2f} ms; PageRank {t_pr * 1e3:.2f} ms")
+    # The sync set taken after every superstep (lazy upload of the changed
+    # vertices other parts need, and the skip decision), untimed.
+    gbuf = torch.empty(p.V, dtype=torch.int32, device="cuda:0")
+    vbuf = torch.empty_like(gbuf)
+
+    def per_step_deltas(state, max_steps, until_idle):
+        out = []
+        state.reset()
+        for _ in range(max_steps):
+            _, _, changed = state.superstep(stats=True)
+            g_, _, skip = state.sync_delta(on_device=True, out=(gbuf, vbuf))
+            out.append((int(g_.numel()), bool(skip)))
+            if until_idle and changed == 0:
+                break
+        return out
+
+    cc_d = per_step_deltas(cc, 100_000, True)
+    pr_d = per_step_deltas(st, 30, False)
+    log(f"partition sync sets per superstep: CC {[n for n, _ in cc_d]} ({sum(k for _, k in cc_d)} skipped); "
+        f"PageRank {pr_d[0][0]}..{pr_d[-1][0]} ({sum(k for _, k in pr_d)} skipped)")
     return {"workload": f"part 0 of an 8-way hash vertex-cut of R-MAT scale 25 (seed 3): V_p={p.V}, E_p={p.E}; "
                         "PageRank 30 supersteps + min-label CC to convergence + final sync set",
             "pagerank_ms": t_pr * 1e3, "pagerank_gteps": 30 * p.E / t_pr / 1e9,
@@ -847,6 +867,11 @@ def bench_partition(gx, torch, np, gen, reps=3):
             "cc_supersteps": int(rs_cc.supersteps), "cc_gteps": cc_edges / reps / t_cc / 1e9,
             "cc_kernel_ms": sum(d["kernel_ms"] for d in steps),
             "sync_set_final": int(gids.numel()),
+            "sync_set_per_superstep": {"cc": [n for n, _ in cc_d], "cc_skipped": sum(k for _, k in cc_d),
+                                       "pagerank": [n for n, _ in pr_d],
+                                       "pagerank_skipped": sum(k for _, k in pr_d),
+                                       "what": "changed vertices another part needs, emitted after every "
+                                               "superstep (lazy upload); skipped = empty sets"},
             "cc_per_superstep": [dict(edges=d["edges"], pulled=d["pulled"], us=round(d["kernel_ms"] * 1e3, 1))
                                  for d in steps]}, p
 
@@ -991,6 +1016,23 @@ def bench_sssp(args, gx, torch, np, gen):
     assert np.array_equal(state.values_numpy(), dist_ref)
     log(f"{dt * 1e3 / args.steps:.3f} ms/solve, relaxation kernel {kern_ms / args.steps:.3f} ms/solve "
         f"over {launches / args.steps:.1f} launches")
+    # The timed solves repeat one source; one solve from each of 16 other
+    # sources (seeded, out-degree > 0, no sync set) shows the spread.
+    src_ms, src_msgs, src_steps = [], 0, []
+    for s_ in (gen.pick_sources(g, args.other_sources, seed=21) if args.other_sources > 0 else []):
+        stx = gx.State(dg, gx.GX_SSSP, source=int(s_), pull_fraction=args.pull_fraction)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rsx, _ = stx.run(100_000)
+        torch.cuda.synchronize()
+        src_ms.append((time.perf_counter() - t1) * 1e3)
+        src_msgs += rsx.edges
+        src_steps.append(int(rsx.supersteps))
+        stx.close()
+    if src_ms:
+        log(f"{len(src_ms)} other sources: {np.mean(src_ms):.3f} ms/solve on average ({min(src_ms):.3f}-"
+            f"{max(src_ms):.3f}), {src_msgs / (sum(src_ms) / 1e3) / 1e9:.1f} GTEPS, "
+            f"{min(src_steps)}-{max(src_steps)} supersteps")
 
     achieved = bytes_per_solve * args.steps / (kern_ms / 1e3) / 1e9
     bytes_upper = sum(p["bytes_upper"] for p in per_step)
@@ -1008,6 +1050,12 @@ def bench_sssp(args, gx, torch, np, gen):
             "V": g.V, "E": g.E, "supersteps": K, "messages_per_solve": edges_per_solve,
             "parallelism": "single GPU",
         },
+        "other_sources": None if not src_ms else {
+            "what": f"one solve from each of {len(src_ms)} seeded sources with out-degree > 0 (seed 21), "
+                    "no sync set; the timed solves above repeat source 0",
+            "ms_per_solve_mean": float(np.mean(src_ms)), "ms_per_solve_min": min(src_ms),
+            "ms_per_solve_max": max(src_ms), "gteps": src_msgs / (sum(src_ms) / 1e3) / 1e9,
+            "supersteps": src_steps},
         "load": {"what": "gx_graph_load: host validation and packaging (out-CSR, in-edge records), "
                          "16 MiB blocks through three rotating pinned buffers on a copy stream",
                  "seconds": load_s, "device_bytes": load_bytes, "GBps": load_bytes / load_s / 1e9},
@@ -1048,6 +1096,8 @@ def main():
     ap.add_argument("--pull-fraction", type=float, default=0.0,
                     help="SSSP switch point to the pull form (0 = library default, >= 1 = push only)")
     ap.add_argument("--serving-queries", type=int, default=10000)
+    ap.add_argument("--other-sources", type=int, default=16,
+                    help="after the timed solves, one solve from each of this many other sources (0 = none)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the traffic record from two rocprofv3 --pmc output folders and exit")
     ap.add_argument("--pmc-solves", type=int, default=0,

@@ -91,6 +91,10 @@ __device__ __forceinline__ void block_max_scan(int32_t *s, int n, int32_t *lds) 
 }
 
 
+// The XCD (accelerator complex die) the calling wave runs on: bits 3:0 of
+// the XCC_ID hardware register.
+__device__ __forceinline__ uint32_t xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | 20) & 15u; }
+
 // Grid-wide barrier for a cooperative launch (all workgroups co-resident).
 // Sense is a generation counter.  The wait is bounded in time: a workgroup
 // that has waited `limit_ticks` of the constant-rate wall clock

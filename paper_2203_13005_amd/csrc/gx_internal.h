@@ -184,7 +184,8 @@ struct DevStep {
     unsigned long long list;      // (entries << 32) | edges, via one 64-bit add per workgroup
     unsigned long long changed;   // PageRank changed values
     unsigned long long pad;       // 1 when the superstep pulled
-    unsigned long long spare0[13];
+    unsigned long long faults;    // bit 0: a pull or fix-up workgroup ran on another XCD than its slice's
+    unsigned long long spare0[12];
     unsigned long long frontier;  // |F_k|
     unsigned long long spare1[15];
 };
@@ -211,6 +212,7 @@ struct gx_state {
     int64_t k = 0;
     bool dev_error = false;
     int relax_grid = 0;   // persistent grid of the relaxation kernel
+    uint32_t xcd_shift = 0;  // added to the XCD a workgroup is expected on (non-zero only to exercise the check)
     uint2 *fix = nullptr;         // fix-up regions, fix_cap entries per relaxation workgroup
     uint32_t *fixn = nullptr;     // entries recorded per workgroup
     uint32_t fix_cap = 0;

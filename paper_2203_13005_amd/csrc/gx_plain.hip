@@ -47,6 +47,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <mutex>
 
 #include "gx_device.h"
@@ -470,26 +471,35 @@ __global__ __launch_bounds__(256) void k_relax(const uint4 *__restrict__ list, c
                                                const uint32_t *__restrict__ snap, uint32_t *__restrict__ val,
                                                const uint8_t *__restrict__ front_cur, uint8_t *__restrict__ front_next,
                                                DevStep *__restrict__ step, uint32_t pull_edges,
-                                               uint2 *__restrict__ fix, uint32_t *__restrict__ fixn, uint32_t fix_cap) {
+                                               uint2 *__restrict__ fix, uint32_t *__restrict__ fixn, uint32_t fix_cap,
+                                               uint32_t xcd_shift) {
     __shared__ RelaxLds lds;
     __shared__ uint32_t s_fixn;
     if (threadIdx.x == 0) s_fixn = 0;
     __syncthreads();
     const FixRegion fr{fix + (size_t)blockIdx.x * fix_cap, fix_cap, &s_fixn};
     const unsigned long long le = step->list;
-    if ((uint32_t)le >= pull_edges)
+    if ((uint32_t)le >= pull_edges) {
+        // the pull's plain stores are correct only while workgroup b runs on
+        // XCD b mod 8 (the one that owns slice b mod 8); a workgroup that finds
+        // itself elsewhere reports it, and the host fails the run
+        if (threadIdx.x == 0 && xcc_id() != (blockIdx.x + xcd_shift) % PULL_SLICES) atomicOr(&step->faults, 1ull);
         pull_body<WEIGHTED>(pa.rec, pa.units, pa.sl, V, snap, front_cur, val, front_next, step, lds.pull_snap, fr);
-    else
+    } else {
         push_body<WEIGHTED>(list, tile_start, adj, val, front_next, le, lds.push);
+    }
     __syncthreads();
     if (threadIdx.x == 0) fixn[blockIdx.x] = min(s_fixn, fix_cap);
 }
 
 // The relaxation's fix-up: workgroup b re-applies the recorded candidates of
-// relaxation workgroup b that are still below the stored value.
+// relaxation workgroup b that are still below the stored value (it reads
+// them through the L2 of XCD b mod 8, where they were stored).
 __global__ __launch_bounds__(256) void k_fixup(const uint2 *__restrict__ fix, const uint32_t *__restrict__ fixn,
-                                               uint32_t fix_cap, uint32_t *__restrict__ val) {
+                                               uint32_t fix_cap, uint32_t *__restrict__ val, DevStep *__restrict__ step,
+                                               uint32_t xcd_shift) {
     const uint32_t n = fixn[blockIdx.x];
+    if (n > 0 && threadIdx.x == 0 && xcc_id() != (blockIdx.x + xcd_shift) % PULL_SLICES) atomicOr(&step->faults, 1ull);
     const uint2 *e = fix + (size_t)blockIdx.x * fix_cap;
     for (uint32_t i = threadIdx.x; i < n; i += 256) {
         const uint2 q = e[i];
@@ -1295,6 +1305,9 @@ extern "C" gx_status gx_state_init(gx_graph *g, const gx_params *p, void *dev_st
     GX_REQUIRE(s, GX_ENOMEM, "host allocation failed");
     s->g = g;
     s->p = *p;
+    // GX_XCD_CHECK_SHIFT (tests only) shifts the XCD the pull's workgroups are
+    // expected on, so that the placement check fires without a real fault
+    if (const char *e = std::getenv("GX_XCD_CHECK_SHIFT")) s->xcd_shift = (uint32_t)std::strtoul(e, nullptr, 10);
     Carver c(dev_state, bytes);
     state_layout(g, p, c, s);
     if (p->algo == GX_SSSP || p->algo == GX_CC) {
@@ -1511,14 +1524,15 @@ static gx_status enqueue_superstep(gx_state *s, hipStream_t hs) {
                 const PullArgs pa{d.pull_w, d.pull_w_units, d.pull_w_off};
                 hipLaunchKernelGGL(k_relax<true>, dim3(s->relax_grid), dim3(256), 0, hs, s->list, s->tile_start,
                                    (const void *)d.out_adj, pa, d.V, s->snap, s->val, s->front8[cur], s->front8[cur ^ 1],
-                                   step, s->pull_edges, s->fix, s->fixn, s->fix_cap);
+                                   step, s->pull_edges, s->fix, s->fixn, s->fix_cap, s->xcd_shift);
             } else {
                 const PullArgs pa{d.pull_sym, d.pull_sym_units, d.pull_sym_off};
                 hipLaunchKernelGGL(k_relax<false>, dim3(s->relax_grid), dim3(256), 0, hs, s->list, s->tile_start,
                                    (const void *)d.sym_col, pa, d.V, s->snap, s->val, s->front8[cur], s->front8[cur ^ 1],
-                                   step, s->pull_edges, s->fix, s->fixn, s->fix_cap);
+                                   step, s->pull_edges, s->fix, s->fixn, s->fix_cap, s->xcd_shift);
             }
-            hipLaunchKernelGGL(k_fixup, dim3(s->relax_grid), dim3(256), 0, hs, s->fix, s->fixn, s->fix_cap, s->val);
+            hipLaunchKernelGGL(k_fixup, dim3(s->relax_grid), dim3(256), 0, hs, s->fix, s->fixn, s->fix_cap, s->val,
+                               step, s->xcd_shift);
             if (e1) (void)hipEventRecord(e1, hs);
             hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(d.V, CBLOCK * CVT)), dim3(CBLOCK), 0, hs,
                                s->front8[cur ^ 1], s->front8[cur], rp, s->val, s->snap, d.V, s->list, s->tile_start,
@@ -1620,6 +1634,15 @@ static gx_status read_steps(gx_state *s, int64_t kfirst, uint32_t n, hipStream_t
         std::memcpy(out.data() + done, s->host_steps, chunk * sizeof(DevStep));
         done += chunk;
     }
+    for (uint32_t i = 0; i < n; i++)
+        if (out[i].faults & 1ull) {
+            s->dev_error = true;
+            set_error("superstep %lld pulled with a workgroup on another XCD than the slice it owns (the pull's "
+                      "plain stores need workgroup b on XCD b mod 8); the values may be wrong; run with "
+                      "pull_fraction >= 1 (push only) on this device",
+                      (long long)(kfirst + i));
+            return GX_EDEVICE;
+        }
     return GX_OK;
 }
 
@@ -1939,14 +1962,15 @@ extern "C" gx_status gx_msg_merge(gx_state *s, void *stream) {
                 const PullArgs pa{d.pull_w, d.pull_w_units, d.pull_w_off};
                 hipLaunchKernelGGL(k_relax<true>, dim3(s->relax_grid), dim3(256), 0, hs, s->list, s->tile_start,
                                    (const void *)d.out_adj, pa, d.V, s->snap, s->acc, cur, s->junk8, step,
-                                   s->pull_edges, s->fix, s->fixn, s->fix_cap);
+                                   s->pull_edges, s->fix, s->fixn, s->fix_cap, s->xcd_shift);
             } else {
                 const PullArgs pa{d.pull_sym, d.pull_sym_units, d.pull_sym_off};
                 hipLaunchKernelGGL(k_relax<false>, dim3(s->relax_grid), dim3(256), 0, hs, s->list, s->tile_start,
                                    (const void *)d.sym_col, pa, d.V, s->snap, s->acc, cur, s->junk8, step,
-                                   s->pull_edges, s->fix, s->fixn, s->fix_cap);
+                                   s->pull_edges, s->fix, s->fixn, s->fix_cap, s->xcd_shift);
             }
-            hipLaunchKernelGGL(k_fixup, dim3(s->relax_grid), dim3(256), 0, hs, s->fix, s->fixn, s->fix_cap, s->acc);
+            hipLaunchKernelGGL(k_fixup, dim3(s->relax_grid), dim3(256), 0, hs, s->fix, s->fixn, s->fix_cap, s->acc,
+                               step, s->xcd_shift);
         }
         GX_CHECK_HIP(hipGetLastError(), s);
     }

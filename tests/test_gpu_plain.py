@@ -52,6 +52,35 @@ def star_into(V, hub=0):
 MODES = [1.0, 1e-9, 0.0]
 
 
+def test_pull_reports_workgroup_off_its_xcd(gx, monkeypatch):
+    """The pull's plain stores rely on workgroup b running on XCD b mod 8, and
+    every pull and fix-up workgroup checks the XCD it runs on (every other
+    pulling test passes that check).  Shifting the expected XCD from the host
+    makes each pull superstep report a misplaced workgroup: the run fails with
+    GX_EDEVICE and the state stays failed, while a push-only state and an
+    unshifted state give the oracle's distances."""
+    g = gen.rmat(12, seed=3)
+    dg = load(gx, g, gx.GX_NEED_OUT)
+    ref = oracle.sssp(g, 0)
+    monkeypatch.setenv("GX_XCD_CHECK_SHIFT", "1")
+    st = gx.State(dg, gx.GX_SSSP, source=0, pull_fraction=1e-9)
+    with pytest.raises(gx.GxError) as ei:
+        st.run(10_000)
+    assert ei.value.status == gx.binding.GX_EDEVICE and "XCD" in str(ei.value)
+    with pytest.raises(gx.GxError):
+        st.superstep()
+    st.close()
+    push = gx.State(dg, gx.GX_SSSP, source=0, pull_fraction=1.0)
+    push.run(10_000)
+    assert np.array_equal(push.values_numpy(), ref.state)
+    push.close()
+    monkeypatch.delenv("GX_XCD_CHECK_SHIFT")
+    ok = gx.State(dg, gx.GX_SSSP, source=0, pull_fraction=1e-9)
+    ok.run(10_000)
+    assert np.array_equal(ok.values_numpy(), ref.state)
+    ok.close()
+
+
 def check_sssp_stepwise(gx, g, s, pull_fraction=0.0):
     dg = load(gx, g, gx.GX_NEED_OUT)
     st = gx.State(dg, gx.GX_SSSP, source=s, pull_fraction=pull_fraction)
