@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <cstdint>
 #include <cstring>
 #include <string>
@@ -72,9 +73,9 @@ constexpr int PR_TILE_MAX = PR_BLOCK * 8;
 // destination values; a bin's records are grouped by source band
 // (source >> PULL_BAND_BITS) and ordered by (destination, source) inside a
 // group.  Groups are padded to whole PULL_VT records with sentinels and cut
-// into work units of at most PULL_UNIT records.  Workgroup b takes the units
-// of slice b mod PULL_SLICES in order; workgroups are dealt round-robin to
-// the 8 XCDs, so each XCD's L2 holds one bin's destination values, and a
+// into work units of at most PULL_UNIT records.  The workgroups of a pull
+// take the units of the slice of the XCD they run on (slice x belongs to XCD
+// x of the 8), so each XCD's L2 holds one bin's destination values, and a
 // unit's band of source snapshots (PULL_BAND words) is staged in LDS.
 constexpr int PULL_SLICES = 8;
 constexpr int PULL_SLICE_SHIFT = 6;
@@ -169,6 +170,25 @@ struct gx_graph {
     // of the next run's first speculative group (solves on one graph tend to
     // need similar superstep counts)
     std::atomic<uint32_t> last_supersteps[2] = {0u, 0u};
+    // PageRank runs replayed as HIP graphs: n supersteps from ring slot `slot`
+    // (which also fixes the buffer parity) of a state laid out in `mem` with
+    // damping `damping`; a state re-created in the same memory finds its graph
+    // again.  Captured on `cap_stream`; the oldest entry goes past PR_GRAPHS.
+    struct PrGraph {
+        const void *mem;
+        double damping;
+        int64_t slot;
+        uint32_t n;
+        hipGraphExec_t exec;
+    };
+    static constexpr size_t PR_GRAPHS = 8;
+    std::mutex pr_mu;
+    std::vector<PrGraph> pr_graphs;
+    hipStream_t cap_stream = nullptr;
+    ~gx_graph() {
+        for (auto &e : pr_graphs) (void)hipGraphExecDestroy(e.exec);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
 };
 
 namespace gx {
@@ -184,7 +204,7 @@ struct DevStep {
     unsigned long long list;      // (entries << 32) | edges, via one 64-bit add per workgroup
     unsigned long long changed;   // PageRank changed values
     unsigned long long pad;       // 1 when the superstep pulled
-    unsigned long long faults;    // bit 0: a pull or fix-up workgroup ran on another XCD than its slice's
+    unsigned long long rot_mixed; // pull: 1 when its workgroups saw different XCD rotations
     unsigned long long spare0[12];
     unsigned long long frontier;  // |F_k|
     unsigned long long spare1[15];
@@ -237,6 +257,7 @@ struct gx_state {
     double *fix_d = nullptr;          // their dangling-mass partials
     unsigned long long *fix_c = nullptr;  // and changed counts
     uint32_t *fix_done = nullptr;     // workgroups finished (the last resets it)
+    void *mem = nullptr;              // the caller's state buffer (keys the graph's replay cache)
     // label propagation: lab[k & 1] holds the labels at the start of superstep k
     uint32_t *lab[2] = {nullptr, nullptr};
     uint32_t *lp_list = nullptr;              // vertices with neighbours, grouped by degree class

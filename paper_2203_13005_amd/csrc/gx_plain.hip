@@ -248,11 +248,15 @@ struct PushLds {
 // candidate; the fix-up kernel then re-applies every recorded candidate
 // still below the stored value with an atomic minimum.  Min atomics cost
 // several times a plain store here.  This is sound because every writer of
-// a destination in the pull, and the fix-up workgroup that reads its
-// entries, run on the XCD that owns the destination's slice (one L2 sees
-// all of its plain stores); regions are sized for every record a workgroup
-// can meet, so no candidate ever bypasses them (plain stores and atomics on
-// one word in one kernel would not be ordered).
+// a destination in the pull runs on the XCD that owns the destination's
+// slice (one L2 sees all of its plain stores) and the fix-up is a later
+// launch; regions are sized for every record a workgroup can meet, so no
+// candidate bypasses them (plain stores and atomics on one word in one
+// kernel would not be ordered).
+// A relaxation workgroup leaves its fix-up count in the low bits of its word
+// and, from a pull, the XCD rotation it saw in the top three.
+constexpr int FIX_ROT_SHIFT = 29;
+
 struct FixRegion {
     uint2 *ent;        // this workgroup's region
     uint32_t cap;      // its capacity
@@ -370,9 +374,10 @@ __device__ __forceinline__ void push_body(const uint4 *__restrict__ list, const 
 // Pull form of the same superstep, for large frontiers.  The in-edges are
 // stored as records {dst, (src mod PULL_BAND) << 8 | w} (CC: {dst, src}) in
 // work units of one destination slice and one band of PULL_BAND sources
-// (layout built at load).  Workgroup b takes the units of slice b mod
-// PULL_SLICES in order; since workgroups are dealt round-robin to the XCDs,
-// each XCD's L2 holds its slice's destination values.  A unit's band of
+// (layout built at load).  A workgroup takes the units of the slice of the
+// XCD it runs on (the j-th workgroup of an XCD takes units j, j + grid/8,
+// ...), so each XCD's L2 holds its slice's destination values and every
+// writer of a destination shares that L2.  A unit's band of
 // snapshots is staged in LDS, INF where the frontier map A_k says the source
 // is inactive, so a record's gather is an LDS read.  The 64 lanes of a wave
 // take 64 consecutive records (destinations in ascending order), so lanes
@@ -390,11 +395,23 @@ __device__ __forceinline__ void pull_body(const uint2 *__restrict__ rec, const u
                                           const PullSlices &sl, int64_t V, const uint32_t *__restrict__ snap,
                                           const uint8_t *__restrict__ front_cur, uint32_t *__restrict__ val,
                                           uint8_t *__restrict__ front_next, DevStep *__restrict__ step,
-                                          uint32_t *__restrict__ s_snap, const FixRegion &fr) {
+                                          uint32_t *__restrict__ s_snap, const FixRegion &fr, uint32_t xcd_shift,
+                                          uint32_t *rot) {
     const int tid = threadIdx.x;
     if (blockIdx.x == 0 && tid == 0) step->pad = 1;
     const __amdgpu_buffer_rsrc_t vrs = __builtin_amdgcn_make_buffer_rsrc(val, (short)0, (int)(uint32_t)(V * 4), 0x00020000);
-    const int x = (int)(blockIdx.x % PULL_SLICES);
+    // The workgroup takes the slice of the XCD it runs on, so every writer of
+    // a destination shares one L2.  The hardware deals a launch's workgroups
+    // to the XCDs in turn, from XCD r for workgroup 0 (r has been seen to
+    // differ between launches), so workgroup b runs on XCD (b + r) mod 8 and
+    // is the (b / 8)-th of its XCD (the grid is a multiple of 8).  Each
+    // workgroup leaves the r it saw beside its fix-up count, and the fix-up
+    // pass flags the superstep if the workgroups of one launch saw more than
+    // one.  (xcd_shift, zero outside tests, offsets the odd workgroups' XCD
+    // to exercise that check.)
+    const uint32_t xr = (xcc_id() + ((blockIdx.x & 1u) ? xcd_shift : 0u)) % PULL_SLICES;
+    *rot = (xr + PULL_SLICES - blockIdx.x % PULL_SLICES) % PULL_SLICES;
+    const int x = (int)xr;
     const int64_t nblk = gridDim.x / PULL_SLICES;
     for (int64_t ui = sl.uoff[x] + blockIdx.x / PULL_SLICES; ui < sl.uoff[x + 1]; ui += nblk) {
         const uint4 un = units[ui];
@@ -479,27 +496,27 @@ __global__ __launch_bounds__(256) void k_relax(const uint4 *__restrict__ list, c
     __syncthreads();
     const FixRegion fr{fix + (size_t)blockIdx.x * fix_cap, fix_cap, &s_fixn};
     const unsigned long long le = step->list;
+    uint32_t rot = 0;
     if ((uint32_t)le >= pull_edges) {
-        // the pull's plain stores are correct only while workgroup b runs on
-        // XCD b mod 8 (the one that owns slice b mod 8); a workgroup that finds
-        // itself elsewhere reports it, and the host fails the run
-        if (threadIdx.x == 0 && xcc_id() != (blockIdx.x + xcd_shift) % PULL_SLICES) atomicOr(&step->faults, 1ull);
-        pull_body<WEIGHTED>(pa.rec, pa.units, pa.sl, V, snap, front_cur, val, front_next, step, lds.pull_snap, fr);
+        pull_body<WEIGHTED>(pa.rec, pa.units, pa.sl, V, snap, front_cur, val, front_next, step, lds.pull_snap, fr,
+                            xcd_shift, &rot);
     } else {
         push_body<WEIGHTED>(list, tile_start, adj, val, front_next, le, lds.push);
     }
     __syncthreads();
-    if (threadIdx.x == 0) fixn[blockIdx.x] = min(s_fixn, fix_cap);
+    if (threadIdx.x == 0) fixn[blockIdx.x] = min(s_fixn, fix_cap) | (rot << FIX_ROT_SHIFT);
 }
 
 // The relaxation's fix-up: workgroup b re-applies the recorded candidates of
-// relaxation workgroup b that are still below the stored value (it reads
-// them through the L2 of XCD b mod 8, where they were stored).
+// relaxation workgroup b that are still below the stored value (a separate
+// launch: the relaxation's stores are visible to every XCD by then), and
+// flags the superstep if relaxation workgroup b saw another XCD rotation
+// than workgroup 0 (a push leaves rotation 0 everywhere).
 __global__ __launch_bounds__(256) void k_fixup(const uint2 *__restrict__ fix, const uint32_t *__restrict__ fixn,
-                                               uint32_t fix_cap, uint32_t *__restrict__ val, DevStep *__restrict__ step,
-                                               uint32_t xcd_shift) {
-    const uint32_t n = fixn[blockIdx.x];
-    if (n > 0 && threadIdx.x == 0 && xcc_id() != (blockIdx.x + xcd_shift) % PULL_SLICES) atomicOr(&step->faults, 1ull);
+                                               uint32_t fix_cap, uint32_t *__restrict__ val, DevStep *__restrict__ step) {
+    const uint32_t w = fixn[blockIdx.x];
+    if (threadIdx.x == 0 && (w >> FIX_ROT_SHIFT) != (fixn[0] >> FIX_ROT_SHIFT)) step->rot_mixed = 1ull;
+    const uint32_t n = w & ((1u << FIX_ROT_SHIFT) - 1u);
     const uint2 *e = fix + (size_t)blockIdx.x * fix_cap;
     for (uint32_t i = threadIdx.x; i < n; i += 256) {
         const uint2 q = e[i];
@@ -1161,15 +1178,16 @@ static int persistent_grid(gx_graph *g, K kernel, int block) {
 }
 
 // Persistent grid of the relaxation: whole multiples of the slice count (a
-// pulling workgroup b sweeps slice b mod PULL_SLICES).
+// pulling XCD's workgroups share its slice's units evenly).
 static int relax_grid_for(gx_graph *g, const gx_params *p) {
     const int pg = p->algo == GX_CC ? persistent_grid(g, k_relax<false>, 256) : persistent_grid(g, k_relax<true>, 256);
     return std::max(PULL_SLICES, pg / PULL_SLICES * PULL_SLICES);
 }
 
-// Fix-up entries per relaxation workgroup: the records of the pull units the
-// workgroup sweeps (workgroup b takes units b/8, b/8 + nper, ... of slice
-// b mod 8), maximised over workgroups, so a region never overflows.
+// Fix-up entries per relaxation workgroup: the records of the pull units a
+// workgroup sweeps (the j-th workgroup on the XCD of slice x takes units j,
+// j + nper, ... of slice x), maximised over x and j, so a region never
+// overflows.
 static uint32_t fix_cap_for(const gx_graph *g, const gx_params *p, int grid) {
     const DevGraph &d = g->d;
     const bool cc = p->algo == GX_CC;
@@ -1185,7 +1203,7 @@ static uint32_t fix_cap_for(const gx_graph *g, const gx_params *p, int grid) {
             for (int64_t u = sl.uoff[x] + j; u < sl.uoff[x + 1]; u += nper) sum += recs[(size_t)u];
             bound = std::max(bound, sum);
         }
-    return (uint32_t)bound;
+    return (uint32_t)std::min<uint64_t>(bound, (1u << FIX_ROT_SHIFT) - 1u);
 }
 
 static size_t state_layout(gx_graph *g, const gx_params *p, Carver &c, gx_state *s) {
@@ -1305,8 +1323,9 @@ extern "C" gx_status gx_state_init(gx_graph *g, const gx_params *p, void *dev_st
     GX_REQUIRE(s, GX_ENOMEM, "host allocation failed");
     s->g = g;
     s->p = *p;
-    // GX_XCD_CHECK_SHIFT (tests only) shifts the XCD the pull's workgroups are
-    // expected on, so that the placement check fires without a real fault
+    s->mem = dev_state;
+    // GX_XCD_CHECK_SHIFT (tests only) offsets the XCD the odd pull workgroups
+    // see, so that the rotation check fires without a real fault
     if (const char *e = std::getenv("GX_XCD_CHECK_SHIFT")) s->xcd_shift = (uint32_t)std::strtoul(e, nullptr, 10);
     Carver c(dev_state, bytes);
     state_layout(g, p, c, s);
@@ -1532,7 +1551,7 @@ static gx_status enqueue_superstep(gx_state *s, hipStream_t hs) {
                                    step, s->pull_edges, s->fix, s->fixn, s->fix_cap, s->xcd_shift);
             }
             hipLaunchKernelGGL(k_fixup, dim3(s->relax_grid), dim3(256), 0, hs, s->fix, s->fixn, s->fix_cap, s->val,
-                               step, s->xcd_shift);
+                               step);
             if (e1) (void)hipEventRecord(e1, hs);
             hipLaunchKernelGGL(k_compact, dim3(grid_for<int64_t>(d.V, CBLOCK * CVT)), dim3(CBLOCK), 0, hs,
                                s->front8[cur ^ 1], s->front8[cur], rp, s->val, s->snap, d.V, s->list, s->tile_start,
@@ -1635,15 +1654,66 @@ static gx_status read_steps(gx_state *s, int64_t kfirst, uint32_t n, hipStream_t
         done += chunk;
     }
     for (uint32_t i = 0; i < n; i++)
-        if (out[i].faults & 1ull) {
+        if (out[i].rot_mixed) {
             s->dev_error = true;
-            set_error("superstep %lld pulled with a workgroup on another XCD than the slice it owns (the pull's "
-                      "plain stores need workgroup b on XCD b mod 8); the values may be wrong; run with "
-                      "pull_fraction >= 1 (push only) on this device",
+            set_error("superstep %lld pulled with workgroups dealt to the XCDs in more than one rotation; some "
+                      "work units may have run on an XCD other than the one owning their destinations, so the "
+                      "values may be wrong; run with pull_fraction >= 1 (push only) on this device",
                       (long long)(kfirst + i));
             return GX_EDEVICE;
         }
     return GX_OK;
+}
+
+// PageRank supersteps k .. k+n-1 as one HIP graph launch on `hs`.  The
+// kernels' arguments depend only on the state's memory, the damping and the
+// ring slot of k (which also fixes the buffer parity), so the graph is
+// captured once, on the graph handle's private stream, and replayed by every
+// run that starts from the same slot with the same count, also by a state
+// created again in the same memory (what a reset does).  A superstep
+// enqueues two kernels and no memory set.  Returns false, having enqueued
+// nothing, when timing events are on, for a single superstep, or when capture
+// is not available; the caller then enqueues the supersteps one by one.
+static bool pr_replay(gx_state *s, uint32_t n, hipStream_t hs) {
+    gx_graph *g = s->g;
+    if (s->p.timing || n < 2 || g->d.V == 0) return false;
+    const int64_t slot = s->k % STEP_RING, k0 = s->k;
+    const double damping = s->p.damping;
+    std::lock_guard<std::mutex> lk(g->pr_mu);
+    hipGraphExec_t exec = nullptr;
+    for (auto &e : g->pr_graphs)
+        if (e.mem == s->mem && e.damping == damping && e.slot == slot && e.n == n) exec = e.exec;
+    if (!exec) {
+        if (!g->cap_stream && hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+            g->cap_stream = nullptr;
+            return false;
+        }
+        if (hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+        bool ok = true;
+        for (uint32_t i = 0; i < n && ok; i++) ok = enqueue_superstep(s, g->cap_stream) == GX_OK;
+        hipGraph_t graph = nullptr;
+        ok = hipStreamEndCapture(g->cap_stream, &graph) == hipSuccess && ok && graph;
+        ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+        if (graph) (void)hipGraphDestroy(graph);
+        s->k = k0;
+        (void)hipGetLastError();
+        if (!ok) {
+            s->dev_error = false;  // a capture that failed launched nothing
+            clear_error();
+            return false;
+        }
+        if (g->pr_graphs.size() >= gx_graph::PR_GRAPHS) {
+            (void)hipGraphExecDestroy(g->pr_graphs.front().exec);
+            g->pr_graphs.erase(g->pr_graphs.begin());
+        }
+        g->pr_graphs.push_back({s->mem, damping, slot, n, exec});
+    }
+    if (hipGraphLaunch(exec, hs) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    s->k = k0 + n;
+    return true;
 }
 
 extern "C" gx_status gx_run_until_converged(gx_state *s, uint32_t max_supersteps, void *stream, gx_run_stats *out,
@@ -1666,9 +1736,11 @@ extern "C" gx_status gx_run_until_converged(gx_state *s, uint32_t max_supersteps
         for (uint32_t done = 0; done < max_supersteps;) {
             const uint32_t g = std::min<uint32_t>(max_supersteps - done, STEP_RING - 2);
             const int64_t kfirst = s->k;
-            for (uint32_t i = 0; i < g; i++) {
-                gx_status st = enqueue_superstep(s, hs);
-                if (st != GX_OK) return st;
+            if (!pr_replay(s, g, hs)) {
+                for (uint32_t i = 0; i < g; i++) {
+                    gx_status st = enqueue_superstep(s, hs);
+                    if (st != GX_OK) return st;
+                }
             }
             gx_status st = read_steps(s, kfirst, g + 1, hs, host);
             if (st != GX_OK) return st;
@@ -1970,7 +2042,7 @@ extern "C" gx_status gx_msg_merge(gx_state *s, void *stream) {
                                    s->pull_edges, s->fix, s->fixn, s->fix_cap, s->xcd_shift);
             }
             hipLaunchKernelGGL(k_fixup, dim3(s->relax_grid), dim3(256), 0, hs, s->fix, s->fixn, s->fix_cap, s->acc,
-                               step, s->xcd_shift);
+                               step);
         }
         GX_CHECK_HIP(hipGetLastError(), s);
     }

@@ -52,13 +52,15 @@ def star_into(V, hub=0):
 MODES = [1.0, 1e-9, 0.0]
 
 
-def test_pull_reports_workgroup_off_its_xcd(gx, monkeypatch):
-    """The pull's plain stores rely on workgroup b running on XCD b mod 8, and
-    every pull and fix-up workgroup checks the XCD it runs on (every other
-    pulling test passes that check).  Shifting the expected XCD from the host
-    makes each pull superstep report a misplaced workgroup: the run fails with
-    GX_EDEVICE and the state stays failed, while a push-only state and an
-    unshifted state give the oracle's distances."""
+def test_pull_reports_mixed_xcd_rotations(gx, monkeypatch):
+    """A pull workgroup takes the slice of the XCD it runs on, assuming the
+    hardware deals a launch's workgroups to the 8 XCDs in turn from some
+    starting XCD; each records the rotation it sees and the host fails the
+    superstep if one launch saw two (every other pulling test passes that
+    check).  Offsetting the odd workgroups' XCD from the host makes every pull
+    superstep see two rotations: the run fails with GX_EDEVICE and the state
+    stays failed, while a push-only state and an unshifted state give the
+    oracle's distances."""
     g = gen.rmat(12, seed=3)
     dg = load(gx, g, gx.GX_NEED_OUT)
     ref = oracle.sssp(g, 0)
@@ -66,7 +68,7 @@ def test_pull_reports_workgroup_off_its_xcd(gx, monkeypatch):
     st = gx.State(dg, gx.GX_SSSP, source=0, pull_fraction=1e-9)
     with pytest.raises(gx.GxError) as ei:
         st.run(10_000)
-    assert ei.value.status == gx.binding.GX_EDEVICE and "XCD" in str(ei.value)
+    assert ei.value.status == gx.binding.GX_EDEVICE and "rotation" in str(ei.value)
     with pytest.raises(gx.GxError):
         st.superstep()
     st.close()
@@ -373,6 +375,38 @@ def test_pagerank_rmat_scale14_20_steps(gx):
     st, x, ref = check_pr(gx, g, 20)
     rel = np.max(np.abs(x - ref) / ref)
     assert rel < 1e-4
+
+
+def test_pagerank_graph_replay_equals_eager(gx):
+    """A PageRank run without timing events is captured once as a HIP graph
+    and replayed, also after a reset (the state re-created in the same
+    memory).  Every replay, with other eager device work in between, equals
+    the run enqueued superstep by superstep (timing events on) bit for bit,
+    per-superstep counts included, and so does a run that continues from
+    superstep 20 (another ring slot: another graph)."""
+    g = gen.rmat(12, seed=7)
+    dg = gx.DeviceGraph(g, gx.GX_NEED_IN)
+    eager = gx.State(dg, gx.GX_PAGERANK, damping=0.85, timing=True)
+    _, s20 = eager.run(20, per_step=True)
+    e20 = eager.values_numpy().view(np.uint32).copy()
+    _, s40 = eager.run(20, per_step=True)
+    e40 = eager.values_numpy().view(np.uint32).copy()
+    eager.close()
+    st = gx.State(dg, gx.GX_PAGERANK, damping=0.85)
+    for rep in range(4):
+        st.reset()
+        _, steps = st.run(20, per_step=True)
+        assert np.array_equal(st.values_numpy().view(np.uint32), e20), rep
+        assert steps == s20, rep
+        other = gx.State(dg, gx.GX_PAGERANK, damping=0.85, timing=True)
+        other.run(3)
+        other.close()
+    _, steps = st.run(20, per_step=True)
+    assert np.array_equal(st.values_numpy().view(np.uint32), e40)
+    assert steps == s40
+    ref = oracle.pagerank(g, 40)
+    assert np.max(np.abs(st.values_numpy().astype(np.float64) - ref)) <= PR_TOL
+    st.close()
 
 
 PR_TILES = [0, 256, 512, 1024, 2048]  # 0 = the size the library picks
