@@ -1055,6 +1055,9 @@ def bench_sssp(args, gx, torch, np, gen):
     achieved_upper = bytes_upper * args.steps / (kern_ms / 1e3) / 1e9
     copy_gbps = copy_ceiling_gbps(torch)
     log(f"device copy ceiling {copy_gbps:.0f} GB/s")
+    link_gbps = host_link_gbps(torch)
+    log(f"host link (pinned host to device) {link_gbps:.1f} GB/s; the load moved {load_bytes / 1e9:.2f} GB at "
+        f"{load_bytes / load_s / 1e9:.2f} GB/s")
     traffic = load_traffic()
     out = {
         "value": edges / dt / 1e9,
@@ -1074,7 +1077,10 @@ def bench_sssp(args, gx, torch, np, gen):
             "supersteps": src_steps},
         "load": {"what": "gx_graph_load: host validation and packaging (out-CSR, in-edge records), "
                          "16 MiB blocks through three rotating pinned buffers on a copy stream",
-                 "seconds": load_s, "device_bytes": load_bytes, "GBps": load_bytes / load_s / 1e9},
+                 "seconds": load_s, "device_bytes": load_bytes, "GBps": load_bytes / load_s / 1e9,
+                 "host_link_GBps": link_gbps,
+                 "bound": "host packaging on the CPU threads (the copies would take "
+                          f"{load_bytes / link_gbps / 1e9 * 1e3:.0f} ms of the {load_s * 1e3:.0f} ms at the link's rate)"},
         "roofline": {
             "bound": "hbm",
             "kernel": "relaxation: k_relax<true> (push or pull as the frontier decides) + k_fixup, per superstep",

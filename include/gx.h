@@ -481,9 +481,14 @@ gx_status gx_batch_run(gx_graph *g, int32_t algo, const int32_t *sources, uint32
 
 /*
  * Times the candidate launch shapes of gx_batch_run on this graph (each
- * candidate runs once on `sources`) and writes the fastest to *best.
- * Every candidate must produce the same result; the call fails with
- * GX_EDEVICE if one does not.
+ * candidate runs once on `sources`) and writes the fastest to *best;
+ * dev_out then holds that shape's result.  Every candidate must produce
+ * the same result; the call fails with GX_EDEVICE if one does not.  When
+ * the environment variable GX_TUNE_CACHE names a file, results are kept
+ * there, one line per (graph signature: size, out-degrees and the device's
+ * CU count; algorithm; B; iterations for PPR), and a later call with the
+ * same key, in any process, returns the stored shape and time after one
+ * run of it, without timing the candidates.
  */
 gx_status gx_batch_autotune(gx_graph *g, int32_t algo, const int32_t *sources, uint32_t B,
                             float damping, uint32_t iters, void *dev_work, size_t work_bytes,

@@ -27,7 +27,11 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <map>
+#include <mutex>
+#include <string>
 #include <tuple>
 
 #include "gx_device.h"
@@ -925,6 +929,67 @@ extern "C" gx_status gx_batch_run(gx_graph *g, int32_t algo, const int32_t *sour
     return GX_OK;
 }
 
+// Autotune results kept on disk when GX_TUNE_CACHE names a file: one line
+// per (graph signature, algorithm, lanes, iterations) with the chosen shape
+// and its time.  The signature hashes the graph's size, its out-degrees and
+// the device's CU count (FNV-1a), so a cached shape is reused only for the
+// same graph on the same kind of device.
+namespace {
+struct TuneKey {
+    uint64_t sig;
+    int32_t algo;
+    uint32_t B, iters;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(sig, algo, B, iters) < std::tie(o.sig, o.algo, o.B, o.iters);
+    }
+};
+struct TuneCache {
+    std::mutex mu;
+    std::string path;  // the file the map was read from
+    std::map<TuneKey, std::pair<gx_tune, double>> map;
+};
+TuneCache &tune_cache() {
+    static TuneCache c;
+    return c;
+}
+
+uint64_t graph_signature(const gx_graph *g) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+        for (int i = 0; i < 8; i++) {
+            h ^= (v >> (8 * i)) & 0xFFu;
+            h *= 1099511628211ull;
+        }
+    };
+    mix((uint64_t)g->d.V);
+    mix((uint64_t)g->d.E);
+    mix((uint64_t)g->num_cus);
+    for (int32_t d : g->host_outdeg) mix((uint64_t)(uint32_t)d);
+    return h;
+}
+
+// Reads the file named by GX_TUNE_CACHE into the map (again when the name
+// changes); returns false when the variable is not set.
+bool tune_cache_open(TuneCache &c) {
+    const char *p = std::getenv("GX_TUNE_CACHE");
+    if (!p || !*p) return false;
+    if (c.path == p) return true;
+    c.path = p;
+    c.map.clear();
+    if (FILE *f = std::fopen(p, "r")) {
+        unsigned long long sig;
+        int algo;
+        unsigned B, iters, block, tile, width, grid;
+        double ms;
+        while (std::fscanf(f, "%llx %d %u %u %u %u %u %u %lf", &sig, &algo, &B, &iters, &block, &tile, &width,
+                           &grid, &ms) == 9)
+            c.map[TuneKey{sig, algo, B, iters}] = {gx_tune{block, tile, width, grid}, ms};
+        std::fclose(f);
+    }
+    return true;
+}
+}  // namespace
+
 extern "C" gx_status gx_batch_autotune(gx_graph *g, int32_t algo, const int32_t *sources, uint32_t B, float damping,
                                        uint32_t iters, void *dev_work, size_t work_bytes, void *dev_out,
                                        void *stream, gx_tune *best, double *best_ms) {
@@ -935,6 +1000,22 @@ extern "C" gx_status gx_batch_autotune(gx_graph *g, int32_t algo, const int32_t 
     gx_status st = batch_common(g, algo, sources, B, dev_work, work_bytes, dev_out, &bsw, &bpw);
     if (st != GX_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const TuneKey key{graph_signature(g), algo, B, algo == GX_PPR ? iters : 0u};
+    {
+        TuneCache &tc = tune_cache();
+        std::lock_guard<std::mutex> lk(tc.mu);
+        auto it = tune_cache_open(tc) ? tc.map.find(key) : tc.map.end();
+        if (it != tc.map.end()) {  // a stored shape: run it once so dev_out holds its result
+            *best = it->second.first;
+            if (best_ms) *best_ms = it->second.second;
+            if (algo == GX_SSSP) {
+                GX_CHECK_HIP(hipMemcpyAsync(bsw.src, sources, B * 4, hipMemcpyHostToDevice, s), g);
+                return run_bsssp(g, bsw.src, B, bsw, static_cast<uint32_t *>(dev_out), *best, s, nullptr);
+            }
+            GX_CHECK_HIP(hipMemcpyAsync(bpw.seed, sources, B * 4, hipMemcpyHostToDevice, s), g);
+            return run_bppr(g, bpw.seed, B, bpw, damping, iters, static_cast<float *>(dev_out), s, (int)best->grid);
+        }
+    }
     std::vector<gx_tune> cands;
     if (algo == GX_SSSP) {
         int nv = 0;
@@ -992,6 +1073,18 @@ extern "C" gx_status gx_batch_autotune(gx_graph *g, int32_t algo, const int32_t 
     (void)hipEventDestroy(e1);
     if (result != GX_OK) return result;
     if (best_ms) *best_ms = bms;
+    {
+        TuneCache &tc = tune_cache();
+        std::lock_guard<std::mutex> lk(tc.mu);
+        if (tune_cache_open(tc)) {
+            tc.map[key] = {*best, bms};
+            if (FILE *f = std::fopen(tc.path.c_str(), "a")) {
+                std::fprintf(f, "%llx %d %u %u %u %u %u %u %.6f\n", (unsigned long long)key.sig, key.algo, key.B,
+                             key.iters, best->block, best->tile, best->width, best->grid, bms);
+                std::fclose(f);
+            }
+        }
+    }
     // leave the best candidate's result in dev_out
     if (algo == GX_SSSP)
         return run_bsssp(g, bsw.src, B, bsw, static_cast<uint32_t *>(dev_out), *best, s, nullptr);

@@ -125,6 +125,32 @@ def test_batched_ppr_lane_independent_of_batch(gx):
     assert np.array_equal(big.cpu().numpy().view(np.uint32), grid2.cpu().numpy().view(np.uint32))
 
 
+def test_autotune_cache_file(gx, tmp_path, monkeypatch):
+    """With GX_TUNE_CACHE naming a file, the first autotune times the
+    candidates and appends its choice; a second call on the same graph,
+    algorithm and lanes returns the stored shape and time without timing
+    them (one line in the file still), a run with that shape equals the
+    oracle, and another graph gets a line of its own."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("GX_TUNE_CACHE", str(path))
+    g = gen.rmat(11, seed=12)
+    dg = load(gx, g)
+    src = gen.pick_sources(g, 64, seed=47)
+    best1, ms1 = gx.batch_autotune(dg, gx.GX_SSSP, src)
+    assert len(path.read_text().splitlines()) == 1
+    best2, ms2 = gx.batch_autotune(dg, gx.GX_SSSP, src)
+    assert (best2.block, best2.tile, best2.width, best2.grid) == (best1.block, best1.tile, best1.width, best1.grid)
+    assert ms2 == pytest.approx(ms1, abs=1e-5)
+    assert len(path.read_text().splitlines()) == 1
+    out, _ = gx.batch_run(dg, gx.GX_SSSP, src, tune=best2)
+    D = lanes_u32(out)
+    for b in (0, 31, 63):
+        assert np.array_equal(D[:, b], oracle.sssp(g, int(src[b])).state), b
+    g2 = gen.rmat(11, seed=13)
+    gx.batch_autotune(load(gx, g2), gx.GX_SSSP, gen.pick_sources(g2, 64, seed=47))
+    assert len(path.read_text().splitlines()) == 2
+
+
 def test_batched_ppr_narrow_workers_bitwise(gx):
     """Batches of at most 16 or 32 lanes run two or four tiles per wave; each
     lane still adds its row's contributions in edge order, so a batch of 3,
