@@ -259,7 +259,7 @@ def bench_batched_ppr(gx, torch, g, dg, src, iters=50, reps=3):
 
 
 def bench_serving(gx, torch, np, gen, n_queries=10000, qps_frac=0.7, lanes=64, max_pools=4, budget_frac=0.5,
-                  sample=16, outstanding=512, records=None):
+                  sample=16, outstanding=512, records=None, epoch=4):
     """16 resident R-MAT graphs (scales 16..22, seeds 100..115), 50% SSSP /
     50% PPR (50 iterations), Poisson arrivals (seed 5) at a fixed rate of
     qps_frac x the capacity measured closed-loop with `outstanding` queries
@@ -298,7 +298,7 @@ def bench_serving(gx, torch, np, gen, n_queries=10000, qps_frac=0.7, lanes=64, m
         return qs
 
     def run(qs, arrivals, keep=()):
-        srv = gx.Server(budget, lanes_per_pool=lanes, max_pools=max_pools, epoch_supersteps=4, ppr_iters=50)
+        srv = gx.Server(budget, lanes_per_pool=lanes, max_pools=max_pools, epoch_supersteps=epoch, ppr_iters=50)
         ids = [srv.add_graph(d) for d in dgs]
         done, qid_of, kept = [], {}, {}
         t_start = time.perf_counter()
@@ -322,7 +322,7 @@ def bench_serving(gx, torch, np, gen, n_queries=10000, qps_frac=0.7, lanes=64, m
 
     def run_closed(qs, outstanding):
         # a fixed number of queries in flight: each completion submits the next
-        srv = gx.Server(budget, lanes_per_pool=lanes, max_pools=max_pools, epoch_supersteps=4, ppr_iters=50)
+        srv = gx.Server(budget, lanes_per_pool=lanes, max_pools=max_pools, epoch_supersteps=epoch, ppr_iters=50)
         ids = [srv.add_graph(d) for d in dgs]
         t_start = time.perf_counter()
         i = n_done = 0
