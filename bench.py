@@ -114,7 +114,7 @@ def cpu_baseline(np, g, edges_per_solve, g4=None, src4=None, part=None, budget_s
            "single_core": {"value": edges_per_solve / t1 / 1e9, "unit": "GTEPS", "cores": 1,
                            "sample": f"reference mode, median of {n1} runs ({t1:.2f} s each)"},
            "dijkstra_single_core_s": t_dij,
-           "host_cpu": platform.processor() or platform.machine(), "host_nproc": os.cpu_count()}
+           "host_cpu": host_cpu_model(), "host_nproc": os.cpu_count()}
     if g4 is not None:
         t0 = time.perf_counter()
         D, K = oracle.sssp_many(g4, src4)
@@ -634,6 +634,17 @@ def bench_phases(gx, torch, np, gen, g=None, reps=5):
     log(f"template calls: fused {out['fused_ms_per_solve']:.2f} ms, BSP order "
         f"{out['bsp_separate_calls_ms_per_solve']:.2f} ms, GAS order {out['gas_separate_calls_ms_per_solve']:.2f} ms")
     return out
+
+
+def host_cpu_model():
+    """The host CPU's model name (/proc/cpuinfo), else the machine type."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
 
 
 def host_link_gbps(torch, nbytes=1 << 30, reps=3):
@@ -1158,6 +1169,7 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
+        "gpu": torch.cuda.get_device_name(0) if torch.cuda.is_available() else None,
         "config": {"workload": "none (headline leg not run)"},
     }
     g = edges_per_solve = None
