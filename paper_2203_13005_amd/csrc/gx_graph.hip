@@ -10,6 +10,7 @@
 #include <functional>
 #include <map>
 #include <mutex>
+#include <memory>
 #include <thread>
 #include <tuple>
 
@@ -52,9 +53,9 @@ int occupancy_per_cu(const void *kernel, int block) {
 }
 
 template <class F>
-static void parallel_for(int64_t n, F f) {
+static void parallel_for(int64_t n, F f, int64_t serial_below = 65536) {
     unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    if (n < 65536 || nt == 1) {
+    if (n < serial_below || nt == 1) {
         f(0, n);
         return;
     }
@@ -67,11 +68,34 @@ static void parallel_for(int64_t n, F f) {
 }
 
 // Host images built from the description before upload.
+// Vectors whose elements start uninitialised (resize leaves them as they
+// are): the edge-sized images are written in full by parallel passes, so a
+// value fill on one thread first would only cost time.
+template <class T>
+struct NoInit : std::allocator<T> {
+    template <class U>
+    struct rebind {
+        using other = NoInit<U>;
+    };
+    NoInit() = default;
+    template <class U>
+    NoInit(const NoInit<U> &) {}
+    template <class U, class... A>
+    void construct(U *p, A &&...a) {
+        if constexpr (sizeof...(A) == 0) ::new ((void *)p) U;
+        else ::new ((void *)p) U(std::forward<A>(a)...);
+    }
+};
+template <class T>
+using EdgeVec = std::vector<T, NoInit<T>>;
+
 struct HostImages {
-    std::vector<int32_t> in_rp, in_col, outdeg, tile_row, pr_slot, pr_src;
-    std::vector<uint32_t> in_w;
-    std::vector<int32_t> sym_rp, sym_col;
-    std::vector<uint2> pull_w, pull_sym;
+    std::vector<int32_t> in_rp, outdeg, tile_row, pr_slot;
+    EdgeVec<int32_t> in_col, pr_src;
+    EdgeVec<uint32_t> in_w;
+    std::vector<int32_t> sym_rp;
+    EdgeVec<int32_t> sym_col;
+    EdgeVec<uint2> pull_w, pull_sym;
     std::vector<uint4> pull_w_units, pull_sym_units;
     PullSlices pull_w_off{}, pull_sym_off{};
     std::vector<uint32_t> rem_out, rem_any, master, master_rep;
@@ -100,15 +124,19 @@ static gx_status validate(const gx_graph_desc *d) {
     GX_REQUIRE(d->row_ptr[d->V] == d->E, GX_EINVAL, "row_ptr[V]=%d != E=%lld", d->row_ptr[d->V], (long long)d->E);
     for (int64_t v = 0; v < d->V; v++)
         GX_REQUIRE(d->row_ptr[v + 1] >= d->row_ptr[v], GX_EINVAL, "row_ptr decreases at %lld", (long long)v);
-    bool bad = false;
-    int64_t badpos = -1;
-    for (int64_t e = 0; e < d->E; e++)
-        if ((uint32_t)d->col[e] >= (uint32_t)d->V) {
-            bad = true;
-            badpos = e;
-            break;
-        }
-    GX_REQUIRE(!bad, GX_EINVAL, "col[%lld]=%d out of [0,V)", (long long)badpos, bad ? d->col[badpos] : 0);
+    std::atomic<int64_t> badpos{INT64_MAX};  // the first column out of range, over the host threads
+    parallel_for(d->E, [&](int64_t lo, int64_t hi) {
+        for (int64_t e = lo; e < hi; e++)
+            if ((uint32_t)d->col[e] >= (uint32_t)d->V) {
+                int64_t cur = badpos.load();
+                while (e < cur && !badpos.compare_exchange_weak(cur, e)) {
+                }
+                return;
+            }
+    });
+    const int64_t bp = badpos.load();
+    GX_REQUIRE(bp == INT64_MAX, GX_EINVAL, "col[%lld]=%d out of [0,V)", (long long)bp,
+               bp == INT64_MAX ? 0 : d->col[bp]);
     GX_REQUIRE((d->V_global == 0) == (d->outdeg_global == nullptr), GX_EINVAL,
                "V_global and outdeg_global come together");
     if (d->outdeg_global) {
@@ -129,48 +157,88 @@ static gx_status validate(const gx_graph_desc *d) {
 static unsigned host_threads() { return std::max(1u, std::min(16u, std::thread::hardware_concurrency())); }
 
 // Stable counting sort of the edges by destination: in-rows list their
-// sources in ascending order.  Each thread owns a range of destinations
-// (equal in-edge counts for the scatter) and scans every edge in source
-// order, keeping only its own: no shared counters, the same result as one
-// sequential pass.
+// sources in ascending order, the same result as one sequential pass.  The
+// destinations are cut into buckets of equal vertex ranges; the edges, in
+// source order, are cut into one chunk per thread.  Each thread counts its
+// chunk's edges per bucket, the counts are laid out bucket by bucket and
+// chunk by chunk (so a bucket keeps the chunks' source order), each thread
+// copies its chunk's edges to their buckets, and the buckets, handed out
+// one at a time, are sorted by destination with a counting sort of their
+// own.  Every edge is read a bounded number of times whatever the thread
+// count.
 static void build_in_csr(const gx_graph_desc *d, HostImages &h) {
     const int64_t V = d->V, E = d->E;
     h.in_rp.assign(V + 1, 0);
     h.in_col.resize(E);
     const bool wts = d->w && (d->needs & GX_NEED_OUT);
     if (wts) h.in_w.resize(E);
+    if (E == 0) return;
     const unsigned nt = E < 4096 ? 1u : host_threads();
-    std::vector<std::thread> th;
-    for (unsigned t = 0; t < nt; t++)  // counts: equal destination ranges
-        th.emplace_back([&, t] {
-            const int64_t lo = V * t / nt, hi = V * (t + 1) / nt;
-            for (int64_t e = 0; e < E; e++) {
-                const int64_t v = d->col[e];
-                if (v >= lo && v < hi) h.in_rp[v + 1]++;
-            }
-        });
-    for (auto &x : th) x.join();
-    th.clear();
-    for (int64_t v = 0; v < V; v++) h.in_rp[v + 1] += h.in_rp[v];
-    std::vector<int64_t> cut(nt + 1, V);  // destination ranges of equal in-edge counts
-    cut[0] = 0;
+    const int64_t NB = std::max<int64_t>(1, std::min<int64_t>(256, V / 64));  // destination buckets
+    const int64_t span = (V + NB - 1) / NB;                                    // vertices per bucket
+    // source-ordered edge chunks: chunk t holds the out-rows of sources [src_cut[t], src_cut[t+1])
+    std::vector<int64_t> src_cut(nt + 1, V);
+    src_cut[0] = 0;
     for (unsigned t = 1; t < nt; t++)
-        cut[t] = std::lower_bound(h.in_rp.begin(), h.in_rp.end() - 1, (int32_t)(E * t / nt)) - h.in_rp.begin();
-    for (unsigned t = 0; t < nt; t++)
-        th.emplace_back([&, t] {
-            const int64_t lo = cut[t], hi = cut[t + 1];
-            if (lo >= hi) return;
-            std::vector<int32_t> pos(h.in_rp.begin() + lo, h.in_rp.begin() + hi);
-            for (int64_t u = 0; u < V; u++)
-                for (int32_t e = d->row_ptr[u]; e < d->row_ptr[u + 1]; e++) {
-                    const int64_t v = d->col[e];
-                    if (v < lo || v >= hi) continue;
-                    const int32_t p = pos[v - lo]++;
-                    h.in_col[p] = (int32_t)u;
-                    if (wts) h.in_w[p] = d->w[e];
-                }
-        });
-    for (auto &x : th) x.join();
+        src_cut[t] = std::upper_bound(d->row_ptr, d->row_ptr + V, (int32_t)(E * t / nt)) - d->row_ptr - 1;
+    for (unsigned t = 1; t <= nt; t++) src_cut[t] = std::max(src_cut[t], src_cut[t - 1]);
+    std::vector<int64_t> cnt((size_t)nt * NB, 0);  // [chunk][bucket]
+    auto run = [&](auto &&body) {
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nt; t++) th.emplace_back([&, t] { body(t); });
+        for (auto &x : th) x.join();
+    };
+    run([&](unsigned t) {
+        int64_t *c = cnt.data() + (size_t)t * NB;
+        for (int64_t e = d->row_ptr[src_cut[t]]; e < d->row_ptr[src_cut[t + 1]]; e++) c[d->col[e] / span]++;
+    });
+    // offsets: bucket-major, then chunk order inside a bucket
+    std::vector<int64_t> boff(NB + 1, 0);
+    std::vector<int64_t> off((size_t)nt * NB);
+    int64_t acc = 0;
+    for (int64_t bk = 0; bk < NB; bk++) {
+        boff[bk] = acc;
+        for (unsigned t = 0; t < nt; t++) {
+            off[(size_t)t * NB + bk] = acc;
+            acc += cnt[(size_t)t * NB + bk];
+        }
+    }
+    boff[NB] = acc;
+    // edges grouped by bucket: (destination, source[, weight])
+    std::unique_ptr<int32_t[]> bdst(new int32_t[E]), bsrc(new int32_t[E]);  // (no zero fill)
+    std::unique_ptr<uint32_t[]> bw(wts ? new uint32_t[E] : nullptr);
+    run([&](unsigned t) {
+        int64_t *o = off.data() + (size_t)t * NB;
+        for (int64_t u = src_cut[t]; u < src_cut[t + 1]; u++)
+            for (int32_t e = d->row_ptr[u]; e < d->row_ptr[u + 1]; e++) {
+                const int32_t v = d->col[e];
+                const int64_t p = o[v / span]++;
+                bdst[p] = v;
+                bsrc[p] = (int32_t)u;
+                if (wts) bw[p] = d->w[e];
+            }
+    });
+    // each bucket: counting sort by destination (stable), row pointers of its range
+    std::atomic<int64_t> next{0};
+    run([&](unsigned) {
+        std::vector<int32_t> pos;
+        for (int64_t bk; (bk = next.fetch_add(1)) < NB;) {
+            const int64_t vlo = bk * span, vhi = std::min<int64_t>(V, vlo + span);
+            if (vlo >= vhi) continue;
+            const int64_t e0 = boff[bk], e1 = boff[bk + 1];
+            pos.assign((size_t)(vhi - vlo) + 1, 0);
+            for (int64_t i = e0; i < e1; i++) pos[bdst[i] - vlo + 1]++;
+            for (int64_t j = 0; j < vhi - vlo; j++) {  // pos[j]: first slot of destination vlo + j
+                pos[j + 1] += pos[j];
+                h.in_rp[vlo + j + 1] = (int32_t)(e0 + pos[j + 1]);
+            }
+            for (int64_t i = e0; i < e1; i++) {
+                const int64_t p = e0 + pos[bdst[i] - vlo]++;
+                h.in_col[p] = bsrc[i];
+                if (wts) h.in_w[p] = bw[i];
+            }
+        }
+    });
 }
 
 // PageRank contribution slots: the PR_HOT vertices with the most out-edges
@@ -234,7 +302,7 @@ static void build_tiles(const std::vector<int32_t> &rp, std::vector<int32_t> &ti
 // takes 12 bits and any vertex count fits; with `w` null they are {dst, src}
 // (sentinel source: the band base).
 static void build_pull(const std::vector<int32_t> &rp, const int32_t *src, const uint32_t *w,
-                       std::vector<uint2> &out, std::vector<uint4> &units, PullSlices &sl) {
+                       EdgeVec<uint2> &out, std::vector<uint4> &units, PullSlices &sl) {
     const int64_t V = (int64_t)rp.size() - 1;
     const int64_t nb = (V >> PULL_BAND_BITS) + 1;
     const int64_t nbin = pull_bins(V), S = nbin / PULL_SLICES;
@@ -275,10 +343,10 @@ static void build_pull(const std::vector<int32_t> &rp, const int32_t *src, const
     });
     std::vector<int64_t> pos((size_t)ng + 1, 0);
     for (int64_t g = 0; g < ng; g++) pos[g + 1] = pos[g] + (cnt[g] + PULL_VT - 1) / PULL_VT * PULL_VT;
-    out.assign((size_t)pos[ng], make_uint2(PULL_SENTINEL, 0u));
+    out.resize((size_t)pos[ng]);  // every slot is written below: a record or a sentinel
     for (int64_t g = 0; g < ng; g++) {  // sentinels: a source inside their band, weight 0
         const uint32_t bb = (uint32_t)((g % nb) << PULL_BAND_BITS);
-        for (int64_t i = pos[g] + cnt[g]; i < pos[g + 1]; i++) out[i].y = w ? 0u : bb;
+        for (int64_t i = pos[g] + cnt[g]; i < pos[g + 1]; i++) out[i] = make_uint2(PULL_SENTINEL, w ? 0u : bb);
     }
     std::vector<int64_t> fill(pos.begin(), pos.end() - 1);
     per_slice([&](int64_t v, int64_t g0) {
@@ -440,8 +508,17 @@ struct Uploader {
         return err;
     }
     hipError_t put_array(void *dev, const void *host, size_t bytes) {
-        return put(dev, bytes, [host](char *dst, size_t off, size_t n) {
-            std::memcpy(dst, static_cast<const char *>(host) + off, n);
+        return put(dev, bytes, [host](char *dst, size_t off, size_t n) {  // copied in 1 MiB pieces on the host threads
+            const int64_t pieces = (int64_t)((n + (size_t(1) << 20) - 1) >> 20);
+            parallel_for(
+                pieces,
+                [&](int64_t lo, int64_t hi) {
+                    for (int64_t i = lo; i < hi; i++) {
+                        const size_t a = (size_t)i << 20, len = std::min(n - a, size_t(1) << 20);
+                        std::memcpy(dst + a, static_cast<const char *>(host) + off + a, len);
+                    }
+                },
+                2);
         });
     }
     hipError_t finish(hipStream_t user) {
