@@ -5,6 +5,7 @@
 // next buffer; pointers rotate instead of data being copied between stages).
 #include <algorithm>
 #include <atomic>
+#include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
 #include <functional>
@@ -52,19 +53,89 @@ int occupancy_per_cu(const void *kernel, int block) {
     return per_cu;
 }
 
+// Host threads kept for the packaging passes (a load runs hundreds of them,
+// one per 16 MiB block, and starting threads for each would cost more than
+// the pass).  One pass at a time; a pass started from inside a pass, or
+// while another load holds the workers, runs on the calling thread.
+class HostWorkers {
+  public:
+    static HostWorkers &get() {
+        static HostWorkers w;
+        return w;
+    }
+    unsigned size() const { return (unsigned)workers_.size() + 1; }
+    // Runs job(t) for t = 0 .. size()-1, share 0 on the calling thread; false
+    // (nothing run) when the workers are busy.
+    bool run(const std::function<void(unsigned)> &job) {
+        std::unique_lock<std::mutex> busy(pass_, std::try_to_lock);
+        if (!busy.owns_lock() || in_pass_) return false;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            job_ = &job;
+            left_ = (unsigned)workers_.size();
+            gen_++;
+        }
+        cv_.notify_all();
+        in_pass_ = true;
+        job(0);
+        in_pass_ = false;
+        std::unique_lock<std::mutex> lk(mu_);
+        done_.wait(lk, [this] { return left_ == 0; });
+        job_ = nullptr;
+        return true;
+    }
+    ~HostWorkers() {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stop_ = true;
+            gen_++;
+        }
+        cv_.notify_all();
+        for (auto &t : workers_) t.join();
+    }
+
+  private:
+    HostWorkers() {
+        const unsigned n = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        for (unsigned t = 1; t < n; t++) workers_.emplace_back([this, t] { loop(t); });
+    }
+    void loop(unsigned t) {
+        uint64_t seen = 0;
+        std::unique_lock<std::mutex> lk(mu_);
+        while (true) {
+            cv_.wait(lk, [&] { return gen_ != seen; });
+            seen = gen_;
+            if (stop_) return;
+            const std::function<void(unsigned)> *job = job_;
+            lk.unlock();
+            in_pass_ = true;
+            (*job)(t);
+            in_pass_ = false;
+            lk.lock();
+            if (--left_ == 0) done_.notify_all();
+        }
+    }
+    std::vector<std::thread> workers_;
+    std::mutex pass_, mu_;
+    std::condition_variable cv_, done_;
+    const std::function<void(unsigned)> *job_ = nullptr;
+    unsigned left_ = 0;
+    uint64_t gen_ = 0;
+    bool stop_ = false;
+    static thread_local bool in_pass_;
+};
+thread_local bool HostWorkers::in_pass_ = false;
+
 template <class F>
 static void parallel_for(int64_t n, F f, int64_t serial_below = 65536) {
-    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    HostWorkers &w = HostWorkers::get();
+    const unsigned nt = w.size();
     if (n < serial_below || nt == 1) {
         f(0, n);
         return;
     }
-    std::vector<std::thread> th;
-    for (unsigned t = 0; t < nt; t++) {
-        int64_t lo = n * t / nt, hi = n * (t + 1) / nt;
-        th.emplace_back([=] { f(lo, hi); });
-    }
-    for (auto &x : th) x.join();
+    const std::function<void(unsigned)> job = [&](unsigned t) { f(n * t / nt, n * (t + 1) / nt); };
+    if (!w.run(job)) f(0, n);
 }
 
 // Host images built from the description before upload.
