@@ -1030,6 +1030,7 @@ def bench_sssp(args, gx, torch, np, gen):
     log(f"timing {args.steps} solves")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    marks = [t0]  # host clock after each solve (its run returns after the solve's last superstep)
     for _ in range(args.steps):
         state.reset()
         rs, _ = state.run(100_000)
@@ -1037,8 +1038,10 @@ def bench_sssp(args, gx, torch, np, gen):
         kern_ms += rs.edge_kernel_ms
         launches += rs.edge_kernel_launches
         edges += rs.edges
+        marks.append(time.perf_counter())
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    solve_ms = np.diff(marks) * 1e3
     assert edges == edges_per_solve * args.steps
     assert np.array_equal(state.values_numpy(), dist_ref)
     log(f"{dt * 1e3 / args.steps:.3f} ms/solve, relaxation kernel {kern_ms / args.steps:.3f} ms/solve "
@@ -1073,6 +1076,10 @@ def bench_sssp(args, gx, torch, np, gen):
     out = {
         "value": edges / dt / 1e9,
         "ms_per_step": dt * 1e3 / args.steps,
+        "solve_ms": {"median": float(np.median(solve_ms)), "min": float(solve_ms.min()),
+                     "max": float(solve_ms.max()),
+                     "what": "host clock between consecutive solves of the timed loop (the sync set of each "
+                             "solve is still in flight at its mark)"},
         "config": {
             "workload": f"Bellman-Ford SSSP to convergence from vertex 0, R-MAT scale {args.scale} "
                         f"({g.V} vertices, {16 * g.V} raw edges, a=0.57 b=0.19 c=0.19 d=0.05, seed 2, "
