@@ -95,7 +95,7 @@ typedef struct gx_graph_desc {
     const uint8_t *flags;
     uint32_t needs;
     uint32_t pr_tile_edges;  /* in-edges per PageRank workgroup tile: 0 = automatic (the largest of
-                                2048, 1024, 512 that still gives 2048 tiles, else 256), or one of
+                                1024, 512 that still gives 2048 tiles, else 256), or one of
                                 256, 512, 1024, 2048 */
     /* One part of a vertex-cut whose PageRank is exchanged between the parts
      * (gx_params.phases == GX_PHASES_MASTERS): the whole graph's vertex count
