@@ -57,10 +57,12 @@ struct ArenaAlloc {
         free_.clear();
         if (cap) free_[0] = cap;
     }
-    void *alloc(size_t n) {
+    // First fit, skipping free ranges that overlap [skip_off, skip_off + skip_len).
+    void *alloc(size_t n, size_t skip_off = 0, size_t skip_len = 0) {
         n = align_up(n);
         for (auto it = free_.begin(); it != free_.end(); ++it) {
             if (it->second < n) continue;
+            if (skip_len && it->first < skip_off + skip_len && skip_off < it->first + it->second) continue;
             size_t off = it->first, sz = it->second;
             free_.erase(it);
             if (sz > n) free_[off + n] = sz - n;
@@ -114,6 +116,7 @@ struct Pool {
     bool stage_busy[SLOTS] = {};
     int pending = 0;                   // copies handed to the completion thread, not yet delivered
     uint32_t *host_cnt = nullptr;      // pinned: SSSP epoch x B activation counts; PPR seeds and ends
+    size_t stage_bytes = 0, cnt_bytes = 0;
     std::vector<int64_t> lane_q;     // query id per lane, -1 = free
     std::vector<int64_t> lane_age;   // supersteps since the lane joined
     std::vector<int64_t> lane_done;  // finished, waiting for a staging slot: supersteps it took (-1 = running)
@@ -163,6 +166,33 @@ struct gx_server {
     std::deque<SQuery> queue;
     std::map<int64_t, SQuery> running;
     std::vector<gx_query_result> completed;
+    // Pinned host buffers of pools that went away, by size, for the next
+    // pools (allocating pinned memory costs milliseconds, paid under the
+    // scheduler's lock); at most PINNED_KEEP bytes are kept.
+    static constexpr size_t PINNED_KEEP = size_t(1) << 30;
+    std::multimap<size_t, void *> pinned_free;
+    size_t pinned_kept = 0;
+    void *pinned_take(size_t bytes) {
+        auto it = pinned_free.find(bytes);
+        if (it != pinned_free.end()) {
+            void *p = it->second;
+            pinned_free.erase(it);
+            pinned_kept -= bytes;
+            return p;
+        }
+        void *p = nullptr;
+        return hipHostMalloc(&p, bytes, hipHostMallocDefault) == hipSuccess ? p : nullptr;
+    }
+    void pinned_give(void *p, size_t bytes) {
+        if (!p) return;
+        if (pinned_kept + bytes > PINNED_KEEP) {
+            (void)hipHostFree(p);
+            return;
+        }
+        pinned_free.emplace(bytes, p);
+        pinned_kept += bytes;
+    }
+
     std::mutex mu;
     std::condition_variable cv_work, cv_done, cv_deliver;
     std::thread worker, deliverer;
@@ -175,6 +205,7 @@ struct gx_server {
     // for it; pools chosen to make room for it drain meanwhile
     bool reserved = false;
     int32_t res_graph = -1, res_algo = -1;
+    size_t res_off = 0, res_len = 0;  // the stretch drained for it (other pools stay out)
 
     ~gx_server() {
         {
@@ -190,6 +221,7 @@ struct gx_server {
         cv_deliver.notify_all();
         if (deliverer.joinable()) deliverer.join();
         for (auto &p : pools) destroy_pool(*p, false);
+        for (auto &f : pinned_free) (void)hipHostFree(f.second);
     }
 
     // Completion thread: waits for each staged copy, copies it into the
@@ -221,12 +253,12 @@ struct gx_server {
         if (p.done) (void)hipEventDestroy(p.done);
         for (int i = 0; i < Pool::SLOTS; i++) {
             if (p.stage_ev[i]) (void)hipEventDestroy(p.stage_ev[i]);
-            if (p.host_stage[i]) (void)hipHostFree(p.host_stage[i]);
+            pinned_give(p.host_stage[i], p.stage_bytes);
             p.stage_ev[i] = nullptr;
             p.host_stage[i] = nullptr;
         }
         if (p.stream) (void)hipStreamDestroy(p.stream);
-        if (p.host_cnt) (void)hipHostFree(p.host_cnt);
+        pinned_give(p.host_cnt, p.cnt_bytes);
         if (give_back && p.mem) arena.release(p.mem, p.bytes);
         p.stream = nullptr;
         p.done = nullptr;
@@ -237,10 +269,12 @@ struct gx_server {
     uint32_t epoch_max(int32_t algo) const { return algo == GX_SSSP ? cfg.sssp_epoch_supersteps : cfg.epoch_supersteps; }
 
     // Creates a pool for (graph, algo) inside the budget; nullptr if it does not fit.
-    Pool *create_pool(int32_t graph, int32_t algo, uint32_t B) {
+    // (skip: keep out of the stretch drained for another pair's reservation)
+    Pool *create_pool(int32_t graph, int32_t algo, uint32_t B, bool skip = false) {
         gx_graph *g = graphs[graph];
         size_t bytes = pool_bytes(g, algo, B, epoch_max(algo));
-        void *mem = arena.alloc(bytes);
+        const size_t so = skip ? res_off : 0, sl = skip ? res_len : 0;
+        void *mem = arena.alloc(bytes, so, sl);
         if (!mem) {  // evict idle empty pools, then retry
             for (size_t i = 0; i < pools.size();) {
                 Pool &p = *pools[i];
@@ -251,7 +285,7 @@ struct gx_server {
                     i++;
                 }
             }
-            mem = arena.alloc(bytes);
+            mem = arena.alloc(bytes, so, sl);
             if (!mem) return nullptr;
         }
         auto p = std::make_unique<Pool>();
@@ -269,14 +303,14 @@ struct gx_server {
         p->ends.assign(B, 0u);
         const DevGraph &d = g->d;
         Carver c(mem, bytes);
+        p->cnt_bytes = std::max<size_t>((size_t)epoch_max(algo), 2) * B * 4;
+        p->stage_bytes = std::max<size_t>(4, d.V * 4);
         bool ok = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) == hipSuccess &&
                   hipEventCreateWithFlags(&p->done, hipEventDisableTiming) == hipSuccess &&
-                  hipHostMalloc((void **)&p->host_cnt, std::max<size_t>((size_t)epoch_max(algo), 2) * B * 4,
-                                hipHostMallocDefault) == hipSuccess;
+                  (p->host_cnt = static_cast<uint32_t *>(pinned_take(p->cnt_bytes))) != nullptr;
         for (int i = 0; i < Pool::SLOTS && ok; i++)
             ok = hipEventCreateWithFlags(&p->stage_ev[i], hipEventDisableTiming) == hipSuccess &&
-                 hipHostMalloc((void **)&p->host_stage[i], std::max<size_t>(4, d.V * 4), hipHostMallocDefault) ==
-                     hipSuccess;
+                 (p->host_stage[i] = static_cast<uint32_t *>(pinned_take(p->stage_bytes))) != nullptr;
         if (algo == GX_SSSP) {
             p->D = c.take<uint32_t>((size_t)d.V * B);
             bs_layout(d, B, c, &p->bw);
@@ -562,6 +596,8 @@ struct gx_server {
             }
         }
         if (best_cost < 0) return;
+        res_off = seg[best_i].off;
+        res_len = seg[best_j].off + seg[best_j].len - res_off;
         for (size_t j = best_i; j <= best_j; j++)
             if (seg[j].pool) seg[j].pool->draining = true;
     }
@@ -572,10 +608,10 @@ struct gx_server {
     // the arena after evicting pools that are idle and empty.  When even that
     // leaves no room, the pair takes the reservation: the cheapest stretch of
     // the arena that would hold its pool is drained (its pools admit nothing
-    // more, finish what they run and are then evicted) and no other pair may
-    // carve a pool until the reserving pair has its own, so that steady
-    // traffic to the resident pairs or small pools filling the holes cannot
-    // starve a pair.
+    // more, finish what they run and are then evicted), and until the
+    // reserving pair has its own pool other pairs carve theirs only outside
+    // that stretch, so that steady traffic to the resident pairs or small
+    // pools filling the holes cannot starve a pair.
     void admit_queued() {
         for (size_t i = 0; i < pools.size();) {  // drained pools leave at once
             Pool &p = *pools[i];
@@ -614,16 +650,21 @@ struct gx_server {
             for (auto &pp : pools) draining_pool |= pp->graph == q.graph && pp->algo == q.algo && pp->draining;
             const bool mine = reserved && res_graph == q.graph && res_algo == q.algo;
             // a pair whose pools all drain waits for their eviction; while another
-            // pair holds the reservation only pools that already exist take queries
-            if (!target && !wait_boundary && (live_pool || !draining_pool || mine) && (!reserved || mine)) {
+            // pair holds the reservation, new pools keep out of its stretch
+            if (!target && !wait_boundary && (live_pool || !draining_pool || mine)) {
+                const bool skip = reserved && !mine;
                 const uint32_t B = pool_lanes(q.graph, q.algo);
-                target = create_pool(q.graph, q.algo, B);
-                if (!target && B > 32) target = create_pool(q.graph, q.algo, 32);
-                if (target && mine) reserved = false;
+                target = create_pool(q.graph, q.algo, B, skip);
+                if (!target && B > 32) target = create_pool(q.graph, q.algo, 32, skip);
+                if (target && mine) {
+                    reserved = false;
+                    res_len = 0;
+                }
                 if (!target && !live_pool && !reserved) {
                     reserved = true;
                     res_graph = q.graph;
                     res_algo = q.algo;
+                    res_len = 0;
                     plan_room(align_up(pool_bytes(graphs[q.graph], q.algo, 32, epoch_max(q.algo))));
                 }
             }
