@@ -322,9 +322,9 @@ __device__ __forceinline__ void ppr_apply(const BpArgs &a, int32_t r, int od, co
 }
 
 // PPR phase P of superstep k: pull tiles, one worker of W threads per tile,
-// lanes across the worker (W = 64: a wave, LPT lanes per thread; W = 32 or
-// 16: two or four workers per wave, one lane per thread, for batches of at
-// most W lanes).  The tile's edges are streamed in order: the worker loads
+// lanes across the worker (W = 64: a wave, LPT lanes per thread; W = 32, 16
+// or 8: two, four or eight workers per wave, one lane per thread, for
+// batches of at most W lanes).  The tile's edges are streamed in order: the worker loads
 // the tile's source ids at once (edge position p sits in lane p mod W of
 // register p / W), then loads the contribution rows of EB edges at a time
 // before adding any, so the row loads of consecutive edges overlap whatever
@@ -816,13 +816,15 @@ hipError_t bp_launch_superstep(const BpArgs &a, uint32_t k, int grid, hipStream_
     (void)hipGetDevice(&dev);
     const int cus = device_cus(dev);
     // the pull keeps its row gathers in flight from every wave the CUs hold
-    // (batches of at most 32 or 16 lanes run two or four tiles per wave)
+    // (batches of at most 32, 16 or 8 lanes run two, four or eight tiles per wave)
 #define GX_BP_PHASES(L, W)                                                                                  \
     hipLaunchKernelGGL((k_bp_pull<L, W>),                                                                   \
                        dim3(std::max(grid, cus * occupancy_per_cu((const void *)k_bp_pull<L, W>, 256))),  \
                        dim3(256), 0, s, a, k);                                                             \
     hipLaunchKernelGGL(k_bp_fix<L>, dim3(grid), dim3(256), 0, s, a, k);
-    if (a.Bw <= 16) {
+    if (a.Bw <= 8) {
+        GX_BP_PHASES(1, 8)
+    } else if (a.Bw <= 16) {
         GX_BP_PHASES(1, 16)
     } else if (a.Bw <= 32) {
         GX_BP_PHASES(1, 32)

@@ -152,17 +152,18 @@ def test_autotune_cache_file(gx, tmp_path, monkeypatch):
 
 
 def test_batched_ppr_narrow_workers_bitwise(gx):
-    """Batches of at most 16 or 32 lanes run two or four tiles per wave; each
-    lane still adds its row's contributions in edge order, so a batch of 3,
-    16, 17 or 32 lanes equals the same seeds inside a 64-lane batch bit for
-    bit (R-MAT scale 14: hub rows span many 256-edge tiles)."""
+    """Batches of at most 32, 16 or 8 lanes run two, four or eight tiles per
+    wave; each lane still adds its row's contributions in edge order, so a
+    batch of 3, 8, 9, 16, 17 or 32 lanes equals the same seeds inside a
+    64-lane batch bit for bit (R-MAT scale 14: hub rows span many 256-edge
+    tiles)."""
     g = gen.rmat(14, seed=9)
     dg = load(gx, g)
     src = gen.pick_sources(g, 64, seed=46)
     src[0] = 0
     wide, _ = gx.batch_run(dg, gx.GX_PPR, src, iters=20)
     W = wide.cpu().numpy().view(np.uint32)
-    for B in (3, 16, 17, 32):
+    for B in (3, 8, 9, 16, 17, 32):
         narrow, _ = gx.batch_run(dg, gx.GX_PPR, src[:B], iters=20)
         assert np.array_equal(narrow.cpu().numpy().view(np.uint32), W[:, :B]), B
     ref = oracle.ppr(g, int(src[2]), 20)
