@@ -281,11 +281,10 @@ __global__ __launch_bounds__(256) void k_bs_lane_reset(uint32_t *D, uint32_t *Mc
 // ------------------------------------------------------------------ PPR
 
 // Per-lane constants of one PPR superstep, held in registers: lane b =
-// lane + W i (W threads per worker) is live when it is inside the processed
-// width, holds a query and has not reached its end superstep (a finished
-// lane is frozen: its values stay as they were after its last superstep, in
-// x[end & 1]).
-template <int LPT, int W = 64>
+// lane + 64 i is live when it is inside the processed width, holds a query
+// and has not reached its end superstep (a finished lane is frozen: its
+// values stay as they were after its last superstep, in x[end & 1]).
+template <int LPT>
 struct PprLanes {
     uint32_t bl[LPT];  // load column (clamped into the processed width)
     bool live[LPT];
@@ -294,7 +293,7 @@ struct PprLanes {
     __device__ PprLanes(const BpArgs &a, uint32_t k, const double *Dcur, int lane) {
 #pragma unroll
         for (int i = 0; i < LPT; i++) {
-            const uint32_t b = lane + W * i;
+            const uint32_t b = lane + 64 * i;
             bl[i] = min(b, a.Bw - 1);
             const int32_t sd = b < a.Bw ? a.seed[b] : -1;
             live[i] = sd >= 0 && (!a.end || (int32_t)((uint32_t)a.end[b] - k) > 0);
@@ -304,14 +303,14 @@ struct PprLanes {
     }
 };
 
-template <int LPT, int W = 64>
+template <int LPT>
 __device__ __forceinline__ void ppr_apply(const BpArgs &a, int32_t r, int od, const double (&acc)[LPT],
-                                          const PprLanes<LPT, W> &L, float *x_out, float *c_out,
-                                          double (&dang)[LPT], int lane) {
+                                          const PprLanes<LPT> &L, float *x_out, float *c_out, double (&dang)[LPT],
+                                          int lane) {
 #pragma unroll
     for (int i = 0; i < LPT; i++) {
         if (!L.live[i]) continue;
-        const uint32_t b = lane + W * i;
+        const uint32_t b = lane + 64 * i;
         double v = (double)a.d * acc[i];
         if (L.seed[i] == r) v += (1.0 - (double)a.d) + (double)a.d * L.dc[i];
         const float xn = (float)v;
@@ -321,35 +320,29 @@ __device__ __forceinline__ void ppr_apply(const BpArgs &a, int32_t r, int od, co
     }
 }
 
-// PPR phase P of superstep k: pull tiles, one worker of W threads per tile,
-// lanes across the worker (W = 64: a wave, LPT lanes per thread; W = 32, 16
-// or 8: two, four or eight workers per wave, one lane per thread, for
-// batches of at most W lanes).  The tile's edges are streamed in order: the worker loads
-// the tile's source ids at once (edge position p sits in lane p mod W of
-// register p / W), then loads the contribution rows of EB edges at a time
+// PPR phase P of superstep k: pull tiles, one wave per tile, lanes across
+// the wave.  The tile's edges are streamed in order: the wave loads the
+// tile's source ids at once (edge position p sits in lane p mod 64 of
+// register p / 64), then loads the contribution rows of EB edges at a time
 // before adding any, so the row loads of consecutive edges overlap whatever
 // rows they belong to.  A running segment (the head of a row begun in an earlier
 // tile, then the rows that start in this tile) closes when the position
-// passes its end; row ends and out-degrees come from a window of W rows
+// passes its end; row ends and out-degrees come from a window of 64 rows
 // loaded one per lane.  Each lane adds its row's contributions in edge
-// order whatever W is, so results depend neither on the batching nor on
-// the worker width.
-template <int LPT, int W>
+// order, so results do not depend on the batching.
+template <int LPT>
 __device__ __forceinline__ void bp_pull(const BpArgs &a, uint32_t k, const double *Dcur) {
-    static_assert(W == 64 || LPT == 1, "narrow workers hold one lane per thread");
-    constexpr int NW = 64 / W;                     // workers per wave
     constexpr int EB = 16 / (LPT == 3 ? 4 : LPT);  // edges whose rows are loaded before any is added
-    constexpr int CR = BP_TILE / W;                // source-id registers per lane
-    __shared__ int2 s_win[4][64];        // per wave (blocks of 256 threads): W rows per worker
-    const int lane = threadIdx.x & (W - 1), wv = (threadIdx.x >> 6) & 3, sub = (threadIdx.x & 63) / W;
-    int2 *win = &s_win[wv][sub * W];
-    const int64_t gwork = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * NW + sub;
-    const int64_t nwork = (int64_t)gridDim.x * (blockDim.x >> 6) * NW;
+    constexpr int CR = BP_TILE / 64;               // source-id registers per lane
+    __shared__ int2 s_win[4][64];        // per wave (blocks of 256 threads)
+    const int lane = threadIdx.x & 63, wv = (threadIdx.x >> 6) & 3;
+    const int64_t gwave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
     float *x_out = a.x[(k + 1) & 1];
     const float *c_in = a.c[k & 1];
     float *c_out = a.c[(k + 1) & 1];
-    const PprLanes<LPT, W> L(a, k, Dcur, lane);
-    for (int64_t t = gwork; t < a.ntiles; t += nwork) {
+    const PprLanes<LPT> L(a, k, Dcur, lane);
+    for (int64_t t = gwave; t < a.ntiles; t += nwaves) {
         const int32_t e0 = (int32_t)(t * BP_TILE);
         const int32_t e1 = (int32_t)std::min<int64_t>((int64_t)e0 + BP_TILE, a.E);
         const int n = e1 - e0;  // 0 only when E == 0
@@ -358,7 +351,7 @@ __device__ __forceinline__ void bp_pull(const BpArgs &a, uint32_t k, const doubl
         if (lane == 0) a.spill[t] = -1;
         int32_t col[CR];
 #pragma unroll
-        for (int q = 0; q < CR; q++) col[q] = n > 0 ? a.in_col[e0 + min(lane + W * q, n - 1)] : 0;
+        for (int q = 0; q < CR; q++) col[q] = n > 0 ? a.in_col[e0 + min(lane + 64 * q, n - 1)] : 0;
         const int32_t first_start = r_lo < a.V ? a.in_rp[r_lo] : (int32_t)a.E;
         // Row window in LDS: entry j holds the end and out-degree of row
         // r_lo + wb + j.  (Values in LDS are waited for on their own counter;
@@ -368,7 +361,7 @@ __device__ __forceinline__ void bp_pull(const BpArgs &a, uint32_t k, const doubl
         auto load_window = [&]() {
             const int32_t rq = r_lo + wb + min(lane, nrows - wb - 1);
             const int32_t re = a.in_rp[rq + 1], od = a.outdeg[rq];
-            win[lane] = make_int2(re, od);
+            s_win[wv][lane] = make_int2(re, od);
             __builtin_amdgcn_wave_barrier();
         };
         if (nrows > 0) load_window();
@@ -387,30 +380,30 @@ __device__ __forceinline__ void bp_pull(const BpArgs &a, uint32_t k, const doubl
                 if (head_end > 0)
 #pragma unroll
                     for (int i = 0; i < LPT; i++)
-                        if (lane + W * i < (int)a.Bw) a.head[t * a.B + lane + W * i] = acc[i];
+                        if (lane + 64 * i < (int)a.Bw) a.head[t * a.B + lane + 64 * i] = acc[i];
             } else {
                 const int32_t r = r_lo + seg;
-                const int2 w = win[seg - wb];
+                const int2 w = s_win[wv][seg - wb];
                 const int32_t re = w.x;
                 if (re > e1) {  // continues into later tiles: a partial for the fix phase
 #pragma unroll
                     for (int i = 0; i < LPT; i++)
-                        if (lane + W * i < (int)a.Bw) a.tailp[t * a.B + lane + W * i] = acc[i];
+                        if (lane + 64 * i < (int)a.Bw) a.tailp[t * a.B + lane + 64 * i] = acc[i];
                     if (lane == 0) a.spill[t] = r;
                 } else {
-                    ppr_apply<LPT, W>(a, r, w.y, acc, L, x_out, c_out, dang, lane);
+                    ppr_apply<LPT>(a, r, w.y, acc, L, x_out, c_out, dang, lane);
                 }
             }
 #pragma unroll
             for (int i = 0; i < LPT; i++) acc[i] = 0.0;
             seg++;
             if (seg < nrows) {
-                if (seg - wb == W) {  // next window of rows
+                if (seg - wb == 64) {  // next window of rows
                     wb = seg;
                     __builtin_amdgcn_wave_barrier();
                     load_window();
                 }
-                seg_end = std::min(win[seg - wb].x, e1) - e0;
+                seg_end = std::min(s_win[wv][seg - wb].x, e1) - e0;
             } else {
                 seg_end = 0x7FFFFFFF;
             }
@@ -429,8 +422,8 @@ __device__ __forceinline__ void bp_pull(const BpArgs &a, uint32_t k, const doubl
                 int32_t c = col[0];
 #pragma unroll
                 for (int q = 1; q < CR; q++)
-                    if (p / W == q) c = col[q];
-                const int32_t u = __shfl(c, p & (W - 1), W);
+                    if ((p >> 6) == q) c = col[q];
+                const int32_t u = __shfl(c, p & 63, 64);
                 const float *row = c_in + (size_t)u * a.B;
 #pragma unroll
                 for (int i = 0; i < LPT; i++) v[jj][i] = row[L.bl[i]];
@@ -450,7 +443,7 @@ __device__ __forceinline__ void bp_pull(const BpArgs &a, uint32_t k, const doubl
         while (seg < nrows) close();  // the open segment, then rows with no edges left in this tile
 #pragma unroll
         for (int i = 0; i < LPT; i++)
-            if (lane + W * i < (int)a.Bw) a.dsum[t * a.B + lane + W * i] = dang[i];
+            if (lane + 64 * i < (int)a.Bw) a.dsum[t * a.B + lane + 64 * i] = dang[i];
     }
 }
 
@@ -530,8 +523,8 @@ __device__ __forceinline__ void bp_dang2(const BpArgs &a, double *Dnext) {
 }
 
 // The four phases as ordinary launches (batched runs and serving).
-template <int LPT, int W>
-__global__ __launch_bounds__(256) void k_bp_pull(BpArgs a, uint32_t k) { bp_pull<LPT, W>(a, k, a.D[k & 1]); }
+template <int LPT>
+__global__ __launch_bounds__(256) void k_bp_pull(BpArgs a, uint32_t k) { bp_pull<LPT>(a, k, a.D[k & 1]); }
 template <int LPT>
 __global__ __launch_bounds__(256) void k_bp_fix(BpArgs a, uint32_t k) { bp_fix<LPT>(a, k, a.D[k & 1]); }
 __global__ __launch_bounds__(256) void k_bp_dang1(BpArgs a) { bp_dang1(a); }
@@ -816,25 +809,16 @@ hipError_t bp_launch_superstep(const BpArgs &a, uint32_t k, int grid, hipStream_
     (void)hipGetDevice(&dev);
     const int cus = device_cus(dev);
     // the pull keeps its row gathers in flight from every wave the CUs hold
-    // (batches of at most 32, 16 or 8 lanes run two, four or eight tiles per wave)
-#define GX_BP_PHASES(L, W)                                                                                  \
-    hipLaunchKernelGGL((k_bp_pull<L, W>),                                                                   \
-                       dim3(std::max(grid, cus * occupancy_per_cu((const void *)k_bp_pull<L, W>, 256))),  \
-                       dim3(256), 0, s, a, k);                                                             \
+#define GX_BP_PHASES(L)                                                                                  \
+    hipLaunchKernelGGL(k_bp_pull<L>,                                                                     \
+                       dim3(std::max(grid, cus * occupancy_per_cu((const void *)k_bp_pull<L>, 256))),  \
+                       dim3(256), 0, s, a, k);                                                          \
     hipLaunchKernelGGL(k_bp_fix<L>, dim3(grid), dim3(256), 0, s, a, k);
-    if (a.Bw <= 8) {
-        GX_BP_PHASES(1, 8)
-    } else if (a.Bw <= 16) {
-        GX_BP_PHASES(1, 16)
-    } else if (a.Bw <= 32) {
-        GX_BP_PHASES(1, 32)
-    } else {
-        switch (lpt) {
-            case 1: GX_BP_PHASES(1, 64) break;
-            case 2: GX_BP_PHASES(2, 64) break;
-            case 3: GX_BP_PHASES(3, 64) break;
-            default: GX_BP_PHASES(4, 64) break;
-        }
+    switch (lpt) {
+        case 1: GX_BP_PHASES(1) break;
+        case 2: GX_BP_PHASES(2) break;
+        case 3: GX_BP_PHASES(3) break;
+        default: GX_BP_PHASES(4) break;
     }
 #undef GX_BP_PHASES
     hipLaunchKernelGGL(k_bp_dang1, dim3(grid), dim3(256), 0, s, a);

@@ -536,7 +536,7 @@ struct gx_server {
             uint32_t hi = 0;
             for (uint32_t b = 0; b < p.B; b++)
                 if (p.lane_q[b] >= 0) hi = b + 1;
-            a.Bw = std::min<uint32_t>(p.B, hi <= 8 ? 8u : (hi + 15) / 16 * 16);
+            a.Bw = std::min<uint32_t>(p.B, (hi + 15) / 16 * 16);
             for (uint32_t it = 0; it < p.epoch_len; it++)
                 if (bp_launch_superstep(a, p.k + it, grid, p.stream) != hipSuccess) return false;
         }

@@ -151,12 +151,11 @@ def test_autotune_cache_file(gx, tmp_path, monkeypatch):
     assert len(path.read_text().splitlines()) == 2
 
 
-def test_batched_ppr_narrow_workers_bitwise(gx):
-    """Batches of at most 32, 16 or 8 lanes run two, four or eight tiles per
-    wave; each lane still adds its row's contributions in edge order, so a
-    batch of 3, 8, 9, 16, 17 or 32 lanes equals the same seeds inside a
-    64-lane batch bit for bit (R-MAT scale 14: hub rows span many 256-edge
-    tiles)."""
+def test_batched_ppr_batch_widths_bitwise(gx):
+    """Each lane adds its row's contributions in edge order whatever the
+    batch width, so a batch of 3, 8, 9, 16, 17 or 32 lanes (fewer processed
+    lanes than a wave holds) equals the same seeds inside a 64-lane batch bit
+    for bit (R-MAT scale 14: hub rows span many 256-edge tiles)."""
     g = gen.rmat(14, seed=9)
     dg = load(gx, g)
     src = gen.pick_sources(g, 64, seed=46)
